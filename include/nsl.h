@@ -1,0 +1,303 @@
+/*
+ * nsl.h -- C ABI of the NeRF-SLAM mapping step on AMD Instinct MI355X (gfx950).
+ *
+ * The paper (Rosinol, Leonard, Carlone, "NeRF-SLAM") trains a hash-grid
+ * radiance field from the output of dense monocular SLAM: keyframe images,
+ * poses, dense depth maps and their marginal covariances (Sec. 3.1, Eq. 2,
+ * and Sec. 3.3: the tracking thread sends them on every new keyframe).  The
+ * mapping thread minimises  L_M = L_rgb + lambda_D * L_D  over the field
+ * parameters (Sec. 3.2, Eq. 3, lambda_D = 1.0) using all keyframes received,
+ * with the depth loss weighted by the depth covariance (Eq. 4), rendered
+ * depth as the expected termination distance (Eq. 5), transmittance (Eq. 6)
+ * and the photometric loss (Eq. 7).  This library is that training step, one
+ * call per iteration, plus forward rendering (Sec. 3.3, last paragraph).
+ *
+ * Conventions (every call):
+ *  - Every function returns an int status: NSL_OK (0) or a negative NSL_E_*.
+ *    On error nsl_last_error() returns a thread-local message.  No C++
+ *    exception crosses the ABI.
+ *  - All device memory is owned by the caller and passed as plain device
+ *    pointers; the library never allocates device memory.  Calls that need
+ *    scratch space take a caller workspace whose size a *_workspace_bytes
+ *    query returns (NSL_E_WORKSPACE if too small).  Host-side handles
+ *    (nsl_field, nsl_mapper) are small host allocations.
+ *  - Calls are asynchronous on the given stream; results are valid after the
+ *    stream is synchronised.  Pointers must stay valid until then.
+ *  - Camera model: pinhole, OpenCV axes (x right, y down, z forward);
+ *    pose = camera-to-world [R | t], 3x4 row-major float; intrinsics
+ *    (fx, fy, cx, cy); pixel (u, v) has its centre at (u+1/2, v+1/2).
+ *    Depths and variances at the boundary are z-depth D_z and its variance
+ *    Sigma_D in m^2 (the paper's Sigma_D, Eq. 4); internally distances are
+ *    measured along the unit ray direction.
+ *  - Pixel ids address keyframe slot k, row v, column u as k*H*W + v*W + u.
+ *  - Unusable depth measurements (non-finite D_z, non-finite or non-positive
+ *    Sigma_D) are masked (weight 0), not errors; their count is reported.
+ */
+#ifndef NSL_H_
+#define NSL_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NSL_OK 0
+#define NSL_E_INVALID -1     /* null pointer, bad shape, bad or unsupported config */
+#define NSL_E_WORKSPACE -2   /* workspace smaller than the size query returned */
+#define NSL_E_HIP -3         /* a HIP runtime call failed; message has the code */
+#define NSL_E_BUDGET -4      /* request exceeds the configured memory budget */
+#define NSL_E_CAPACITY -5    /* keyframe store full */
+
+#define NSL_F32 0
+#define NSL_F16 1
+#define NSL_BF16 2
+
+#define NSL_SAMPLER_UNIFORM 0
+#define NSL_SAMPLER_OCCUPANCY 1
+
+#define NSL_MAX_LEVELS 16
+#define NSL_MAX_LAYERS 8
+
+/* Last error message of the calling thread ("" if none). */
+const char* nsl_last_error(void);
+
+/* ABI version (major*100 + minor). */
+int nsl_version(void);
+
+/* ------------------------------------------------------------------------
+ * Field: multiresolution hash grid + density net + colour net.
+ *
+ * The paper builds its map on Instant-NGP and defers the network inputs to
+ * it (Sec. 3.2 after Eq. 5; Sec. 3.4).  Level l has resolution
+ * N_l = floor(base_res * b^l) (b = per_level_scale, or, if that is <= 0,
+ * b = exp((ln max_res - ln base_res)/(levels-1)); with max_res > 0 the top
+ * level is max_res).  A level with (N_l+1)^3 <= 2^log2_table entries is
+ * dense (index x + (N+1)(y + (N+1)z)), otherwise hashed
+ * ((x ^ 2654435761 y ^ 805459861 z) mod 2^log2_table).  Trilinear weights
+ * use p = xn*N_l, i0 = min(floor(p), N_l-1).  Density: h = ReLU(e W1),
+ * o = h W2 (geo_dim = 16 wide), sigma = exp(o_0).  Colour: c =
+ * sigmoid(MLP([o_0..o_15, SH(d)])) with ReLU hidden layers, real
+ * orthonormal SH of sh_bands bands.  Layers are bias-free.
+ *
+ * Supported shapes (compiled kernels): feat_per_level 2, geo_dim 16 and
+ *   levels 4,  density_hidden 32, colour_hidden {32},     sh_bands 3, or
+ *   levels 16, density_hidden 64, colour_hidden {64, 64}, sh_bands 4.
+ * Anything else returns NSL_E_INVALID from nsl_field_create.
+ * ------------------------------------------------------------------------ */
+typedef struct nsl_field_config {
+  int32_t levels;
+  int32_t feat_per_level;
+  int32_t log2_table;
+  int32_t base_res;
+  float per_level_scale; /* <= 0: derived from max_res */
+  int32_t max_res;       /* 0: none */
+  int32_t density_hidden;
+  int32_t geo_dim;
+  int32_t sh_bands;
+  int32_t n_colour_hidden;
+  int32_t colour_hidden[4];
+  float aabb_min[3];
+  float aabb_max[3];
+} nsl_field_config;
+
+/* Parameter vector layout: FP32, the tables first (level-major, then entry,
+ * then feature), then every weight matrix [fan_in, fan_out] row-major in
+ * network order (W1, W2, colour layers...), each block starting at a
+ * multiple of 64 floats. */
+typedef struct nsl_param_layout {
+  int32_t levels;
+  int32_t res[NSL_MAX_LEVELS];
+  int32_t dense[NSL_MAX_LEVELS];
+  int64_t level_entries[NSL_MAX_LEVELS];
+  int64_t level_offset[NSL_MAX_LEVELS]; /* in entries */
+  int64_t table_floats;
+  int32_t n_layers;
+  int64_t w_offset[NSL_MAX_LAYERS]; /* in floats */
+  int32_t w_in[NSL_MAX_LAYERS];
+  int32_t w_out[NSL_MAX_LAYERS];
+  int64_t total_floats;
+} nsl_param_layout;
+
+typedef struct nsl_field nsl_field;
+
+/* Fill *out from cfg (host-only arithmetic). */
+int nsl_field_layout(const nsl_field_config* cfg, nsl_param_layout* out);
+int nsl_field_create(const nsl_field_config* cfg, nsl_field** out);
+void nsl_field_destroy(nsl_field* f);
+
+/* ------------------------------------------------------------------------
+ * Mapper: keyframe store and occupancy grid (Sec. 3.3: the mapping thread
+ * optimises all keyframes received; tracking re-sends the keyframes of its
+ * window, whose poses and depths it keeps re-estimating).
+ *
+ * Storage is a caller-owned device buffer of nsl_mapper_storage_bytes().
+ * ------------------------------------------------------------------------ */
+typedef struct nsl_mapper nsl_mapper;
+
+size_t nsl_mapper_storage_bytes(int max_keyframes, int H, int W, int grid_res);
+int nsl_mapper_create(int max_keyframes, int H, int W, int grid_res, void* storage,
+                      size_t storage_bytes, nsl_mapper** out);
+void nsl_mapper_destroy(nsl_mapper* m);
+/* Number of keyframe slots in use. */
+int nsl_mapper_count(const nsl_mapper* m);
+
+/* Insert or update n keyframes.  ids: host array of caller ids; an id seen
+ * before overwrites its slot, a new id takes the next free slot (slots in
+ * order of first arrival; NSL_E_CAPACITY when full, nothing copied).
+ *   rgb       [n,H,W,3] float in [0,1]
+ *   pose      [n,3,4]   camera-to-world
+ *   intr      [n,4]     fx, fy, cx, cy
+ *   depth     [n,H,W]   z-depth D_z
+ *   depth_var [n,H,W]   Sigma_D (m^2)
+ * src_on_host: 1 if the arrays are host memory, 0 if device memory. */
+int nsl_keyframes_upsert(nsl_mapper* m, int n, const int32_t* ids, const float* rgb,
+                         const float* pose, const float* intr, const float* depth,
+                         const float* depth_var, int src_on_host, hipStream_t stream);
+/* Slot of caller id, or -1. */
+int nsl_keyframe_slot(const nsl_mapper* m, int32_t id);
+
+/* Occupancy bitfield over the field's AABB: res^3 bits (res given at
+ * creation), cell (x,y,z) -> bit x + res*(y + res*z), uint32 words, least
+ * significant bit first. */
+int nsl_occupancy_set(nsl_mapper* m, const uint32_t* bits, int src_on_host,
+                      hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Training step.
+ *
+ * Rays: pixel_ids[n_candidates] (device) in keyframe slots.  Samples:
+ *  - NSL_SAMPLER_UNIFORM:   t_i = t_near + (i+1/2)*dt, i < n_uniform;
+ *  - NSL_SAMPLER_OCCUPANCY: lattice t_k = (k+1/2)*dt from the ray origin,
+ *    kept iff t_near <= t_k <= t_far, the point is inside the closed AABB
+ *    and its occupancy bit is set; at most max_per_ray per ray.
+ * Every sample has bin width delta = dt (Eq. 5 takes delta_i = d_{i+1}-d_i;
+ * with midpoint bins this is dt for every interior pair, and empty space
+ * skipped by the grid has sigma = 0).  Candidates are kept in order while
+ * their inclusive sample prefix is <= max_samples; kept candidates with at
+ * least one sample are the R rays of the batch.
+ *
+ * Loss (Eq. 3, 4, 7), mean over the R rays:
+ *   L_rgb = mean_r sum_ch (I*_r - I_r)^2
+ *   L_D   = mean_r (d*_r - D_r)^2 / Sigma_D,r   (ray units; invariant to z/ray)
+ *   L     = L_rgb + lambda_d * L_D
+ * Rendering (Eq. 5, 6): w_i = T_i (1 - exp(-sigma_i delta)), I* = sum w_i c_i,
+ * d* = sum w_i t_i; also V* = sum w_i (t_i - d*)^2 and A = sum w_i; no
+ * background colour, no normalisation by A.
+ *
+ * Gradients are ACCUMULATED (+=) into grads, scaled by loss_scale, unless
+ * zero_grads = 1 (grads are cleared first).  With do_adam = 1 the step then
+ * applies bias-corrected Adam at step adam_step (>= 1) to every parameter
+ * with gradient grads/loss_scale and clears grads afterwards.
+ *
+ * loss_out (device, 3 floats): L, L_rgb, L_D.  stats_out (device, may be
+ * NULL).  ray_out (device, may be NULL): [n_candidates, 6] per candidate:
+ * r, g, b, depth_z = d* / s, var_z = V* / s^2, opacity A (zeros for candidates
+ * that are not rays of the batch).
+ * ------------------------------------------------------------------------ */
+typedef struct nsl_step_config {
+  int32_t sampler;
+  float t_near, t_far, dt;
+  int32_t n_uniform;
+  int32_t max_per_ray;
+  int32_t max_samples;
+  float lambda_d;
+  int32_t zero_grads;
+  int32_t do_adam;
+  float lr, beta1, beta2, eps;
+  int32_t adam_step;
+  float loss_scale;
+} nsl_step_config;
+
+typedef struct nsl_step_stats {
+  uint32_t n_rays;        /* R */
+  uint32_t n_samples;     /* S */
+  uint32_t n_kept;        /* kept candidates (including zero-sample ones) */
+  uint32_t n_masked;      /* rays whose depth measurement was unusable */
+} nsl_step_stats;
+
+size_t nsl_step_workspace_bytes(const nsl_field* f, const nsl_step_config* cfg,
+                                int n_candidates);
+int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grads,
+                   float* adam_m, float* adam_v, const nsl_step_config* cfg,
+                   const uint32_t* pixel_ids, int n_candidates, void* workspace,
+                   size_t workspace_bytes, float* loss_out, nsl_step_stats* stats_out,
+                   float* ray_out, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Kernel-level entry points: the same kernels as the step, one phase each.
+ * ------------------------------------------------------------------------ */
+
+/* Rays and samples of the step for the given candidates (the sampler of
+ * nsl_train_step).  Outputs (device): counts[n_candidates] samples per
+ * candidate before the cut, offsets[n_candidates+1] exclusive prefix,
+ * t[max_samples] and ray[max_samples] (candidate index of each sample) for
+ * the kept candidates, stats (device).  Workspace: nsl_step_workspace_bytes. */
+int nsl_march(nsl_mapper* m, const nsl_field* f, const nsl_step_config* cfg,
+              const uint32_t* pixel_ids, int n_candidates, void* workspace,
+              size_t workspace_bytes, uint32_t* counts, uint32_t* offsets, float* t,
+              uint32_t* ray, nsl_step_stats* stats_out, hipStream_t stream);
+
+/* Field at S normalised positions xn [S,3] in [0,1]^3 with unit view
+ * directions dirs [S,3]: sigma [S], rgb [S,3].  Workspace:
+ * nsl_field_workspace_bytes (holds the weights laid out for the MFMA
+ * operands, and the per-block weight gradients of nsl_field_bwd). */
+size_t nsl_field_workspace_bytes(const nsl_field* f);
+int nsl_field_fwd(const nsl_field* f, const float* params, const float* xn, const float* dirs,
+                  int S, float* sigma, float* rgb, void* workspace, size_t workspace_bytes,
+                  hipStream_t stream);
+
+/* Adjoint of nsl_field_fwd: accumulates (+=) dL/dparams into grads given
+ * dsigma [S] and drgb [S,3].  The table part is scattered with atomics
+ * (summation order unspecified); the weight part is reduced in a fixed
+ * order. */
+int nsl_field_bwd(const nsl_field* f, const float* params, const float* xn, const float* dirs,
+                  int S, const float* dsigma, const float* drgb, float* grads, void* workspace,
+                  size_t workspace_bytes, hipStream_t stream);
+
+/* Compositing of R rays whose samples are contiguous: ray r owns samples
+ * [ray_off[r], ray_off[r+1]).  out[R,6] = (r, g, b, d*, V*, A) in ray
+ * units (Eq. 5, 6).  With stop_T > 0 a ray stops before the first sample
+ * with T_i < stop_T (early termination; 0 disables). */
+int nsl_composite_fwd(const float* sigma, const float* rgb, const float* t,
+                      const uint32_t* ray_off, int R, float delta, float stop_T, float* out,
+                      hipStream_t stream);
+
+/* Adjoint of nsl_composite_fwd (stop_T = 0) for seeds g_rgb [R,3],
+ * g_depth [R], g_var [R] (any of the three may be NULL = 0):
+ * g_sigma [S], g_rgb_s [S,3]. */
+int nsl_composite_bwd(const float* sigma, const float* rgb, const float* t,
+                      const uint32_t* ray_off, int R, float delta, const float* g_rgb,
+                      const float* g_depth, const float* g_var, float* g_sigma,
+                      float* g_rgb_s, hipStream_t stream);
+
+/* Bias-corrected Adam over n parameters, gradient = grads * grad_scale;
+ * clears grads. */
+int nsl_adam(float* params, float* grads, float* m, float* v, int64_t n, float lr, float beta1,
+             float beta2, float eps, int step, float grad_scale, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Rendering (Sec. 3.3: the mapping thread renders for visualisation).
+ * Uniform samples t_i = t_near + (i+1/2)*dt, i < n_samples, early
+ * termination before the first sample with T_i < stop_T.  Outputs [H*W]
+ * (rgb [H*W,3]); opacity may be NULL.
+ * ------------------------------------------------------------------------ */
+typedef struct nsl_render_config {
+  float t_near, dt;
+  int32_t n_samples;
+  float stop_T;
+} nsl_render_config;
+
+size_t nsl_render_workspace_bytes(const nsl_field* f, int H, int W,
+                                  const nsl_render_config* cfg);
+int nsl_render(const nsl_field* f, const float* params, const float* pose, const float* intr,
+               int H, int W, const nsl_render_config* cfg, float* rgb, float* depth_z,
+               float* var_z, float* opacity, void* workspace, size_t workspace_bytes,
+               hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSL_H_ */

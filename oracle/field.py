@@ -243,9 +243,15 @@ def mlp_fwd(spec, ws, e, e_mag, sh, band=1e-5):
         ambs.append(amb)
         cur, cur_m = h, pre_m * np.where(amb, 1.0, mk)
     z = cur @ W[-1]
+    z_m = cur_m @ np.abs(W[-1])
     colour = 1.0 / (1.0 + np.exp(-z))
+    # value magnitudes of the outputs: sigma = exp(o_0) inherits the absolute
+    # error of o_0 as a relative error; sigmoid damps it by c(1-c).
+    sigma_mag = sigma * (1.0 + o_m[:, 0])
+    colour_mag = colour + colour * (1.0 - colour) * z_m
     a.update(pre1=pre1, h1=h1, mask1=m1, amb1=amb1, o=o, sigma=sigma, hidden_in=hs,
-             masks=ms, ambs=ambs, last_in=cur, z=z, colour=colour)
+             masks=ms, ambs=ambs, last_in=cur, z=z, colour=colour, sigma_mag=sigma_mag,
+             colour_mag=colour_mag)
     return a
 
 

@@ -70,6 +70,7 @@ def train_step(spec, sampler, kf, table, ws, pixel_ids, occupancy=None, lam=1.0,
     out_d = np.zeros(R)
     out_v = np.zeros(R)
     out_a = np.zeros(R)
+    var_mag = np.zeros(R)
     fws = []
     for i in range(R):
         a, b = offs[i], offs[i + 1]
@@ -77,6 +78,9 @@ def train_step(spec, sampler, kf, table, ws, pixel_ids, occupancy=None, lam=1.0,
                                   np.full(b - a, sampler.dt))
         fws.append(fw)
         out_rgb[i], out_d[i], out_v[i], out_a[i] = fw["C"], fw["D"], fw["V"], fw["A"]
+        # magnitude of V*: sum of w (|t| + |d*|)^2 bounds the rounding of the
+        # differences t - d* as well as of the sum itself
+        var_mag[i] = float((fw["w"] * (np.abs(t_all[a:b]) + abs(fw["D"])) ** 2).sum())
     l_rgb, l_d, gC, gD, gC_m, gD_m = render.loss_seeds(out_rgb, out_d, I[sel], Dray[sel],
                                                        prec[sel], R, lam)
     L_rgb = l_rgb.sum() / R if R else 0.0
@@ -99,6 +103,7 @@ def train_step(spec, sampler, kf, table, ws, pixel_ids, occupancy=None, lam=1.0,
         sel=sel, counts=fs["counts"], kept=fs["kept"], ray_mask=fs["ray_mask"], R=R, S=S,
         t=t_all, ray_of=ray_of, offsets=offs, xn=xn, sigma=sigma, colour=colour,
         rgb=out_rgb, depth_z=out_d / s64[sel], var_z=out_v / s64[sel] ** 2, opacity=out_a,
+        var_z_mag=var_mag / s64[sel] ** 2,
         depth_ray=out_d, var_ray=out_v, scale=s64[sel],
         loss=L_rgb + lam * L_D, loss_rgb=L_rgb, loss_d=L_D,
         dsigma=dsig, dsigma_mag=dsig_m, dcolour=dcol, dcolour_mag=dcol_m,

@@ -1,0 +1,568 @@
+// C ABI of the mapping step: validation, layouts, workspace carving and the
+// launch sequence.  All device memory comes from the caller.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/nsl.h"
+#include "kernels.h"
+
+using namespace nsl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(NSL_E_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+#define HIP_TRY(expr, what)                       \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Sequential carving of a caller buffer into 256-byte aligned pieces.
+struct Carver {
+  char* base;
+  size_t used = 0;
+  explicit Carver(void* p) : base(static_cast<char*>(p)) {}
+  template <class T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+    used += align256(count * sizeof(T));
+    return p;
+  }
+};
+
+constexpr int kBwdBlocks = 256;  // persistent backward grid (one block per CU)
+
+}  // namespace
+
+struct nsl_field {
+  nsl_field_config cfg;
+  nsl_param_layout lay;
+  int shape;
+  LevelInfo lv;
+  Aabb box;
+  WOffsets wo;
+};
+
+struct nsl_mapper {
+  int max_kf, H, W, grid_res;
+  char* storage;
+  size_t bytes;
+  float *rgb, *depth, *var, *pose, *intr;
+  uint32_t* occ;
+  std::unordered_map<int32_t, int> slots;
+  int used;
+};
+
+extern "C" {
+
+const char* nsl_last_error(void) { return g_err.c_str(); }
+
+int nsl_version(void) { return 100; }
+
+int nsl_field_layout(const nsl_field_config* c, nsl_param_layout* out) {
+  if (!c || !out) return fail(NSL_E_INVALID, "null argument");
+  if (c->levels < 1 || c->levels > NSL_MAX_LEVELS) return fail(NSL_E_INVALID, "levels must be in [1, %d]", NSL_MAX_LEVELS);
+  if (c->feat_per_level != 2) return fail(NSL_E_INVALID, "feat_per_level must be 2");
+  if (c->log2_table < 4 || c->log2_table > 24) return fail(NSL_E_INVALID, "log2_table must be in [4, 24]");
+  if (c->base_res < 1) return fail(NSL_E_INVALID, "base_res must be >= 1");
+  if (c->per_level_scale <= 0.0f && (c->max_res <= 0 || c->levels < 2))
+    return fail(NSL_E_INVALID, "per_level_scale <= 0 needs max_res > 0 and levels >= 2");
+  if (c->n_colour_hidden < 1 || c->n_colour_hidden > 4) return fail(NSL_E_INVALID, "n_colour_hidden must be in [1, 4]");
+  if (c->sh_bands < 1 || c->sh_bands > 4) return fail(NSL_E_INVALID, "sh_bands must be in [1, 4]");
+  for (int i = 0; i < 3; ++i)
+    if (!(c->aabb_max[i] > c->aabb_min[i])) return fail(NSL_E_INVALID, "empty AABB");
+  std::memset(out, 0, sizeof *out);
+  const int L = c->levels;
+  const double b = c->per_level_scale > 0.0f
+                       ? (double)c->per_level_scale
+                       : std::exp((std::log((double)c->max_res) - std::log((double)c->base_res)) / (L - 1));
+  const int64_t T = (int64_t)1 << c->log2_table;
+  int64_t off = 0;
+  out->levels = L;
+  for (int l = 0; l < L; ++l) {
+    int n = (int)std::floor((double)c->base_res * std::pow(b, (double)l));
+    if (l == L - 1 && c->max_res > 0) n = c->max_res;
+    if (n < 1 || n > (1 << 20)) return fail(NSL_E_INVALID, "level %d resolution %d out of range", l, n);
+    const int64_t full = (int64_t)(n + 1) * (n + 1) * (n + 1);
+    out->res[l] = n;
+    out->dense[l] = full <= T;
+    out->level_entries[l] = full <= T ? full : T;
+    out->level_offset[l] = off;
+    off += out->level_entries[l];
+  }
+  out->table_floats = off * c->feat_per_level;
+  auto al = [](int64_t x) { return (x + 63) / 64 * 64; };
+  int64_t w = al(out->table_floats);
+  std::vector<std::pair<int, int>> dims;
+  dims.push_back({2 * L, c->density_hidden});
+  dims.push_back({c->density_hidden, c->geo_dim});
+  int prev = c->geo_dim + c->sh_bands * c->sh_bands;
+  for (int i = 0; i < c->n_colour_hidden; ++i) {
+    dims.push_back({prev, c->colour_hidden[i]});
+    prev = c->colour_hidden[i];
+  }
+  dims.push_back({prev, 3});
+  out->n_layers = (int)dims.size();
+  for (size_t j = 0; j < dims.size(); ++j) {
+    out->w_offset[j] = w;
+    out->w_in[j] = dims[j].first;
+    out->w_out[j] = dims[j].second;
+    w = al(w + (int64_t)dims[j].first * dims[j].second);
+  }
+  out->total_floats = w;
+  if (off > 0xFFFFFFFFll) return fail(NSL_E_INVALID, "table too large");
+  return NSL_OK;
+}
+
+int nsl_field_create(const nsl_field_config* c, nsl_field** out) {
+  if (!out) return fail(NSL_E_INVALID, "null out");
+  *out = nullptr;
+  nsl_param_layout lay;
+  int rc = nsl_field_layout(c, &lay);
+  if (rc) return rc;
+  int shape = -1;
+  if (c->geo_dim == 16) {
+    if (c->levels == 4 && c->density_hidden == 32 && c->n_colour_hidden == 1 && c->colour_hidden[0] == 32 &&
+        c->sh_bands == 3)
+      shape = kShapeTiny;
+    if (c->levels == 16 && c->density_hidden == 64 && c->n_colour_hidden == 2 && c->colour_hidden[0] == 64 &&
+        c->colour_hidden[1] == 64 && c->sh_bands == 4)
+      shape = kShapeFull;
+  }
+  if (shape < 0) return fail(NSL_E_INVALID, "unsupported network shape (see nsl.h for the compiled shapes)");
+  nsl_field* f = new (std::nothrow) nsl_field;
+  if (!f) return fail(NSL_E_INVALID, "out of host memory");
+  f->cfg = *c;
+  f->lay = lay;
+  f->shape = shape;
+  std::memset(&f->lv, 0, sizeof f->lv);
+  f->lv.levels = c->levels;
+  f->lv.table_mask = (uint32_t)((1u << c->log2_table) - 1u);
+  for (int l = 0; l < c->levels; ++l) {
+    f->lv.res[l] = lay.res[l];
+    f->lv.offset[l] = (uint32_t)lay.level_offset[l];
+    if (lay.dense[l]) f->lv.dense_bits |= 1u << l;
+  }
+  for (int i = 0; i < 3; ++i) {
+    f->box.lo[i] = c->aabb_min[i];
+    f->box.hi[i] = c->aabb_max[i];
+    f->box.inv[i] = (float)(1.0 / ((double)c->aabb_max[i] - (double)c->aabb_min[i]));
+  }
+  for (int j = 0; j < 8; ++j) f->wo.off[j] = j < lay.n_layers ? (int)lay.w_offset[j] : 0;
+  *out = f;
+  return NSL_OK;
+}
+
+void nsl_field_destroy(nsl_field* f) { delete f; }
+
+// ---------------------------------------------------------------------------
+// Mapper
+// ---------------------------------------------------------------------------
+
+static size_t mapper_carve(nsl_mapper* m, int K, int H, int W, int G, void* base) {
+  Carver cv(base);
+  const size_t px = (size_t)K * H * W;
+  float* rgb = cv.take<float>(px * 3);
+  float* depth = cv.take<float>(px);
+  float* var = cv.take<float>(px);
+  float* pose = cv.take<float>((size_t)K * 12);
+  float* intr = cv.take<float>((size_t)K * 4);
+  uint32_t* occ = cv.take<uint32_t>(((size_t)G * G * G + 31) / 32);
+  if (m) {
+    m->rgb = rgb; m->depth = depth; m->var = var; m->pose = pose; m->intr = intr; m->occ = occ;
+  }
+  return cv.used;
+}
+
+size_t nsl_mapper_storage_bytes(int K, int H, int W, int G) {
+  if (K < 1 || H < 1 || W < 1 || G < 1) return 0;
+  return mapper_carve(nullptr, K, H, W, G, nullptr);
+}
+
+int nsl_mapper_create(int K, int H, int W, int G, void* storage, size_t bytes, nsl_mapper** out) {
+  if (!out) return fail(NSL_E_INVALID, "null out");
+  *out = nullptr;
+  if (K < 1 || H < 1 || W < 1 || G < 1) return fail(NSL_E_INVALID, "bad mapper shape");
+  if ((int64_t)K * H * W > 0xFFFFFFFFll) return fail(NSL_E_INVALID, "pixel ids exceed 32 bits");
+  if (!storage) return fail(NSL_E_INVALID, "null storage");
+  if ((reinterpret_cast<uintptr_t>(storage) & 255) != 0) return fail(NSL_E_INVALID, "storage must be 256-byte aligned");
+  if (bytes < nsl_mapper_storage_bytes(K, H, W, G)) return fail(NSL_E_WORKSPACE, "mapper storage too small");
+  nsl_mapper* m = new (std::nothrow) nsl_mapper;
+  if (!m) return fail(NSL_E_INVALID, "out of host memory");
+  m->max_kf = K; m->H = H; m->W = W; m->grid_res = G;
+  m->storage = static_cast<char*>(storage);
+  m->bytes = bytes;
+  m->used = 0;
+  mapper_carve(m, K, H, W, G, storage);
+  *out = m;
+  return NSL_OK;
+}
+
+void nsl_mapper_destroy(nsl_mapper* m) { delete m; }
+
+int nsl_mapper_count(const nsl_mapper* m) { return m ? m->used : 0; }
+
+int nsl_keyframe_slot(const nsl_mapper* m, int32_t id) {
+  if (!m) return -1;
+  auto it = m->slots.find(id);
+  return it == m->slots.end() ? -1 : it->second;
+}
+
+int nsl_keyframes_upsert(nsl_mapper* m, int n, const int32_t* ids, const float* rgb, const float* pose,
+                         const float* intr, const float* depth, const float* depth_var, int src_on_host,
+                         hipStream_t st) {
+  if (!m || !ids || !rgb || !pose || !intr || !depth || !depth_var) return fail(NSL_E_INVALID, "null argument");
+  if (n < 0) return fail(NSL_E_INVALID, "negative count");
+  int fresh = 0;
+  for (int i = 0; i < n; ++i) {
+    bool dup = false;
+    for (int j = 0; j < i; ++j) dup |= ids[j] == ids[i];
+    if (dup) return fail(NSL_E_INVALID, "duplicate id %d in one call", ids[i]);
+    if (m->slots.find(ids[i]) == m->slots.end()) ++fresh;
+  }
+  if (m->used + fresh > m->max_kf) return fail(NSL_E_CAPACITY, "keyframe store full (%d slots)", m->max_kf);
+  const hipMemcpyKind kind = src_on_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  const size_t px = (size_t)m->H * m->W;
+  for (int i = 0; i < n; ++i) {
+    auto it = m->slots.find(ids[i]);
+    int slot;
+    if (it == m->slots.end()) {
+      slot = m->used++;
+      m->slots[ids[i]] = slot;
+    } else {
+      slot = it->second;
+    }
+    HIP_TRY(hipMemcpyAsync(m->rgb + slot * px * 3, rgb + i * px * 3, px * 3 * sizeof(float), kind, st), "copy rgb");
+    HIP_TRY(hipMemcpyAsync(m->depth + slot * px, depth + i * px, px * sizeof(float), kind, st), "copy depth");
+    HIP_TRY(hipMemcpyAsync(m->var + slot * px, depth_var + i * px, px * sizeof(float), kind, st), "copy var");
+    HIP_TRY(hipMemcpyAsync(m->pose + slot * 12, pose + i * 12, 12 * sizeof(float), kind, st), "copy pose");
+    HIP_TRY(hipMemcpyAsync(m->intr + slot * 4, intr + i * 4, 4 * sizeof(float), kind, st), "copy intr");
+  }
+  return NSL_OK;
+}
+
+int nsl_occupancy_set(nsl_mapper* m, const uint32_t* bits, int src_on_host, hipStream_t st) {
+  if (!m || !bits) return fail(NSL_E_INVALID, "null argument");
+  const size_t words = ((size_t)m->grid_res * m->grid_res * m->grid_res + 31) / 32;
+  HIP_TRY(hipMemcpyAsync(m->occ, bits, words * 4, src_on_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, st),
+          "copy occupancy");
+  return NSL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Step
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct StepBuffers {
+  RayBuffers rb;
+  float* wprep;
+  float* t;
+  uint32_t* ray;
+  float* sigma;
+  float* rgb;
+  float* dsigma;
+  float* drgb;
+  float* partial;
+};
+
+size_t step_carve(const nsl_field* f, int n, int max_samples, void* base, StepBuffers* b) {
+  Carver cv(base);
+  StepBuffers s{};
+  s.rb.rays = cv.take<float4>(2 * (size_t)n);
+  s.rb.target = cv.take<float4>((size_t)n);
+  s.rb.prec = cv.take<float>((size_t)n);
+  s.rb.counts = cv.take<uint32_t>((size_t)n);
+  s.rb.offsets = cv.take<uint32_t>((size_t)n + 1);
+  s.rb.stats = cv.take<uint32_t>(4);
+  s.rb.block_sums = nullptr;
+  s.wprep = cv.take<float>(field_prep_floats(f->shape));
+  s.t = cv.take<float>((size_t)max_samples);
+  s.ray = cv.take<uint32_t>((size_t)max_samples);
+  s.sigma = cv.take<float>((size_t)max_samples);
+  s.rgb = cv.take<float>(3 * (size_t)max_samples);
+  s.dsigma = cv.take<float>((size_t)max_samples);
+  s.drgb = cv.take<float>(3 * (size_t)max_samples);
+  s.partial = cv.take<float>((size_t)kBwdBlocks * field_nweights(f->shape));
+  if (b) *b = s;
+  return cv.used;
+}
+
+int check_step_cfg(const nsl_step_config* c) {
+  if (!c) return fail(NSL_E_INVALID, "null step config");
+  if (c->sampler != NSL_SAMPLER_UNIFORM && c->sampler != NSL_SAMPLER_OCCUPANCY) return fail(NSL_E_INVALID, "bad sampler");
+  if (!(c->dt > 0.0f) || !(c->t_far >= c->t_near) || !(c->t_near >= 0.0f)) return fail(NSL_E_INVALID, "bad t range or dt");
+  if (c->max_samples < 1 || c->max_samples > (1 << 26)) return fail(NSL_E_INVALID, "max_samples must be in [1, 2^26]");
+  if (c->sampler == NSL_SAMPLER_UNIFORM && (c->n_uniform < 1 || c->n_uniform > 4096))
+    return fail(NSL_E_INVALID, "n_uniform must be in [1, 4096]");
+  if (c->sampler == NSL_SAMPLER_OCCUPANCY && (c->max_per_ray < 1 || c->max_per_ray > 4096))
+    return fail(NSL_E_INVALID, "max_per_ray must be in [1, 4096]");
+  if (c->sampler == NSL_SAMPLER_OCCUPANCY && (double)c->t_far / c->dt > 1e7) return fail(NSL_E_INVALID, "lattice too long");
+  if (c->do_adam && c->adam_step < 1) return fail(NSL_E_INVALID, "adam_step must be >= 1");
+  if (!(c->loss_scale > 0.0f)) return fail(NSL_E_INVALID, "loss_scale must be > 0");
+  return NSL_OK;
+}
+
+KeyframeStore store_of(const nsl_mapper* m) {
+  KeyframeStore k;
+  k.rgb = m->rgb; k.depth = m->depth; k.var = m->var; k.pose = m->pose; k.intr = m->intr; k.occ = m->occ;
+  k.H = m->H; k.W = m->W; k.K = m->used; k.grid_res = m->grid_res;
+  return k;
+}
+
+MarchParams march_of(const nsl_field* f, const nsl_step_config* c) {
+  MarchParams p;
+  p.sampler = c->sampler;
+  p.t_near = c->t_near; p.t_far = c->t_far; p.dt = c->dt;
+  p.n_uniform = c->n_uniform;
+  p.max_per_ray = c->sampler == NSL_SAMPLER_UNIFORM ? c->n_uniform : c->max_per_ray;
+  p.max_samples = c->max_samples;
+  p.box = f->box;
+  return p;
+}
+
+int check_ids_range(const nsl_mapper* m, int n) {
+  if (n < 0) return fail(NSL_E_INVALID, "negative candidate count");
+  if (m->used < 1) return fail(NSL_E_INVALID, "no keyframes in the store");
+  return NSL_OK;
+}
+
+}  // namespace
+
+size_t nsl_step_workspace_bytes(const nsl_field* f, const nsl_step_config* c, int n) {
+  if (!f || !c || n < 0) return 0;
+  return step_carve(f, n, c->max_samples, nullptr, nullptr);
+}
+
+static int run_march(nsl_mapper* m, const nsl_field* f, const nsl_step_config* c, const uint32_t* ids, int n,
+                     StepBuffers& b, hipStream_t st) {
+  const KeyframeStore kf = store_of(m);
+  const MarchParams mp = march_of(f, c);
+  HIP_TRY(march_rays(kf, mp, ids, n, b.rb, st), "march count");
+  HIP_TRY(march_emit(kf, mp, ids, n, b.rb, b.t, b.ray, st), "march emit");
+  return NSL_OK;
+}
+
+int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grads, float* adam_m, float* adam_v,
+                   const nsl_step_config* c, const uint32_t* ids, int n, void* ws, size_t ws_bytes,
+                   float* loss_out, nsl_step_stats* stats_out, float* ray_out, hipStream_t st) {
+  if (!m || !f || !params || !grads || !ids || !ws || !loss_out) return fail(NSL_E_INVALID, "null argument");
+  int rc = check_step_cfg(c);
+  if (rc) return rc;
+  if ((rc = check_ids_range(m, n))) return rc;
+  if (c->do_adam && (!adam_m || !adam_v)) return fail(NSL_E_INVALID, "adam needs m and v");
+  if (c->sampler == NSL_SAMPLER_OCCUPANCY && m->grid_res < 1) return fail(NSL_E_INVALID, "no occupancy grid");
+  if (ws_bytes < nsl_step_workspace_bytes(f, c, n)) return fail(NSL_E_WORKSPACE, "step workspace too small");
+  StepBuffers b;
+  step_carve(f, n, c->max_samples, ws, &b);
+  if (stats_out) b.rb.stats = reinterpret_cast<uint32_t*>(stats_out);
+  b.rb.loss = loss_out;
+  const int64_t total = f->lay.total_floats;
+  if (c->zero_grads) HIP_TRY(fill_zero(grads, total, st), "zero grads");
+  HIP_TRY(field_prep(f->shape, params, f->wo, b.wprep, st), "prep weights");
+  if ((rc = run_march(m, f, c, ids, n, b, st))) return rc;
+
+  FieldArgs fa{params, b.wprep, f->lv};
+  SampleSrc src{};
+  src.t = b.t; src.ray = b.ray; src.rays = b.rb.rays; src.box = f->box; src.n_dev = b.rb.stats + 1; src.n = 0;
+  HIP_TRY(field_forward(f->shape, fa, src, c->max_samples, b.sigma, b.rgb, st), "field forward");
+
+  CompositeIO io{};
+  io.sigma = b.sigma; io.rgb = b.rgb; io.t = b.t; io.off = b.rb.offsets; io.counts = b.rb.counts;
+  io.max_samples = c->max_samples; io.R = n; io.delta = c->dt; io.stop_T = 0.0f; io.out6 = nullptr;
+  LossIO lo{};
+  lo.target = b.rb.target; lo.prec = b.rb.prec; lo.rays = b.rb.rays; lo.stats = b.rb.stats;
+  lo.lambda_d = c->lambda_d; lo.loss_scale = c->loss_scale; lo.loss = loss_out; lo.ray_out = ray_out;
+  HIP_TRY(composite_loss_backward(io, lo, b.dsigma, b.drgb, st), "composite");
+
+  HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, b.dsigma, b.drgb, grads, b.partial, f->wo, grads, st),
+          "field backward");
+  if (c->do_adam)
+    HIP_TRY(adam_update(params, grads, adam_m, adam_v, total, c->lr, c->beta1, c->beta2, c->eps, c->adam_step,
+                        1.0f / c->loss_scale, st),
+            "adam");
+  return NSL_OK;
+}
+
+int nsl_march(nsl_mapper* m, const nsl_field* f, const nsl_step_config* c, const uint32_t* ids, int n, void* ws,
+              size_t ws_bytes, uint32_t* counts, uint32_t* offsets, float* t, uint32_t* ray,
+              nsl_step_stats* stats_out, hipStream_t st) {
+  if (!m || !f || !ids || !ws || !counts || !offsets || !t || !ray) return fail(NSL_E_INVALID, "null argument");
+  int rc = check_step_cfg(c);
+  if (rc) return rc;
+  if ((rc = check_ids_range(m, n))) return rc;
+  if (ws_bytes < nsl_step_workspace_bytes(f, c, n)) return fail(NSL_E_WORKSPACE, "march workspace too small");
+  StepBuffers b;
+  step_carve(f, n, c->max_samples, ws, &b);
+  b.rb.counts = counts;
+  b.rb.offsets = offsets;
+  b.t = t;
+  b.ray = ray;
+  if (stats_out) b.rb.stats = reinterpret_cast<uint32_t*>(stats_out);
+  b.rb.loss = nullptr;
+  return run_march(m, f, c, ids, n, b, st);
+}
+
+size_t nsl_field_workspace_bytes(const nsl_field* f) {
+  if (!f) return 0;
+  Carver cv(nullptr);
+  cv.take<float>(field_prep_floats(f->shape));
+  cv.take<float>((size_t)kBwdBlocks * field_nweights(f->shape));
+  return cv.used;
+}
+
+static int field_common(const nsl_field* f, const float* params, const float* xn, const float* dirs, int S,
+                        void* ws, size_t ws_bytes, float** wprep, float** partial, SampleSrc& src) {
+  if (!f || !params || !xn || !dirs || !ws) return fail(NSL_E_INVALID, "null argument");
+  if (S < 0) return fail(NSL_E_INVALID, "negative sample count");
+  if (ws_bytes < nsl_field_workspace_bytes(f)) return fail(NSL_E_WORKSPACE, "field workspace too small");
+  Carver cv(ws);
+  *wprep = cv.take<float>(field_prep_floats(f->shape));
+  *partial = cv.take<float>((size_t)kBwdBlocks * field_nweights(f->shape));
+  src = SampleSrc{};
+  src.xn = xn; src.dir = dirs; src.box = f->box; src.n = S; src.n_dev = nullptr;
+  return NSL_OK;
+}
+
+int nsl_field_fwd(const nsl_field* f, const float* params, const float* xn, const float* dirs, int S, float* sigma,
+                  float* rgb, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (!sigma || !rgb) return fail(NSL_E_INVALID, "null output");
+  float *wprep, *partial;
+  SampleSrc src;
+  int rc = field_common(f, params, xn, dirs, S, ws, ws_bytes, &wprep, &partial, src);
+  if (rc) return rc;
+  HIP_TRY(field_prep(f->shape, params, f->wo, wprep, st), "prep weights");
+  FieldArgs fa{params, wprep, f->lv};
+  HIP_TRY(field_forward(f->shape, fa, src, S, sigma, rgb, st), "field forward");
+  return NSL_OK;
+}
+
+int nsl_field_bwd(const nsl_field* f, const float* params, const float* xn, const float* dirs, int S,
+                  const float* dsigma, const float* drgb, float* grads, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (!dsigma || !drgb || !grads) return fail(NSL_E_INVALID, "null argument");
+  float *wprep, *partial;
+  SampleSrc src;
+  int rc = field_common(f, params, xn, dirs, S, ws, ws_bytes, &wprep, &partial, src);
+  if (rc) return rc;
+  HIP_TRY(field_prep(f->shape, params, f->wo, wprep, st), "prep weights");
+  FieldArgs fa{params, wprep, f->lv};
+  HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, dsigma, drgb, grads, partial, f->wo, grads, st),
+          "field backward");
+  return NSL_OK;
+}
+
+int nsl_composite_fwd(const float* sigma, const float* rgb, const float* t, const uint32_t* off, int R, float delta,
+                      float stop_T, float* out, hipStream_t st) {
+  if (!sigma || !rgb || !t || !off || !out) return fail(NSL_E_INVALID, "null argument");
+  if (R < 0) return fail(NSL_E_INVALID, "negative ray count");
+  if (!(delta > 0.0f) || !(stop_T >= 0.0f)) return fail(NSL_E_INVALID, "bad delta or stop_T");
+  CompositeIO io{};
+  io.sigma = sigma; io.rgb = rgb; io.t = t; io.off = off; io.counts = nullptr; io.R = R; io.delta = delta;
+  io.stop_T = stop_T; io.out6 = out;
+  HIP_TRY(composite_forward(io, st), "composite forward");
+  return NSL_OK;
+}
+
+int nsl_composite_bwd(const float* sigma, const float* rgb, const float* t, const uint32_t* off, int R, float delta,
+                      const float* g_rgb, const float* g_depth, const float* g_var, float* g_sigma, float* g_rgb_s,
+                      hipStream_t st) {
+  if (!sigma || !rgb || !t || !off || !g_sigma || !g_rgb_s) return fail(NSL_E_INVALID, "null argument");
+  if (R < 0) return fail(NSL_E_INVALID, "negative ray count");
+  if (!(delta > 0.0f)) return fail(NSL_E_INVALID, "bad delta");
+  CompositeIO io{};
+  io.sigma = sigma; io.rgb = rgb; io.t = t; io.off = off; io.counts = nullptr; io.R = R; io.delta = delta;
+  io.stop_T = 0.0f;
+  HIP_TRY(composite_backward(io, g_rgb, g_depth, g_var, g_sigma, g_rgb_s, st), "composite backward");
+  return NSL_OK;
+}
+
+int nsl_adam(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps, int step,
+             float grad_scale, hipStream_t st) {
+  if (!p || !g || !m || !v) return fail(NSL_E_INVALID, "null argument");
+  if (n < 0 || step < 1) return fail(NSL_E_INVALID, "bad count or step");
+  HIP_TRY(adam_update(p, g, m, v, n, lr, b1, b2, eps, step, grad_scale, st), "adam");
+  return NSL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Render
+// ---------------------------------------------------------------------------
+
+static size_t render_carve(const nsl_field* f, int H, int W, int ns, void* base, float4** rays, float** t,
+                           uint32_t** ray, uint32_t** off, float** sigma, float** rgb, float** out6, float** wprep) {
+  Carver cv(base);
+  const size_t n = (size_t)H * W, S = n * ns;
+  float4* a = cv.take<float4>(2 * n);
+  float* b = cv.take<float>(S);
+  uint32_t* c = cv.take<uint32_t>(S);
+  uint32_t* d = cv.take<uint32_t>(n + 1);
+  float* e = cv.take<float>(S);
+  float* g = cv.take<float>(3 * S);
+  float* h = cv.take<float>(6 * n);
+  float* w = cv.take<float>(field_prep_floats(f->shape));
+  if (rays) {
+    *rays = a; *t = b; *ray = c; *off = d; *sigma = e; *rgb = g; *out6 = h; *wprep = w;
+  }
+  return cv.used;
+}
+
+size_t nsl_render_workspace_bytes(const nsl_field* f, int H, int W, const nsl_render_config* c) {
+  if (!f || !c || H < 1 || W < 1 || c->n_samples < 1) return 0;
+  return render_carve(f, H, W, c->n_samples, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                      nullptr);
+}
+
+int nsl_render(const nsl_field* f, const float* params, const float* pose, const float* intr, int H, int W,
+               const nsl_render_config* c, float* rgb, float* depth, float* var, float* opacity, void* ws,
+               size_t ws_bytes, hipStream_t st) {
+  if (!f || !params || !pose || !intr || !c || !rgb || !depth || !var || !ws) return fail(NSL_E_INVALID, "null argument");
+  if (H < 1 || W < 1 || c->n_samples < 1 || c->n_samples > 4096 || !(c->dt > 0.0f) || !(c->stop_T >= 0.0f))
+    return fail(NSL_E_INVALID, "bad render config");
+  if ((int64_t)H * W * c->n_samples > 0x7FFFFFFFll) return fail(NSL_E_INVALID, "image too large");
+  if (ws_bytes < nsl_render_workspace_bytes(f, H, W, c)) return fail(NSL_E_WORKSPACE, "render workspace too small");
+  float4* rays;
+  float *t, *sigma, *srgb, *out6, *wprep;
+  uint32_t *ray, *off;
+  render_carve(f, H, W, c->n_samples, ws, &rays, &t, &ray, &off, &sigma, &srgb, &out6, &wprep);
+  const int n = H * W, S = n * c->n_samples;
+  HIP_TRY(render_setup(pose, intr, H, W, c->t_near, c->dt, c->n_samples, f->box, rays, t, ray, off, st), "render setup");
+  HIP_TRY(field_prep(f->shape, params, f->wo, wprep, st), "prep weights");
+  FieldArgs fa{params, wprep, f->lv};
+  SampleSrc src{};
+  src.t = t; src.ray = ray; src.rays = rays; src.box = f->box; src.n = S; src.n_dev = nullptr;
+  HIP_TRY(field_forward(f->shape, fa, src, S, sigma, srgb, st), "render field");
+  CompositeIO io{};
+  io.sigma = sigma; io.rgb = srgb; io.t = t; io.off = off; io.counts = nullptr; io.R = n; io.delta = c->dt;
+  io.stop_T = c->stop_T; io.out6 = out6;
+  HIP_TRY(composite_forward(io, st), "render composite");
+  HIP_TRY(render_finish(out6, rays, n, rgb, depth, var, opacity, st), "render finish");
+  return NSL_OK;
+}
+
+}  // extern "C"

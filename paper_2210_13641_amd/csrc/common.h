@@ -1,0 +1,112 @@
+// Device helpers shared by the gfx950 kernels of the mapping step.
+//
+// Sample positions decide integer quantities (occupancy cell, trilinear
+// cell, AABB membership), so they are formed in IEEE single precision with
+// every operation rounded separately, in a fixed order:
+//   a = ((u + 0.5) - cx) / fx,  b = ((v + 0.5) - cy) / fy,
+//   s = sqrt((a*a + b*b) + 1),  d_i = ((R_i0*a + R_i1*b) + R_i2) / s,
+//   x_i = o_i + t*d_i,  xn_i = clamp((x_i - lo_i) * inv_i, 0, 1).
+// Contraction into FMA is switched off in these functions, and division and
+// square root are the correctly rounded ones (the library is built with
+// -fhip-fp32-correctly-rounded-divide-sqrt), so any IEEE implementation of the
+// same sequence lands on the same bits.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nsl {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+constexpr int kMaxLevels = 16;
+constexpr uint32_t kPrime1 = 2654435761u;
+constexpr uint32_t kPrime2 = 805459861u;
+
+struct LevelInfo {
+  int levels;
+  uint32_t table_mask;          // table entries per hashed level - 1 (power of two)
+  uint32_t dense_bits;          // bit l set: level l is dense
+  int res[kMaxLevels];          // N_l
+  uint32_t offset[kMaxLevels];  // first entry of level l
+};
+
+struct Aabb {
+  float lo[3], hi[3], inv[3];
+};
+
+__device__ __forceinline__ void camera_ray(const float* __restrict__ pose,
+                                           const float* __restrict__ intr, int u, int v,
+                                           float o[3], float d[3], float& s) {
+#pragma clang fp contract(off)
+  const float a = (((float)u + 0.5f) - intr[2]) / intr[0];
+  const float b = (((float)v + 0.5f) - intr[3]) / intr[1];
+  s = __builtin_sqrtf((a * a + b * b) + 1.0f);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    d[i] = ((pose[4 * i] * a + pose[4 * i + 1] * b) + pose[4 * i + 2]) / s;
+    o[i] = pose[4 * i + 3];
+  }
+}
+
+__device__ __forceinline__ float pos_axis(float o, float d, float t) {
+#pragma clang fp contract(off)
+  return o + t * d;
+}
+
+__device__ __forceinline__ float normalise_axis(float x, float lo, float inv) {
+#pragma clang fp contract(off)
+  float xn = (x - lo) * inv;
+  return fminf(fmaxf(xn, 0.0f), 1.0f);
+}
+
+// floor(xn*N) taken on the exact product (TwoProduct: xn*N = ph + pl exactly),
+// clamped to N-1; f = xn*N - i0 rounded once.
+__device__ __forceinline__ int cell_floor(float xn, int n, float& f) {
+  const float nf = (float)n;
+  const float ph = xn * nf;
+  const float pl = __builtin_fmaf(xn, nf, -ph);
+  float fl = __builtin_floorf(ph);
+  if (ph == fl && pl < 0.0f) fl -= 1.0f;
+  int i = (int)fl;
+  if (i > n - 1) i = n - 1;
+  f = (ph - (float)i) + pl;
+  return i;
+}
+
+__device__ __forceinline__ uint32_t grid_index(uint32_t x, uint32_t y, uint32_t z, int n,
+                                               bool dense, uint32_t mask) {
+  if (dense) {
+    const uint32_t m = (uint32_t)n + 1u;
+    return x + m * (y + m * z);
+  }
+  return (x ^ (y * kPrime1) ^ (z * kPrime2)) & mask;
+}
+
+__device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+// Wave-wide helpers (wave64).
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Inclusive scan across the wave.
+__device__ __forceinline__ float wave_incl_scan(float v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    float n = __shfl_up(v, o, kWave);
+    if (l >= o) v += n;
+  }
+  return v;
+}
+
+__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+}  // namespace nsl

@@ -1,0 +1,230 @@
+// Volume rendering (Eq. 5, 6), the mapping loss (Eq. 3, 4, 7) and their
+// adjoint on gfx950.  One wave owns one ray and walks its samples 64 at a
+// time; the transmittance exponent sum_{j<i} tau_j is a wave-level prefix
+// scan carried across chunks, so T_i = exp(-prefix) never multiplies
+// rounding errors along the ray.  Everything is FP32.
+//
+// Adjoint, for Q = sum_i w_i q_i:  dQ/dtau_k = T_{k+1} q_k - (Q - Q_{<=k}),
+// dV*/dtau_k = [T_{k+1} u_k - (V* - V_{<=k})] - 2 d* (1 - A) dd*/dtau_k with
+// u_i = (t_i - d*)^2; dL/dsigma_k = delta dL/dtau_k and dL/dc_k = g_C w_k.
+#include "kernels.h"
+
+namespace nsl {
+
+namespace {
+
+constexpr int kWavesPerBlock = 4;
+
+struct RaySums {
+  float C[3], D, A, V;
+};
+
+// Bounds of ray r, or false if it is not composited.
+__device__ __forceinline__ bool ray_span(const CompositeIO& io, int r, uint32_t& b, uint32_t& n) {
+  b = io.off[r];
+  if (io.counts) {
+    n = io.counts[r];
+    return n > 0 && b + n <= (uint32_t)io.max_samples;
+  }
+  n = io.off[r + 1] - b;
+  return n > 0;
+}
+
+struct Chunk {
+  float tau, T, Tn, w, t, c[3];
+  bool on;
+};
+
+// Load chunk [i0, i0+64) of the ray and its transmittance given the carried
+// exponent; returns the chunk's total tau.
+__device__ __forceinline__ float load_chunk(const CompositeIO& io, uint32_t b, uint32_t n, uint32_t i0,
+                                            float carry, Chunk& c) {
+  const int lane = lane_id();
+  const uint32_t i = i0 + lane;
+  c.on = i < n;
+  float sg = 0.0f;
+  c.t = 0.0f;
+  c.c[0] = c.c[1] = c.c[2] = 0.0f;
+  if (c.on) {
+    const uint32_t s = b + i;
+    sg = io.sigma[s];
+    c.t = io.t[s];
+    c.c[0] = io.rgb[3 * s];
+    c.c[1] = io.rgb[3 * s + 1];
+    c.c[2] = io.rgb[3 * s + 2];
+  }
+  c.tau = sg * io.delta;
+  const float incl = wave_incl_scan(c.tau);
+  const float excl = incl - c.tau;
+  c.T = expf(-(carry + excl));
+  c.Tn = expf(-(carry + incl));
+  const float alpha = -expm1f(-c.tau);
+  c.w = c.on ? c.T * alpha : 0.0f;
+  if (io.stop_T > 0.0f && c.T < io.stop_T) {
+    c.w = 0.0f;
+    c.on = false;
+  }
+  return __shfl(incl, kWave - 1, kWave);
+}
+
+// Forward sums of one ray (two passes: V* about the final d*).
+__device__ __forceinline__ RaySums ray_forward(const CompositeIO& io, uint32_t b, uint32_t n) {
+  RaySums r{};
+  float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f, A = 0.0f;
+  float carry = 0.0f;
+  for (uint32_t i0 = 0; i0 < n; i0 += kWave) {
+    Chunk c;
+    carry += load_chunk(io, b, n, i0, carry, c);
+    C0 += c.w * c.c[0];
+    C1 += c.w * c.c[1];
+    C2 += c.w * c.c[2];
+    D += c.w * c.t;
+    A += c.w;
+    if (io.stop_T > 0.0f && __ballot(c.on && lane_id() < (int)(n - i0)) == 0ull) break;
+  }
+  r.C[0] = wave_sum(C0);
+  r.C[1] = wave_sum(C1);
+  r.C[2] = wave_sum(C2);
+  r.D = wave_sum(D);
+  r.A = wave_sum(A);
+  float V = 0.0f;
+  carry = 0.0f;
+  for (uint32_t i0 = 0; i0 < n; i0 += kWave) {
+    Chunk c;
+    carry += load_chunk(io, b, n, i0, carry, c);
+    const float e = c.t - r.D;
+    V += c.w * e * e;
+    if (io.stop_T > 0.0f && __ballot(c.on && lane_id() < (int)(n - i0)) == 0ull) break;
+  }
+  r.V = wave_sum(V);
+  return r;
+}
+
+// Adjoint of one ray for seeds (gC, gD, gV); writes dL/dsigma and dL/dc.
+__device__ __forceinline__ void ray_backward(const CompositeIO& io, uint32_t b, uint32_t n,
+                                             const RaySums& r, const float gC[3], float gD, float gV,
+                                             float* __restrict__ g_sigma, float* __restrict__ g_rgb) {
+  float carry = 0.0f, p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, pD = 0.0f, pV = 0.0f;
+  const float kV = 2.0f * r.D * (1.0f - r.A);
+  for (uint32_t i0 = 0; i0 < n; i0 += kWave) {
+    Chunk c;
+    carry += load_chunk(io, b, n, i0, carry, c);
+    const float u = (c.t - r.D) * (c.t - r.D);
+    const float q0 = wave_incl_scan(c.w * c.c[0]) + p0;
+    const float q1 = wave_incl_scan(c.w * c.c[1]) + p1;
+    const float q2 = wave_incl_scan(c.w * c.c[2]) + p2;
+    const float qD = wave_incl_scan(c.w * c.t) + pD;
+    const float qV = wave_incl_scan(c.w * u) + pV;
+    const float dC0 = c.Tn * c.c[0] - (r.C[0] - q0);
+    const float dC1 = c.Tn * c.c[1] - (r.C[1] - q1);
+    const float dC2 = c.Tn * c.c[2] - (r.C[2] - q2);
+    const float dD = c.Tn * c.t - (r.D - qD);
+    const float dV = (c.Tn * u - (r.V - qV)) - kV * dD;
+    const float dtau = gC[0] * dC0 + gC[1] * dC1 + gC[2] * dC2 + gD * dD + gV * dV;
+    const uint32_t i = i0 + lane_id();
+    if (i < n) {
+      const uint32_t s = b + i;
+      g_sigma[s] = io.delta * dtau;
+      g_rgb[3 * s] = gC[0] * c.w;
+      g_rgb[3 * s + 1] = gC[1] * c.w;
+      g_rgb[3 * s + 2] = gC[2] * c.w;
+    }
+    p0 = __shfl(q0, kWave - 1, kWave);
+    p1 = __shfl(q1, kWave - 1, kWave);
+    p2 = __shfl(q2, kWave - 1, kWave);
+    pD = __shfl(qD, kWave - 1, kWave);
+    pV = __shfl(qV, kWave - 1, kWave);
+  }
+}
+
+__global__ __launch_bounds__(256) void composite_fwd_kernel(CompositeIO io) {
+  const int r = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (r >= io.R) return;
+  uint32_t b, n;
+  RaySums s{};
+  if (ray_span(io, r, b, n)) s = ray_forward(io, b, n);
+  if (lane_id() == 0 && io.out6) {
+    float* o = io.out6 + 6 * (size_t)r;
+    o[0] = s.C[0]; o[1] = s.C[1]; o[2] = s.C[2]; o[3] = s.D; o[4] = s.V; o[5] = s.A;
+  }
+}
+
+__global__ __launch_bounds__(256) void composite_bwd_kernel(CompositeIO io, const float* __restrict__ g_rgb,
+                                                            const float* __restrict__ g_depth,
+                                                            const float* __restrict__ g_var,
+                                                            float* __restrict__ g_sigma,
+                                                            float* __restrict__ g_rgb_s) {
+  const int r = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (r >= io.R) return;
+  uint32_t b, n;
+  if (!ray_span(io, r, b, n)) return;
+  const RaySums s = ray_forward(io, b, n);
+  const float gC[3] = {g_rgb ? g_rgb[3 * r] : 0.0f, g_rgb ? g_rgb[3 * r + 1] : 0.0f,
+                       g_rgb ? g_rgb[3 * r + 2] : 0.0f};
+  ray_backward(io, b, n, s, gC, g_depth ? g_depth[r] : 0.0f, g_var ? g_var[r] : 0.0f, g_sigma, g_rgb_s);
+}
+
+// Train step: forward sums, loss terms and seeds, adjoint.
+__global__ __launch_bounds__(256) void composite_loss_kernel(CompositeIO io, LossIO lo,
+                                                             float* __restrict__ g_sigma,
+                                                             float* __restrict__ g_rgb_s) {
+  const int r = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+  if (r >= io.R) return;
+  uint32_t b, n;
+  const bool on = ray_span(io, r, b, n);
+  if (!on) {
+    if (lane_id() == 0 && lo.ray_out) {
+      float* o = lo.ray_out + 6 * (size_t)r;
+      o[0] = o[1] = o[2] = o[3] = o[4] = o[5] = 0.0f;
+    }
+    return;
+  }
+  const RaySums s = ray_forward(io, b, n);
+  const float Rf = (float)lo.stats[0];
+  const float4 tg = lo.target[r];
+  const float pi = lo.prec[r];
+  const float e0 = s.C[0] - tg.x, e1 = s.C[1] - tg.y, e2 = s.C[2] - tg.z, ed = s.D - tg.w;
+  const float l_rgb = e0 * e0 + e1 * e1 + e2 * e2;
+  const float l_d = pi * ed * ed;
+  const float k = 2.0f * lo.loss_scale / Rf;
+  const float gC[3] = {k * e0, k * e1, k * e2};
+  const float gD = k * lo.lambda_d * pi * ed;
+  if (lane_id() == 0) {
+    atomicAdd(lo.loss + 0, (l_rgb + lo.lambda_d * l_d) / Rf);
+    atomicAdd(lo.loss + 1, l_rgb / Rf);
+    atomicAdd(lo.loss + 2, l_d / Rf);
+    if (lo.ray_out) {
+      const float sc = lo.rays[2 * r].w;
+      float* o = lo.ray_out + 6 * (size_t)r;
+      o[0] = s.C[0]; o[1] = s.C[1]; o[2] = s.C[2];
+      o[3] = s.D / sc; o[4] = s.V / (sc * sc); o[5] = s.A;
+    }
+  }
+  ray_backward(io, b, n, s, gC, gD, 0.0f, g_sigma, g_rgb_s);
+}
+
+dim3 grid_for(int R) { return dim3((R + kWavesPerBlock - 1) / kWavesPerBlock); }
+
+}  // namespace
+
+hipError_t composite_forward(const CompositeIO& io, hipStream_t st) {
+  if (io.R > 0) hipLaunchKernelGGL(composite_fwd_kernel, grid_for(io.R), dim3(256), 0, st, io);
+  return hipGetLastError();
+}
+
+hipError_t composite_backward(const CompositeIO& io, const float* g_rgb, const float* g_depth,
+                              const float* g_var, float* g_sigma, float* g_rgb_s, hipStream_t st) {
+  if (io.R > 0)
+    hipLaunchKernelGGL(composite_bwd_kernel, grid_for(io.R), dim3(256), 0, st, io, g_rgb, g_depth,
+                       g_var, g_sigma, g_rgb_s);
+  return hipGetLastError();
+}
+
+hipError_t composite_loss_backward(const CompositeIO& io, const LossIO& lo, float* g_sigma,
+                                   float* g_rgb_s, hipStream_t st) {
+  if (io.R > 0)
+    hipLaunchKernelGGL(composite_loss_kernel, grid_for(io.R), dim3(256), 0, st, io, lo, g_sigma, g_rgb_s);
+  return hipGetLastError();
+}
+
+}  // namespace nsl

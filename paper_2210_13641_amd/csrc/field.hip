@@ -1,0 +1,580 @@
+// Hash-grid field on gfx950: fused encode + density/colour MLP forward, and
+// the recompute adjoint (encode, MLP forward again, MLP backward with
+// weight gradients, scatter into the table gradient).
+//
+// One wave evaluates 16 samples: lane (g, j) = (lane/16, lane%16) gathers
+// levels g, g+4, ... of sample j, which are exactly its B-operand slots of
+// the first MFMA layer (net.h).  Nothing but sigma and colour leaves the
+// forward kernel; the backward kernel re-derives every activation from the
+// sample position instead of reading stored activations.
+#include "kernels.h"
+#include "net.h"
+
+namespace nsl {
+
+// ---------------------------------------------------------------------------
+// Per-sample inputs
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void load_sample(const SampleSrc& src, int s, float xn[3],
+                                            float d[3]) {
+  if (src.t) {
+    const uint32_t r = src.ray[s];
+    const float t = src.t[s];
+    const float4 o = src.rays[2 * r];
+    const float4 dd = src.rays[2 * r + 1];
+    d[0] = dd.x; d[1] = dd.y; d[2] = dd.z;
+    xn[0] = normalise_axis(pos_axis(o.x, dd.x, t), src.box.lo[0], src.box.inv[0]);
+    xn[1] = normalise_axis(pos_axis(o.y, dd.y, t), src.box.lo[1], src.box.inv[1]);
+    xn[2] = normalise_axis(pos_axis(o.z, dd.z, t), src.box.lo[2], src.box.inv[2]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      xn[i] = fminf(fmaxf(src.xn[3 * s + i], 0.0f), 1.0f);
+      d[i] = src.dir[3 * s + i];
+    }
+  }
+}
+
+// Per-lane level constants (levels g, g+4, ... of this lane group).
+template <class N>
+struct LaneLevels {
+  int res[N::LPL];
+  uint32_t off[N::LPL];
+  bool dense[N::LPL];
+};
+
+template <class N>
+__device__ __forceinline__ void lane_levels(const LevelInfo& lv, int g, LaneLevels<N>& ll) {
+#pragma unroll
+  for (int q = 0; q < N::LPL; ++q) {
+    const int l = g + 4 * q;
+    ll.res[q] = lv.res[l];
+    ll.off[q] = lv.offset[l];
+    ll.dense[q] = (lv.dense_bits >> l) & 1u;
+  }
+}
+
+struct Corner8 {
+  uint32_t idx[8];
+  float w[8];
+};
+
+__device__ __forceinline__ void corners(float x, float y, float z, int n, bool dense,
+                                        uint32_t mask, uint32_t off, Corner8& c) {
+  float fx, fy, fz;
+  const uint32_t ix = (uint32_t)cell_floor(x, n, fx);
+  const uint32_t iy = (uint32_t)cell_floor(y, n, fy);
+  const uint32_t iz = (uint32_t)cell_floor(z, n, fz);
+  const float gx[2] = {1.0f - fx, fx}, gy[2] = {1.0f - fy, fy}, gz[2] = {1.0f - fz, fz};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
+    c.idx[k] = off + grid_index(ix + cx, iy + cy, iz + cz, n, dense, mask);
+    c.w[k] = (gx[cx] * gy[cy]) * gz[cz];
+  }
+}
+
+template <class N>
+__device__ __forceinline__ void encode(const float* __restrict__ table, uint32_t mask,
+                                       const LaneLevels<N>& ll, const float xn[3],
+                                       float e[N::NSLOT]) {
+#pragma unroll
+  for (int q = 0; q < N::LPL; ++q) {
+    Corner8 c;
+    corners(xn[0], xn[1], xn[2], ll.res[q], ll.dense[q], mask, ll.off[q], c);
+    float2 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = *reinterpret_cast<const float2*>(table + 2 * (size_t)c.idx[k]);
+    float a0 = 0.0f, a1 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      a0 += c.w[k] * v[k].x;
+      a1 += c.w[k] * v[k].y;
+    }
+    e[2 * q] = a0;
+    e[2 * q + 1] = a1;
+  }
+}
+
+// Real orthonormal SH coefficients 4g..4g+3 of direction d (0 beyond NSH).
+template <class N>
+__device__ __forceinline__ void sh_lane(const float d[3], int g, float out[4]) {
+  const float x = d[0], y = d[1], z = d[2];
+  float Y[16];
+  Y[0] = 0.28209479177387814f;
+  Y[1] = 0.4886025119029199f * y;
+  Y[2] = 0.4886025119029199f * z;
+  Y[3] = 0.4886025119029199f * x;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  Y[4] = 1.0925484305920792f * x * y;
+  Y[5] = 1.0925484305920792f * y * z;
+  Y[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);
+  Y[7] = 1.0925484305920792f * x * z;
+  Y[8] = 0.5462742152960396f * (xx - yy);
+  if (N::SHB > 3) {
+    Y[9] = 0.5900435899266435f * y * (3.0f * xx - yy);
+    Y[10] = 2.890611442640554f * x * y * z;
+    Y[11] = 0.4570457994644658f * y * (5.0f * zz - 1.0f);
+    Y[12] = 0.3731763325901154f * z * (5.0f * zz - 3.0f);
+    Y[13] = 0.4570457994644658f * x * (5.0f * zz - 1.0f);
+    Y[14] = 1.445305721320277f * z * (xx - yy);
+    Y[15] = 0.5900435899266435f * x * (xx - 3.0f * yy);
+  } else {
+#pragma unroll
+    for (int k = 9; k < 16; ++k) Y[k] = 0.0f;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    out[r] = g == 0 ? Y[r] : g == 1 ? Y[4 + r] : g == 2 ? Y[8 + r] : Y[12 + r];
+}
+
+// ---------------------------------------------------------------------------
+// MLP forward (activations kept for the adjoint)
+// ---------------------------------------------------------------------------
+
+template <class N>
+struct Acts {
+  float e[N::NSLOT];
+  f4 h1[N::HD / 16];
+  f4 o;
+  float sh[4];
+  f4 h3[N::HC / 16];
+  f4 h4[N::HC / 16];
+  f4 z;
+};
+
+__device__ __forceinline__ f4 relu4(f4 v) {
+  return f4{fmaxf(v[0], 0.0f), fmaxf(v[1], 0.0f), fmaxf(v[2], 0.0f), fmaxf(v[3], 0.0f)};
+}
+
+template <class N>
+__device__ __forceinline__ void mlp_fwd(const float* __restrict__ Af, int lane, Acts<N>& a) {
+  constexpr f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  // layer 0: encoding -> h1
+  {
+    const float* A = Af + N::foff(0) + lane;
+    f4 acc[N::HD / 16];
+#pragma unroll
+    for (int m = 0; m < N::HD / 16; ++m) acc[m] = zero;
+#pragma unroll
+    for (int s = 0; s < N::fks(0); ++s)
+#pragma unroll
+      for (int m = 0; m < N::HD / 16; ++m) acc[m] = mfma4(A[(m * N::fks(0) + s) * kWave], a.e[s], acc[m]);
+#pragma unroll
+    for (int m = 0; m < N::HD / 16; ++m) a.h1[m] = relu4(acc[m]);
+  }
+  // layer 1: h1 -> o (geometry, 16)
+  {
+    const float* A = Af + N::foff(1) + lane;
+    f4 acc = zero;
+#pragma unroll
+    for (int s = 0; s < N::fks(1); ++s) acc = mfma4(A[s * kWave], a.h1[s >> 2][s & 3], acc);
+    a.o = acc;
+  }
+  // layer 2: [o, sh] -> h3
+  {
+    const float* A = Af + N::foff(2) + lane;
+    f4 acc[N::HC / 16];
+#pragma unroll
+    for (int m = 0; m < N::HC / 16; ++m) acc[m] = zero;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const float b = s < 4 ? a.o[s & 3] : a.sh[s & 3];
+#pragma unroll
+      for (int m = 0; m < N::HC / 16; ++m) acc[m] = mfma4(A[(m * 8 + s) * kWave], b, acc[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < N::HC / 16; ++m) a.h3[m] = relu4(acc[m]);
+  }
+  const f4* hl = a.h3;
+  if constexpr (N::NCH == 2) {
+    const float* A = Af + N::foff(3) + lane;
+    f4 acc[N::HC / 16];
+#pragma unroll
+    for (int m = 0; m < N::HC / 16; ++m) acc[m] = zero;
+#pragma unroll
+    for (int s = 0; s < N::HC / 4; ++s)
+#pragma unroll
+      for (int m = 0; m < N::HC / 16; ++m)
+        acc[m] = mfma4(A[(m * (N::HC / 4) + s) * kWave], a.h3[s >> 2][s & 3], acc[m]);
+#pragma unroll
+    for (int m = 0; m < N::HC / 16; ++m) a.h4[m] = relu4(acc[m]);
+    hl = a.h4;
+  }
+  // last layer -> z (rows 0..2 valid, held by lane group 0)
+  {
+    const float* A = Af + N::foff(N::NW - 1) + lane;
+    f4 acc = zero;
+#pragma unroll
+    for (int s = 0; s < N::HC / 4; ++s) acc = mfma4(A[s * kWave], hl[s >> 2][s & 3], acc);
+    a.z = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight-operand preparation (once per step from the FP32 parameters)
+// ---------------------------------------------------------------------------
+
+template <class N>
+__global__ void prep_weights_kernel(const float* __restrict__ params, WOffsets wo,
+                                    float* __restrict__ out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N::FWD_FLOATS + N::BWD_FLOATS) return;
+  float v = 0.0f;
+  if (idx < N::FWD_FLOATS) {
+    int j = 0;
+    while (j + 1 < N::NW && idx >= N::foff(j + 1)) ++j;
+    const int r = idx - N::foff(j);
+    const int lane = r % kWave, ms = r / kWave;
+    const int s = ms % N::fks(j), m = ms / N::fks(j);
+    const int g = lane >> 4, i = lane & 15;
+    const int row = fwd_in_feature<N>(j, s, g), col = 16 * m + i;
+    if (row >= 0 && row < N::kin(j) && col < N::kout(j)) v = params[wo.off[j] + row * N::kout(j) + col];
+  } else {
+    const int b = idx - N::FWD_FLOATS;
+    int j = 0;
+    while (j + 1 < N::NW && b >= N::boff(j + 1)) ++j;
+    const int r = b - N::boff(j);
+    const int lane = r % kWave, ms = r / kWave;
+    const int s = ms % N::bks(j), m = ms / N::bks(j);
+    const int g = lane >> 4, i = lane & 15;
+    const int row = bwd_row_feature<N>(j, m, i), col = bwd_k_feature<N>(j, s, g);
+    if (row >= 0 && row < N::kin(j) && col < N::kout(j)) v = params[wo.off[j] + row * N::kout(j) + col];
+  }
+  out[idx] = v;
+}
+
+template <class N>
+__device__ __forceinline__ void load_operands(float* dst, const float* __restrict__ src, int n) {
+  for (int i = threadIdx.x * 4; i < n; i += blockDim.x * 4)
+    *reinterpret_cast<float4*>(dst + i) = *reinterpret_cast<const float4*>(src + i);
+}
+
+// ---------------------------------------------------------------------------
+// Forward: sigma and colour per sample
+// ---------------------------------------------------------------------------
+
+template <class N>
+__global__ __launch_bounds__(256) void field_fwd_kernel(FieldArgs a, SampleSrc src,
+                                                        float* __restrict__ sigma_out,
+                                                        float* __restrict__ rgb_out) {
+  __shared__ __attribute__((aligned(16))) float Af[N::FWD_FLOATS];
+  load_operands<N>(Af, a.wprep, N::FWD_FLOATS);
+  __syncthreads();
+  const int S = src.n_dev ? (int)*src.n_dev : src.n;
+  const int lane = lane_id(), g = lane >> 4, jc = lane & 15;
+  const int tile = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int s = tile * 16 + jc;
+  if (tile * 16 >= S) return;
+  const bool valid = s < S;
+  LaneLevels<N> ll;
+  lane_levels<N>(a.lv, g, ll);
+  Acts<N> act;
+  float xn[3] = {0.5f, 0.5f, 0.5f}, d[3] = {0.0f, 0.0f, 1.0f};
+  if (valid) load_sample(src, s, xn, d);
+  encode<N>(a.table, a.lv.table_mask, ll, xn, act.e);
+  sh_lane<N>(d, g, act.sh);
+  mlp_fwd<N>(Af, lane, act);
+  if (g == 0 && valid) {
+    sigma_out[s] = __expf(act.o[0]) ;
+    rgb_out[3 * s + 0] = sigmoidf(act.z[0]);
+    rgb_out[3 * s + 1] = sigmoidf(act.z[1]);
+    rgb_out[3 * s + 2] = sigmoidf(act.z[2]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Backward
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void wave_lds_fence() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// dW[in][out] += sum over the wave's 16 samples of X[in] * dY[out], with X and
+// dY staged [feature][sample] (stride SROW) in this wave's LDS area.
+template <class N, int KIN, int KOUT>
+__device__ __forceinline__ void dw_accumulate(const float* Xs, const float* Ys, float* dW, int lane) {
+  constexpr int MI = (KIN + 15) / 16, NJ = (KOUT + 15) / 16;
+  const int gk = lane >> 4, i = lane & 15;
+  f4 xa[MI], yb[NJ];
+#pragma unroll
+  for (int m = 0; m < MI; ++m) xa[m] = *reinterpret_cast<const f4*>(Xs + (16 * m + i) * N::SROW + 4 * gk);
+#pragma unroll
+  for (int n = 0; n < NJ; ++n) yb[n] = *reinterpret_cast<const f4*>(Ys + (16 * n + i) * N::SROW + 4 * gk);
+#pragma unroll
+  for (int m = 0; m < MI; ++m)
+#pragma unroll
+    for (int n = 0; n < NJ; ++n) {
+      f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) acc = mfma4(xa[m][s], yb[n][s], acc);
+      const int col = 16 * n + i;
+      if (col < KOUT) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * m + 4 * gk + r;
+          if (row < KIN) atomicAdd(dW + row * KOUT + col, acc[r]);
+        }
+      }
+    }
+}
+
+// Stage a D-layout activation block (tiles of 16 rows) as rows [row0, ...).
+template <class N, int TILES>
+__device__ __forceinline__ void stage_d(float* S, const f4* v, int g, int jc) {
+#pragma unroll
+  for (int m = 0; m < TILES; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) S[(16 * m + 4 * g + r) * N::SROW + jc] = v[m][r];
+}
+
+template <class N>
+__global__ __launch_bounds__(256, 1) void field_bwd_kernel(FieldArgs a, SampleSrc src,
+                                                           const float* __restrict__ dsigma,
+                                                           const float* __restrict__ drgb,
+                                                           float* __restrict__ grad_table,
+                                                           float* __restrict__ dw_partial) {
+  __shared__ __attribute__((aligned(16))) float Af[N::FWD_FLOATS];
+  __shared__ __attribute__((aligned(16))) float Ab[N::BWD_FLOATS];
+  __shared__ __attribute__((aligned(16))) float dW[N::NWEIGHTS];
+  __shared__ __attribute__((aligned(16))) float stage_all[4 * N::STAGE_FLOATS];
+  load_operands<N>(Af, a.wprep, N::FWD_FLOATS);
+  load_operands<N>(Ab, a.wprep + N::FWD_FLOATS, N::BWD_FLOATS);
+  for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) dW[i] = 0.0f;
+  __syncthreads();
+
+  const int S = src.n_dev ? (int)*src.n_dev : src.n;
+  const int ntiles = (S + 15) / 16;
+  const int wave = threadIdx.x / kWave;
+  const int lane = lane_id(), g = lane >> 4, jc = lane & 15;
+  float* Xs = stage_all + wave * N::STAGE_FLOATS;
+  float* Ys = Xs + N::XROWS * N::SROW;
+  LaneLevels<N> ll;
+  lane_levels<N>(a.lv, g, ll);
+  constexpr f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+
+  for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += gridDim.x * 4) {
+    const int s = tile * 16 + jc;
+    const bool valid = s < S;
+    float xn[3] = {0.5f, 0.5f, 0.5f}, d[3] = {0.0f, 0.0f, 1.0f};
+    if (valid) load_sample(src, s, xn, d);
+    Acts<N> act;
+    encode<N>(a.table, a.lv.table_mask, ll, xn, act.e);
+    if (!valid) {
+#pragma unroll
+      for (int k = 0; k < N::NSLOT; ++k) act.e[k] = 0.0f;
+    }
+    sh_lane<N>(d, g, act.sh);
+    mlp_fwd<N>(Af, lane, act);
+
+    // seeds: dz = dc * c (1 - c) and dsigma, on lane group 0
+    float ds = 0.0f;
+    f4 dz = zero;
+    if (g == 0 && valid) {
+      ds = dsigma[s];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const float c = sigmoidf(act.z[r]);
+        dz[r] = drgb[3 * s + r] * c * (1.0f - c);
+      }
+    }
+    // last layer: dh_last = W_last dz, masked
+    const f4* hl = (N::NCH == 2) ? act.h4 : act.h3;
+    f4 dhl[N::HC / 16];
+    {
+      const float* A = Ab + N::boff(N::NW - 1) + lane;
+#pragma unroll
+      for (int m = 0; m < N::HC / 16; ++m) {
+        f4 acc = zero;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc = mfma4(A[(m * 3 + k) * kWave], dz[k], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = hl[m][r] > 0.0f ? acc[r] : 0.0f;
+        dhl[m] = acc;
+      }
+    }
+    // dW of the last layer
+    stage_d<N, N::HC / 16>(Xs, hl, g, jc);
+    stage_d<N, 1>(Ys, &dz, g, jc);
+    wave_lds_fence();
+    dw_accumulate<N, N::HC, 3>(Xs, Ys, dW + N::woff(N::NW - 1), lane);
+    wave_lds_fence();
+
+    f4 dh3[N::HC / 16];
+    if constexpr (N::NCH == 2) {
+      const float* A = Ab + N::boff(3) + lane;
+#pragma unroll
+      for (int m = 0; m < N::HC / 16; ++m) {
+        f4 acc = zero;
+#pragma unroll
+        for (int k = 0; k < N::HC / 4; ++k) acc = mfma4(A[(m * (N::HC / 4) + k) * kWave], dhl[k >> 2][k & 3], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = act.h3[m][r] > 0.0f ? acc[r] : 0.0f;
+        dh3[m] = acc;
+      }
+      stage_d<N, N::HC / 16>(Xs, act.h3, g, jc);
+      stage_d<N, N::HC / 16>(Ys, dhl, g, jc);
+      wave_lds_fence();
+      dw_accumulate<N, N::HC, N::HC>(Xs, Ys, dW + N::woff(3), lane);
+      wave_lds_fence();
+    } else {
+#pragma unroll
+      for (int m = 0; m < N::HC / 16; ++m) dh3[m] = dhl[m];
+    }
+    // colour input layer: d(geo) = W3[geo rows] dh3; dW3 with X = [o, sh]
+    f4 dgeo = zero;
+    {
+      const float* A = Ab + N::boff(2) + lane;
+#pragma unroll
+      for (int k = 0; k < N::HC / 4; ++k) dgeo = mfma4(A[k * kWave], dh3[k >> 2][k & 3], dgeo);
+    }
+    stage_d<N, 1>(Xs, &act.o, g, jc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Xs[(16 + 4 * g + r) * N::SROW + jc] = act.sh[r];
+    stage_d<N, N::HC / 16>(Ys, dh3, g, jc);
+    wave_lds_fence();
+    dw_accumulate<N, N::CIN, N::HC>(Xs, Ys, dW + N::woff(2), lane);
+    wave_lds_fence();
+    // density output: do = dgeo, do_0 += sigma * dsigma
+    if (g == 0) dgeo[0] += __expf(act.o[0]) * ds;
+    f4 dh1[N::HD / 16];
+    {
+      const float* A = Ab + N::boff(1) + lane;
+#pragma unroll
+      for (int m = 0; m < N::HD / 16; ++m) {
+        f4 acc = zero;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc = mfma4(A[(m * 4 + k) * kWave], dgeo[k], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = act.h1[m][r] > 0.0f ? acc[r] : 0.0f;
+        dh1[m] = acc;
+      }
+    }
+    stage_d<N, N::HD / 16>(Xs, act.h1, g, jc);
+    stage_d<N, 1>(Ys, &dgeo, g, jc);
+    wave_lds_fence();
+    dw_accumulate<N, N::HD, 16>(Xs, Ys, dW + N::woff(1), lane);
+    wave_lds_fence();
+    // encoding gradient: de = W1 dh1 (rows = this lane group's slots)
+    constexpr int MT0 = N::bmt(0);
+    f4 de[MT0];
+    {
+      const float* A = Ab + N::boff(0) + lane;
+#pragma unroll
+      for (int m = 0; m < MT0; ++m) {
+        f4 acc = zero;
+#pragma unroll
+        for (int k = 0; k < N::HD / 4; ++k) acc = mfma4(A[(m * (N::HD / 4) + k) * kWave], dh1[k >> 2][k & 3], acc);
+        de[m] = acc;
+      }
+    }
+    // dW1 with X = e (slots -> features)
+#pragma unroll
+    for (int k = 0; k < N::NSLOT; ++k) Xs[fwd_in_feature<N>(0, k, g) * N::SROW + jc] = act.e[k];
+    if constexpr (N::ENC < 16) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) Xs[(N::ENC + 2 * g + k) * N::SROW + jc] = 0.0f;
+    }
+    stage_d<N, N::HD / 16>(Ys, dh1, g, jc);
+    wave_lds_fence();
+    dw_accumulate<N, N::ENC, N::HD>(Xs, Ys, dW + N::woff(0), lane);
+    wave_lds_fence();
+    // scatter into the table gradient
+    if (valid) {
+#pragma unroll
+      for (int q = 0; q < N::LPL; ++q) {
+        const int k0 = 2 * q, k1 = 2 * q + 1;
+        const float d0 = de[k0 >> 2][k0 & 3], d1 = de[k1 >> 2][k1 & 3];
+        Corner8 c;
+        corners(xn[0], xn[1], xn[2], ll.res[q], ll.dense[q], a.lv.table_mask, ll.off[q], c);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          float* p = grad_table + 2 * (size_t)c.idx[k];
+          unsafeAtomicAdd(p, c.w[k] * d0);
+          unsafeAtomicAdd(p + 1, c.w[k] * d1);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  float* out = dw_partial + (size_t)blockIdx.x * N::NWEIGHTS;
+  for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) out[i] = dW[i];
+}
+
+// grads[w] += sum over blocks of the per-block weight gradients.
+template <class N>
+__global__ void dw_reduce_kernel(const float* __restrict__ partial, int nblocks, WOffsets wo,
+                                 float* __restrict__ grads) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N::NWEIGHTS) return;
+  float acc = 0.0f;
+  for (int b = 0; b < nblocks; ++b) acc += partial[(size_t)b * N::NWEIGHTS + i];
+  int j = 0;
+  while (j + 1 < N::NW && i >= N::woff(j + 1)) ++j;
+  grads[wo.off[j] + (i - N::woff(j))] += acc;
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+
+template <class N>
+static hipError_t launch_prep(const float* params, const WOffsets& wo, float* out, hipStream_t st) {
+  const int n = N::FWD_FLOATS + N::BWD_FLOATS;
+  hipLaunchKernelGGL(prep_weights_kernel<N>, dim3((n + 255) / 256), dim3(256), 0, st, params, wo, out);
+  return hipGetLastError();
+}
+
+template <class N>
+static hipError_t launch_fwd(const FieldArgs& a, const SampleSrc& src, int max_samples,
+                             float* sigma, float* rgb, hipStream_t st) {
+  const int tiles = (max_samples + 15) / 16;
+  if (tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(field_fwd_kernel<N>, dim3((tiles + 3) / 4), dim3(256), 0, st, a, src, sigma, rgb);
+  return hipGetLastError();
+}
+
+template <class N>
+static hipError_t launch_bwd(const FieldArgs& a, const SampleSrc& src, int nblocks,
+                             const float* dsigma, const float* drgb, float* grad_table,
+                             float* partial, const WOffsets& wo, float* grads, hipStream_t st) {
+  hipLaunchKernelGGL(field_bwd_kernel<N>, dim3(nblocks), dim3(256), 0, st, a, src, dsigma, drgb,
+                     grad_table, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(dw_reduce_kernel<N>, dim3((N::NWEIGHTS + 255) / 256), dim3(256), 0, st,
+                     partial, nblocks, wo, grads);
+  return hipGetLastError();
+}
+
+size_t field_prep_floats(int shape) {
+  return shape == kShapeTiny ? NetTiny::FWD_FLOATS + NetTiny::BWD_FLOATS
+                             : NetFull::FWD_FLOATS + NetFull::BWD_FLOATS;
+}
+size_t field_nweights(int shape) {
+  return shape == kShapeTiny ? NetTiny::NWEIGHTS : NetFull::NWEIGHTS;
+}
+
+hipError_t field_prep(int shape, const float* params, const WOffsets& wo, float* out, hipStream_t st) {
+  return shape == kShapeTiny ? launch_prep<NetTiny>(params, wo, out, st)
+                             : launch_prep<NetFull>(params, wo, out, st);
+}
+
+hipError_t field_forward(int shape, const FieldArgs& a, const SampleSrc& src, int max_samples,
+                         float* sigma, float* rgb, hipStream_t st) {
+  return shape == kShapeTiny ? launch_fwd<NetTiny>(a, src, max_samples, sigma, rgb, st)
+                             : launch_fwd<NetFull>(a, src, max_samples, sigma, rgb, st);
+}
+
+hipError_t field_backward(int shape, const FieldArgs& a, const SampleSrc& src, int nblocks,
+                          const float* dsigma, const float* drgb, float* grad_table,
+                          float* partial, const WOffsets& wo, float* grads, hipStream_t st) {
+  return shape == kShapeTiny
+             ? launch_bwd<NetTiny>(a, src, nblocks, dsigma, drgb, grad_table, partial, wo, grads, st)
+             : launch_bwd<NetFull>(a, src, nblocks, dsigma, drgb, grad_table, partial, wo, grads, st);
+}
+
+}  // namespace nsl

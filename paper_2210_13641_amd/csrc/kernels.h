@@ -1,0 +1,124 @@
+// Internal interface between the C ABI (api.cpp) and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace nsl {
+
+enum { kShapeTiny = 0, kShapeFull = 1 };
+
+struct WOffsets {
+  int off[8];  // float offset of each weight matrix in the parameter vector
+};
+
+struct FieldArgs {
+  const float* table;  // parameter vector (the tables start at 0)
+  const float* wprep;  // MFMA-ready weight operands (field_prep output)
+  LevelInfo lv;
+};
+
+// Where the field's samples come from: either compacted march samples
+// (t, ray) with per-ray records rays[2r] = (o, s), rays[2r+1] = (d, 0), or
+// explicit normalised positions and directions.  The sample count is n, or
+// *n_dev when n_dev is set (known on the device only).
+struct SampleSrc {
+  const float* t;
+  const uint32_t* ray;
+  const float4* rays;
+  const float* xn;
+  const float* dir;
+  Aabb box;
+  const uint32_t* n_dev;
+  int n;
+};
+
+// field.hip
+size_t field_prep_floats(int shape);
+size_t field_nweights(int shape);
+hipError_t field_prep(int shape, const float* params, const WOffsets& wo, float* out, hipStream_t st);
+hipError_t field_forward(int shape, const FieldArgs& a, const SampleSrc& src, int max_samples,
+                         float* sigma, float* rgb, hipStream_t st);
+hipError_t field_backward(int shape, const FieldArgs& a, const SampleSrc& src, int nblocks,
+                          const float* dsigma, const float* drgb, float* grad_table,
+                          float* partial, const WOffsets& wo, float* grads, hipStream_t st);
+
+// march.hip
+struct KeyframeStore {
+  const float* rgb;        // [K,H,W,3]
+  const float* depth;      // [K,H,W]
+  const float* var;        // [K,H,W]
+  const float* pose;       // [K,12]
+  const float* intr;       // [K,4]
+  const uint32_t* occ;     // bitfield
+  int H, W, K, grid_res;
+};
+
+struct MarchParams {
+  int sampler;
+  float t_near, t_far, dt;
+  int n_uniform, max_per_ray, max_samples;
+  Aabb box;
+};
+
+// Per-candidate ray records and targets written by the ray kernel.
+struct RayBuffers {
+  float4* rays;        // [2*n]: (o, s), (d, 0)
+  float4* target;      // [n]: (r, g, b, D_ray)
+  float* prec;         // [n]: 1/Sigma_ray or 0
+  uint32_t* counts;    // [n]
+  uint32_t* offsets;   // [n+1]
+  uint32_t* block_sums;
+  uint32_t* stats;     // [4]: R, S, kept, masked
+  float* loss;         // [3]
+};
+
+hipError_t march_rays(const KeyframeStore& kf, const MarchParams& mp, const uint32_t* ids, int n,
+                      const RayBuffers& rb, hipStream_t st);
+hipError_t march_emit(const KeyframeStore& kf, const MarchParams& mp, const uint32_t* ids, int n,
+                      const RayBuffers& rb, float* t_out, uint32_t* ray_out, hipStream_t st);
+size_t march_block_count(int n);
+
+// composite.hip
+struct CompositeIO {
+  const float* sigma;
+  const float* rgb;
+  const float* t;
+  const uint32_t* off;     // ray r owns [off[r], off[r+1])  (train step: candidate offsets)
+  const uint32_t* counts;  // optional: kept iff off[r+1] <= max_samples and counts[r] > 0
+  int max_samples;
+  int R;
+  float delta;
+  float stop_T;
+  float* out6;             // [R,6] ray units (or null)
+};
+
+struct LossIO {
+  const float4* target;    // (r, g, b, D_ray)
+  const float* prec;
+  const float4* rays;      // for s (z units)
+  const uint32_t* stats;   // R at stats[0]
+  float lambda_d;
+  float loss_scale;
+  float* loss;             // [3] accumulated
+  float* ray_out;          // [R,6] z units or null
+};
+
+hipError_t composite_forward(const CompositeIO& io, hipStream_t st);
+hipError_t composite_backward(const CompositeIO& io, const float* g_rgb, const float* g_depth,
+                              const float* g_var, float* g_sigma, float* g_rgb_s, hipStream_t st);
+hipError_t composite_loss_backward(const CompositeIO& io, const LossIO& lo, float* g_sigma,
+                                   float* g_rgb_s, hipStream_t st);
+
+// misc.hip
+hipError_t adam_update(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, int step, float grad_scale, hipStream_t st);
+hipError_t fill_zero(float* p, int64_t n, hipStream_t st);
+hipError_t render_setup(const float* pose, const float* intr, int H, int W, float t_near, float dt,
+                        int n_samples, Aabb box, float4* rays, float* t, uint32_t* ray,
+                        uint32_t* off, hipStream_t st);
+hipError_t render_finish(const float* out6, const float4* rays, int n, float* rgb, float* depth,
+                         float* var, float* opacity, hipStream_t st);
+
+}  // namespace nsl

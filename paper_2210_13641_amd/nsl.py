@@ -1,0 +1,310 @@
+"""ctypes binding of libnsl.so (include/nsl.h): argument marshalling only.
+
+Every function here forwards torch device pointers and the current HIP
+stream to the library; all computation runs in the library's gfx950
+kernels.  If the library is not built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnsl.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2210_13641_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+OK = 0
+E_INVALID, E_WORKSPACE, E_HIP, E_BUDGET, E_CAPACITY = -1, -2, -3, -4, -5
+SAMPLER_UNIFORM, SAMPLER_OCCUPANCY = 0, 1
+MAX_LEVELS, MAX_LAYERS = 16, 8
+
+
+class FieldConfig(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("feat_per_level", C.c_int32), ("log2_table", C.c_int32),
+                ("base_res", C.c_int32), ("per_level_scale", C.c_float), ("max_res", C.c_int32),
+                ("density_hidden", C.c_int32), ("geo_dim", C.c_int32), ("sh_bands", C.c_int32),
+                ("n_colour_hidden", C.c_int32), ("colour_hidden", C.c_int32 * 4),
+                ("aabb_min", C.c_float * 3), ("aabb_max", C.c_float * 3)]
+
+
+class ParamLayout(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("res", C.c_int32 * MAX_LEVELS), ("dense", C.c_int32 * MAX_LEVELS),
+                ("level_entries", C.c_int64 * MAX_LEVELS), ("level_offset", C.c_int64 * MAX_LEVELS),
+                ("table_floats", C.c_int64), ("n_layers", C.c_int32), ("w_offset", C.c_int64 * MAX_LAYERS),
+                ("w_in", C.c_int32 * MAX_LAYERS), ("w_out", C.c_int32 * MAX_LAYERS),
+                ("total_floats", C.c_int64)]
+
+
+class StepConfig(C.Structure):
+    _fields_ = [("sampler", C.c_int32), ("t_near", C.c_float), ("t_far", C.c_float), ("dt", C.c_float),
+                ("n_uniform", C.c_int32), ("max_per_ray", C.c_int32), ("max_samples", C.c_int32),
+                ("lambda_d", C.c_float), ("zero_grads", C.c_int32), ("do_adam", C.c_int32),
+                ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("adam_step", C.c_int32), ("loss_scale", C.c_float)]
+
+
+class RenderConfig(C.Structure):
+    _fields_ = [("t_near", C.c_float), ("dt", C.c_float), ("n_samples", C.c_int32), ("stop_T", C.c_float)]
+
+
+_vp, _i, _sz, _f = C.c_void_p, C.c_int, C.c_size_t, C.c_float
+
+
+def _sig(name, res, args):
+    fn = getattr(_lib, name)
+    fn.restype = res
+    fn.argtypes = args
+    return fn
+
+
+_sig("nsl_last_error", C.c_char_p, [])
+_sig("nsl_version", _i, [])
+_sig("nsl_field_layout", _i, [C.POINTER(FieldConfig), C.POINTER(ParamLayout)])
+_sig("nsl_field_create", _i, [C.POINTER(FieldConfig), C.POINTER(_vp)])
+_sig("nsl_field_destroy", None, [_vp])
+_sig("nsl_mapper_storage_bytes", _sz, [_i, _i, _i, _i])
+_sig("nsl_mapper_create", _i, [_i, _i, _i, _i, _vp, _sz, C.POINTER(_vp)])
+_sig("nsl_mapper_destroy", None, [_vp])
+_sig("nsl_mapper_count", _i, [_vp])
+_sig("nsl_keyframes_upsert", _i, [_vp, _i, _vp, _vp, _vp, _vp, _vp, _vp, _i, _vp])
+_sig("nsl_keyframe_slot", _i, [_vp, C.c_int32])
+_sig("nsl_occupancy_set", _i, [_vp, _vp, _i, _vp])
+_sig("nsl_step_workspace_bytes", _sz, [_vp, C.POINTER(StepConfig), _i])
+_sig("nsl_train_step", _i, [_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(StepConfig), _vp, _i, _vp, _sz, _vp,
+                            _vp, _vp, _vp])
+_sig("nsl_march", _i, [_vp, _vp, C.POINTER(StepConfig), _vp, _i, _vp, _sz, _vp, _vp, _vp, _vp, _vp, _vp])
+_sig("nsl_field_workspace_bytes", _sz, [_vp])
+_sig("nsl_field_fwd", _i, [_vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _sz, _vp])
+_sig("nsl_field_bwd", _i, [_vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp])
+_sig("nsl_composite_fwd", _i, [_vp, _vp, _vp, _vp, _i, _f, _f, _vp, _vp])
+_sig("nsl_composite_bwd", _i, [_vp, _vp, _vp, _vp, _i, _f, _vp, _vp, _vp, _vp, _vp, _vp])
+_sig("nsl_adam", _i, [_vp, _vp, _vp, _vp, C.c_int64, _f, _f, _f, _f, _i, _f, _vp])
+_sig("nsl_render_workspace_bytes", _sz, [_vp, _i, _i, C.POINTER(RenderConfig)])
+_sig("nsl_render", _i, [_vp, _vp, _vp, _vp, _i, _i, C.POINTER(RenderConfig), _vp, _vp, _vp, _vp, _vp, _sz, _vp])
+
+EXPORTED = [n for n in dir(_lib) if n.startswith("nsl_")]
+
+
+class NslError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nsl error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != OK:
+        raise NslError(rc, _lib.nsl_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype):
+    if t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    return _ptr(t)
+
+
+def version():
+    return _lib.nsl_version()
+
+
+# ---------------------------------------------------------------------------
+# Field
+# ---------------------------------------------------------------------------
+
+def field_config(spec) -> FieldConfig:
+    """nsl_field_config from a workloads.FieldSpec-like object."""
+    c = FieldConfig()
+    c.levels, c.feat_per_level, c.log2_table, c.base_res = spec.levels, spec.feat_per_level, spec.log2_table, spec.base_res
+    c.per_level_scale = spec.per_level_scale if spec.per_level_scale is not None else 0.0
+    c.max_res = spec.max_res or 0
+    c.density_hidden, c.geo_dim, c.sh_bands = spec.density_hidden, spec.geo_dim, spec.sh_bands
+    c.n_colour_hidden = len(spec.colour_hidden)
+    for i, h in enumerate(spec.colour_hidden):
+        c.colour_hidden[i] = h
+    for i in range(3):
+        c.aabb_min[i], c.aabb_max[i] = spec.aabb_min[i], spec.aabb_max[i]
+    return c
+
+
+def field_layout(spec) -> dict:
+    cfg = field_config(spec)
+    lay = ParamLayout()
+    _check(_lib.nsl_field_layout(C.byref(cfg), C.byref(lay)))
+    L, nl = lay.levels, lay.n_layers
+    return dict(res=list(lay.res[:L]), dense=[bool(x) for x in lay.dense[:L]],
+                level_entries=list(lay.level_entries[:L]), level_offset=list(lay.level_offset[:L]),
+                table_floats=lay.table_floats, w_offsets=list(lay.w_offset[:nl]),
+                w_shapes=list(zip(lay.w_in[:nl], lay.w_out[:nl])), total=lay.total_floats)
+
+
+class Field:
+    def __init__(self, spec):
+        self.spec = spec
+        self.cfg = field_config(spec)
+        h = C.c_void_p()
+        _check(_lib.nsl_field_create(C.byref(self.cfg), C.byref(h)))
+        self.handle = h
+        self.layout = field_layout(spec)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.nsl_field_destroy(self.handle)
+            self.handle = None
+
+    def workspace_bytes(self):
+        return _lib.nsl_field_workspace_bytes(self.handle)
+
+    def fwd(self, params, xn, dirs, ws):
+        S = xn.shape[0]
+        sigma = torch.empty(S, device=xn.device, dtype=torch.float32)
+        rgb = torch.empty(S, 3, device=xn.device, dtype=torch.float32)
+        _check(_lib.nsl_field_fwd(self.handle, _dev(params, torch.float32), _dev(xn, torch.float32),
+                                  _dev(dirs, torch.float32), S, _ptr(sigma), _ptr(rgb), _ptr(ws),
+                                  ws.numel(), _stream()))
+        return sigma, rgb
+
+    def bwd(self, params, xn, dirs, dsigma, drgb, grads, ws):
+        S = xn.shape[0]
+        _check(_lib.nsl_field_bwd(self.handle, _dev(params, torch.float32), _dev(xn, torch.float32),
+                                  _dev(dirs, torch.float32), S, _dev(dsigma, torch.float32),
+                                  _dev(drgb, torch.float32), _dev(grads, torch.float32), _ptr(ws),
+                                  ws.numel(), _stream()))
+
+
+# ---------------------------------------------------------------------------
+# Mapper
+# ---------------------------------------------------------------------------
+
+def mapper_storage_bytes(max_kf, H, W, grid_res):
+    return _lib.nsl_mapper_storage_bytes(max_kf, H, W, grid_res)
+
+
+class Mapper:
+    def __init__(self, max_kf, H, W, grid_res=1, device="cuda"):
+        self.H, self.W, self.grid_res = H, W, grid_res
+        nbytes = mapper_storage_bytes(max_kf, H, W, grid_res)
+        self.storage = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        h = C.c_void_p()
+        _check(_lib.nsl_mapper_create(max_kf, H, W, grid_res, _ptr(self.storage), nbytes, C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.nsl_mapper_destroy(self.handle)
+            self.handle = None
+
+    def count(self):
+        return _lib.nsl_mapper_count(self.handle)
+
+    def slot(self, kf_id):
+        return _lib.nsl_keyframe_slot(self.handle, kf_id)
+
+    def upsert(self, ids, rgb, pose, intr, depth, depth_var):
+        """ids: sequence of ints; arrays are device tensors (float32)."""
+        ids_c = (C.c_int32 * len(ids))(*ids)
+        _check(_lib.nsl_keyframes_upsert(self.handle, len(ids), ids_c, _dev(rgb, torch.float32),
+                                         _dev(pose, torch.float32), _dev(intr, torch.float32),
+                                         _dev(depth, torch.float32), _dev(depth_var, torch.float32), 0,
+                                         _stream()))
+
+    def set_occupancy(self, bits):
+        _check(_lib.nsl_occupancy_set(self.handle, _dev(bits, torch.int32), 0, _stream()))
+
+
+# ---------------------------------------------------------------------------
+# Step
+# ---------------------------------------------------------------------------
+
+def step_config(sampler_spec, lambda_d=1.0, zero_grads=True, do_adam=False, lr=1e-2, betas=(0.9, 0.99),
+                eps=1e-15, adam_step=1, loss_scale=1.0) -> StepConfig:
+    c = StepConfig()
+    c.sampler = SAMPLER_UNIFORM if sampler_spec.mode == "uniform" else SAMPLER_OCCUPANCY
+    c.t_near, c.t_far, c.dt = sampler_spec.t_near, sampler_spec.t_far, sampler_spec.dt
+    c.n_uniform, c.max_per_ray, c.max_samples = sampler_spec.n_uniform, sampler_spec.max_per_ray, sampler_spec.max_samples
+    c.lambda_d, c.zero_grads, c.do_adam = lambda_d, int(zero_grads), int(do_adam)
+    c.lr, c.beta1, c.beta2, c.eps = lr, betas[0], betas[1], eps
+    c.adam_step, c.loss_scale = adam_step, loss_scale
+    return c
+
+
+def step_workspace_bytes(field: Field, cfg: StepConfig, n_candidates: int) -> int:
+    return _lib.nsl_step_workspace_bytes(field.handle, C.byref(cfg), n_candidates)
+
+
+def train_step(mapper: Mapper, field: Field, params, grads, adam_m, adam_v, cfg: StepConfig, pixel_ids,
+               ws, loss_out, stats_out=None, ray_out=None):
+    _check(_lib.nsl_train_step(mapper.handle, field.handle, _dev(params, torch.float32), _dev(grads, torch.float32),
+                               _ptr(adam_m), _ptr(adam_v), C.byref(cfg), _dev(pixel_ids, torch.int32),
+                               pixel_ids.numel(), _ptr(ws), ws.numel(), _dev(loss_out, torch.float32),
+                               _ptr(stats_out), _ptr(ray_out), _stream()))
+
+
+def march(mapper: Mapper, field: Field, cfg: StepConfig, pixel_ids, ws, counts, offsets, t, ray, stats_out=None):
+    _check(_lib.nsl_march(mapper.handle, field.handle, C.byref(cfg), _dev(pixel_ids, torch.int32),
+                          pixel_ids.numel(), _ptr(ws), ws.numel(), _dev(counts, torch.int32),
+                          _dev(offsets, torch.int32), _dev(t, torch.float32), _dev(ray, torch.int32),
+                          _ptr(stats_out), _stream()))
+
+
+def composite_fwd(sigma, rgb, t, ray_off, delta, stop_T=0.0):
+    R = ray_off.numel() - 1
+    out = torch.empty(R, 6, device=sigma.device, dtype=torch.float32)
+    _check(_lib.nsl_composite_fwd(_dev(sigma, torch.float32), _dev(rgb, torch.float32), _dev(t, torch.float32),
+                                  _dev(ray_off, torch.int32), R, delta, stop_T, _ptr(out), _stream()))
+    return out
+
+
+def composite_bwd(sigma, rgb, t, ray_off, delta, g_rgb=None, g_depth=None, g_var=None):
+    R = ray_off.numel() - 1
+    g_sigma = torch.zeros_like(sigma)
+    g_rgb_s = torch.zeros_like(rgb)
+    _check(_lib.nsl_composite_bwd(_dev(sigma, torch.float32), _dev(rgb, torch.float32), _dev(t, torch.float32),
+                                  _dev(ray_off, torch.int32), R, delta, _ptr(g_rgb), _ptr(g_depth), _ptr(g_var),
+                                  _ptr(g_sigma), _ptr(g_rgb_s), _stream()))
+    return g_sigma, g_rgb_s
+
+
+def adam(params, grads, m, v, lr, beta1, beta2, eps, step, grad_scale=1.0):
+    _check(_lib.nsl_adam(_dev(params, torch.float32), _dev(grads, torch.float32), _dev(m, torch.float32),
+                         _dev(v, torch.float32), params.numel(), lr, beta1, beta2, eps, step, grad_scale,
+                         _stream()))
+
+
+def render_config(t_near, dt, n_samples, stop_T=0.0) -> RenderConfig:
+    c = RenderConfig()
+    c.t_near, c.dt, c.n_samples, c.stop_T = t_near, dt, n_samples, stop_T
+    return c
+
+
+def render_workspace_bytes(field: Field, H, W, cfg: RenderConfig):
+    return _lib.nsl_render_workspace_bytes(field.handle, H, W, C.byref(cfg))
+
+
+def render(field: Field, params, pose, intr, H, W, cfg: RenderConfig, ws, rgb=None, depth=None, var=None,
+           opacity=None):
+    dev = params.device
+    rgb = torch.empty(H * W, 3, device=dev) if rgb is None else rgb
+    depth = torch.empty(H * W, device=dev) if depth is None else depth
+    var = torch.empty(H * W, device=dev) if var is None else var
+    _check(_lib.nsl_render(field.handle, _dev(params, torch.float32), _dev(pose, torch.float32),
+                           _dev(intr, torch.float32), H, W, C.byref(cfg), _ptr(rgb), _ptr(depth), _ptr(var),
+                           _ptr(opacity), _ptr(ws), ws.numel(), _stream()))
+    return rgb, depth, var, opacity
