@@ -226,6 +226,20 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
                    size_t workspace_bytes, float* loss_out, nsl_step_stats* stats_out,
                    float* ray_out, hipStream_t stream);
 
+/* Phase timing.  While enabled, every nsl_train_step records a HIP event on
+ * its stream before each phase and after the last one, waits for the last
+ * event (so profiled steps synchronise the host), and accumulates the
+ * elapsed milliseconds per phase:
+ *   0 gradient clearing and weight-operand preparation, 1 rays + march +
+ *   batch cut, 2 field forward, 3 compositing + loss + its adjoint,
+ *   4 field backward (recompute, MLP adjoint, scatter, weight reduction),
+ *   5 Adam.
+ * nsl_profile_read copies the sums (ms[NSL_PHASES]) and the number of
+ * profiled steps; enabling again resets them. */
+#define NSL_PHASES 6
+int nsl_profile_enable(int on);
+int nsl_profile_read(double* ms, int* n_steps);
+
 /* ------------------------------------------------------------------------
  * Kernel-level entry points: the same kernels as the step, one phase each.
  * ------------------------------------------------------------------------ */

@@ -57,6 +57,14 @@ struct Carver {
 
 constexpr int kBwdBlocks = 256;  // persistent backward grid (one block per CU)
 
+struct Profiler {
+  bool on = false;
+  hipEvent_t ev[NSL_PHASES + 1] = {};
+  double ms[NSL_PHASES] = {};
+  int steps = 0;
+};
+Profiler g_prof;
+
 }  // namespace
 
 struct nsl_field {
@@ -384,14 +392,20 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   if (stats_out) b.rb.stats = reinterpret_cast<uint32_t*>(stats_out);
   b.rb.loss = loss_out;
   const int64_t total = f->lay.total_floats;
+  const bool prof = g_prof.on;
+  auto mark = [&](int i) -> hipError_t { return prof ? hipEventRecord(g_prof.ev[i], st) : hipSuccess; };
+  HIP_TRY(mark(0), "profile event");
   if (c->zero_grads) HIP_TRY(fill_zero(grads, total, st), "zero grads");
   HIP_TRY(field_prep(f->shape, params, f->wo, b.wprep, st), "prep weights");
+  HIP_TRY(mark(1), "profile event");
   if ((rc = run_march(m, f, c, ids, n, b, st))) return rc;
+  HIP_TRY(mark(2), "profile event");
 
   FieldArgs fa{params, b.wprep, f->lv};
   SampleSrc src{};
   src.t = b.t; src.ray = b.ray; src.rays = b.rb.rays; src.box = f->box; src.n_dev = b.rb.stats + 1; src.n = 0;
   HIP_TRY(field_forward(f->shape, fa, src, c->max_samples, b.sigma, b.rgb, st), "field forward");
+  HIP_TRY(mark(3), "profile event");
 
   CompositeIO io{};
   io.sigma = b.sigma; io.rgb = b.rgb; io.t = b.t; io.off = b.rb.offsets; io.counts = b.rb.counts;
@@ -400,13 +414,25 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   lo.target = b.rb.target; lo.prec = b.rb.prec; lo.rays = b.rb.rays; lo.stats = b.rb.stats;
   lo.lambda_d = c->lambda_d; lo.loss_scale = c->loss_scale; lo.loss = loss_out; lo.ray_out = ray_out;
   HIP_TRY(composite_loss_backward(io, lo, b.dsigma, b.drgb, st), "composite");
+  HIP_TRY(mark(4), "profile event");
 
   HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, b.dsigma, b.drgb, grads, b.partial, f->wo, grads, st),
           "field backward");
+  HIP_TRY(mark(5), "profile event");
   if (c->do_adam)
     HIP_TRY(adam_update(params, grads, adam_m, adam_v, total, c->lr, c->beta1, c->beta2, c->eps, c->adam_step,
                         1.0f / c->loss_scale, st),
             "adam");
+  HIP_TRY(mark(6), "profile event");
+  if (prof) {
+    HIP_TRY(hipEventSynchronize(g_prof.ev[NSL_PHASES]), "profile sync");
+    for (int i = 0; i < NSL_PHASES; ++i) {
+      float ms = 0.0f;
+      HIP_TRY(hipEventElapsedTime(&ms, g_prof.ev[i], g_prof.ev[i + 1]), "profile elapsed");
+      g_prof.ms[i] += ms;
+    }
+    ++g_prof.steps;
+  }
   return NSL_OK;
 }
 
@@ -427,6 +453,29 @@ int nsl_march(nsl_mapper* m, const nsl_field* f, const nsl_step_config* c, const
   if (stats_out) b.rb.stats = reinterpret_cast<uint32_t*>(stats_out);
   b.rb.loss = nullptr;
   return run_march(m, f, c, ids, n, b, st);
+}
+
+int nsl_profile_enable(int on) {
+  if (on && !g_prof.on) {
+    for (auto& e : g_prof.ev) HIP_TRY(hipEventCreate(&e), "create profile event");
+  }
+  if (!on && g_prof.on) {
+    for (auto& e : g_prof.ev) {
+      (void)hipEventDestroy(e);
+      e = nullptr;
+    }
+  }
+  g_prof.on = on != 0;
+  for (double& x : g_prof.ms) x = 0.0;
+  g_prof.steps = 0;
+  return NSL_OK;
+}
+
+int nsl_profile_read(double* ms, int* n_steps) {
+  if (!ms || !n_steps) return fail(NSL_E_INVALID, "null argument");
+  for (int i = 0; i < NSL_PHASES; ++i) ms[i] = g_prof.ms[i];
+  *n_steps = g_prof.steps;
+  return NSL_OK;
 }
 
 size_t nsl_field_workspace_bytes(const nsl_field* f) {

@@ -105,6 +105,67 @@ __device__ __forceinline__ float wave_incl_scan(float v) {
   return v;
 }
 
+// DPP row shift towards lower lanes: lane i of each 16-lane row receives the
+// value of lane i+N of the same row (0 when i+N leaves the row).
+template <int N>
+__device__ __forceinline__ int row_from_above(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x100 + N, 0xF, 0xF, true);
+}
+template <int N>
+__device__ __forceinline__ float row_from_above(float v) {
+  return __int_as_float(row_from_above<N>(__float_as_int(v)));
+}
+// Lane i receives lane i-N of its row (0 when i-N leaves the row).
+template <int N>
+__device__ __forceinline__ int row_from_below(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x110 + N, 0xF, 0xF, true);
+}
+
+// Runs of equal keys among consecutive lanes of each 16-lane row: the first
+// lane of every run gets the sums of a and b over the run (segmented suffix
+// scan); returns whether this lane starts a run.
+__device__ __forceinline__ bool row_run_sums(uint32_t key, float& a, float& b) {
+  const int r = threadIdx.x & 15;
+  const uint32_t above = (uint32_t)row_from_above<1>((int)key);
+  const uint32_t below = (uint32_t)row_from_below<1>((int)key);
+  const bool head = r == 0 || below != key;
+  int tail = (r == 15 || above != key) ? 1 : 0;  // a run ends within [r, r + span)
+#define NSL_RUN_STEP(N)                               \
+  {                                                   \
+    const float na = row_from_above<N>(a);            \
+    const float nb = row_from_above<N>(b);            \
+    const int nt = row_from_above<N>(tail);           \
+    if (!tail) {                                      \
+      a += na;                                        \
+      b += nb;                                        \
+      tail = nt;                                      \
+    }                                                 \
+  }
+  NSL_RUN_STEP(1)
+  NSL_RUN_STEP(2)
+  NSL_RUN_STEP(4)
+  NSL_RUN_STEP(8)
+#undef NSL_RUN_STEP
+  return head;
+}
+
+// p[0] += a, p[1] += b as one 64-bit compare-and-swap loop: one memory-side
+// atomic per table entry instead of two (the two features of an entry share
+// 8 aligned bytes).  The first read may be stale; the CAS corrects it.
+__device__ __forceinline__ void atomic_add_pair(float* p, float a, float b) {
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+  unsigned long long seen = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned long long want;
+  do {
+    want = seen;
+    const float x = __uint_as_float((unsigned)(want & 0xFFFFFFFFull)) + a;
+    const float y = __uint_as_float((unsigned)(want >> 32)) + b;
+    const unsigned long long next = (unsigned long long)__float_as_uint(x) |
+                                    ((unsigned long long)__float_as_uint(y) << 32);
+    seen = atomicCAS(q, want, next);
+  } while (seen != want);
+}
+
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }

@@ -482,19 +482,23 @@ __global__ __launch_bounds__(256, 1) void field_bwd_kernel(FieldArgs a, SampleSr
     wave_lds_fence();
     dw_accumulate<N, N::ENC, N::HD>(Xs, Ys, dW + N::woff(0), lane);
     wave_lds_fence();
-    // scatter into the table gradient
-    if (valid) {
+    // Scatter into the table gradient.  The 16 lanes of a row hold 16
+    // consecutive samples (mostly along one ray) at the same level, so equal
+    // corners form runs of neighbouring lanes; each run is summed in
+    // registers and issues one 64-bit atomic update of the entry.
 #pragma unroll
-      for (int q = 0; q < N::LPL; ++q) {
-        const int k0 = 2 * q, k1 = 2 * q + 1;
-        const float d0 = de[k0 >> 2][k0 & 3], d1 = de[k1 >> 2][k1 & 3];
-        Corner8 c;
-        corners(xn[0], xn[1], xn[2], ll.res[q], ll.dense[q], a.lv.table_mask, ll.off[q], c);
+    for (int q = 0; q < N::LPL; ++q) {
+      const int k0 = 2 * q, k1 = 2 * q + 1;
+      const float d0 = valid ? de[k0 >> 2][k0 & 3] : 0.0f;
+      const float d1 = valid ? de[k1 >> 2][k1 & 3] : 0.0f;
+      Corner8 c;
+      corners(xn[0], xn[1], xn[2], ll.res[q], ll.dense[q], a.lv.table_mask, ll.off[q], c);
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          float* p = grad_table + 2 * (size_t)c.idx[k];
-          unsafeAtomicAdd(p, c.w[k] * d0);
-          unsafeAtomicAdd(p + 1, c.w[k] * d1);
+      for (int k = 0; k < 8; ++k) {
+        float v0 = c.w[k] * d0, v1 = c.w[k] * d1;
+        const uint32_t key = valid ? c.idx[k] : 0xFFFFFFFFu;
+        if (row_run_sums(key, v0, v1) && valid) {
+          atomic_add_pair(grad_table + 2 * (size_t)c.idx[k], v0, v1);
         }
       }
     }

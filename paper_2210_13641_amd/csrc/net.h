@@ -48,7 +48,11 @@ struct Net {
   }
   static constexpr int fmt(int j) { return j == 1 || j == NW - 1 ? 1 : (j == 0 ? HD : HC) / 16; }
   static constexpr int fsize(int j) { return fks(j) * fmt(j) * kWave; }
-  static constexpr int foff(int j) { return j == 0 ? 0 : foff(j - 1) + fsize(j - 1); }
+  static constexpr int foff(int j) {
+    int o = 0;
+    for (int i = 0; i < j; ++i) o += fsize(i);
+    return o;
+  }
   static constexpr int FWD_FLOATS = foff(NW - 1) + fsize(NW - 1);
 
   // backward (input-gradient) products, indexed by the layer they undo
@@ -57,12 +61,20 @@ struct Net {
     return j == NW - 1 ? HC / 16 : j == 2 ? 1 : j == 1 ? HD / 16 : j == 0 ? (NSLOT + 3) / 4 : HC / 16;
   }
   static constexpr int bsize(int j) { return bks(j) * bmt(j) * kWave; }
-  static constexpr int boff(int j) { return j == 0 ? 0 : boff(j - 1) + bsize(j - 1); }
+  static constexpr int boff(int j) {
+    int o = 0;
+    for (int i = 0; i < j; ++i) o += bsize(i);
+    return o;
+  }
   static constexpr int BWD_FLOATS = boff(NW - 1) + bsize(NW - 1);
 
   // compact dW layout (true shapes, [in][out] row-major per layer)
   static constexpr int wsize(int j) { return kin(j) * kout(j); }
-  static constexpr int woff(int j) { return j == 0 ? 0 : woff(j - 1) + wsize(j - 1); }
+  static constexpr int woff(int j) {
+    int o = 0;
+    for (int i = 0; i < j; ++i) o += wsize(i);
+    return o;
+  }
   static constexpr int NWEIGHTS = woff(NW - 1) + wsize(NW - 1);
 
   // staging rows for the dW transposes (X rows then dY rows), 20-float stride

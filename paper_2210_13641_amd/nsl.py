@@ -87,6 +87,9 @@ _sig("nsl_adam", _i, [_vp, _vp, _vp, _vp, C.c_int64, _f, _f, _f, _f, _i, _f, _vp
 _sig("nsl_render_workspace_bytes", _sz, [_vp, _i, _i, C.POINTER(RenderConfig)])
 _sig("nsl_render", _i, [_vp, _vp, _vp, _vp, _i, _i, C.POINTER(RenderConfig), _vp, _vp, _vp, _vp, _vp, _sz, _vp])
 
+_sig("nsl_profile_enable", _i, [_i])
+_sig("nsl_profile_read", _i, [C.POINTER(C.c_double), C.POINTER(_i)])
+
 EXPORTED = [n for n in dir(_lib) if n.startswith("nsl_")]
 
 
@@ -119,6 +122,20 @@ def _dev(t, dtype):
     if t.dtype != dtype:
         raise ValueError(f"expected {dtype}, got {t.dtype}")
     return _ptr(t)
+
+
+PHASES = ("prep", "march", "field_fwd", "composite_loss", "field_bwd", "adam")
+
+
+def profile_enable(on=True):
+    _check(_lib.nsl_profile_enable(int(on)))
+
+
+def profile_read():
+    ms = (C.c_double * len(PHASES))()
+    n = C.c_int()
+    _check(_lib.nsl_profile_read(ms, C.byref(n)))
+    return dict(zip(PHASES, list(ms))), n.value
 
 
 def version():
