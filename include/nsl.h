@@ -280,12 +280,12 @@ int nsl_composite_fwd(const float* sigma, const float* rgb, const float* t,
                       hipStream_t stream);
 
 /* Adjoint of nsl_composite_fwd (stop_T = 0) for seeds g_rgb [R,3],
- * g_depth [R], g_var [R] (any of the three may be NULL = 0):
- * g_sigma [S], g_rgb_s [S,3]. */
+ * g_depth [R], g_var [R], g_opacity [R] (any of them may be NULL = 0):
+ * g_sigma [S], g_rgb_s [S,3] (overwritten). */
 int nsl_composite_bwd(const float* sigma, const float* rgb, const float* t,
                       const uint32_t* ray_off, int R, float delta, const float* g_rgb,
-                      const float* g_depth, const float* g_var, float* g_sigma,
-                      float* g_rgb_s, hipStream_t stream);
+                      const float* g_depth, const float* g_var, const float* g_opacity,
+                      float* g_sigma, float* g_rgb_s, hipStream_t stream);
 
 /* Bias-corrected Adam over n parameters, gradient = grads * grad_scale;
  * clears grads. */

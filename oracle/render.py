@@ -22,7 +22,8 @@ where D_r is the measured depth along the ray and pi_r = 1/Sigma_D,r the
 precision (0 when the measurement is unusable).  ||x||^2_Sigma is read as
 the Mahalanobis norm x^2 / Sigma with Sigma a variance.
 
-Adjoint: for a sum Q = sum_i w_i q_i with q independent of tau,
+Adjoint: for a sum Q = sum_i w_i q_i with q independent of tau (q = c, t, or 1
+for the opacity A),
 dQ/dtau_k = T_{k+1} q_k - sum_{i>k} w_i q_i, where T_{k+1} = T_k e^{-tau_k};
 dV*/dtau_k adds -2 d*(1-A) dd*/dtau_k for the d* inside the square.
 """
@@ -60,7 +61,7 @@ def composite_ray(sigma, colour, t, delta, stop_T=0.0):
     return dict(tau=tau, T=T, w=w, C=C, D=D, A=A, V=V, n_used=n_used)
 
 
-def composite_ray_bwd(fw, colour, t, delta, gC, gD, gV, gC_m=None, gD_m=None, gV_m=None):
+def composite_ray_bwd(fw, colour, t, delta, gC, gD, gV, gC_m=None, gD_m=None, gV_m=None, gA=0.0):
     """Adjoint of ``composite_ray``: (dsigma, dcolour, magnitudes).
 
     Magnitudes evaluate the same formulas with |.|, with each suffix sum
@@ -87,11 +88,13 @@ def composite_ray_bwd(fw, colour, t, delta, gC, gD, gV, gC_m=None, gD_m=None, gV
     dD = Tn * tt - (D - Dp)
     dVraw = Tn * u - (V - Vp)
     dV = dVraw - 2.0 * D * (1.0 - A) * dD
-    dtau = dC @ gC + gD * dD + gV * dV
+    Ap = np.cumsum(w)
+    dA = Tn - (A - Ap)
+    dtau = dC @ gC + gD * dD + gV * dV + gA * dA
     mC = Tn[:, None] * np.abs(c) + np.abs(fw["C"])[None, :] + np.abs(Cp)
     mD = Tn * tt + abs(D) + np.abs(Dp)
     mV = Tn * u + abs(V) + np.abs(Vp) + 2.0 * abs(D) * (1.0 + A) * mD
-    dtau_m = mC @ gC_m + gD_m * mD + gV_m * mV
+    dtau_m = mC @ gC_m + gD_m * mD + gV_m * mV + abs(gA) * (Tn + A + Ap)
     dtau = np.where(act, dtau, 0.0)
     dtau_m = np.where(act, dtau_m, 0.0)
     dsig = dl * dtau

@@ -539,15 +539,15 @@ int nsl_composite_fwd(const float* sigma, const float* rgb, const float* t, cons
 }
 
 int nsl_composite_bwd(const float* sigma, const float* rgb, const float* t, const uint32_t* off, int R, float delta,
-                      const float* g_rgb, const float* g_depth, const float* g_var, float* g_sigma, float* g_rgb_s,
-                      hipStream_t st) {
+                      const float* g_rgb, const float* g_depth, const float* g_var, const float* g_opacity,
+                      float* g_sigma, float* g_rgb_s, hipStream_t st) {
   if (!sigma || !rgb || !t || !off || !g_sigma || !g_rgb_s) return fail(NSL_E_INVALID, "null argument");
   if (R < 0) return fail(NSL_E_INVALID, "negative ray count");
   if (!(delta > 0.0f)) return fail(NSL_E_INVALID, "bad delta");
   CompositeIO io{};
   io.sigma = sigma; io.rgb = rgb; io.t = t; io.off = off; io.counts = nullptr; io.R = R; io.delta = delta;
   io.stop_T = 0.0f;
-  HIP_TRY(composite_backward(io, g_rgb, g_depth, g_var, g_sigma, g_rgb_s, st), "composite backward");
+  HIP_TRY(composite_backward(io, g_rgb, g_depth, g_var, g_opacity, g_sigma, g_rgb_s, st), "composite backward");
   return NSL_OK;
 }
 

@@ -4,7 +4,8 @@
 // scan carried across chunks, so T_i = exp(-prefix) never multiplies
 // rounding errors along the ray.  Everything is FP32.
 //
-// Adjoint, for Q = sum_i w_i q_i:  dQ/dtau_k = T_{k+1} q_k - (Q - Q_{<=k}),
+// Adjoint, for Q = sum_i w_i q_i:  dQ/dtau_k = T_{k+1} q_k - (Q - Q_{<=k})
+// (q = c for colour, t for d*, 1 for the opacity A),
 // dV*/dtau_k = [T_{k+1} u_k - (V* - V_{<=k})] - 2 d* (1 - A) dd*/dtau_k with
 // u_i = (t_i - d*)^2; dL/dsigma_k = delta dL/dtau_k and dL/dc_k = g_C w_k.
 #include "kernels.h"
@@ -102,9 +103,9 @@ __device__ __forceinline__ RaySums ray_forward(const CompositeIO& io, uint32_t b
 
 // Adjoint of one ray for seeds (gC, gD, gV); writes dL/dsigma and dL/dc.
 __device__ __forceinline__ void ray_backward(const CompositeIO& io, uint32_t b, uint32_t n,
-                                             const RaySums& r, const float gC[3], float gD, float gV,
+                                             const RaySums& r, const float gC[3], float gD, float gV, float gA,
                                              float* __restrict__ g_sigma, float* __restrict__ g_rgb) {
-  float carry = 0.0f, p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, pD = 0.0f, pV = 0.0f;
+  float carry = 0.0f, p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, pD = 0.0f, pV = 0.0f, pA = 0.0f;
   const float kV = 2.0f * r.D * (1.0f - r.A);
   for (uint32_t i0 = 0; i0 < n; i0 += kWave) {
     Chunk c;
@@ -115,12 +116,14 @@ __device__ __forceinline__ void ray_backward(const CompositeIO& io, uint32_t b, 
     const float q2 = wave_incl_scan(c.w * c.c[2]) + p2;
     const float qD = wave_incl_scan(c.w * c.t) + pD;
     const float qV = wave_incl_scan(c.w * u) + pV;
+    const float qA = gA != 0.0f ? wave_incl_scan(c.w) + pA : 0.0f;
     const float dC0 = c.Tn * c.c[0] - (r.C[0] - q0);
     const float dC1 = c.Tn * c.c[1] - (r.C[1] - q1);
     const float dC2 = c.Tn * c.c[2] - (r.C[2] - q2);
     const float dD = c.Tn * c.t - (r.D - qD);
     const float dV = (c.Tn * u - (r.V - qV)) - kV * dD;
-    const float dtau = gC[0] * dC0 + gC[1] * dC1 + gC[2] * dC2 + gD * dD + gV * dV;
+    const float dA = c.Tn - (r.A - qA);
+    const float dtau = gC[0] * dC0 + gC[1] * dC1 + gC[2] * dC2 + gD * dD + gV * dV + gA * dA;
     const uint32_t i = i0 + lane_id();
     if (i < n) {
       const uint32_t s = b + i;
@@ -134,6 +137,7 @@ __device__ __forceinline__ void ray_backward(const CompositeIO& io, uint32_t b, 
     p2 = __shfl(q2, kWave - 1, kWave);
     pD = __shfl(qD, kWave - 1, kWave);
     pV = __shfl(qV, kWave - 1, kWave);
+    pA = __shfl(qA, kWave - 1, kWave);
   }
 }
 
@@ -152,6 +156,7 @@ __global__ __launch_bounds__(256) void composite_fwd_kernel(CompositeIO io) {
 __global__ __launch_bounds__(256) void composite_bwd_kernel(CompositeIO io, const float* __restrict__ g_rgb,
                                                             const float* __restrict__ g_depth,
                                                             const float* __restrict__ g_var,
+                                                            const float* __restrict__ g_opacity,
                                                             float* __restrict__ g_sigma,
                                                             float* __restrict__ g_rgb_s) {
   const int r = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
@@ -161,7 +166,8 @@ __global__ __launch_bounds__(256) void composite_bwd_kernel(CompositeIO io, cons
   const RaySums s = ray_forward(io, b, n);
   const float gC[3] = {g_rgb ? g_rgb[3 * r] : 0.0f, g_rgb ? g_rgb[3 * r + 1] : 0.0f,
                        g_rgb ? g_rgb[3 * r + 2] : 0.0f};
-  ray_backward(io, b, n, s, gC, g_depth ? g_depth[r] : 0.0f, g_var ? g_var[r] : 0.0f, g_sigma, g_rgb_s);
+  ray_backward(io, b, n, s, gC, g_depth ? g_depth[r] : 0.0f, g_var ? g_var[r] : 0.0f,
+               g_opacity ? g_opacity[r] : 0.0f, g_sigma, g_rgb_s);
 }
 
 // Train step: forward sums, loss terms and seeds, adjoint.
@@ -200,7 +206,7 @@ __global__ __launch_bounds__(256) void composite_loss_kernel(CompositeIO io, Los
       o[3] = s.D / sc; o[4] = s.V / (sc * sc); o[5] = s.A;
     }
   }
-  ray_backward(io, b, n, s, gC, gD, 0.0f, g_sigma, g_rgb_s);
+  ray_backward(io, b, n, s, gC, gD, 0.0f, 0.0f, g_sigma, g_rgb_s);
 }
 
 dim3 grid_for(int R) { return dim3((R + kWavesPerBlock - 1) / kWavesPerBlock); }
@@ -213,10 +219,11 @@ hipError_t composite_forward(const CompositeIO& io, hipStream_t st) {
 }
 
 hipError_t composite_backward(const CompositeIO& io, const float* g_rgb, const float* g_depth,
-                              const float* g_var, float* g_sigma, float* g_rgb_s, hipStream_t st) {
+                              const float* g_var, const float* g_opacity, float* g_sigma, float* g_rgb_s,
+                              hipStream_t st) {
   if (io.R > 0)
     hipLaunchKernelGGL(composite_bwd_kernel, grid_for(io.R), dim3(256), 0, st, io, g_rgb, g_depth,
-                       g_var, g_sigma, g_rgb_s);
+                       g_var, g_opacity, g_sigma, g_rgb_s);
   return hipGetLastError();
 }
 

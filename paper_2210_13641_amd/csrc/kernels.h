@@ -107,7 +107,8 @@ struct LossIO {
 
 hipError_t composite_forward(const CompositeIO& io, hipStream_t st);
 hipError_t composite_backward(const CompositeIO& io, const float* g_rgb, const float* g_depth,
-                              const float* g_var, float* g_sigma, float* g_rgb_s, hipStream_t st);
+                              const float* g_var, const float* g_opacity, float* g_sigma, float* g_rgb_s,
+                              hipStream_t st);
 hipError_t composite_loss_backward(const CompositeIO& io, const LossIO& lo, float* g_sigma,
                                    float* g_rgb_s, hipStream_t st);
 

@@ -82,7 +82,7 @@ _sig("nsl_field_workspace_bytes", _sz, [_vp])
 _sig("nsl_field_fwd", _i, [_vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _sz, _vp])
 _sig("nsl_field_bwd", _i, [_vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp])
 _sig("nsl_composite_fwd", _i, [_vp, _vp, _vp, _vp, _i, _f, _f, _vp, _vp])
-_sig("nsl_composite_bwd", _i, [_vp, _vp, _vp, _vp, _i, _f, _vp, _vp, _vp, _vp, _vp, _vp])
+_sig("nsl_composite_bwd", _i, [_vp, _vp, _vp, _vp, _i, _f, _vp, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("nsl_adam", _i, [_vp, _vp, _vp, _vp, C.c_int64, _f, _f, _f, _f, _i, _f, _vp])
 _sig("nsl_render_workspace_bytes", _sz, [_vp, _i, _i, C.POINTER(RenderConfig)])
 _sig("nsl_render", _i, [_vp, _vp, _vp, _vp, _i, _i, C.POINTER(RenderConfig), _vp, _vp, _vp, _vp, _vp, _sz, _vp])
@@ -289,13 +289,13 @@ def composite_fwd(sigma, rgb, t, ray_off, delta, stop_T=0.0):
     return out
 
 
-def composite_bwd(sigma, rgb, t, ray_off, delta, g_rgb=None, g_depth=None, g_var=None):
+def composite_bwd(sigma, rgb, t, ray_off, delta, g_rgb=None, g_depth=None, g_var=None, g_opacity=None):
     R = ray_off.numel() - 1
     g_sigma = torch.zeros_like(sigma)
     g_rgb_s = torch.zeros_like(rgb)
     _check(_lib.nsl_composite_bwd(_dev(sigma, torch.float32), _dev(rgb, torch.float32), _dev(t, torch.float32),
                                   _dev(ray_off, torch.int32), R, delta, _ptr(g_rgb), _ptr(g_depth), _ptr(g_var),
-                                  _ptr(g_sigma), _ptr(g_rgb_s), _stream()))
+                                  _ptr(g_opacity), _ptr(g_sigma), _ptr(g_rgb_s), _stream()))
     return g_sigma, g_rgb_s
 
 

@@ -92,14 +92,14 @@ def test_composite_adjoint_by_finite_differences(n):
     t = np.sort(rng.uniform(1, 3, n))
     dl = rng.uniform(0.05, 0.2, n)
     c = rng.uniform(size=(n, 3))
-    gC, gD, gV = rng.normal(size=3), rng.normal(), rng.normal()
+    gC, gD, gV, gA = rng.normal(size=3), rng.normal(), rng.normal(), rng.normal()
 
     def f(s, cc):
         fw = render.composite_ray(s, cc, t, dl)
-        return fw["C"] @ gC + gD * fw["D"] + gV * fw["V"]
+        return fw["C"] @ gC + gD * fw["D"] + gV * fw["V"] + gA * fw["A"]
 
     fw = render.composite_ray(sig, c, t, dl)
-    ds, dc, _, _ = render.composite_ray_bwd(fw, c, t, dl, gC, gD, gV)
+    ds, dc, _, _ = render.composite_ray_bwd(fw, c, t, dl, gC, gD, gV, gA=gA)
     h = 1e-6
     for k in range(n):
         e = np.zeros(n)
