@@ -293,10 +293,11 @@ int nsl_adam(float* params, float* grads, float* m, float* v, int64_t n, float l
              float beta2, float eps, int step, float grad_scale, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
- * Rendering (Sec. 3.3: the mapping thread renders for visualisation).
- * Uniform samples t_i = t_near + (i+1/2)*dt, i < n_samples, early
- * termination before the first sample with T_i < stop_T.  Outputs [H*W]
- * (rgb [H*W,3]); opacity may be NULL.
+ * Rendering (Sec. 3.3: the mapping thread also renders for interactive
+ * visualisation).  Uniform samples t_i = t_near + (i+1/2)*dt,
+ * i < n_samples <= 64; a ray stops before its first sample with
+ * T_i < stop_T (0 disables), which also ends its work.  One wave renders
+ * one ray; per pixel: rgb, depth_z, var_z (z units) and opacity.
  * ------------------------------------------------------------------------ */
 typedef struct nsl_render_config {
   float t_near, dt;
@@ -304,6 +305,45 @@ typedef struct nsl_render_config {
   float stop_T;
 } nsl_render_config;
 
+#define NSL_RENDER_TILE 64  /* pixels per render tile (one workgroup) */
+
+/* Parameter snapshot operands: the weights of `params` laid out for the
+ * MFMA kernels.  A snapshot (params copy + prepared operands) stays valid
+ * while training updates the live parameters. */
+size_t nsl_field_prepared_bytes(const nsl_field* f);
+int nsl_field_prepare(const nsl_field* f, const float* params, void* prepared, hipStream_t stream);
+
+/* One render request as the kernels read it (device memory). */
+typedef struct nsl_render_request {
+  const float* params;    /* snapshot parameter vector (device) */
+  const void* prepared;   /* its nsl_field_prepare output (device) */
+  float pose[12];         /* camera-to-world, row-major */
+  float intr[4];          /* fx, fy, cx, cy */
+  int32_t H, W;
+  float* rgb;             /* [H*W,3] */
+  float* depth_z;         /* [H*W] */
+  float* var_z;           /* [H*W] */
+  float* opacity;         /* [H*W] or NULL */
+} nsl_render_request;
+
+/* Pixels [first_pixel, first_pixel + n_pixels) of request `request`,
+ * n_pixels <= NSL_RENDER_TILE. */
+typedef struct nsl_render_tile {
+  int32_t request;
+  int32_t first_pixel;
+  int32_t n_pixels;
+} nsl_render_tile;
+
+/* Render n_tiles tiles of n_req requests in one launch (continuous batching:
+ * tiles of different requests and snapshots share the launch; each tile
+ * uses its own request's snapshot).  requests and tiles are device arrays;
+ * tiles naming a request >= n_req or pixels outside the image are skipped.
+ * Results per pixel do not depend on which other tiles share the launch. */
+int nsl_render_batch(const nsl_field* f, const nsl_render_request* requests, int n_req,
+                     const nsl_render_tile* tiles, int n_tiles, const nsl_render_config* cfg,
+                     hipStream_t stream);
+
+/* Single image with the live parameters (prepares them in the workspace). */
 size_t nsl_render_workspace_bytes(const nsl_field* f, int H, int W,
                                   const nsl_render_config* cfg);
 int nsl_render(const nsl_field* f, const float* params, const float* pose, const float* intr,

@@ -144,13 +144,14 @@ def render_image(spec, table, ws, pose, intr, H, W, sampler, stop_T=0.0, pixel_i
     sig = cache["sigma"].reshape(R, n)
     col = cache["colour"].reshape(R, n, 3)
     out = dict(rgb=np.zeros((R, 3)), depth_z=np.zeros(R), var_z=np.zeros(R),
-               opacity=np.zeros(R), n_used=np.zeros(R, np.int64),
+               var_z_mag=np.zeros(R), opacity=np.zeros(R), n_used=np.zeros(R, np.int64),
                alt=dict())
     dl = np.full(n, sampler.dt)
     for r in range(R):
         fw = render.composite_ray(sig[r], col[r], t, dl, stop_T)
         out["rgb"][r], out["depth_z"][r] = fw["C"], fw["D"] / s64[r]
         out["var_z"][r], out["opacity"][r], out["n_used"][r] = fw["V"] / s64[r] ** 2, fw["A"], fw["n_used"]
+        out["var_z_mag"][r] = float((fw["w"] * (np.abs(t) + abs(fw["D"])) ** 2).sum()) / s64[r] ** 2
         if stop_T > 0.0:
             k = fw["n_used"]
             near = [j for j in (k - 1, k) if 0 <= j < n and abs(fw["T"][j] / stop_T - 1.0) < 1e-5]

@@ -563,54 +563,73 @@ int nsl_adam(float* p, float* g, float* m, float* v, int64_t n, float lr, float 
 // Render
 // ---------------------------------------------------------------------------
 
-static size_t render_carve(const nsl_field* f, int H, int W, int ns, void* base, float4** rays, float** t,
-                           uint32_t** ray, uint32_t** off, float** sigma, float** rgb, float** out6, float** wprep) {
-  Carver cv(base);
-  const size_t n = (size_t)H * W, S = n * ns;
-  float4* a = cv.take<float4>(2 * n);
-  float* b = cv.take<float>(S);
-  uint32_t* c = cv.take<uint32_t>(S);
-  uint32_t* d = cv.take<uint32_t>(n + 1);
-  float* e = cv.take<float>(S);
-  float* g = cv.take<float>(3 * S);
-  float* h = cv.take<float>(6 * n);
-  float* w = cv.take<float>(field_prep_floats(f->shape));
-  if (rays) {
-    *rays = a; *t = b; *ray = c; *off = d; *sigma = e; *rgb = g; *out6 = h; *wprep = w;
-  }
-  return cv.used;
+static int check_render_cfg(const nsl_render_config* c) {
+  if (!c) return fail(NSL_E_INVALID, "null render config");
+  if (c->n_samples < 1 || c->n_samples > 64) return fail(NSL_E_INVALID, "n_samples must be in [1, 64]");
+  if (!(c->dt > 0.0f) || !(c->stop_T >= 0.0f) || !(c->t_near >= 0.0f)) return fail(NSL_E_INVALID, "bad render config");
+  return NSL_OK;
+}
+
+static RenderParams render_params(const nsl_render_config* c) {
+  RenderParams rp;
+  rp.t_near = c->t_near;
+  rp.dt = c->dt;
+  rp.stop_T = c->stop_T;
+  rp.n_samples = c->n_samples;
+  return rp;
+}
+
+size_t nsl_field_prepared_bytes(const nsl_field* f) {
+  return f ? align256(field_prep_floats(f->shape) * sizeof(float)) : 0;
+}
+
+int nsl_field_prepare(const nsl_field* f, const float* params, void* prepared, hipStream_t st) {
+  if (!f || !params || !prepared) return fail(NSL_E_INVALID, "null argument");
+  HIP_TRY(field_prep(f->shape, params, f->wo, static_cast<float*>(prepared), st), "prepare");
+  return NSL_OK;
+}
+
+int nsl_render_batch(const nsl_field* f, const nsl_render_request* reqs, int n_req, const nsl_render_tile* tiles,
+                     int n_tiles, const nsl_render_config* c, hipStream_t st) {
+  if (!f || !reqs || !tiles) return fail(NSL_E_INVALID, "null argument");
+  if (n_req < 0 || n_tiles < 0) return fail(NSL_E_INVALID, "negative count");
+  int rc = check_render_cfg(c);
+  if (rc) return rc;
+  HIP_TRY(render_tiles(f->shape, f->lv, f->box, reqs, n_req, tiles, n_tiles, render_params(c), st), "render");
+  return NSL_OK;
 }
 
 size_t nsl_render_workspace_bytes(const nsl_field* f, int H, int W, const nsl_render_config* c) {
-  if (!f || !c || H < 1 || W < 1 || c->n_samples < 1) return 0;
-  return render_carve(f, H, W, c->n_samples, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                      nullptr);
+  if (!f || !c || H < 1 || W < 1) return 0;
+  return nsl_field_prepared_bytes(f) + align256(sizeof(nsl_render_request));
 }
 
 int nsl_render(const nsl_field* f, const float* params, const float* pose, const float* intr, int H, int W,
                const nsl_render_config* c, float* rgb, float* depth, float* var, float* opacity, void* ws,
                size_t ws_bytes, hipStream_t st) {
   if (!f || !params || !pose || !intr || !c || !rgb || !depth || !var || !ws) return fail(NSL_E_INVALID, "null argument");
-  if (H < 1 || W < 1 || c->n_samples < 1 || c->n_samples > 4096 || !(c->dt > 0.0f) || !(c->stop_T >= 0.0f))
-    return fail(NSL_E_INVALID, "bad render config");
-  if ((int64_t)H * W * c->n_samples > 0x7FFFFFFFll) return fail(NSL_E_INVALID, "image too large");
+  if (H < 1 || W < 1 || (int64_t)H * W > (1 << 30)) return fail(NSL_E_INVALID, "bad image size");
+  int rc = check_render_cfg(c);
+  if (rc) return rc;
   if (ws_bytes < nsl_render_workspace_bytes(f, H, W, c)) return fail(NSL_E_WORKSPACE, "render workspace too small");
-  float4* rays;
-  float *t, *sigma, *srgb, *out6, *wprep;
-  uint32_t *ray, *off;
-  render_carve(f, H, W, c->n_samples, ws, &rays, &t, &ray, &off, &sigma, &srgb, &out6, &wprep);
-  const int n = H * W, S = n * c->n_samples;
-  HIP_TRY(render_setup(pose, intr, H, W, c->t_near, c->dt, c->n_samples, f->box, rays, t, ray, off, st), "render setup");
-  HIP_TRY(field_prep(f->shape, params, f->wo, wprep, st), "prep weights");
-  FieldArgs fa{params, wprep, f->lv};
-  SampleSrc src{};
-  src.t = t; src.ray = ray; src.rays = rays; src.box = f->box; src.n = S; src.n_dev = nullptr;
-  HIP_TRY(field_forward(f->shape, fa, src, S, sigma, srgb, st), "render field");
-  CompositeIO io{};
-  io.sigma = sigma; io.rgb = srgb; io.t = t; io.off = off; io.counts = nullptr; io.R = n; io.delta = c->dt;
-  io.stop_T = c->stop_T; io.out6 = out6;
-  HIP_TRY(composite_forward(io, st), "render composite");
-  HIP_TRY(render_finish(out6, rays, n, rgb, depth, var, opacity, st), "render finish");
+  char* base = static_cast<char*>(ws);
+  void* prepared = base;
+  nsl_render_request* dev_req = reinterpret_cast<nsl_render_request*>(base + nsl_field_prepared_bytes(f));
+  if ((rc = nsl_field_prepare(f, params, prepared, st))) return rc;
+  nsl_render_request r;
+  r.params = params;
+  r.prepared = prepared;
+  std::memset(r.pose, 0, sizeof r.pose);
+  std::memset(r.intr, 0, sizeof r.intr);
+  r.H = H;
+  r.W = W;
+  r.rgb = rgb;
+  r.depth_z = depth;
+  r.var_z = var;
+  r.opacity = opacity;
+  HIP_TRY(store_request(&r, pose, intr, dev_req, st), "store request");
+  const int n_tiles = (H * W + NSL_RENDER_TILE - 1) / NSL_RENDER_TILE;
+  HIP_TRY(render_tiles(f->shape, f->lv, f->box, dev_req, 1, nullptr, n_tiles, render_params(c), st), "render");
   return NSL_OK;
 }
 

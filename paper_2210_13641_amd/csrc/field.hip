@@ -521,6 +521,116 @@ __global__ void dw_reduce_kernel(const float* __restrict__ partial, int nblocks,
   grads[wo.off[j] + (i - N::woff(j))] += acc;
 }
 
+
+// ---------------------------------------------------------------------------
+// Fused rendering: one wave per ray, 16 consecutive samples of the ray per
+// MFMA tile, compositing by a row scan of the 16 sample lanes, and an early
+// exit once the transmittance left for the ray is below stop_T.
+// ---------------------------------------------------------------------------
+
+constexpr int kRenderMaxTiles = 4;  // n_samples <= 64
+
+// Inclusive prefix sum within each 16-lane row.
+__device__ __forceinline__ float row_incl_scan(float v) {
+  v += __int_as_float(row_from_below<1>(__float_as_int(v)));
+  v += __int_as_float(row_from_below<2>(__float_as_int(v)));
+  v += __int_as_float(row_from_below<4>(__float_as_int(v)));
+  v += __int_as_float(row_from_below<8>(__float_as_int(v)));
+  return v;
+}
+
+__device__ __forceinline__ float row_sum(float v) {
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 16);
+  return v;
+}
+
+template <class N>
+__global__ __launch_bounds__(256) void render_kernel(LevelInfo lv, Aabb box, const nsl_render_request* __restrict__ reqs,
+                                                     int n_req, const nsl_render_tile* __restrict__ tiles,
+                                                     RenderParams rp) {
+  __shared__ __attribute__((aligned(16))) float Af[N::FWD_FLOATS];
+  nsl_render_tile tile;
+  if (tiles) {
+    tile = tiles[blockIdx.x];
+  } else {
+    tile.request = 0;
+    tile.first_pixel = blockIdx.x * NSL_RENDER_TILE;
+    tile.n_pixels = NSL_RENDER_TILE;
+  }
+  if (tile.request < 0 || tile.request >= n_req) return;
+  const nsl_render_request& rq = reqs[tile.request];
+  const int npix = rq.H * rq.W;
+  const int first = max(tile.first_pixel, 0);
+  const int last = min(tile.first_pixel + min(tile.n_pixels, NSL_RENDER_TILE), npix);
+  if (first >= last) return;
+  load_operands<N>(Af, reinterpret_cast<const float*>(rq.prepared), N::FWD_FLOATS);
+  __syncthreads();
+  const int wave = threadIdx.x / kWave, lane = lane_id(), g = lane >> 4, jc = lane & 15;
+  LaneLevels<N> ll;
+  lane_levels<N>(lv, g, ll);
+  const int ntiles = (rp.n_samples + 15) / 16;
+  for (int px = first + wave; px < last; px += 4) {
+    const int v = px / rq.W, u = px - v * rq.W;
+    float o[3], d[3], s;
+    camera_ray(rq.pose, rq.intr, u, v, o, d, s);
+    Acts<N> act;
+    sh_lane<N>(d, g, act.sh);
+    float carry = 0.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f, A = 0.0f;
+    float wt[kRenderMaxTiles], tt[kRenderMaxTiles];
+#pragma unroll
+    for (int ti = 0; ti < kRenderMaxTiles; ++ti) {
+      wt[ti] = 0.0f;
+      tt[ti] = 0.0f;
+      if (ti >= ntiles) continue;
+      const int j = ti * 16 + jc;
+      const bool valid = j < rp.n_samples;
+      float t;
+      {
+#pragma clang fp contract(off)
+        t = rp.t_near + ((float)j + 0.5f) * rp.dt;
+      }
+      float xn[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) xn[i] = normalise_axis(pos_axis(o[i], d[i], t), box.lo[i], box.inv[i]);
+      encode<N>(rq.params, lv.table_mask, ll, xn, act.e);
+      mlp_fwd<N>(Af, lane, act);
+      // lanes of row 0 hold sample jc's density and colour
+      const float tau = valid ? expf(act.o[0]) * rp.dt : 0.0f;
+      const float incl = row_incl_scan(tau);
+      const float T = expf(-(carry + (incl - tau)));
+      const bool on = valid && !(rp.stop_T > 0.0f && T < rp.stop_T);
+      const float w = on ? T * -expm1f(-tau) : 0.0f;
+      wt[ti] = w;
+      tt[ti] = t;
+      C0 += w * sigmoidf(act.z[0]);
+      C1 += w * sigmoidf(act.z[1]);
+      C2 += w * sigmoidf(act.z[2]);
+      D += w * t;
+      A += w;
+      carry += __shfl(incl, 15, kWave);
+      if (rp.stop_T > 0.0f && expf(-carry) < rp.stop_T) break;
+    }
+    C0 = row_sum(C0);
+    C1 = row_sum(C1);
+    C2 = row_sum(C2);
+    D = row_sum(D);
+    A = row_sum(A);
+    float V = 0.0f;
+#pragma unroll
+    for (int ti = 0; ti < kRenderMaxTiles; ++ti) V += wt[ti] * (tt[ti] - D) * (tt[ti] - D);
+    V = row_sum(V);
+    if (lane == 0) {
+      rq.rgb[3 * (size_t)px] = C0;
+      rq.rgb[3 * (size_t)px + 1] = C1;
+      rq.rgb[3 * (size_t)px + 2] = C2;
+      rq.depth_z[px] = D / s;
+      rq.var_z[px] = V / (s * s);
+      if (rq.opacity) rq.opacity[px] = A;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
@@ -553,6 +663,23 @@ static hipError_t launch_bwd(const FieldArgs& a, const SampleSrc& src, int nbloc
                      partial, nblocks, wo, grads);
   return hipGetLastError();
 }
+
+template <class N>
+static hipError_t launch_render(const LevelInfo& lv, const Aabb& box, const nsl_render_request* reqs, int n_req,
+                                const nsl_render_tile* tiles, int n_tiles, const RenderParams& rp, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(render_kernel<N>, dim3(n_tiles), dim3(256), 0, st, lv, box, reqs, n_req, tiles, rp);
+  return hipGetLastError();
+}
+
+hipError_t render_tiles(int shape, const LevelInfo& lv, const Aabb& box, const nsl_render_request* reqs,
+                        int n_req, const nsl_render_tile* tiles, int n_tiles, const RenderParams& rp,
+                        hipStream_t st) {
+  return shape == kShapeTiny ? launch_render<NetTiny>(lv, box, reqs, n_req, tiles, n_tiles, rp, st)
+                             : launch_render<NetFull>(lv, box, reqs, n_req, tiles, n_tiles, rp, st);
+}
+
+size_t field_fwd_floats(int shape) { return shape == kShapeTiny ? NetTiny::FWD_FLOATS : NetFull::FWD_FLOATS; }
 
 size_t field_prep_floats(int shape) {
   return shape == kShapeTiny ? NetTiny::FWD_FLOATS + NetTiny::BWD_FLOATS

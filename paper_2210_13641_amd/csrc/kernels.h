@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/nsl.h"
 #include "common.h"
 
 namespace nsl {
@@ -43,6 +44,17 @@ hipError_t field_forward(int shape, const FieldArgs& a, const SampleSrc& src, in
 hipError_t field_backward(int shape, const FieldArgs& a, const SampleSrc& src, int nblocks,
                           const float* dsigma, const float* drgb, float* grad_table,
                           float* partial, const WOffsets& wo, float* grads, hipStream_t st);
+
+struct RenderParams {
+  float t_near, dt, stop_T;
+  int n_samples;
+};
+// Fused ray-major rendering of tiles (tiles == nullptr: tile t covers pixels
+// [64t, 64t+64) of request 0).
+hipError_t render_tiles(int shape, const LevelInfo& lv, const Aabb& box, const nsl_render_request* reqs,
+                        int n_req, const nsl_render_tile* tiles, int n_tiles, const RenderParams& rp,
+                        hipStream_t st);
+size_t field_fwd_floats(int shape);
 
 // march.hip
 struct KeyframeStore {
@@ -116,10 +128,9 @@ hipError_t composite_loss_backward(const CompositeIO& io, const LossIO& lo, floa
 hipError_t adam_update(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1,
                        float b2, float eps, int step, float grad_scale, hipStream_t st);
 hipError_t fill_zero(float* p, int64_t n, hipStream_t st);
-hipError_t render_setup(const float* pose, const float* intr, int H, int W, float t_near, float dt,
-                        int n_samples, Aabb box, float4* rays, float* t, uint32_t* ray,
-                        uint32_t* off, hipStream_t st);
-hipError_t render_finish(const float* out6, const float4* rays, int n, float* rgb, float* depth,
-                         float* var, float* opacity, hipStream_t st);
+// Writes one request record to device memory (taken by value at launch),
+// with its pose [12] and intrinsics [4] read from device memory.
+hipError_t store_request(const nsl_render_request* r, const float* pose, const float* intr,
+                         nsl_render_request* dst, hipStream_t st);
 
 }  // namespace nsl

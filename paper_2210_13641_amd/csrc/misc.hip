@@ -1,4 +1,4 @@
-// Adam, buffer clearing and render ray setup on gfx950.
+// Adam, buffer clearing and small helpers on gfx950.
 #include "kernels.h"
 
 namespace nsl {
@@ -52,43 +52,11 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(float* __restrict__ p, i
   }
 }
 
-// One thread per pixel: ray record, uniform samples, offsets.
-__global__ __launch_bounds__(256) void render_setup_kernel(const float* __restrict__ pose,
-                                                           const float* __restrict__ intr, int H, int W,
-                                                           float t_near, float dt, int n_samples,
-                                                           float4* __restrict__ rays, float* __restrict__ t,
-                                                           uint32_t* __restrict__ ray, uint32_t* __restrict__ off) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  const int n = H * W;
-  if (r > n) return;
-  off[r] = (uint32_t)r * (uint32_t)n_samples;
-  if (r == n) return;
-  const int v = r / W, u = r - v * W;
-  float o[3], d[3], s;
-  camera_ray(pose, intr, u, v, o, d, s);
-  rays[2 * r] = make_float4(o[0], o[1], o[2], s);
-  rays[2 * r + 1] = make_float4(d[0], d[1], d[2], 0.0f);
-  for (int i = 0; i < n_samples; ++i) {
-#pragma clang fp contract(off)
-    t[(size_t)r * n_samples + i] = t_near + ((float)i + 0.5f) * dt;
-    ray[(size_t)r * n_samples + i] = (uint32_t)r;
-  }
-}
-
-__global__ __launch_bounds__(256) void render_finish_kernel(const float* __restrict__ out6,
-                                                            const float4* __restrict__ rays, int n,
-                                                            float* __restrict__ rgb, float* __restrict__ depth,
-                                                            float* __restrict__ var, float* __restrict__ opacity) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const float* o = out6 + 6 * (size_t)r;
-  const float s = rays[2 * r].w;
-  rgb[3 * r] = o[0];
-  rgb[3 * r + 1] = o[1];
-  rgb[3 * r + 2] = o[2];
-  depth[r] = o[3] / s;
-  var[r] = o[4] / (s * s);
-  if (opacity) opacity[r] = o[5];
+__global__ void store_request_kernel(nsl_render_request r, const float* __restrict__ pose,
+                                     const float* __restrict__ intr, nsl_render_request* dst) {
+  for (int i = 0; i < 12; ++i) r.pose[i] = pose[i];
+  for (int i = 0; i < 4; ++i) r.intr[i] = intr[i];
+  *dst = r;
 }
 
 }  // namespace
@@ -111,21 +79,9 @@ hipError_t fill_zero(float* p, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t render_setup(const float* pose, const float* intr, int H, int W, float t_near, float dt,
-                        int n_samples, Aabb box, float4* rays, float* t, uint32_t* ray, uint32_t* off,
-                        hipStream_t st) {
-  (void)box;
-  const int n = H * W + 1;
-  hipLaunchKernelGGL(render_setup_kernel, dim3((n + 255) / 256), dim3(256), 0, st, pose, intr, H, W,
-                     t_near, dt, n_samples, rays, t, ray, off);
-  return hipGetLastError();
-}
-
-hipError_t render_finish(const float* out6, const float4* rays, int n, float* rgb, float* depth,
-                         float* var, float* opacity, hipStream_t st) {
-  if (n > 0)
-    hipLaunchKernelGGL(render_finish_kernel, dim3((n + 255) / 256), dim3(256), 0, st, out6, rays, n, rgb,
-                       depth, var, opacity);
+hipError_t store_request(const nsl_render_request* r, const float* pose, const float* intr,
+                         nsl_render_request* dst, hipStream_t st) {
+  hipLaunchKernelGGL(store_request_kernel, dim3(1), dim3(1), 0, st, *r, pose, intr, dst);
   return hipGetLastError();
 }
 

@@ -52,6 +52,20 @@ class RenderConfig(C.Structure):
     _fields_ = [("t_near", C.c_float), ("dt", C.c_float), ("n_samples", C.c_int32), ("stop_T", C.c_float)]
 
 
+class RenderRequest(C.Structure):
+    """Mirror of nsl_render_request (the kernels read an array of these)."""
+    _fields_ = [("params", C.c_void_p), ("prepared", C.c_void_p), ("pose", C.c_float * 12),
+                ("intr", C.c_float * 4), ("H", C.c_int32), ("W", C.c_int32), ("rgb", C.c_void_p),
+                ("depth_z", C.c_void_p), ("var_z", C.c_void_p), ("opacity", C.c_void_p)]
+
+
+class RenderTile(C.Structure):
+    _fields_ = [("request", C.c_int32), ("first_pixel", C.c_int32), ("n_pixels", C.c_int32)]
+
+
+RENDER_TILE = 64
+
+
 _vp, _i, _sz, _f = C.c_void_p, C.c_int, C.c_size_t, C.c_float
 
 
@@ -85,6 +99,9 @@ _sig("nsl_composite_fwd", _i, [_vp, _vp, _vp, _vp, _i, _f, _f, _vp, _vp])
 _sig("nsl_composite_bwd", _i, [_vp, _vp, _vp, _vp, _i, _f, _vp, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("nsl_adam", _i, [_vp, _vp, _vp, _vp, C.c_int64, _f, _f, _f, _f, _i, _f, _vp])
 _sig("nsl_render_workspace_bytes", _sz, [_vp, _i, _i, C.POINTER(RenderConfig)])
+_sig("nsl_field_prepared_bytes", _sz, [_vp])
+_sig("nsl_field_prepare", _i, [_vp, _vp, _vp, _vp])
+_sig("nsl_render_batch", _i, [_vp, _vp, _i, _vp, _i, C.POINTER(RenderConfig), _vp])
 _sig("nsl_render", _i, [_vp, _vp, _vp, _vp, _i, _i, C.POINTER(RenderConfig), _vp, _vp, _vp, _vp, _vp, _sz, _vp])
 
 _sig("nsl_profile_enable", _i, [_i])
@@ -325,3 +342,41 @@ def render(field: Field, params, pose, intr, H, W, cfg: RenderConfig, ws, rgb=No
                            _dev(intr, torch.float32), H, W, C.byref(cfg), _ptr(rgb), _ptr(depth), _ptr(var),
                            _ptr(opacity), _ptr(ws), ws.numel(), _stream()))
     return rgb, depth, var, opacity
+
+
+def prepared_bytes(field: Field) -> int:
+    return _lib.nsl_field_prepared_bytes(field.handle)
+
+
+def prepare(field: Field, params, out=None):
+    """MFMA operands of a parameter snapshot (device uint8 buffer)."""
+    out = torch.empty(prepared_bytes(field), dtype=torch.uint8, device=params.device) if out is None else out
+    _check(_lib.nsl_field_prepare(field.handle, _dev(params, torch.float32), _ptr(out), _stream()))
+    return out
+
+
+def render_request(params, prepared, pose, intr, H, W, rgb, depth, var, opacity=None) -> RenderRequest:
+    """Host record of one request; pose/intr are host sequences."""
+    r = RenderRequest()
+    r.params, r.prepared = params.data_ptr(), prepared.data_ptr()
+    for i, x in enumerate(list(pose)):
+        r.pose[i] = float(x)
+    for i, x in enumerate(list(intr)):
+        r.intr[i] = float(x)
+    r.H, r.W = H, W
+    r.rgb, r.depth_z, r.var_z = rgb.data_ptr(), depth.data_ptr(), var.data_ptr()
+    r.opacity = opacity.data_ptr() if opacity is not None else None
+    return r
+
+
+def records_to_device(records, ctype, device):
+    """Pack ctypes records into a device byte tensor."""
+    n = len(records)
+    buf = (ctype * max(n, 1))(*records)
+    raw = torch.frombuffer(bytearray(bytes(buf)), dtype=torch.uint8)
+    return raw.to(device, non_blocking=False)
+
+
+def render_batch(field: Field, requests_dev, n_req, tiles_dev, n_tiles, cfg: RenderConfig):
+    _check(_lib.nsl_render_batch(field.handle, _ptr(requests_dev), n_req, _ptr(tiles_dev), n_tiles, C.byref(cfg),
+                                 _stream()))
