@@ -293,6 +293,28 @@ int nsl_adam(float* params, float* grads, float* m, float* v, int64_t n, float l
              float beta2, float eps, int step, float grad_scale, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Depth covariances from the tracking Hessian (Sec. 3.1, Eq. 1 and 2): the
+ * producer of the Sigma_D that weights the depth loss (Eq. 4).
+ *
+ * The dense-BA system of a keyframe window is [[C, E], [E^T, P]] with P
+ * diagonal (one inverse depth per pixel).  In FP64:
+ *   H_T = C - E P^{-1} E^T = L L^T,  Sigma_T = (L L^T)^{-1},
+ *   Sigma_d,j = 1/P_j + e_j^T Sigma_T e_j / P_j^2   (diagonal of Eq. 2),
+ *   depth_var_j = Sigma_d,j / d_j^4                 (variance of D = 1/d,
+ *                                                    first order).
+ * Arguments (device): C [c,c] row-major (c = 6 per keyframe, c <= 60);
+ * Et [p,c] = E^T row-major (pixel j's coupling e_j contiguous); P [p] > 0;
+ * inv_depth [p]; outputs sigma_T [c,c], sigma_d [p] (may be NULL),
+ * depth_var [p] float (may be NULL, ready for nsl_keyframes_upsert);
+ * status [1] int: 0, or 1 if H_T is not positive definite (sigma_T is then
+ * NaN).  Workspace: nsl_covariance_workspace_bytes.
+ * ------------------------------------------------------------------------ */
+size_t nsl_covariance_workspace_bytes(int c, int p);
+int nsl_depth_covariance(int c, int p, const double* C, const double* Et, const double* P,
+                         const double* inv_depth, double* sigma_T, double* sigma_d, float* depth_var,
+                         int* status, void* workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Rendering (Sec. 3.3: the mapping thread also renders for interactive
  * visualisation).  Uniform samples t_i = t_near + (i+1/2)*dt,
  * i < n_samples <= 64; a ray stops before its first sample with

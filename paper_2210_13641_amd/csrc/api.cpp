@@ -633,4 +633,26 @@ int nsl_render(const nsl_field* f, const float* params, const float* pose, const
   return NSL_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Covariances
+// ---------------------------------------------------------------------------
+
+size_t nsl_covariance_workspace_bytes(int c, int p) {
+  if (c < 1 || p < 0) return 0;
+  return align256(cov_partial_blocks(p) * (size_t)c * c * sizeof(double));
+}
+
+int nsl_depth_covariance(int c, int p, const double* C, const double* Et, const double* P, const double* inv_depth,
+                         double* sigma_T, double* sigma_d, float* depth_var, int* status, void* ws,
+                         size_t ws_bytes, hipStream_t st) {
+  if (!C || !Et || !P || !sigma_T || !status || !ws) return fail(NSL_E_INVALID, "null argument");
+  if (c < 1 || c > 60) return fail(NSL_E_INVALID, "c must be in [1, 60]");
+  if (p < 0) return fail(NSL_E_INVALID, "negative pixel count");
+  if (depth_var && !inv_depth) return fail(NSL_E_INVALID, "depth_var needs inv_depth");
+  if (ws_bytes < nsl_covariance_workspace_bytes(c, p)) return fail(NSL_E_WORKSPACE, "covariance workspace too small");
+  HIP_TRY(depth_covariance(c, p, C, Et, P, inv_depth, sigma_T, sigma_d, depth_var, status, static_cast<double*>(ws), st),
+          "covariance");
+  return NSL_OK;
+}
+
 }  // extern "C"

@@ -124,6 +124,12 @@ hipError_t composite_backward(const CompositeIO& io, const float* g_rgb, const f
 hipError_t composite_loss_backward(const CompositeIO& io, const LossIO& lo, float* g_sigma,
                                    float* g_rgb_s, hipStream_t st);
 
+// cov.hip
+size_t cov_partial_blocks(int p);
+hipError_t depth_covariance(int c, int p, const double* C, const double* Et, const double* P,
+                            const double* inv_depth, double* sigma_T, double* sigma_d, float* depth_var,
+                            int* status, double* partial, hipStream_t st);
+
 // misc.hip
 hipError_t adam_update(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1,
                        float b2, float eps, int step, float grad_scale, hipStream_t st);

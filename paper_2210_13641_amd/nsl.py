@@ -104,6 +104,8 @@ _sig("nsl_field_prepare", _i, [_vp, _vp, _vp, _vp])
 _sig("nsl_render_batch", _i, [_vp, _vp, _i, _vp, _i, C.POINTER(RenderConfig), _vp])
 _sig("nsl_render", _i, [_vp, _vp, _vp, _vp, _i, _i, C.POINTER(RenderConfig), _vp, _vp, _vp, _vp, _vp, _sz, _vp])
 
+_sig("nsl_covariance_workspace_bytes", _sz, [_i, _i])
+_sig("nsl_depth_covariance", _i, [_i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
 _sig("nsl_profile_enable", _i, [_i])
 _sig("nsl_profile_read", _i, [C.POINTER(C.c_double), C.POINTER(_i)])
 
@@ -380,3 +382,19 @@ def records_to_device(records, ctype, device):
 def render_batch(field: Field, requests_dev, n_req, tiles_dev, n_tiles, cfg: RenderConfig):
     _check(_lib.nsl_render_batch(field.handle, _ptr(requests_dev), n_req, _ptr(tiles_dev), n_tiles, C.byref(cfg),
                                  _stream()))
+
+
+def depth_covariance(C, Et, P, inv_depth=None, want_sigma_d=True):
+    """Sigma_T [c,c], Sigma_d [p] (FP64) and depth variances [p] (float32)
+    from a window's Hessian blocks (device float64 tensors)."""
+    c, p = C.shape[0], Et.shape[0]
+    dev = C.device
+    ws = torch.empty(_lib.nsl_covariance_workspace_bytes(c, p), dtype=torch.uint8, device=dev)
+    sT = torch.empty(c, c, dtype=torch.float64, device=dev)
+    sd = torch.empty(p, dtype=torch.float64, device=dev) if want_sigma_d else None
+    dv = torch.empty(p, dtype=torch.float32, device=dev) if inv_depth is not None else None
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    _check(_lib.nsl_depth_covariance(c, p, _dev(C, torch.float64), _dev(Et, torch.float64), _dev(P, torch.float64),
+                                     _ptr(inv_depth), _ptr(sT), _ptr(sd), _ptr(dv), _ptr(st), _ptr(ws), ws.numel(),
+                                     _stream()))
+    return sT, sd, dv, st

@@ -535,3 +535,28 @@ def test_mlp_forward_with_constructed_weights():
     assert np.allclose(c["colour"][:, 0], sig(2 * e[:, 7]), rtol=1e-15)
     assert np.allclose(c["colour"][:, 1], 0.5)
     assert np.allclose(c["colour"][:, 2], sig(-np.maximum(sh[:, 0], 0)), rtol=1e-15)
+
+
+# ----------------------------------------------------------------------------
+# Marginal covariances (Eq. 1, 2)
+# ----------------------------------------------------------------------------
+
+def test_marginals_equal_blocks_of_the_dense_inverse():
+    from oracle import covariance
+    C, E, P, d = W.ba_window(seed=1, n_kf=3, h=4, w=5)
+    c = C.shape[0]
+    H = np.block([[C, E], [E.T, np.diag(P)]])
+    Hinv = np.linalg.inv(H)
+    ST, sd = covariance.marginals(C, E, P)
+    assert np.allclose(ST, Hinv[:c, :c], rtol=1e-9, atol=1e-14)
+    assert np.allclose(sd, np.diag(Hinv)[c:], rtol=1e-9, atol=1e-14)
+    assert np.all(sd > 0) and np.all(np.linalg.eigvalsh(ST) > 0)
+
+
+def test_depth_variance_is_the_delta_method():
+    from oracle import covariance
+    rng = np.random.default_rng(0)
+    d0, s = 0.8, 0.004
+    d = rng.normal(d0, s, 400000)
+    mc = np.var(1.0 / d)
+    assert covariance.depth_variance(s * s, d0) == pytest.approx(mc, rel=2e-2)

@@ -425,3 +425,57 @@ def serve_requests(n, seed=7, rate=200.0, radius=1.5):
         intr = np.array([0.9375 * W, 0.9375 * W, W / 2.0, H / 2.0], np.float32)
         out.append(dict(arrival=t, H=H, W=W, pose=pose.astype(np.float32), intr=intr))
     return out
+
+
+# ----------------------------------------------------------------------------
+# Tracking Hessian of a keyframe window (input of the covariance recovery)
+# ----------------------------------------------------------------------------
+
+def ba_window(seed=0, n_kf=8, h=30, w=40, obs_per_pixel=2, gauge=1e4, pose_dim=6):
+    """A synthetic dense-BA linear system of a keyframe window with the
+    arrow structure of Sec. 3.1 / Eq. 1: per-pixel inverse depths (diagonal
+    block P), camera poses (block C), and their coupling E.
+
+    Every pixel of keyframe i is observed in ``obs_per_pixel`` other
+    keyframes k; an observation contributes J^T W J with a 2-row Jacobian
+    [J_i (2 x 6) | J_k (2 x 6) | J_d (2 x 1)] and weights W = diag(w1, w2),
+    w ~ U(0.1, 1) (the flow confidences).  A prior of ``gauge`` on the first
+    pose fixes the gauge.  Draw order per keyframe i: inverse depths
+    U(0.2, 2) [h*w]; then per observation slot: target offsets, J_i, J_k,
+    J_d, w.  Returns (C [c,c], E [c,p], P [p], inv_depth [p]) in FP64 with
+    c = 6 n_kf, p = n_kf h w; pixel j of keyframe i is column i*h*w + j.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = pose_dim * n_kf
+    npx = h * w
+    p = n_kf * npx
+    C = np.zeros((c, c))
+    E = np.zeros((c, p))
+    P = np.zeros(p)
+    inv_depth = np.empty(p)
+    for i in range(n_kf):
+        inv_depth[i * npx:(i + 1) * npx] = rng.uniform(0.2, 2.0, npx)
+        for _ in range(obs_per_pixel):
+            off = rng.integers(1, n_kf, size=npx)
+            k = (i + off) % n_kf
+            Ji = rng.normal(size=(npx, 2, pose_dim))
+            Jk = rng.normal(size=(npx, 2, pose_dim))
+            Jd = rng.normal(size=(npx, 2)) * 3.0
+            wt = rng.uniform(0.1, 1.0, size=(npx, 2))
+            cols = i * npx + np.arange(npx)
+            P[cols] += np.sum(wt * Jd * Jd, axis=1)
+            si = slice(pose_dim * i, pose_dim * (i + 1))
+            C[si, si] += np.einsum("nra,nr,nrb->ab", Ji, wt, Ji)
+            E[si, cols] += np.einsum("nra,nr,nr->an", Ji, wt, Jd)
+            for kk in range(n_kf):
+                sel = k == kk
+                if not sel.any():
+                    continue
+                sk = slice(pose_dim * kk, pose_dim * (kk + 1))
+                C[sk, sk] += np.einsum("nra,nr,nrb->ab", Jk[sel], wt[sel], Jk[sel])
+                cross = np.einsum("nra,nr,nrb->ab", Ji[sel], wt[sel], Jk[sel])
+                C[si, sk] += cross
+                C[sk, si] += cross.T
+                E[sk, cols[sel]] += np.einsum("nra,nr,nr->an", Jk[sel], wt[sel], Jd[sel])
+    C[:pose_dim, :pose_dim] += gauge * np.eye(pose_dim)
+    return C, E, P, inv_depth
