@@ -55,6 +55,9 @@ extern "C" {
 #define NSL_F16 1
 #define NSL_BF16 2
 
+#define NSL_PRECISION_FP32 0   /* FP32 tables, FP32 MLP on FP32 MFMA */
+#define NSL_PRECISION_MIXED 1  /* FP16 tables, BF16 MLP on MFMA, FP32 accumulation */
+
 #define NSL_SAMPLER_UNIFORM 0
 #define NSL_SAMPLER_OCCUPANCY 1
 
@@ -187,10 +190,22 @@ int nsl_occupancy_set(nsl_mapper* m, const uint32_t* bits, int src_on_host,
  * d* = sum w_i t_i; also V* = sum w_i (t_i - d*)^2 and A = sum w_i; no
  * background colour, no normalisation by A.
  *
- * Gradients are ACCUMULATED (+=) into grads, scaled by loss_scale, unless
+ * Gradients are ACCUMULATED (+=) into grads, scaled by the loss scale, unless
  * zero_grads = 1 (grads are cleared first).  With do_adam = 1 the step then
  * applies bias-corrected Adam at step adam_step (>= 1) to every parameter
- * with gradient grads/loss_scale and clears grads afterwards.
+ * with gradient grads / loss scale and clears grads afterwards.
+ *
+ * precision: NSL_PRECISION_FP32, or NSL_PRECISION_MIXED: the step converts
+ * the FP32 master parameters to an FP16 table copy and BF16 MLP operands,
+ * evaluates and differentiates the field with BF16 MFMA and FP32
+ * accumulation, and accumulates every gradient in FP32; transmittance, the
+ * depth-variance reduction and the Sigma_D-weighted loss stay FP32.
+ * scale_state (device float[4], may be NULL): dynamic loss scaling.  The
+ * scale is read from scale_state[0] (loss_scale is then ignored); after the
+ * backward pass a non-finite gradient sets scale_state[3] = 1, Adam skips the
+ * update (gradients are cleared), the scale is halved and scale_state[2]
+ * counts the skip; otherwise scale_state[1] counts clean steps and the scale
+ * doubles after 2000 of them.
  *
  * loss_out (device, 3 floats): L, L_rgb, L_D.  stats_out (device, may be
  * NULL).  ray_out (device, may be NULL): [n_candidates, 6] per candidate:
@@ -209,6 +224,8 @@ typedef struct nsl_step_config {
   float lr, beta1, beta2, eps;
   int32_t adam_step;
   float loss_scale;
+  int32_t precision;     /* NSL_PRECISION_FP32 or NSL_PRECISION_MIXED */
+  float* scale_state;    /* device float[4] or NULL (static loss_scale) */
 } nsl_step_config;
 
 typedef struct nsl_step_stats {
@@ -270,6 +287,20 @@ int nsl_field_fwd(const nsl_field* f, const float* params, const float* xn, cons
 int nsl_field_bwd(const nsl_field* f, const float* params, const float* xn, const float* dirs,
                   int S, const float* dsigma, const float* drgb, float* grads, void* workspace,
                   size_t workspace_bytes, hipStream_t stream);
+
+/* Mixed precision at the kernel level: nsl_field_prepare_mixed converts the
+ * FP32 parameters into a shadow buffer (BF16 MLP operands and an FP16 copy
+ * of the tables, nsl_mixed_shadow_bytes); nsl_field_fwd_mixed and
+ * nsl_field_bwd_mixed evaluate and differentiate the field from it (FP32
+ * accumulation; gradients with respect to the FP32 parameters, accumulated
+ * into grads).  Workspace of the backward: nsl_field_workspace_bytes. */
+size_t nsl_mixed_shadow_bytes(const nsl_field* f);
+int nsl_field_prepare_mixed(const nsl_field* f, const float* params, void* shadow, hipStream_t stream);
+int nsl_field_fwd_mixed(const nsl_field* f, const void* shadow, const float* xn, const float* dirs, int S,
+                        float* sigma, float* rgb, hipStream_t stream);
+int nsl_field_bwd_mixed(const nsl_field* f, const void* shadow, const float* xn, const float* dirs, int S,
+                        const float* dsigma, const float* drgb, float* grads, void* workspace,
+                        size_t workspace_bytes, hipStream_t stream);
 
 /* Compositing of R rays whose samples are contiguous: ray r owns samples
  * [ray_off[r], ray_off[r+1]).  out[R,6] = (r, g, b, d*, V*, A) in ray

@@ -291,6 +291,7 @@ namespace {
 struct StepBuffers {
   RayBuffers rb;
   float* wprep;
+  void* shadow;  // mixed precision: BF16 operands + FP16 tables
   float* t;
   uint32_t* ray;
   float* sigma;
@@ -300,7 +301,7 @@ struct StepBuffers {
   float* partial;
 };
 
-size_t step_carve(const nsl_field* f, int n, int max_samples, void* base, StepBuffers* b) {
+size_t step_carve(const nsl_field* f, int n, int max_samples, bool mixed, void* base, StepBuffers* b) {
   Carver cv(base);
   StepBuffers s{};
   s.rb.rays = cv.take<float4>(2 * (size_t)n);
@@ -318,6 +319,7 @@ size_t step_carve(const nsl_field* f, int n, int max_samples, void* base, StepBu
   s.dsigma = cv.take<float>((size_t)max_samples);
   s.drgb = cv.take<float>(3 * (size_t)max_samples);
   s.partial = cv.take<float>((size_t)kBwdBlocks * field_nweights(f->shape));
+  s.shadow = mixed ? cv.take<char>(mixed_shadow_bytes(f->shape, f->lay.table_floats)) : nullptr;
   if (b) *b = s;
   return cv.used;
 }
@@ -334,6 +336,7 @@ int check_step_cfg(const nsl_step_config* c) {
   if (c->sampler == NSL_SAMPLER_OCCUPANCY && (double)c->t_far / c->dt > 1e7) return fail(NSL_E_INVALID, "lattice too long");
   if (c->do_adam && c->adam_step < 1) return fail(NSL_E_INVALID, "adam_step must be >= 1");
   if (!(c->loss_scale > 0.0f)) return fail(NSL_E_INVALID, "loss_scale must be > 0");
+  if (c->precision != NSL_PRECISION_FP32 && c->precision != NSL_PRECISION_MIXED) return fail(NSL_E_INVALID, "bad precision");
   return NSL_OK;
 }
 
@@ -365,7 +368,7 @@ int check_ids_range(const nsl_mapper* m, int n) {
 
 size_t nsl_step_workspace_bytes(const nsl_field* f, const nsl_step_config* c, int n) {
   if (!f || !c || n < 0) return 0;
-  return step_carve(f, n, c->max_samples, nullptr, nullptr);
+  return step_carve(f, n, c->max_samples, c->precision == NSL_PRECISION_MIXED, nullptr, nullptr);
 }
 
 static int run_march(nsl_mapper* m, const nsl_field* f, const nsl_step_config* c, const uint32_t* ids, int n,
@@ -388,15 +391,20 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   if (c->sampler == NSL_SAMPLER_OCCUPANCY && m->grid_res < 1) return fail(NSL_E_INVALID, "no occupancy grid");
   if (ws_bytes < nsl_step_workspace_bytes(f, c, n)) return fail(NSL_E_WORKSPACE, "step workspace too small");
   StepBuffers b;
-  step_carve(f, n, c->max_samples, ws, &b);
+  const bool mixed = c->precision == NSL_PRECISION_MIXED;
+  step_carve(f, n, c->max_samples, mixed, ws, &b);
   if (stats_out) b.rb.stats = reinterpret_cast<uint32_t*>(stats_out);
   b.rb.loss = loss_out;
   const int64_t total = f->lay.total_floats;
   const bool prof = g_prof.on;
   auto mark = [&](int i) -> hipError_t { return prof ? hipEventRecord(g_prof.ev[i], st) : hipSuccess; };
   HIP_TRY(mark(0), "profile event");
+  if (c->scale_state) HIP_TRY(scale_begin(c->scale_state, st), "loss scale");
   if (c->zero_grads) HIP_TRY(fill_zero(grads, total, st), "zero grads");
-  HIP_TRY(field_prep(f->shape, params, f->wo, b.wprep, st), "prep weights");
+  if (mixed)
+    HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, b.shadow, st), "prep mixed");
+  else
+    HIP_TRY(field_prep(f->shape, params, f->wo, b.wprep, st), "prep weights");
   HIP_TRY(mark(1), "profile event");
   if ((rc = run_march(m, f, c, ids, n, b, st))) return rc;
   HIP_TRY(mark(2), "profile event");
@@ -404,7 +412,10 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   FieldArgs fa{params, b.wprep, f->lv};
   SampleSrc src{};
   src.t = b.t; src.ray = b.ray; src.rays = b.rb.rays; src.box = f->box; src.n_dev = b.rb.stats + 1; src.n = 0;
-  HIP_TRY(field_forward(f->shape, fa, src, c->max_samples, b.sigma, b.rgb, st), "field forward");
+  if (mixed)
+    HIP_TRY(mixed_forward(f->shape, f->lv, b.shadow, src, c->max_samples, b.sigma, b.rgb, st), "field forward");
+  else
+    HIP_TRY(field_forward(f->shape, fa, src, c->max_samples, b.sigma, b.rgb, st), "field forward");
   HIP_TRY(mark(3), "profile event");
 
   CompositeIO io{};
@@ -412,17 +423,25 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   io.max_samples = c->max_samples; io.R = n; io.delta = c->dt; io.stop_T = 0.0f; io.out6 = nullptr;
   LossIO lo{};
   lo.target = b.rb.target; lo.prec = b.rb.prec; lo.rays = b.rb.rays; lo.stats = b.rb.stats;
-  lo.lambda_d = c->lambda_d; lo.loss_scale = c->loss_scale; lo.loss = loss_out; lo.ray_out = ray_out;
+  lo.lambda_d = c->lambda_d; lo.loss_scale = c->loss_scale; lo.scale_dev = c->scale_state;
+  lo.loss = loss_out; lo.ray_out = ray_out;
   HIP_TRY(composite_loss_backward(io, lo, b.dsigma, b.drgb, st), "composite");
   HIP_TRY(mark(4), "profile event");
 
-  HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, b.dsigma, b.drgb, grads, b.partial, f->wo, grads, st),
-          "field backward");
+  if (mixed)
+    HIP_TRY(mixed_backward(f->shape, f->lv, b.shadow, src, kBwdBlocks, b.dsigma, b.drgb, grads, b.partial, f->wo,
+                           grads, st),
+            "field backward");
+  else
+    HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, b.dsigma, b.drgb, grads, b.partial, f->wo, grads, st),
+            "field backward");
+  if (c->scale_state) HIP_TRY(scale_check(grads, total, c->scale_state, st), "loss scale");
   HIP_TRY(mark(5), "profile event");
   if (c->do_adam)
     HIP_TRY(adam_update(params, grads, adam_m, adam_v, total, c->lr, c->beta1, c->beta2, c->eps, c->adam_step,
-                        1.0f / c->loss_scale, st),
+                        1.0f / c->loss_scale, c->scale_state, st),
             "adam");
+  if (c->scale_state) HIP_TRY(scale_end(c->scale_state, st), "loss scale");
   HIP_TRY(mark(6), "profile event");
   if (prof) {
     HIP_TRY(hipEventSynchronize(g_prof.ev[NSL_PHASES]), "profile sync");
@@ -445,7 +464,7 @@ int nsl_march(nsl_mapper* m, const nsl_field* f, const nsl_step_config* c, const
   if ((rc = check_ids_range(m, n))) return rc;
   if (ws_bytes < nsl_step_workspace_bytes(f, c, n)) return fail(NSL_E_WORKSPACE, "march workspace too small");
   StepBuffers b;
-  step_carve(f, n, c->max_samples, ws, &b);
+  step_carve(f, n, c->max_samples, c->precision == NSL_PRECISION_MIXED, ws, &b);
   b.rb.counts = counts;
   b.rb.offsets = offsets;
   b.t = t;
@@ -526,6 +545,42 @@ int nsl_field_bwd(const nsl_field* f, const float* params, const float* xn, cons
   return NSL_OK;
 }
 
+size_t nsl_mixed_shadow_bytes(const nsl_field* f) {
+  return f ? mixed_shadow_bytes(f->shape, f->lay.table_floats) : 0;
+}
+
+int nsl_field_prepare_mixed(const nsl_field* f, const float* params, void* shadow, hipStream_t st) {
+  if (!f || !params || !shadow) return fail(NSL_E_INVALID, "null argument");
+  HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, shadow, st), "prepare mixed");
+  return NSL_OK;
+}
+
+int nsl_field_fwd_mixed(const nsl_field* f, const void* shadow, const float* xn, const float* dirs, int S,
+                        float* sigma, float* rgb, hipStream_t st) {
+  if (!f || !shadow || !xn || !dirs || !sigma || !rgb) return fail(NSL_E_INVALID, "null argument");
+  if (S < 0) return fail(NSL_E_INVALID, "negative sample count");
+  SampleSrc src{};
+  src.xn = xn; src.dir = dirs; src.box = f->box; src.n = S;
+  HIP_TRY(mixed_forward(f->shape, f->lv, shadow, src, S, sigma, rgb, st), "field forward (mixed)");
+  return NSL_OK;
+}
+
+int nsl_field_bwd_mixed(const nsl_field* f, const void* shadow, const float* xn, const float* dirs, int S,
+                        const float* dsigma, const float* drgb, float* grads, void* ws, size_t ws_bytes,
+                        hipStream_t st) {
+  if (!f || !shadow || !xn || !dirs || !dsigma || !drgb || !grads || !ws) return fail(NSL_E_INVALID, "null argument");
+  if (S < 0) return fail(NSL_E_INVALID, "negative sample count");
+  if (ws_bytes < nsl_field_workspace_bytes(f)) return fail(NSL_E_WORKSPACE, "field workspace too small");
+  Carver cv(ws);
+  cv.take<float>(field_prep_floats(f->shape));
+  float* partial = cv.take<float>((size_t)kBwdBlocks * field_nweights(f->shape));
+  SampleSrc src{};
+  src.xn = xn; src.dir = dirs; src.box = f->box; src.n = S;
+  HIP_TRY(mixed_backward(f->shape, f->lv, shadow, src, kBwdBlocks, dsigma, drgb, grads, partial, f->wo, grads, st),
+          "field backward (mixed)");
+  return NSL_OK;
+}
+
 int nsl_composite_fwd(const float* sigma, const float* rgb, const float* t, const uint32_t* off, int R, float delta,
                       float stop_T, float* out, hipStream_t st) {
   if (!sigma || !rgb || !t || !off || !out) return fail(NSL_E_INVALID, "null argument");
@@ -555,7 +610,7 @@ int nsl_adam(float* p, float* g, float* m, float* v, int64_t n, float lr, float 
              float grad_scale, hipStream_t st) {
   if (!p || !g || !m || !v) return fail(NSL_E_INVALID, "null argument");
   if (n < 0 || step < 1) return fail(NSL_E_INVALID, "bad count or step");
-  HIP_TRY(adam_update(p, g, m, v, n, lr, b1, b2, eps, step, grad_scale, st), "adam");
+  HIP_TRY(adam_update(p, g, m, v, n, lr, b1, b2, eps, step, grad_scale, nullptr, st), "adam");
   return NSL_OK;
 }
 

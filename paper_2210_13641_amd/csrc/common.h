@@ -149,21 +149,37 @@ __device__ __forceinline__ bool row_run_sums(uint32_t key, float& a, float& b) {
   return head;
 }
 
-// p[0] += a, p[1] += b as one 64-bit compare-and-swap loop: one memory-side
-// atomic per table entry instead of two (the two features of an entry share
-// 8 aligned bytes).  The first read may be stale; the CAS corrects it.
-__device__ __forceinline__ void atomic_add_pair(float* p, float a, float b) {
-  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
-  unsigned long long seen = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  unsigned long long want;
-  do {
-    want = seen;
-    const float x = __uint_as_float((unsigned)(want & 0xFFFFFFFFull)) + a;
-    const float y = __uint_as_float((unsigned)(want >> 32)) + b;
-    const unsigned long long next = (unsigned long long)__float_as_uint(x) |
-                                    ((unsigned long long)__float_as_uint(y) << 32);
-    seen = atomicCAS(q, want, next);
-  } while (seen != want);
+// p_k[0] += a_k, p_k[1] += b_k for K table entries, each as one 64-bit
+// compare-and-swap (one memory-side atomic per entry instead of two: the two
+// features of an entry share 8 aligned bytes).  All K reads, then all K
+// swaps are issued before any result is awaited; only swaps that lost a race
+// (or started from a stale read) go round again.
+__device__ __forceinline__ unsigned long long add_pair_bits(unsigned long long v, float a, float b) {
+  const float x = __uint_as_float((unsigned)(v & 0xFFFFFFFFull)) + a;
+  const float y = __uint_as_float((unsigned)(v >> 32)) + b;
+  return (unsigned long long)__float_as_uint(x) | ((unsigned long long)__float_as_uint(y) << 32);
+}
+
+template <int K>
+__device__ __forceinline__ void atomic_add_pairs(float* const p[K], const bool on[K], const float a[K],
+                                                 const float b[K]) {
+  unsigned long long seen[K], got[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    seen[k] = on[k] ? __hip_atomic_load(reinterpret_cast<unsigned long long*>(p[k]), __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT)
+                    : 0ull;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    got[k] = on[k] ? atomicCAS(reinterpret_cast<unsigned long long*>(p[k]), seen[k], add_pair_bits(seen[k], a[k], b[k]))
+                   : seen[k];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    while (got[k] != seen[k]) {
+      seen[k] = got[k];
+      got[k] = atomicCAS(reinterpret_cast<unsigned long long*>(p[k]), seen[k], add_pair_bits(seen[k], a[k], b[k]));
+    }
+  }
 }
 
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {

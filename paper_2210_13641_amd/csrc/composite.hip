@@ -192,7 +192,8 @@ __global__ __launch_bounds__(256) void composite_loss_kernel(CompositeIO io, Los
   const float e0 = s.C[0] - tg.x, e1 = s.C[1] - tg.y, e2 = s.C[2] - tg.z, ed = s.D - tg.w;
   const float l_rgb = e0 * e0 + e1 * e1 + e2 * e2;
   const float l_d = pi * ed * ed;
-  const float k = 2.0f * lo.loss_scale / Rf;
+  const float scale = lo.scale_dev ? lo.scale_dev[0] : lo.loss_scale;
+  const float k = 2.0f * scale / Rf;
   const float gC[3] = {k * e0, k * e1, k * e2};
   const float gD = k * lo.lambda_d * pi * ed;
   if (lane_id() == 0) {

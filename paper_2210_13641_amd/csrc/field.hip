@@ -7,127 +7,9 @@
 // the first MFMA layer (net.h).  Nothing but sigma and colour leaves the
 // forward kernel; the backward kernel re-derives every activation from the
 // sample position instead of reading stored activations.
-#include "kernels.h"
-#include "net.h"
+#include "field_common.h"
 
 namespace nsl {
-
-// ---------------------------------------------------------------------------
-// Per-sample inputs
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ void load_sample(const SampleSrc& src, int s, float xn[3],
-                                            float d[3]) {
-  if (src.t) {
-    const uint32_t r = src.ray[s];
-    const float t = src.t[s];
-    const float4 o = src.rays[2 * r];
-    const float4 dd = src.rays[2 * r + 1];
-    d[0] = dd.x; d[1] = dd.y; d[2] = dd.z;
-    xn[0] = normalise_axis(pos_axis(o.x, dd.x, t), src.box.lo[0], src.box.inv[0]);
-    xn[1] = normalise_axis(pos_axis(o.y, dd.y, t), src.box.lo[1], src.box.inv[1]);
-    xn[2] = normalise_axis(pos_axis(o.z, dd.z, t), src.box.lo[2], src.box.inv[2]);
-  } else {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      xn[i] = fminf(fmaxf(src.xn[3 * s + i], 0.0f), 1.0f);
-      d[i] = src.dir[3 * s + i];
-    }
-  }
-}
-
-// Per-lane level constants (levels g, g+4, ... of this lane group).
-template <class N>
-struct LaneLevels {
-  int res[N::LPL];
-  uint32_t off[N::LPL];
-  bool dense[N::LPL];
-};
-
-template <class N>
-__device__ __forceinline__ void lane_levels(const LevelInfo& lv, int g, LaneLevels<N>& ll) {
-#pragma unroll
-  for (int q = 0; q < N::LPL; ++q) {
-    const int l = g + 4 * q;
-    ll.res[q] = lv.res[l];
-    ll.off[q] = lv.offset[l];
-    ll.dense[q] = (lv.dense_bits >> l) & 1u;
-  }
-}
-
-struct Corner8 {
-  uint32_t idx[8];
-  float w[8];
-};
-
-__device__ __forceinline__ void corners(float x, float y, float z, int n, bool dense,
-                                        uint32_t mask, uint32_t off, Corner8& c) {
-  float fx, fy, fz;
-  const uint32_t ix = (uint32_t)cell_floor(x, n, fx);
-  const uint32_t iy = (uint32_t)cell_floor(y, n, fy);
-  const uint32_t iz = (uint32_t)cell_floor(z, n, fz);
-  const float gx[2] = {1.0f - fx, fx}, gy[2] = {1.0f - fy, fy}, gz[2] = {1.0f - fz, fz};
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const uint32_t cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
-    c.idx[k] = off + grid_index(ix + cx, iy + cy, iz + cz, n, dense, mask);
-    c.w[k] = (gx[cx] * gy[cy]) * gz[cz];
-  }
-}
-
-template <class N>
-__device__ __forceinline__ void encode(const float* __restrict__ table, uint32_t mask,
-                                       const LaneLevels<N>& ll, const float xn[3],
-                                       float e[N::NSLOT]) {
-#pragma unroll
-  for (int q = 0; q < N::LPL; ++q) {
-    Corner8 c;
-    corners(xn[0], xn[1], xn[2], ll.res[q], ll.dense[q], mask, ll.off[q], c);
-    float2 v[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = *reinterpret_cast<const float2*>(table + 2 * (size_t)c.idx[k]);
-    float a0 = 0.0f, a1 = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      a0 += c.w[k] * v[k].x;
-      a1 += c.w[k] * v[k].y;
-    }
-    e[2 * q] = a0;
-    e[2 * q + 1] = a1;
-  }
-}
-
-// Real orthonormal SH coefficients 4g..4g+3 of direction d (0 beyond NSH).
-template <class N>
-__device__ __forceinline__ void sh_lane(const float d[3], int g, float out[4]) {
-  const float x = d[0], y = d[1], z = d[2];
-  float Y[16];
-  Y[0] = 0.28209479177387814f;
-  Y[1] = 0.4886025119029199f * y;
-  Y[2] = 0.4886025119029199f * z;
-  Y[3] = 0.4886025119029199f * x;
-  const float xx = x * x, yy = y * y, zz = z * z;
-  Y[4] = 1.0925484305920792f * x * y;
-  Y[5] = 1.0925484305920792f * y * z;
-  Y[6] = 0.31539156525252005f * (3.0f * zz - 1.0f);
-  Y[7] = 1.0925484305920792f * x * z;
-  Y[8] = 0.5462742152960396f * (xx - yy);
-  if (N::SHB > 3) {
-    Y[9] = 0.5900435899266435f * y * (3.0f * xx - yy);
-    Y[10] = 2.890611442640554f * x * y * z;
-    Y[11] = 0.4570457994644658f * y * (5.0f * zz - 1.0f);
-    Y[12] = 0.3731763325901154f * z * (5.0f * zz - 3.0f);
-    Y[13] = 0.4570457994644658f * x * (5.0f * zz - 1.0f);
-    Y[14] = 1.445305721320277f * z * (xx - yy);
-    Y[15] = 0.5900435899266435f * x * (xx - 3.0f * yy);
-  } else {
-#pragma unroll
-    for (int k = 9; k < 16; ++k) Y[k] = 0.0f;
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-    out[r] = g == 0 ? Y[r] : g == 1 ? Y[4 + r] : g == 2 ? Y[8 + r] : Y[12 + r];
-}
 
 // ---------------------------------------------------------------------------
 // MLP forward (activations kept for the adjoint)
@@ -143,10 +25,6 @@ struct Acts {
   f4 h4[N::HC / 16];
   f4 z;
 };
-
-__device__ __forceinline__ f4 relu4(f4 v) {
-  return f4{fmaxf(v[0], 0.0f), fmaxf(v[1], 0.0f), fmaxf(v[2], 0.0f), fmaxf(v[3], 0.0f)};
-}
 
 template <class N>
 __device__ __forceinline__ void mlp_fwd(const float* __restrict__ Af, int lane, Acts<N>& a) {
@@ -245,12 +123,6 @@ __global__ void prep_weights_kernel(const float* __restrict__ params, WOffsets w
   out[idx] = v;
 }
 
-template <class N>
-__device__ __forceinline__ void load_operands(float* dst, const float* __restrict__ src, int n) {
-  for (int i = threadIdx.x * 4; i < n; i += blockDim.x * 4)
-    *reinterpret_cast<float4*>(dst + i) = *reinterpret_cast<const float4*>(src + i);
-}
-
 // ---------------------------------------------------------------------------
 // Forward: sigma and colour per sample
 // ---------------------------------------------------------------------------
@@ -287,11 +159,6 @@ __global__ __launch_bounds__(256) void field_fwd_kernel(FieldArgs a, SampleSrc s
 // ---------------------------------------------------------------------------
 // Backward
 // ---------------------------------------------------------------------------
-
-__device__ __forceinline__ void wave_lds_fence() {
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-  __builtin_amdgcn_wave_barrier();
-}
 
 // dW[in][out] += sum over the wave's 16 samples of X[in] * dY[out], with X and
 // dY staged [feature][sample] (stride SROW) in this wave's LDS area.
@@ -493,14 +360,18 @@ __global__ __launch_bounds__(256, 1) void field_bwd_kernel(FieldArgs a, SampleSr
       const float d1 = valid ? de[k1 >> 2][k1 & 3] : 0.0f;
       Corner8 c;
       corners(xn[0], xn[1], xn[2], ll.res[q], ll.dense[q], a.lv.table_mask, ll.off[q], c);
+      float* ptr[8];
+      bool on[8];
+      float v0[8], v1[8];
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        float v0 = c.w[k] * d0, v1 = c.w[k] * d1;
+        v0[k] = c.w[k] * d0;
+        v1[k] = c.w[k] * d1;
         const uint32_t key = valid ? c.idx[k] : 0xFFFFFFFFu;
-        if (row_run_sums(key, v0, v1) && valid) {
-          atomic_add_pair(grad_table + 2 * (size_t)c.idx[k], v0, v1);
-        }
+        on[k] = row_run_sums(key, v0[k], v1[k]) && valid;
+        ptr[k] = grad_table + 2 * (size_t)c.idx[k];
       }
+      atomic_add_pairs<8>(ptr, on, v0, v1);
     }
   }
   __syncthreads();
@@ -529,21 +400,6 @@ __global__ void dw_reduce_kernel(const float* __restrict__ partial, int nblocks,
 // ---------------------------------------------------------------------------
 
 constexpr int kRenderMaxTiles = 4;  // n_samples <= 64
-
-// Inclusive prefix sum within each 16-lane row.
-__device__ __forceinline__ float row_incl_scan(float v) {
-  v += __int_as_float(row_from_below<1>(__float_as_int(v)));
-  v += __int_as_float(row_from_below<2>(__float_as_int(v)));
-  v += __int_as_float(row_from_below<4>(__float_as_int(v)));
-  v += __int_as_float(row_from_below<8>(__float_as_int(v)));
-  return v;
-}
-
-__device__ __forceinline__ float row_sum(float v) {
-#pragma unroll
-  for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 16);
-  return v;
-}
 
 template <class N>
 __global__ __launch_bounds__(256) void render_kernel(LevelInfo lv, Aabb box, const nsl_render_request* __restrict__ reqs,

@@ -56,6 +56,17 @@ hipError_t render_tiles(int shape, const LevelInfo& lv, const Aabb& box, const n
                         hipStream_t st);
 size_t field_fwd_floats(int shape);
 
+// field_mixed.hip: FP16 table, BF16 MLP on MFMA, FP32 accumulation.  The
+// shadow buffer holds the BF16 operands and the FP16 table copy.
+size_t mixed_shadow_bytes(int shape, int64_t table_floats);
+hipError_t mixed_prepare(int shape, const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
+                         hipStream_t st);
+hipError_t mixed_forward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
+                         float* sigma, float* rgb, hipStream_t st);
+hipError_t mixed_backward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int nblocks,
+                          const float* dsigma, const float* drgb, float* grad_table, float* partial,
+                          const WOffsets& wo, float* grads, hipStream_t st);
+
 // march.hip
 struct KeyframeStore {
   const float* rgb;        // [K,H,W,3]
@@ -113,6 +124,7 @@ struct LossIO {
   const uint32_t* stats;   // R at stats[0]
   float lambda_d;
   float loss_scale;
+  const float* scale_dev;  // if set, the loss scale is read from scale_dev[0]
   float* loss;             // [3] accumulated
   float* ray_out;          // [R,6] z units or null
 };
@@ -131,8 +143,15 @@ hipError_t depth_covariance(int c, int p, const double* C, const double* Et, con
                             int* status, double* partial, hipStream_t st);
 
 // misc.hip
+// scale_state (nullable): gradient scale 1/scale_state[0], skip if scale_state[3] != 0.
 hipError_t adam_update(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1,
-                       float b2, float eps, int step, float grad_scale, hipStream_t st);
+                       float b2, float eps, int step, float grad_scale, const float* scale_state,
+                       hipStream_t st);
+// Dynamic loss scaling: clear the overflow flag, flag non-finite gradients,
+// then halve (overflow) or count clean steps and double after 2000.
+hipError_t scale_begin(float* state, hipStream_t st);
+hipError_t scale_check(const float* g, int64_t n, float* state, hipStream_t st);
+hipError_t scale_end(float* state, hipStream_t st);
 hipError_t fill_zero(float* p, int64_t n, hipStream_t st);
 // Writes one request record to device memory (taken by value at launch),
 // with its pose [12] and intrinsics [4] read from device memory.

@@ -10,8 +10,16 @@ namespace {
 __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, float* __restrict__ g,
                                                    float* __restrict__ m, float* __restrict__ v,
                                                    int64_t n, float lr, float b1, float b2,
-                                                   float eps, float bc1, float bc2, float gscale) {
+                                                   float eps, float bc1, float bc2, float gscale,
+                                                   const float* __restrict__ state) {
   const int64_t i4 = (int64_t)(blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * 4;
+  if (state) {
+    if (state[3] != 0.0f) {  // overflow: skip the update, clear the gradient
+      for (int64_t i = i4; i < min(n, i4 + 4); ++i) g[i] = 0.0f;
+      return;
+    }
+    gscale = 1.0f / state[0];
+  }
   if (i4 + 4 <= n) {
     float4 pp = *reinterpret_cast<float4*>(p + i4);
     float4 gg = *reinterpret_cast<float4*>(g + i4);
@@ -52,6 +60,30 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(float* __restrict__ p, i
   }
 }
 
+__global__ void scale_begin_kernel(float* state) { state[3] = 0.0f; }
+
+__global__ __launch_bounds__(256) void scale_check_kernel(const float* __restrict__ g, int64_t n,
+                                                          float* __restrict__ state) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !isfinite(g[i]);
+  if (__ballot(bad) != 0ull && lane_id() == 0) state[3] = 1.0f;
+}
+
+__global__ void scale_end_kernel(float* state) {
+  if (state[3] != 0.0f) {
+    state[0] *= 0.5f;
+    state[1] = 0.0f;
+    state[2] += 1.0f;
+  } else {
+    state[1] += 1.0f;
+    if (state[1] >= 2000.0f) {
+      state[0] *= 2.0f;
+      state[1] = 0.0f;
+    }
+  }
+}
+
 __global__ void store_request_kernel(nsl_render_request r, const float* __restrict__ pose,
                                      const float* __restrict__ intr, nsl_render_request* dst) {
   for (int i = 0; i < 12; ++i) r.pose[i] = pose[i];
@@ -62,13 +94,14 @@ __global__ void store_request_kernel(nsl_render_request r, const float* __restri
 }  // namespace
 
 hipError_t adam_update(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1,
-                       float b2, float eps, int step, float grad_scale, hipStream_t st) {
+                       float b2, float eps, int step, float grad_scale, const float* scale_state,
+                       hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const float bc1 = 1.0f - powf(b1, (float)step);
   const float bc2 = 1.0f - powf(b2, (float)step);
   const int64_t threads = (n + 3) / 4;
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, p, g, m, v,
-                     n, lr, b1, b2, eps, bc1, bc2, grad_scale);
+                     n, lr, b1, b2, eps, bc1, bc2, grad_scale, scale_state);
   return hipGetLastError();
 }
 
@@ -76,6 +109,21 @@ hipError_t fill_zero(float* p, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   const int64_t threads = (n + 3) / 4;
   hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t scale_begin(float* state, hipStream_t st) {
+  hipLaunchKernelGGL(scale_begin_kernel, dim3(1), dim3(1), 0, st, state);
+  return hipGetLastError();
+}
+
+hipError_t scale_check(const float* g, int64_t n, float* state, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(scale_check_kernel, dim3(1024), dim3(256), 0, st, g, n, state);
+  return hipGetLastError();
+}
+
+hipError_t scale_end(float* state, hipStream_t st) {
+  hipLaunchKernelGGL(scale_end_kernel, dim3(1), dim3(1), 0, st, state);
   return hipGetLastError();
 }
 

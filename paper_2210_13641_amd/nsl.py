@@ -21,6 +21,7 @@ _lib = C.CDLL(LIB_PATH)
 OK = 0
 E_INVALID, E_WORKSPACE, E_HIP, E_BUDGET, E_CAPACITY = -1, -2, -3, -4, -5
 SAMPLER_UNIFORM, SAMPLER_OCCUPANCY = 0, 1
+PRECISION_FP32, PRECISION_MIXED = 0, 1
 MAX_LEVELS, MAX_LAYERS = 16, 8
 
 
@@ -45,7 +46,8 @@ class StepConfig(C.Structure):
                 ("n_uniform", C.c_int32), ("max_per_ray", C.c_int32), ("max_samples", C.c_int32),
                 ("lambda_d", C.c_float), ("zero_grads", C.c_int32), ("do_adam", C.c_int32),
                 ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
-                ("adam_step", C.c_int32), ("loss_scale", C.c_float)]
+                ("adam_step", C.c_int32), ("loss_scale", C.c_float), ("precision", C.c_int32),
+                ("scale_state", C.c_void_p)]
 
 
 class RenderConfig(C.Structure):
@@ -104,6 +106,10 @@ _sig("nsl_field_prepare", _i, [_vp, _vp, _vp, _vp])
 _sig("nsl_render_batch", _i, [_vp, _vp, _i, _vp, _i, C.POINTER(RenderConfig), _vp])
 _sig("nsl_render", _i, [_vp, _vp, _vp, _vp, _i, _i, C.POINTER(RenderConfig), _vp, _vp, _vp, _vp, _vp, _sz, _vp])
 
+_sig("nsl_mixed_shadow_bytes", _sz, [_vp])
+_sig("nsl_field_prepare_mixed", _i, [_vp, _vp, _vp, _vp])
+_sig("nsl_field_fwd_mixed", _i, [_vp, _vp, _vp, _vp, _i, _vp, _vp, _vp])
+_sig("nsl_field_bwd_mixed", _i, [_vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp])
 _sig("nsl_covariance_workspace_bytes", _sz, [_i, _i])
 _sig("nsl_depth_covariance", _i, [_i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
 _sig("nsl_profile_enable", _i, [_i])
@@ -217,6 +223,28 @@ class Field:
                                   ws.numel(), _stream()))
         return sigma, rgb
 
+    def shadow_bytes(self):
+        return _lib.nsl_mixed_shadow_bytes(self.handle)
+
+    def prepare_mixed(self, params, shadow=None):
+        shadow = torch.empty(self.shadow_bytes(), dtype=torch.uint8, device=params.device) if shadow is None else shadow
+        _check(_lib.nsl_field_prepare_mixed(self.handle, _dev(params, torch.float32), _ptr(shadow), _stream()))
+        return shadow
+
+    def fwd_mixed(self, shadow, xn, dirs):
+        S = xn.shape[0]
+        sigma = torch.empty(S, device=xn.device, dtype=torch.float32)
+        rgb = torch.empty(S, 3, device=xn.device, dtype=torch.float32)
+        _check(_lib.nsl_field_fwd_mixed(self.handle, _ptr(shadow), _dev(xn, torch.float32), _dev(dirs, torch.float32),
+                                        S, _ptr(sigma), _ptr(rgb), _stream()))
+        return sigma, rgb
+
+    def bwd_mixed(self, shadow, xn, dirs, dsigma, drgb, grads, ws):
+        S = xn.shape[0]
+        _check(_lib.nsl_field_bwd_mixed(self.handle, _ptr(shadow), _dev(xn, torch.float32), _dev(dirs, torch.float32),
+                                        S, _dev(dsigma, torch.float32), _dev(drgb, torch.float32),
+                                        _dev(grads, torch.float32), _ptr(ws), ws.numel(), _stream()))
+
     def bwd(self, params, xn, dirs, dsigma, drgb, grads, ws):
         S = xn.shape[0]
         _check(_lib.nsl_field_bwd(self.handle, _dev(params, torch.float32), _dev(xn, torch.float32),
@@ -270,7 +298,7 @@ class Mapper:
 # ---------------------------------------------------------------------------
 
 def step_config(sampler_spec, lambda_d=1.0, zero_grads=True, do_adam=False, lr=1e-2, betas=(0.9, 0.99),
-                eps=1e-15, adam_step=1, loss_scale=1.0) -> StepConfig:
+                eps=1e-15, adam_step=1, loss_scale=1.0, precision=PRECISION_FP32, scale_state=None) -> StepConfig:
     c = StepConfig()
     c.sampler = SAMPLER_UNIFORM if sampler_spec.mode == "uniform" else SAMPLER_OCCUPANCY
     c.t_near, c.t_far, c.dt = sampler_spec.t_near, sampler_spec.t_far, sampler_spec.dt
@@ -278,6 +306,8 @@ def step_config(sampler_spec, lambda_d=1.0, zero_grads=True, do_adam=False, lr=1
     c.lambda_d, c.zero_grads, c.do_adam = lambda_d, int(zero_grads), int(do_adam)
     c.lr, c.beta1, c.beta2, c.eps = lr, betas[0], betas[1], eps
     c.adam_step, c.loss_scale = adam_step, loss_scale
+    c.precision = precision
+    c.scale_state = scale_state.data_ptr() if scale_state is not None else None
     return c
 
 

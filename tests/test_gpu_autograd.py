@@ -50,7 +50,7 @@ def test_autograd_matches_oracle_on_4096_rays(nsl, gpu):
     L, Lr, Ld = ag.mapping_loss(out, _t(torch, dev, s64.astype(np.float32)), _t(torch, dev, kf.rgb[k, v, u]),
                                 _t(torch, dev, kf.depth[k, v, u]), _t(torch, dev, kf.depth_var[k, v, u]))
     L.backward()
-    assert float(L) == pytest.approx(o["loss"], rel=2e-5)
+    assert float(L.detach()) == pytest.approx(o["loss"], rel=2e-5)
     outc = out.detach().cpu().numpy()
     check_mag("rgb", outc[:, :3], o["rgb"], np.abs(o["rgb"]) + 1e-7, TOL)
     check_mag("depth", outc[:, 3], o["depth_ray"], np.abs(o["depth_ray"]) + 1e-7, TOL)
