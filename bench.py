@@ -1,22 +1,26 @@
 """Benchmark of the NeRF-SLAM mapping step on one MI355X.
 
-Workload: the paper-scale step -- 16-level hash grid with 2^19 entries per
-level, density net 32->64->16, colour net 32->64->64->3, 128^3 occupancy grid
-of a 64-blob scene, 8 keyframes of 640x480, 4096 pixel candidates per step
-cut at 2^18 samples (1..256 samples per ray).  A step is nsl_train_step:
-rays + march + field forward + compositing/loss + recompute backward to
-parameter gradients (headline); the full step adds Adam.  Inputs are resident
-in device memory before timing starts.
+Training workload: the paper-scale step -- 16-level hash grid with 2^19
+entries per level, density net 32->64->16, colour net 32->64->64->3, 128^3
+occupancy grid of a 64-blob scene, 8 keyframes of 640x480, 4096 pixel
+candidates per step cut at 2^18 samples (1..256 samples per ray).  A step is
+nsl_train_step: rays + march + field forward + compositing/loss + recompute
+backward to parameter gradients (the headline; gradient clearing included),
+and the full step adds Adam.  It runs in mixed precision (FP16 tables, BF16
+MLP on MFMA, FP32 accumulation and masters; the headline value) and in plain
+FP32.  Inputs are resident in device memory before timing starts.
 
-Prints ONE JSON line.  Extra keys: per-phase times from HIP events recorded
-between the phases on the step's stream, the roofline of the dominant kernel,
-and the FP64 oracle timed on the host on a bounded sample.
+Serving workload: render requests (Poisson arrivals at 200/s, image sizes
+160x120 .. 1280x960, 32 samples, early termination at T < 1e-4) against the
+tiny field after 300 training steps, while training continues at one step
+per 5 ms; p50/p99 latency and rays/s.
+
+Prints ONE JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -29,6 +33,7 @@ sys.path.insert(0, ROOT)
 METRIC = "train samples/s (fwd+bwd) mixed vs FP32; render rays/s; p50/p99 render latency"
 PEAK_HBM = 8.0e12          # B/s, MI355X HBM3E
 PEAK_FP32 = 157.3e12       # FLOP/s, MI355X FP32 (matrix and vector)
+PEAK_BF16 = 2.5e15         # FLOP/s, MI355X dense BF16 MFMA
 N_CANDIDATES = 4096
 N_SETS = 4                 # candidate sets rotated over the timed steps
 
@@ -37,13 +42,30 @@ def mlp_macs(spec):
     """Multiply-accumulates per sample: forward, input-gradient, weight-gradient."""
     dims = spec.mlp_dims()
     fwd = sum(a * b for a, b in dims)
-    # no input gradient for the SH inputs of the first colour layer
-    dx = fwd - spec.sh_bands ** 2 * dims[2][1]
+    dx = fwd - spec.sh_bands ** 2 * dims[2][1]      # no input gradient for the SH inputs
     return fwd, dx, fwd
 
 
-def gather_bytes(spec, elem=4):
-    return 8 * spec.levels * spec.feat_per_level * elem
+def roofline(spec, phase_ms, samples, table_bytes, mlp_peak):
+    """Roofline of the slower of the two field kernels of a step.
+    field_fwd: gather 8*L*F entries of the table and the forward MLP;
+    field_bwd: scatter of FP32 gradients (8*L*F*4 B) and the MLP adjoint
+    (the recompute of the encoding and forward MLP is not counted)."""
+    fwd_mac, dx_mac, dw_mac = mlp_macs(spec)
+    n = 8 * spec.levels * spec.feat_per_level
+    work = {"field_fwd": dict(flops=2 * fwd_mac, bytes=n * table_bytes),
+            "field_bwd": dict(flops=2 * (dx_mac + dw_mac), bytes=n * 4)}
+    dom = max(work, key=lambda k: phase_ms[k])
+    w = work[dom]
+    t = phase_ms[dom] * 1e-3
+    if w["flops"] / mlp_peak >= w["bytes"] / PEAK_HBM:
+        a = w["flops"] * samples / t / 1e12
+        r = dict(bound="mfma", achieved=a, peak=mlp_peak / 1e12, unit="TFLOP/s", frac=a / (mlp_peak / 1e12))
+    else:
+        a = w["bytes"] * samples / t / 1e9
+        r = dict(bound="hbm", achieved=a, peak=PEAK_HBM / 1e9, unit="GB/s", frac=a / (PEAK_HBM / 1e9))
+    r.update(traffic=None, kernel=dom, per_sample=w, samples_per_launch=samples, launch_ms=phase_ms[dom])
+    return r
 
 
 def main(argv=None):
@@ -53,6 +75,9 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-candidates", type=int, default=1536)
+    ap.add_argument("--serve-requests", type=int, default=2200)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-only", action="store_true", help="only the serving workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference kernel for HBM counters)")
     args = ap.parse_args(argv)
@@ -67,6 +92,9 @@ def main(argv=None):
     from paper_2210_13641_amd import nsl
 
     dev = torch.device("cuda:0")
+    if args.serve_only:
+        print(json.dumps({"serving": serving(nsl, torch, dev, W, args.serve_requests, args.serve_warmup)}), flush=True)
+        return 0
     spec, sampler = W.C2_FIELD, W.C2_SAMPLER
     scene = W.c2_scene()
     occ = W.c2_occupancy(scene)
@@ -88,10 +116,18 @@ def main(argv=None):
     M = torch.zeros_like(P)
     V = torch.zeros_like(P)
     id_sets = [t(W.c2_candidates(N_CANDIDATES, seed=3 + i).view(np.int32)) for i in range(N_SETS)]
-    cfg = nsl.step_config(sampler, zero_grads=True)
-    cfg_full = nsl.step_config(sampler, zero_grads=False, do_adam=True, lr=W.ADAM_LR, betas=W.ADAM_BETAS,
-                               eps=W.ADAM_EPS, adam_step=1)
-    wsb = torch.empty(nsl.step_workspace_bytes(field, cfg, N_CANDIDATES), dtype=torch.uint8, device=dev)
+    scale = t(np.array([2.0 ** 15, 0, 0, 0], np.float32))
+    cfgs = {
+        "mixed": nsl.step_config(sampler, zero_grads=True, precision=nsl.PRECISION_MIXED, scale_state=scale),
+        "fp32": nsl.step_config(sampler, zero_grads=True),
+    }
+    full = {
+        "mixed": nsl.step_config(sampler, zero_grads=False, do_adam=True, lr=W.ADAM_LR, betas=W.ADAM_BETAS,
+                                 eps=W.ADAM_EPS, precision=nsl.PRECISION_MIXED, scale_state=scale),
+        "fp32": nsl.step_config(sampler, zero_grads=False, do_adam=True, lr=W.ADAM_LR, betas=W.ADAM_BETAS,
+                                eps=W.ADAM_EPS),
+    }
+    wsb = torch.empty(nsl.step_workspace_bytes(field, cfgs["mixed"], N_CANDIDATES), dtype=torch.uint8, device=dev)
     loss = torch.zeros(3, device=dev)
     stats = torch.zeros(N_SETS, 4, dtype=torch.int32, device=dev)
 
@@ -102,123 +138,166 @@ def main(argv=None):
         torch.cuda.synchronize()
         del a, b
 
-    def step(i, c=cfg, stats_row=None):
-        nsl.train_step(mapper, field, P, G, M, V, c, id_sets[i % N_SETS], wsb, loss,
-                       stats[i % N_SETS] if stats_row is None else stats_row)
+    def step(i, c):
+        nsl.train_step(mapper, field, P, G, M, V, c, id_sets[i % N_SETS], wsb, loss, stats[i % N_SETS])
 
-    # headline: fwd + bwd to parameter gradients
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(i)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    st = stats.cpu().numpy()
-    S_sets = st[:, 1].astype(np.int64)
-    R_sets = st[:, 0].astype(np.int64)
-    samples = sum(int(S_sets[i % N_SETS]) for i in range(args.steps))
-    ms_per_step = 1e3 * dt / args.steps
-    value = samples / dt
+    def timed(c, adam):
+        P.copy_(t(flat))
+        G.zero_()
+        M.zero_()
+        V.zero_()
+        for i in range(args.warmup):
+            c.adam_step = i + 1
+            step(i, c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            c.adam_step = args.warmup + i + 1
+            step(i, c)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
 
-    # full step with Adam (Adam clears the gradient, so no separate clearing)
-    G.zero_()
-    for i in range(args.warmup):
-        cfg_full.adam_step = i + 1
-        step(i, cfg_full)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        cfg_full.adam_step = args.warmup + i + 1
-        step(i, cfg_full)
-    torch.cuda.synchronize()
-    dt_full = time.perf_counter() - t0
-    full_value = samples / dt_full
-
-    # phase times from HIP events on the step's stream
-    n_prof = max(10, min(args.steps, 50))
-    P.copy_(t(flat))
-    nsl.profile_enable(True)
-    for i in range(n_prof):
-        cfg_full.adam_step = i + 1
-        step(i, cfg_full)
-    phases, n_done = nsl.profile_read()
-    nsl.profile_enable(False)
-    phase_ms = {k: v / n_done for k, v in phases.items()}
-    S_prof = float(np.mean([S_sets[i % N_SETS] for i in range(n_prof)]))
-
-    # roofline of the dominant kernel
-    fwd_mac, dx_mac, dw_mac = mlp_macs(spec)
-    gb = gather_bytes(spec)
-    work = {
-        "field_fwd": dict(flops=2 * fwd_mac, bytes=gb),
-        "field_bwd": dict(flops=2 * (dx_mac + dw_mac), bytes=gb),   # scatter of the table gradient
-    }
-    dom = max(("field_fwd", "field_bwd"), key=lambda k: phase_ms[k])
-    w = work[dom]
-    t_s = phase_ms[dom] * 1e-3
-    mfma_bound = w["flops"] / PEAK_FP32 >= w["bytes"] / PEAK_HBM
-    if mfma_bound:
-        achieved = w["flops"] * S_prof / t_s / 1e12
-        roof = dict(bound="mfma", achieved=achieved, peak=PEAK_FP32 / 1e12, unit="TFLOP/s",
-                    frac=achieved / (PEAK_FP32 / 1e12), traffic=None)
-    else:
-        achieved = w["bytes"] * S_prof / t_s / 1e9
-        roof = dict(bound="hbm", achieved=achieved, peak=PEAK_HBM / 1e9, unit="GB/s",
-                    frac=achieved / (PEAK_HBM / 1e9), traffic=None)
-    roof.update(kernel=dom, per_sample=dict(flops=w["flops"], bytes=w["bytes"]), samples_per_launch=S_prof,
-                launch_ms=phase_ms[dom])
-    # whole fwd+bwd step against its own bound
-    step_bytes = 2 * gb
-    step_flops = 2 * (fwd_mac + dx_mac + dw_mac)
-    t_bound = max(step_bytes / PEAK_HBM, step_flops / PEAK_FP32)
-    step_roof = dict(bound_s_per_sample=t_bound, frac=(value * t_bound), per_sample=dict(
-        flops=step_flops, bytes=step_bytes))
+    res = {}
+    for name in ("fp32", "mixed"):
+        dt = timed(cfgs[name], False)
+        st = stats.cpu().numpy()
+        S_sets = st[:, 1].astype(np.int64)
+        samples = sum(int(S_sets[i % N_SETS]) for i in range(args.steps))
+        dt_full = timed(full[name], True)
+        # per-phase HIP events on the step's stream
+        P.copy_(t(flat))
+        nsl.profile_enable(True)
+        n_prof = max(10, min(args.steps, 50))
+        for i in range(n_prof):
+            full[name].adam_step = i + 1
+            step(i, full[name])
+        ph, n_done = nsl.profile_read()
+        nsl.profile_enable(False)
+        res[name] = dict(value=samples / dt, ms=1e3 * dt / args.steps, full_value=samples / dt_full,
+                         full_ms=1e3 * dt_full / args.steps, phases={k: v / n_done for k, v in ph.items()},
+                         S=float(np.mean([S_sets[i % N_SETS] for i in range(n_prof)])), R=st[:, 0].astype(np.int64))
+    mixed, fp32 = res["mixed"], res["fp32"]
+    roof = roofline(spec, mixed["phases"], mixed["S"], 2, PEAK_BF16)
+    roof_fp32 = roofline(spec, fp32["phases"], fp32["S"], 4, PEAK_FP32)
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": mixed["value"],
         "unit": "samples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": mixed["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16",
         "data": "synthetic",
         "config": {
-            "workload": "paper-scale FP32 mapping step: 16 levels x 2^19 hash grid, 2^18-sample cut, "
+            "workload": "paper-scale mapping step: 16 levels x 2^19 hash grid, 2^18-sample cut, "
                         "8 keyframes 640x480, 128^3 occupancy (64-blob scene)",
+            "precision": "mixed: FP16 tables, BF16 MLP on MFMA, FP32 accumulation, FP32 master weights, "
+                         "dynamic loss scale from 2^15; transmittance, variance and loss in FP32",
             "candidates_per_step": N_CANDIDATES,
-            "rays_per_step": float(R_sets.mean()),
-            "samples_per_step": float(S_sets.mean()),
-            "mean_samples_per_ray": float(S_sets.sum() / max(R_sets.sum(), 1)),
+            "rays_per_step": float(mixed["R"].mean()),
+            "samples_per_step": mixed["S"],
             "phase": "fwd+bwd to parameter gradients (gradient clearing included)",
         },
-        "full_step_samples_per_s": full_value,
-        "full_step_ms": 1e3 * dt_full / args.steps,
-        "phases_ms": phase_ms,
+        "fp32_samples_per_s": fp32["value"],
+        "fp32_ms_per_step": fp32["ms"],
+        "mixed_vs_fp32": mixed["value"] / fp32["value"],
+        "full_step_samples_per_s": {"mixed": mixed["full_value"], "fp32": fp32["full_value"]},
+        "phases_ms": {"mixed": mixed["phases"], "fp32": fp32["phases"]},
         "roofline": roof,
-        "roofline_step": step_roof,
+        "roofline_fp32": roof_fp32,
     }
+    if args.serve_requests > 0:
+        out["serving"] = serving(nsl, torch, dev, W, args.serve_requests, args.serve_warmup)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec, sampler, kf, occ, table, ws, lay, args.cpu_candidates)
+        out["cpu_baseline"] = cpu_baseline(spec, sampler, kf, occ, table, ws, args.cpu_candidates)
     print(json.dumps(out), flush=True)
     return 0
 
 
-def cpu_baseline(spec, sampler, kf, occ, table, ws, lay, n_cand):
+def serving(nsl, torch, dev, W, n_req, warmup):
+    """Render requests against the tiny field while it keeps training."""
+    from paper_2210_13641_amd import serve
+    spec = W.C1_FIELD
+    f = nsl.Field(spec)
+    lay = f.layout
+    table, ws = W.init_params(0, lay["table_floats"], spec.mlp_dims())
+    flat = np.zeros(lay["total"], np.float32)
+    flat[:len(table)] = table
+    for off, w in zip(lay["w_offsets"], ws):
+        flat[off:off + w.size] = w.ravel()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    P = t(flat)
+    G, M, V = torch.zeros_like(P), torch.zeros_like(P), torch.zeros_like(P)
+    kf = W.c1_keyframes()
+    m = nsl.Mapper(1, 32, 32, 1, device=dev)
+    m.upsert([0], t(kf.rgb), t(kf.pose.reshape(1, 12)), t(kf.intr), t(kf.depth), t(kf.depth_var))
+    ids = t(W.c1_pixels().view(np.int32))
+    cfg = nsl.step_config(W.C1_SAMPLER, zero_grads=False, do_adam=True, lr=W.ADAM_LR, betas=W.ADAM_BETAS,
+                          eps=W.ADAM_EPS)
+    wsb = torch.empty(nsl.step_workspace_bytes(f, cfg, 1024), dtype=torch.uint8, device=dev)
+    loss = torch.zeros(3, device=dev)
+    n_step = [0]
+
+    def train():
+        n_step[0] += 1
+        cfg.adam_step = n_step[0]
+        nsl.train_step(m, f, P, G, M, V, cfg, ids, wsb, loss)
+
+    for _ in range(300):                            # the trained field that is served
+        train()
+    torch.cuda.synchronize()
+    rcfg = nsl.render_config(0.5, 2.0 / 32, 32, 1e-4)
+    capacity = render_capacity(nsl, torch, dev, W, f, P, rcfg)
+    reqs = W.serve_requests(n_req, seed=7, rate=200.0)
+    for q in reqs:
+        q["pose"] = q["pose"].reshape(12)
+    train_samples = 1024 * 32
+    _, done, st = serve.serve(f, rcfg, dev, reqs, P, train_fn=train, train_period=5e-3, warmup=warmup)
+    st["train_samples_per_s"] = st["train_steps"] * train_samples / st["wall_s"]
+    st["render_rays_per_s_idle"] = capacity
+    st["workload"] = ("Poisson 200 req/s, sizes 160x120/320x240/640x480/1280x960, 32 samples on [0.5, 2.5], "
+                      "stop at T < 1e-4, tiny field trained 300 steps, training 1 step / 5 ms")
+    return st
+
+
+def render_capacity(nsl, torch, dev, W, f, P, rcfg, reps=20):
+    """Rays/s of nsl_render_batch alone: one 1280x960 request per launch
+    (19 200 tiles), nothing else on the GPU."""
+    from paper_2210_13641_amd import serve
+    Wd, H = 1280, 960
+    prep = nsl.prepare(f, P)
+    pose = W.look_at_pose((1.5, 0.0, 0.0)).astype(np.float32).reshape(12)
+    intr = np.array([0.9375 * Wd, 0.9375 * Wd, Wd / 2.0, H / 2.0], np.float32)
+    out = [torch.empty(H * Wd, 3, device=dev)] + [torch.empty(H * Wd, device=dev) for _ in range(3)]
+    rq = nsl.records_to_device([nsl.render_request(P, prep, pose, intr, H, Wd, *out)], nsl.RenderRequest, dev)
+    n_tiles = -(-H * Wd // nsl.RENDER_TILE)
+    tl = nsl.bytes_to_device(serve.tile_run(0, 0, n_tiles, H * Wd).tobytes(), dev)
+    for _ in range(3):
+        nsl.render_batch(f, rq, 1, tl, n_tiles, rcfg)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        nsl.render_batch(f, rq, 1, tl, n_tiles, rcfg)
+    b.record()
+    b.synchronize()
+    return reps * H * Wd / (a.elapsed_time(b) * 1e-3)
+
+
+def cpu_baseline(spec, sampler, kf, occ, table, ws, n_cand):
     """The FP64 oracle as it stands, on the first n_cand candidates of the
-    first candidate set (one step, FP32-rounded parameters)."""
+    first candidate set (one fwd+bwd step, FP32-rounded parameters)."""
     import workloads as W
     from oracle import step as ostep
     try:
         from threadpoolctl import threadpool_info
-        threads = max((i.get("num_threads") or 1) for i in threadpool_info()) if threadpool_info() else 1
-    except Exception:                     # threadpoolctl missing: numpy's default
+        info = threadpool_info()
+        threads = max((i.get("num_threads") or 1) for i in info) if info else 1
+    except Exception:
         threads = os.cpu_count()
     t64 = np.asarray(table, np.float32).astype(np.float64)
     w64 = [np.asarray(w, np.float32).astype(np.float64) for w in ws]

@@ -435,9 +435,9 @@ __global__ __launch_bounds__(256) void render_kernel(LevelInfo lv, Aabb box, con
     float carry = 0.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f, A = 0.0f;
     float wt[kRenderMaxTiles], tt[kRenderMaxTiles];
 #pragma unroll
+    for (int ti = 0; ti < kRenderMaxTiles; ++ti) wt[ti] = tt[ti] = 0.0f;  // tiles after an early exit stay 0
+#pragma unroll
     for (int ti = 0; ti < kRenderMaxTiles; ++ti) {
-      wt[ti] = 0.0f;
-      tt[ti] = 0.0f;
       if (ti >= ntiles) continue;
       const int j = ti * 16 + jc;
       const bool valid = j < rp.n_samples;

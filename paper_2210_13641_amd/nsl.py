@@ -405,8 +405,15 @@ def records_to_device(records, ctype, device):
     """Pack ctypes records into a device byte tensor."""
     n = len(records)
     buf = (ctype * max(n, 1))(*records)
-    raw = torch.frombuffer(bytearray(bytes(buf)), dtype=torch.uint8)
-    return raw.to(device, non_blocking=False)
+    return bytes_to_device(bytes(buf), device)
+
+
+def bytes_to_device(data, device):
+    """Copy host bytes to a new device byte tensor through pinned memory,
+    asynchronously on the current stream (the pinned block is recycled only
+    after the copy has completed)."""
+    raw = torch.frombuffer(bytearray(data), dtype=torch.uint8).pin_memory()
+    return raw.to(device, non_blocking=True)
 
 
 def render_batch(field: Field, requests_dev, n_req, tiles_dev, n_tiles, cfg: RenderConfig):

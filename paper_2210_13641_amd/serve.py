@@ -23,11 +23,23 @@ import collections
 import dataclasses
 import time
 
+import numpy as np
 import torch
 
 from . import nsl
 
 OUT_BYTES_PER_PIXEL = 6 * 4       # rgb, depth, var, opacity (float32)
+
+
+def tile_run(slot, first_pixel, n_tiles, n_pixels):
+    """nsl_render_tile records [n_tiles, 3] (int32) of consecutive 64-pixel
+    tiles of one request starting at first_pixel."""
+    start = first_pixel + nsl.RENDER_TILE * np.arange(n_tiles, dtype=np.int64)
+    out = np.empty((n_tiles, 3), np.int32)
+    out[:, 0] = slot
+    out[:, 1] = start
+    out[:, 2] = np.minimum(nsl.RENDER_TILE, n_pixels - start)
+    return out
 
 
 @dataclasses.dataclass
@@ -131,24 +143,34 @@ class RenderServer:
     def _launch(self):
         if not self.active:
             return
-        reqs, tiles = [], []
+        # Each active request gets a contiguous run of its next tiles; the
+        # launch budget is shared evenly (round robin over requests).
+        reqs, runs = [], []
         budget = self.tiles_per_launch
-        # round-robin over active requests, one tile each per pass
-        while budget > 0 and any(r.next_pixel < r.n_pixels for r in self.active):
-            for r in self.active:
-                if budget == 0 or r.next_pixel >= r.n_pixels:
+        left = [r for r in self.active if r.next_pixel < r.n_pixels]
+        while budget > 0 and left:
+            share = max(1, budget // len(left))
+            nxt = []
+            for r in left:
+                if budget == 0:
+                    nxt.append(r)
                     continue
+                remaining = -(-(r.n_pixels - r.next_pixel) // nsl.RENDER_TILE)
+                k = min(share, remaining, budget)
                 if r.slot < 0:
                     r.slot = len(reqs)
                     reqs.append(nsl.render_request(r.snap.params, r.snap.prepared, r.pose, r.intr, r.H, r.W,
                                                    *r.out))
-                k = min(nsl.RENDER_TILE, r.n_pixels - r.next_pixel)
-                tiles.append(nsl.RenderTile(r.slot, r.next_pixel, k))
-                r.next_pixel += k
-                budget -= 1
+                runs.append((r.slot, r.next_pixel, k, r.n_pixels))
+                r.next_pixel = min(r.n_pixels, r.next_pixel + k * nsl.RENDER_TILE)
+                budget -= k
+                if r.next_pixel < r.n_pixels:
+                    nxt.append(r)
+            left = nxt
+        tiles = np.concatenate([tile_run(*x) for x in runs])
         with torch.cuda.stream(self.stream):
             rq = nsl.records_to_device(reqs, nsl.RenderRequest, self.device)
-            tl = nsl.records_to_device(tiles, nsl.RenderTile, self.device)
+            tl = nsl.bytes_to_device(tiles.tobytes(), self.device)
             nsl.render_batch(self.field, rq, len(reqs), tl, len(tiles), self.cfg)
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(self.stream)
