@@ -88,7 +88,8 @@ int nsl_version(void);
  * Supported shapes (compiled kernels): feat_per_level 2, geo_dim 16 and
  *   levels 4,  density_hidden 32, colour_hidden {32},     sh_bands 3, or
  *   levels 16, density_hidden 64, colour_hidden {64, 64}, sh_bands 4.
- * Anything else returns NSL_E_INVALID from nsl_field_create.
+ * Anything else returns NSL_E_INVALID from nsl_field_create, as does a
+ * table of more than 2^25 entries (all levels together).
  * ------------------------------------------------------------------------ */
 typedef struct nsl_field_config {
   int32_t levels;
@@ -180,7 +181,8 @@ int nsl_occupancy_set(nsl_mapper* m, const uint32_t* bits, int src_on_host,
  * with midpoint bins this is dt for every interior pair, and empty space
  * skipped by the grid has sigma = 0).  Candidates are kept in order while
  * their inclusive sample prefix is <= max_samples; kept candidates with at
- * least one sample are the R rays of the batch.
+ * least one sample are the R rays of the batch.  max_samples * 8 * levels
+ * must stay below 2^32 (the workspace query returns 0 otherwise).
  *
  * Loss (Eq. 3, 4, 7), mean over the R rays:
  *   L_rgb = mean_r sum_ch (I*_r - I_r)^2
@@ -273,17 +275,20 @@ int nsl_march(nsl_mapper* m, const nsl_field* f, const nsl_step_config* cfg,
 
 /* Field at S normalised positions xn [S,3] in [0,1]^3 with unit view
  * directions dirs [S,3]: sigma [S], rgb [S,3].  Workspace:
- * nsl_field_workspace_bytes (holds the weights laid out for the MFMA
- * operands, and the per-block weight gradients of nsl_field_bwd). */
-size_t nsl_field_workspace_bytes(const nsl_field* f);
+ * nsl_field_workspace_bytes(f, S) (the weights laid out for the MFMA
+ * operands, the per-block weight gradients and the table-gradient records of
+ * the backward; one size serves both precisions and any count up to S).
+ * Returns 0 when S * 8 * levels reaches 2^32. */
+size_t nsl_field_workspace_bytes(const nsl_field* f, int S);
 int nsl_field_fwd(const nsl_field* f, const float* params, const float* xn, const float* dirs,
                   int S, float* sigma, float* rgb, void* workspace, size_t workspace_bytes,
                   hipStream_t stream);
 
 /* Adjoint of nsl_field_fwd: accumulates (+=) dL/dparams into grads given
- * dsigma [S] and drgb [S,3].  The table part is scattered with atomics
- * (summation order unspecified); the weight part is reduced in a fixed
- * order. */
+ * dsigma [S] and drgb [S,3].  The table part (the trilinear weights times
+ * dL/de, summed over samples and corners) is written as records, grouped by
+ * table bin and reduced in LDS (summation order unspecified); the weight
+ * part is reduced in a fixed order. */
 int nsl_field_bwd(const nsl_field* f, const float* params, const float* xn, const float* dirs,
                   int S, const float* dsigma, const float* drgb, float* grads, void* workspace,
                   size_t workspace_bytes, hipStream_t stream);

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnsl.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "field.hip", "march.hip", "composite.hip", "misc.hip", "cov.hip", "field_mixed.hip"]
+SOURCES = ["api.cpp", "field.hip", "march.hip", "composite.hip", "misc.hip", "cov.hip", "field_mixed.hip",
+           "scatter.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [

@@ -57,6 +57,29 @@ struct Carver {
 
 constexpr int kBwdBlocks = 256;  // persistent backward grid (one block per CU)
 
+int bwd_regions(bool mixed) { return kBwdBlocks * (mixed ? kMixedBwdWaves : kFieldBwdWaves); }
+
+// Table-gradient records of a backward pass over at most max_samples samples.
+RecordBuffers carve_records(Carver& cv, const BinPlan& p) {
+  RecordBuffers r{};
+  const size_t n = (size_t)p.cap * p.nsub * p.nregions;
+  r.key = cv.take<uint32_t>(n);
+  r.val = cv.take<float2>(n);
+  r.count = cv.take<uint32_t>((size_t)p.nregions * p.nsub);
+  r.cap = p.cap;
+  r.nsub = p.nsub;
+  r.hist = cv.take<uint32_t>((size_t)p.nregions * p.nbins);
+  r.off = cv.take<uint32_t>((size_t)p.nregions * p.nbins);
+  r.bin_total = cv.take<uint32_t>((size_t)p.nbins);
+  r.bin_start = cv.take<uint32_t>((size_t)p.nbins + 1);
+  r.chunk_start = cv.take<uint32_t>((size_t)p.nbins + 1);
+  r.sorted = cv.take<uint3>(n);
+  return r;
+}
+
+// Records are addressed with 32-bit positions.
+bool records_fit(int levels, int64_t max_samples) { return max_samples * 8 * levels < ((int64_t)1 << 32) - 4096; }
+
 struct Profiler {
   bool on = false;
   hipEvent_t ev[NSL_PHASES + 1] = {};
@@ -143,7 +166,7 @@ int nsl_field_layout(const nsl_field_config* c, nsl_param_layout* out) {
     w = al(w + (int64_t)dims[j].first * dims[j].second);
   }
   out->total_floats = w;
-  if (off > 0xFFFFFFFFll) return fail(NSL_E_INVALID, "table too large");
+  if (off > (int64_t)kMaxBins * kBinEntries) return fail(NSL_E_INVALID, "table too large (more than 2^25 entries)");
   return NSL_OK;
 }
 
@@ -299,7 +322,14 @@ struct StepBuffers {
   float* dsigma;
   float* drgb;
   float* partial;
+  float* loss_parts;
+  RecordBuffers rec;
+  BinPlan plan;
 };
+
+BinPlan plan_of(const nsl_field* f, bool mixed, int64_t max_samples) {
+  return bin_plan((uint32_t)(f->lay.table_floats / 2), f->cfg.levels, bwd_regions(mixed), max_samples);
+}
 
 size_t step_carve(const nsl_field* f, int n, int max_samples, bool mixed, void* base, StepBuffers* b) {
   Carver cv(base);
@@ -319,16 +349,21 @@ size_t step_carve(const nsl_field* f, int n, int max_samples, bool mixed, void* 
   s.dsigma = cv.take<float>((size_t)max_samples);
   s.drgb = cv.take<float>(3 * (size_t)max_samples);
   s.partial = cv.take<float>((size_t)kBwdBlocks * field_nweights(f->shape));
+  s.loss_parts = cv.take<float>(2 * (size_t)n);
   s.shadow = mixed ? cv.take<char>(mixed_shadow_bytes(f->shape, f->lay.table_floats)) : nullptr;
+  s.plan = plan_of(f, mixed, max_samples);
+  s.rec = carve_records(cv, s.plan);
   if (b) *b = s;
   return cv.used;
 }
 
-int check_step_cfg(const nsl_step_config* c) {
+int check_step_cfg(const nsl_step_config* c, const nsl_field* f) {
   if (!c) return fail(NSL_E_INVALID, "null step config");
   if (c->sampler != NSL_SAMPLER_UNIFORM && c->sampler != NSL_SAMPLER_OCCUPANCY) return fail(NSL_E_INVALID, "bad sampler");
   if (!(c->dt > 0.0f) || !(c->t_far >= c->t_near) || !(c->t_near >= 0.0f)) return fail(NSL_E_INVALID, "bad t range or dt");
   if (c->max_samples < 1 || c->max_samples > (1 << 26)) return fail(NSL_E_INVALID, "max_samples must be in [1, 2^26]");
+  if (f && !records_fit(f->cfg.levels, c->max_samples))
+    return fail(NSL_E_INVALID, "max_samples * 8 * levels must stay below 2^32");
   if (c->sampler == NSL_SAMPLER_UNIFORM && (c->n_uniform < 1 || c->n_uniform > 4096))
     return fail(NSL_E_INVALID, "n_uniform must be in [1, 4096]");
   if (c->sampler == NSL_SAMPLER_OCCUPANCY && (c->max_per_ray < 1 || c->max_per_ray > 4096))
@@ -367,7 +402,7 @@ int check_ids_range(const nsl_mapper* m, int n) {
 }  // namespace
 
 size_t nsl_step_workspace_bytes(const nsl_field* f, const nsl_step_config* c, int n) {
-  if (!f || !c || n < 0) return 0;
+  if (!f || !c || n < 0 || c->max_samples < 1 || !records_fit(f->cfg.levels, c->max_samples)) return 0;
   return step_carve(f, n, c->max_samples, c->precision == NSL_PRECISION_MIXED, nullptr, nullptr);
 }
 
@@ -384,7 +419,7 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
                    const nsl_step_config* c, const uint32_t* ids, int n, void* ws, size_t ws_bytes,
                    float* loss_out, nsl_step_stats* stats_out, float* ray_out, hipStream_t st) {
   if (!m || !f || !params || !grads || !ids || !ws || !loss_out) return fail(NSL_E_INVALID, "null argument");
-  int rc = check_step_cfg(c);
+  int rc = check_step_cfg(c, f);
   if (rc) return rc;
   if ((rc = check_ids_range(m, n))) return rc;
   if (c->do_adam && (!adam_m || !adam_v)) return fail(NSL_E_INVALID, "adam needs m and v");
@@ -424,17 +459,18 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   LossIO lo{};
   lo.target = b.rb.target; lo.prec = b.rb.prec; lo.rays = b.rb.rays; lo.stats = b.rb.stats;
   lo.lambda_d = c->lambda_d; lo.loss_scale = c->loss_scale; lo.scale_dev = c->scale_state;
-  lo.loss = loss_out; lo.ray_out = ray_out;
+  lo.loss = loss_out; lo.parts = b.loss_parts; lo.ray_out = ray_out;
   HIP_TRY(composite_loss_backward(io, lo, b.dsigma, b.drgb, st), "composite");
   HIP_TRY(mark(4), "profile event");
 
   if (mixed)
-    HIP_TRY(mixed_backward(f->shape, f->lv, b.shadow, src, kBwdBlocks, b.dsigma, b.drgb, grads, b.partial, f->wo,
+    HIP_TRY(mixed_backward(f->shape, f->lv, b.shadow, src, kBwdBlocks, b.dsigma, b.drgb, b.rec, b.partial, f->wo,
                            grads, st),
             "field backward");
   else
-    HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, b.dsigma, b.drgb, grads, b.partial, f->wo, grads, st),
+    HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, b.dsigma, b.drgb, b.rec, b.partial, f->wo, grads, st),
             "field backward");
+  HIP_TRY(bin_scatter(b.plan, b.rec, grads, st), "table gradient");
   if (c->scale_state) HIP_TRY(scale_check(grads, total, c->scale_state, st), "loss scale");
   HIP_TRY(mark(5), "profile event");
   if (c->do_adam)
@@ -459,7 +495,7 @@ int nsl_march(nsl_mapper* m, const nsl_field* f, const nsl_step_config* c, const
               size_t ws_bytes, uint32_t* counts, uint32_t* offsets, float* t, uint32_t* ray,
               nsl_step_stats* stats_out, hipStream_t st) {
   if (!m || !f || !ids || !ws || !counts || !offsets || !t || !ray) return fail(NSL_E_INVALID, "null argument");
-  int rc = check_step_cfg(c);
+  int rc = check_step_cfg(c, f);
   if (rc) return rc;
   if ((rc = check_ids_range(m, n))) return rc;
   if (ws_bytes < nsl_step_workspace_bytes(f, c, n)) return fail(NSL_E_WORKSPACE, "march workspace too small");
@@ -497,22 +533,44 @@ int nsl_profile_read(double* ms, int* n_steps) {
   return NSL_OK;
 }
 
-size_t nsl_field_workspace_bytes(const nsl_field* f) {
-  if (!f) return 0;
-  Carver cv(nullptr);
-  cv.take<float>(field_prep_floats(f->shape));
-  cv.take<float>((size_t)kBwdBlocks * field_nweights(f->shape));
-  return cv.used;
+// Field-level workspace: MFMA operands, per-block weight-gradient partials and
+// the table-gradient records of S samples (sized for either precision).
+struct FieldWs {
+  float* wprep;
+  float* partial;
+  RecordBuffers rec;
+  BinPlan plan;
+};
+
+static size_t field_carve(const nsl_field* f, int S, bool mixed, void* base, FieldWs* w) {
+  size_t bytes = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool m = pass == 1;
+    Carver cv(m == mixed ? base : nullptr);
+    FieldWs x{};
+    x.wprep = cv.take<float>(field_prep_floats(f->shape));
+    x.partial = cv.take<float>((size_t)kBwdBlocks * field_nweights(f->shape));
+    x.plan = plan_of(f, m, S);
+    x.rec = carve_records(cv, x.plan);
+    if (m == mixed && w) *w = x;
+    bytes = cv.used > bytes ? cv.used : bytes;
+  }
+  return bytes;
+}
+
+size_t nsl_field_workspace_bytes(const nsl_field* f, int S) {
+  if (!f || S < 0 || !records_fit(f->cfg.levels, S)) return 0;
+  return field_carve(f, S, false, nullptr, nullptr);
 }
 
 static int field_common(const nsl_field* f, const float* params, const float* xn, const float* dirs, int S,
-                        void* ws, size_t ws_bytes, float** wprep, float** partial, SampleSrc& src) {
-  if (!f || !params || !xn || !dirs || !ws) return fail(NSL_E_INVALID, "null argument");
+                        void* ws, size_t ws_bytes, bool mixed, FieldWs& w, SampleSrc& src) {
+  if (!f || !xn || !dirs || !ws) return fail(NSL_E_INVALID, "null argument");
+  if (!mixed && !params) return fail(NSL_E_INVALID, "null params");
   if (S < 0) return fail(NSL_E_INVALID, "negative sample count");
-  if (ws_bytes < nsl_field_workspace_bytes(f)) return fail(NSL_E_WORKSPACE, "field workspace too small");
-  Carver cv(ws);
-  *wprep = cv.take<float>(field_prep_floats(f->shape));
-  *partial = cv.take<float>((size_t)kBwdBlocks * field_nweights(f->shape));
+  if (!records_fit(f->cfg.levels, S)) return fail(NSL_E_INVALID, "S * 8 * levels must stay below 2^32");
+  if (ws_bytes < nsl_field_workspace_bytes(f, S)) return fail(NSL_E_WORKSPACE, "field workspace too small");
+  field_carve(f, S, mixed, ws, &w);
   src = SampleSrc{};
   src.xn = xn; src.dir = dirs; src.box = f->box; src.n = S; src.n_dev = nullptr;
   return NSL_OK;
@@ -521,12 +579,12 @@ static int field_common(const nsl_field* f, const float* params, const float* xn
 int nsl_field_fwd(const nsl_field* f, const float* params, const float* xn, const float* dirs, int S, float* sigma,
                   float* rgb, void* ws, size_t ws_bytes, hipStream_t st) {
   if (!sigma || !rgb) return fail(NSL_E_INVALID, "null output");
-  float *wprep, *partial;
+  FieldWs w;
   SampleSrc src;
-  int rc = field_common(f, params, xn, dirs, S, ws, ws_bytes, &wprep, &partial, src);
+  int rc = field_common(f, params, xn, dirs, S, ws, ws_bytes, false, w, src);
   if (rc) return rc;
-  HIP_TRY(field_prep(f->shape, params, f->wo, wprep, st), "prep weights");
-  FieldArgs fa{params, wprep, f->lv};
+  HIP_TRY(field_prep(f->shape, params, f->wo, w.wprep, st), "prep weights");
+  FieldArgs fa{params, w.wprep, f->lv};
   HIP_TRY(field_forward(f->shape, fa, src, S, sigma, rgb, st), "field forward");
   return NSL_OK;
 }
@@ -534,14 +592,15 @@ int nsl_field_fwd(const nsl_field* f, const float* params, const float* xn, cons
 int nsl_field_bwd(const nsl_field* f, const float* params, const float* xn, const float* dirs, int S,
                   const float* dsigma, const float* drgb, float* grads, void* ws, size_t ws_bytes, hipStream_t st) {
   if (!dsigma || !drgb || !grads) return fail(NSL_E_INVALID, "null argument");
-  float *wprep, *partial;
+  FieldWs w;
   SampleSrc src;
-  int rc = field_common(f, params, xn, dirs, S, ws, ws_bytes, &wprep, &partial, src);
+  int rc = field_common(f, params, xn, dirs, S, ws, ws_bytes, false, w, src);
   if (rc) return rc;
-  HIP_TRY(field_prep(f->shape, params, f->wo, wprep, st), "prep weights");
-  FieldArgs fa{params, wprep, f->lv};
-  HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, dsigma, drgb, grads, partial, f->wo, grads, st),
+  HIP_TRY(field_prep(f->shape, params, f->wo, w.wprep, st), "prep weights");
+  FieldArgs fa{params, w.wprep, f->lv};
+  HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, dsigma, drgb, w.rec, w.partial, f->wo, grads, st),
           "field backward");
+  HIP_TRY(bin_scatter(w.plan, w.rec, grads, st), "table gradient");
   return NSL_OK;
 }
 
@@ -568,16 +627,14 @@ int nsl_field_fwd_mixed(const nsl_field* f, const void* shadow, const float* xn,
 int nsl_field_bwd_mixed(const nsl_field* f, const void* shadow, const float* xn, const float* dirs, int S,
                         const float* dsigma, const float* drgb, float* grads, void* ws, size_t ws_bytes,
                         hipStream_t st) {
-  if (!f || !shadow || !xn || !dirs || !dsigma || !drgb || !grads || !ws) return fail(NSL_E_INVALID, "null argument");
-  if (S < 0) return fail(NSL_E_INVALID, "negative sample count");
-  if (ws_bytes < nsl_field_workspace_bytes(f)) return fail(NSL_E_WORKSPACE, "field workspace too small");
-  Carver cv(ws);
-  cv.take<float>(field_prep_floats(f->shape));
-  float* partial = cv.take<float>((size_t)kBwdBlocks * field_nweights(f->shape));
-  SampleSrc src{};
-  src.xn = xn; src.dir = dirs; src.box = f->box; src.n = S;
-  HIP_TRY(mixed_backward(f->shape, f->lv, shadow, src, kBwdBlocks, dsigma, drgb, grads, partial, f->wo, grads, st),
+  if (!f || !shadow || !dsigma || !drgb || !grads) return fail(NSL_E_INVALID, "null argument");
+  FieldWs w;
+  SampleSrc src;
+  int rc = field_common(f, nullptr, xn, dirs, S, ws, ws_bytes, true, w, src);
+  if (rc) return rc;
+  HIP_TRY(mixed_backward(f->shape, f->lv, shadow, src, kBwdBlocks, dsigma, drgb, w.rec, w.partial, f->wo, grads, st),
           "field backward (mixed)");
+  HIP_TRY(bin_scatter(w.plan, w.rec, grads, st), "table gradient");
   return NSL_OK;
 }
 

@@ -105,6 +105,16 @@ __device__ __forceinline__ float wave_incl_scan(float v) {
   return v;
 }
 
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+  const int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t n = __shfl_up(v, o, kWave);
+    if (l >= o) v += n;
+  }
+  return v;
+}
+
 // DPP row shift towards lower lanes: lane i of each 16-lane row receives the
 // value of lane i+N of the same row (0 when i+N leaves the row).
 template <int N>

@@ -179,9 +179,12 @@ __global__ __launch_bounds__(256) void composite_loss_kernel(CompositeIO io, Los
   uint32_t b, n;
   const bool on = ray_span(io, r, b, n);
   if (!on) {
-    if (lane_id() == 0 && lo.ray_out) {
-      float* o = lo.ray_out + 6 * (size_t)r;
-      o[0] = o[1] = o[2] = o[3] = o[4] = o[5] = 0.0f;
+    if (lane_id() == 0) {
+      lo.parts[2 * r] = lo.parts[2 * r + 1] = 0.0f;
+      if (lo.ray_out) {
+        float* o = lo.ray_out + 6 * (size_t)r;
+        o[0] = o[1] = o[2] = o[3] = o[4] = o[5] = 0.0f;
+      }
     }
     return;
   }
@@ -197,9 +200,8 @@ __global__ __launch_bounds__(256) void composite_loss_kernel(CompositeIO io, Los
   const float gC[3] = {k * e0, k * e1, k * e2};
   const float gD = k * lo.lambda_d * pi * ed;
   if (lane_id() == 0) {
-    atomicAdd(lo.loss + 0, (l_rgb + lo.lambda_d * l_d) / Rf);
-    atomicAdd(lo.loss + 1, l_rgb / Rf);
-    atomicAdd(lo.loss + 2, l_d / Rf);
+    lo.parts[2 * r] = l_rgb / Rf;
+    lo.parts[2 * r + 1] = l_d / Rf;
     if (lo.ray_out) {
       const float sc = lo.rays[2 * r].w;
       float* o = lo.ray_out + 6 * (size_t)r;
@@ -208,6 +210,34 @@ __global__ __launch_bounds__(256) void composite_loss_kernel(CompositeIO io, Los
     }
   }
   ray_backward(io, b, n, s, gC, gD, 0.0f, 0.0f, g_sigma, g_rgb_s);
+}
+
+// loss = (L_rgb + lambda_d L_D, L_rgb, L_D): sums of the per-ray parts in a
+// fixed order (strided per-thread sums, then a tree in LDS).
+__global__ __launch_bounds__(1024) void loss_reduce_kernel(const float* __restrict__ parts, int R, float lambda_d,
+                                                           float* __restrict__ loss) {
+  __shared__ float s0[1024], s1[1024];
+  const int t = threadIdx.x;
+  float a = 0.0f, b = 0.0f;
+  for (int r = t; r < R; r += 1024) {
+    a += parts[2 * r];
+    b += parts[2 * r + 1];
+  }
+  s0[t] = a;
+  s1[t] = b;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (t < o) {
+      s0[t] += s0[t + o];
+      s1[t] += s1[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    loss[0] = s0[0] + lambda_d * s1[0];
+    loss[1] = s0[0];
+    loss[2] = s1[0];
+  }
 }
 
 dim3 grid_for(int R) { return dim3((R + kWavesPerBlock - 1) / kWavesPerBlock); }
@@ -230,8 +260,10 @@ hipError_t composite_backward(const CompositeIO& io, const float* g_rgb, const f
 
 hipError_t composite_loss_backward(const CompositeIO& io, const LossIO& lo, float* g_sigma,
                                    float* g_rgb_s, hipStream_t st) {
-  if (io.R > 0)
+  if (io.R > 0) {
     hipLaunchKernelGGL(composite_loss_kernel, grid_for(io.R), dim3(256), 0, st, io, lo, g_sigma, g_rgb_s);
+    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(1024), 0, st, lo.parts, io.R, lo.lambda_d, lo.loss);
+  }
   return hipGetLastError();
 }
 

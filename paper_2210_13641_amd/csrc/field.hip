@@ -160,11 +160,11 @@ __global__ __launch_bounds__(256) void field_fwd_kernel(FieldArgs a, SampleSrc s
 // Backward
 // ---------------------------------------------------------------------------
 
-// dW[in][out] += sum over the wave's 16 samples of X[in] * dY[out], with X and
-// dY staged [feature][sample] (stride SROW) in this wave's LDS area.
+// acc[in][out] += sum over the wave's 16 samples of X[in] * dY[out], with X
+// and dY staged [feature][sample] (stride SROW) in this wave's LDS area.
 template <class N, int KIN, int KOUT>
-__device__ __forceinline__ void dw_accumulate(const float* Xs, const float* Ys, float* dW, int lane) {
-  constexpr int MI = (KIN + 15) / 16, NJ = (KOUT + 15) / 16;
+__device__ __forceinline__ void dw_accumulate(const float* Xs, const float* Ys, DWAcc<KIN, KOUT>& acc, int lane) {
+  constexpr int MI = DWAcc<KIN, KOUT>::MI, NJ = DWAcc<KIN, KOUT>::NJ;
   const int gk = lane >> 4, i = lane & 15;
   f4 xa[MI], yb[NJ];
 #pragma unroll
@@ -174,19 +174,9 @@ __device__ __forceinline__ void dw_accumulate(const float* Xs, const float* Ys, 
 #pragma unroll
   for (int m = 0; m < MI; ++m)
 #pragma unroll
-    for (int n = 0; n < NJ; ++n) {
-      f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int n = 0; n < NJ; ++n)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) acc = mfma4(xa[m][s], yb[n][s], acc);
-      const int col = 16 * n + i;
-      if (col < KOUT) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * m + 4 * gk + r;
-          if (row < KIN) atomicAdd(dW + row * KOUT + col, acc[r]);
-        }
-      }
-    }
+      for (int s = 0; s < 4; ++s) acc.v[m * NJ + n] = mfma4(xa[m][s], yb[n][s], acc.v[m * NJ + n]);
 }
 
 // Stage a D-layout activation block (tiles of 16 rows) as rows [row0, ...).
@@ -199,15 +189,14 @@ __device__ __forceinline__ void stage_d(float* S, const f4* v, int g, int jc) {
 }
 
 template <class N>
-__global__ __launch_bounds__(256, 1) void field_bwd_kernel(FieldArgs a, SampleSrc src,
+__global__ __launch_bounds__(kFieldBwdWaves * kWave, 1) void field_bwd_kernel(FieldArgs a, SampleSrc src,
                                                            const float* __restrict__ dsigma,
-                                                           const float* __restrict__ drgb,
-                                                           float* __restrict__ grad_table,
+                                                           const float* __restrict__ drgb, RecordBuffers rec,
                                                            float* __restrict__ dw_partial) {
   __shared__ __attribute__((aligned(16))) float Af[N::FWD_FLOATS];
   __shared__ __attribute__((aligned(16))) float Ab[N::BWD_FLOATS];
   __shared__ __attribute__((aligned(16))) float dW[N::NWEIGHTS];
-  __shared__ __attribute__((aligned(16))) float stage_all[4 * N::STAGE_FLOATS];
+  __shared__ __attribute__((aligned(16))) float stage_all[kFieldBwdWaves * N::STAGE_FLOATS];
   load_operands<N>(Af, a.wprep, N::FWD_FLOATS);
   load_operands<N>(Ab, a.wprep + N::FWD_FLOATS, N::BWD_FLOATS);
   for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) dW[i] = 0.0f;
@@ -222,8 +211,22 @@ __global__ __launch_bounds__(256, 1) void field_bwd_kernel(FieldArgs a, SampleSr
   LaneLevels<N> ll;
   lane_levels<N>(a.lv, g, ll);
   constexpr f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  const int region = blockIdx.x * kFieldBwdWaves + wave;
+  uint32_t* rkey = rec.key + (size_t)region * N::LPL * rec.cap;
+  float2* rval = rec.val + (size_t)region * N::LPL * rec.cap;
+  uint32_t cnt[N::LPL];
+#pragma unroll
+  for (int q = 0; q < N::LPL; ++q) cnt[q] = 0;
+  // weight gradients of the wave, summed over its tiles in registers
+  DWAcc<N::ENC, N::HD> dw0;
+  DWAcc<N::HD, 16> dw1;
+  DWAcc<N::CIN, N::HC> dw2;
+  DWAcc<N::HC, N::HC> dw3;  // second colour hidden layer (unused with one)
+  DWAcc<N::HC, 3> dwl;
+  dw0.zero(); dw1.zero(); dw2.zero(); dwl.zero();
+  if constexpr (N::NCH == 2) dw3.zero();
 
-  for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += gridDim.x * 4) {
+  for (int tile = region; tile < ntiles; tile += gridDim.x * kFieldBwdWaves) {
     const int s = tile * 16 + jc;
     const bool valid = s < S;
     float xn[3] = {0.5f, 0.5f, 0.5f}, d[3] = {0.0f, 0.0f, 1.0f};
@@ -267,7 +270,7 @@ __global__ __launch_bounds__(256, 1) void field_bwd_kernel(FieldArgs a, SampleSr
     stage_d<N, N::HC / 16>(Xs, hl, g, jc);
     stage_d<N, 1>(Ys, &dz, g, jc);
     wave_lds_fence();
-    dw_accumulate<N, N::HC, 3>(Xs, Ys, dW + N::woff(N::NW - 1), lane);
+    dw_accumulate<N, N::HC, 3>(Xs, Ys, dwl, lane);
     wave_lds_fence();
 
     f4 dh3[N::HC / 16];
@@ -285,7 +288,7 @@ __global__ __launch_bounds__(256, 1) void field_bwd_kernel(FieldArgs a, SampleSr
       stage_d<N, N::HC / 16>(Xs, act.h3, g, jc);
       stage_d<N, N::HC / 16>(Ys, dhl, g, jc);
       wave_lds_fence();
-      dw_accumulate<N, N::HC, N::HC>(Xs, Ys, dW + N::woff(3), lane);
+      dw_accumulate<N, N::HC, N::HC>(Xs, Ys, dw3, lane);
       wave_lds_fence();
     } else {
 #pragma unroll
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(256, 1) void field_bwd_kernel(FieldArgs a, SampleSr
     for (int r = 0; r < 4; ++r) Xs[(16 + 4 * g + r) * N::SROW + jc] = act.sh[r];
     stage_d<N, N::HC / 16>(Ys, dh3, g, jc);
     wave_lds_fence();
-    dw_accumulate<N, N::CIN, N::HC>(Xs, Ys, dW + N::woff(2), lane);
+    dw_accumulate<N, N::CIN, N::HC>(Xs, Ys, dw2, lane);
     wave_lds_fence();
     // density output: do = dgeo, do_0 += sigma * dsigma
     if (g == 0) dgeo[0] += __expf(act.o[0]) * ds;
@@ -323,7 +326,7 @@ __global__ __launch_bounds__(256, 1) void field_bwd_kernel(FieldArgs a, SampleSr
     stage_d<N, N::HD / 16>(Xs, act.h1, g, jc);
     stage_d<N, 1>(Ys, &dgeo, g, jc);
     wave_lds_fence();
-    dw_accumulate<N, N::HD, 16>(Xs, Ys, dW + N::woff(1), lane);
+    dw_accumulate<N, N::HD, 16>(Xs, Ys, dw1, lane);
     wave_lds_fence();
     // encoding gradient: de = W1 dh1 (rows = this lane group's slots)
     constexpr int MT0 = N::bmt(0);
@@ -347,31 +350,30 @@ __global__ __launch_bounds__(256, 1) void field_bwd_kernel(FieldArgs a, SampleSr
     }
     stage_d<N, N::HD / 16>(Ys, dh1, g, jc);
     wave_lds_fence();
-    dw_accumulate<N, N::ENC, N::HD>(Xs, Ys, dW + N::woff(0), lane);
+    dw_accumulate<N, N::ENC, N::HD>(Xs, Ys, dw0, lane);
     wave_lds_fence();
-    // Scatter into the table gradient.  The 16 lanes of a row hold 16
-    // consecutive samples (mostly along one ray) at the same level, so equal
-    // corners form runs of neighbouring lanes; each run is summed in
-    // registers and issues one 64-bit atomic update of the entry.
 #pragma unroll
     for (int q = 0; q < N::LPL; ++q) {
       const int k0 = 2 * q, k1 = 2 * q + 1;
       const float d0 = valid ? de[k0 >> 2][k0 & 3] : 0.0f;
       const float d1 = valid ? de[k1 >> 2][k1 & 3] : 0.0f;
-      Corner8 c;
-      corners(xn[0], xn[1], xn[2], ll.res[q], ll.dense[q], a.lv.table_mask, ll.off[q], c);
-      float* ptr[8];
-      bool on[8];
-      float v0[8], v1[8];
+      level_records(xn, ll.res[q], ll.dense[q], a.lv.table_mask, ll.off[q], valid, d0, d1, rkey + q * rec.cap,
+                    rval + q * rec.cap, cnt[q]);
+    }
+  }
+  if (lane == 0) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        v0[k] = c.w[k] * d0;
-        v1[k] = c.w[k] * d1;
-        const uint32_t key = valid ? c.idx[k] : 0xFFFFFFFFu;
-        on[k] = row_run_sums(key, v0[k], v1[k]) && valid;
-        ptr[k] = grad_table + 2 * (size_t)c.idx[k];
-      }
-      atomic_add_pairs<8>(ptr, on, v0, v1);
+    for (int q = 0; q < N::LPL; ++q) rec.count[region * N::LPL + q] = cnt[q];
+  }
+  // workgroup sum of the weight gradients: waves add in turn (no atomics)
+  for (int w = 0; w < kFieldBwdWaves; ++w) {
+    __syncthreads();
+    if (wave == w) {
+      dw0.flush(dW + N::woff(0), lane);
+      dw1.flush(dW + N::woff(1), lane);
+      dw2.flush(dW + N::woff(2), lane);
+      if constexpr (N::NCH == 2) dw3.flush(dW + N::woff(3), lane);
+      dwl.flush(dW + N::woff(N::NW - 1), lane);
     }
   }
   __syncthreads();
@@ -379,18 +381,6 @@ __global__ __launch_bounds__(256, 1) void field_bwd_kernel(FieldArgs a, SampleSr
   for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) out[i] = dW[i];
 }
 
-// grads[w] += sum over blocks of the per-block weight gradients.
-template <class N>
-__global__ void dw_reduce_kernel(const float* __restrict__ partial, int nblocks, WOffsets wo,
-                                 float* __restrict__ grads) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N::NWEIGHTS) return;
-  float acc = 0.0f;
-  for (int b = 0; b < nblocks; ++b) acc += partial[(size_t)b * N::NWEIGHTS + i];
-  int j = 0;
-  while (j + 1 < N::NW && i >= N::woff(j + 1)) ++j;
-  grads[wo.off[j] + (i - N::woff(j))] += acc;
-}
 
 
 // ---------------------------------------------------------------------------
@@ -509,15 +499,13 @@ static hipError_t launch_fwd(const FieldArgs& a, const SampleSrc& src, int max_s
 
 template <class N>
 static hipError_t launch_bwd(const FieldArgs& a, const SampleSrc& src, int nblocks,
-                             const float* dsigma, const float* drgb, float* grad_table,
+                             const float* dsigma, const float* drgb, const RecordBuffers& rec,
                              float* partial, const WOffsets& wo, float* grads, hipStream_t st) {
-  hipLaunchKernelGGL(field_bwd_kernel<N>, dim3(nblocks), dim3(256), 0, st, a, src, dsigma, drgb,
-                     grad_table, partial);
+  hipLaunchKernelGGL(field_bwd_kernel<N>, dim3(nblocks), dim3(kFieldBwdWaves * kWave), 0, st, a, src, dsigma, drgb,
+                     rec, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(dw_reduce_kernel<N>, dim3((N::NWEIGHTS + 255) / 256), dim3(256), 0, st,
-                     partial, nblocks, wo, grads);
-  return hipGetLastError();
+  return launch_dw_reduce<N>(partial, nblocks, wo, grads, st);
 }
 
 template <class N>
@@ -557,11 +545,11 @@ hipError_t field_forward(int shape, const FieldArgs& a, const SampleSrc& src, in
 }
 
 hipError_t field_backward(int shape, const FieldArgs& a, const SampleSrc& src, int nblocks,
-                          const float* dsigma, const float* drgb, float* grad_table,
+                          const float* dsigma, const float* drgb, const RecordBuffers& rec,
                           float* partial, const WOffsets& wo, float* grads, hipStream_t st) {
   return shape == kShapeTiny
-             ? launch_bwd<NetTiny>(a, src, nblocks, dsigma, drgb, grad_table, partial, wo, grads, st)
-             : launch_bwd<NetFull>(a, src, nblocks, dsigma, drgb, grad_table, partial, wo, grads, st);
+             ? launch_bwd<NetTiny>(a, src, nblocks, dsigma, drgb, rec, partial, wo, grads, st)
+             : launch_bwd<NetFull>(a, src, nblocks, dsigma, drgb, rec, partial, wo, grads, st);
 }
 
 }  // namespace nsl

@@ -159,6 +159,105 @@ __device__ __forceinline__ float row_sum(float v) {
   return v;
 }
 
+// Weight-gradient tile set of one layer (KIN x KOUT, padded to 16 x 16
+// tiles), kept as MFMA accumulators in registers across all tiles a wave
+// processes: tile (m, n), lane (gk, i) holds dW[16m + 4gk + r][16n + i].
+template <int KIN, int KOUT>
+struct DWAcc {
+  static constexpr int MI = (KIN + 15) / 16, NJ = (KOUT + 15) / 16;
+  f4 v[MI * NJ];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int t = 0; t < MI * NJ; ++t) v[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+  // dW (LDS, row-major KIN x KOUT) += this wave's sums; plain read-modify-
+  // write, so the waves of a workgroup call it one at a time.
+  __device__ __forceinline__ void flush(float* dW, int lane) const {
+    const int gk = lane >> 4, i = lane & 15;
+#pragma unroll
+    for (int m = 0; m < MI; ++m)
+#pragma unroll
+      for (int n = 0; n < NJ; ++n) {
+        const int col = 16 * n + i;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * m + 4 * gk + r;
+          if (row < KIN && col < KOUT) dW[row * KOUT + col] += v[m * NJ + n][r];
+        }
+      }
+  }
+};
+
+// Appends the records of the lanes with on[k] to the wave's region,
+// compacted in lane order; cnt (wave-uniform) counts the records so far.
+template <int K>
+__device__ __forceinline__ void emit_records(uint32_t* __restrict__ key, float2* __restrict__ val, uint32_t& cnt,
+                                             const bool on[K], const uint32_t idx[K], const float v0[K],
+                                             const float v1[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const uint64_t m = __ballot(on[k]);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (on[k]) {
+      key[cnt + below] = idx[k];
+      val[cnt + below] = make_float2(v0[k], v1[k]);
+    }
+    cnt += (uint32_t)__popcll(m);
+  }
+}
+
+// Table-gradient records of one level group: the 16 lanes of a row hold 16
+// consecutive samples (mostly along one ray) at the same level, so equal
+// corners form runs of neighbouring lanes; each run is summed in registers
+// and only its first lane writes a record.
+__device__ __forceinline__ void level_records(const float xn[3], int res, bool dense, uint32_t mask, uint32_t off,
+                                              bool valid, float d0, float d1, uint32_t* __restrict__ key,
+                                              float2* __restrict__ val, uint32_t& cnt) {
+  Corner8 c;
+  corners(xn[0], xn[1], xn[2], res, dense, mask, off, c);
+  bool on[8];
+  float v0[8], v1[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    v0[k] = c.w[k] * d0;
+    v1[k] = c.w[k] * d1;
+    const uint32_t rk = valid ? c.idx[k] : 0xFFFFFFFFu;
+    on[k] = row_run_sums(rk, v0[k], v1[k]) && valid;
+  }
+  emit_records<8>(key, val, cnt, on, c.idx, v0, v1);
+}
+
+// grads[weights] += sum over blocks of the per-block weight gradients, in a
+// fixed order: a block takes 64 weights, its four waves sum every fourth
+// partial, and the four sums are added in LDS.
+template <class N>
+__global__ __launch_bounds__(256) void dw_reduce_kernel(const float* __restrict__ partial, int nblocks, WOffsets wo,
+                                                        float* __restrict__ grads) {
+  __shared__ float red[4][64];
+  const int wl = threadIdx.x & 63, pg = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + wl;
+  float acc = 0.0f;
+  if (i < N::NWEIGHTS) {
+#pragma unroll 8
+    for (int b = pg; b < nblocks; b += 4) acc += partial[(size_t)b * N::NWEIGHTS + i];
+  }
+  red[pg][wl] = acc;
+  __syncthreads();
+  if (pg != 0 || i >= N::NWEIGHTS) return;
+  const float sum = (red[0][wl] + red[1][wl]) + (red[2][wl] + red[3][wl]);
+  int j = 0;
+  while (j + 1 < N::NW && i >= N::woff(j + 1)) ++j;
+  grads[wo.off[j] + (i - N::woff(j))] += sum;
+}
+
+template <class N>
+__host__ inline hipError_t launch_dw_reduce(const float* partial, int nblocks, const WOffsets& wo, float* grads,
+                                           hipStream_t st) {
+  hipLaunchKernelGGL(dw_reduce_kernel<N>, dim3((N::NWEIGHTS + 63) / 64), dim3(256), 0, st, partial, nblocks, wo,
+                     grads);
+  return hipGetLastError();
+}
+
 template <class N>
 __device__ __forceinline__ void load_operands(float* dst, const float* __restrict__ src, int n) {
   for (int i = threadIdx.x * 4; i < n; i += blockDim.x * 4)

@@ -231,40 +231,27 @@ __device__ __forceinline__ void stage_bf(__bf16* S, const f4* v, int g, int jc) 
 }
 
 template <class N, int KIN, int KOUT>
-__device__ __forceinline__ void dw_mixed(const __bf16* Xs, const __bf16* Ys, float* dW, int lane) {
-  constexpr int MI = (KIN + 15) / 16, NJ = (KOUT + 15) / 16, SR = Mixed<N>::SROW;
+__device__ __forceinline__ void dw_mixed(const __bf16* Xs, const __bf16* Ys, DWAcc<KIN, KOUT>& acc, int lane) {
+  constexpr int MI = DWAcc<KIN, KOUT>::MI, NJ = DWAcc<KIN, KOUT>::NJ, SR = Mixed<N>::SROW;
   const int gk = lane >> 4, i = lane & 15;
   s4 xa[MI], yb[NJ];
 #pragma unroll
   for (int m = 0; m < MI; ++m) xa[m] = *reinterpret_cast<const s4*>(Xs + (16 * m + i) * SR + 4 * gk);
 #pragma unroll
   for (int n = 0; n < NJ; ++n) yb[n] = *reinterpret_cast<const s4*>(Ys + (16 * n + i) * SR + 4 * gk);
-  constexpr f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int m = 0; m < MI; ++m)
 #pragma unroll
-    for (int n = 0; n < NJ; ++n) {
-      const f4 acc = mfma16(xa[m], yb[n], zero);
-      const int col = 16 * n + i;
-      if (col < KOUT) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 16 * m + 4 * gk + r;
-          if (row < KIN) atomicAdd(dW + row * KOUT + col, acc[r]);
-        }
-      }
-    }
+    for (int n = 0; n < NJ; ++n) acc.v[m * NJ + n] = mfma16(xa[m], yb[n], acc.v[m * NJ + n]);
 }
 
-// Eight waves per workgroup: two per SIMD fit the registers and LDS.
-constexpr int kMixedBwdWaves = 8;
-
+// kMixedBwdWaves waves per workgroup, one per SIMD: the weight-gradient
+// accumulators of a wave live in registers for the whole kernel.
 template <class N>
 __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(LevelInfo lv, const _Float16* __restrict__ table,
                                                            const __bf16* __restrict__ prep, SampleSrc src,
                                                            const float* __restrict__ dsigma,
-                                                           const float* __restrict__ drgb,
-                                                           float* __restrict__ grad_table,
+                                                           const float* __restrict__ drgb, RecordBuffers rec,
                                                            float* __restrict__ dw_partial) {
   using M = Mixed<N>;
   __shared__ __attribute__((aligned(16))) __bf16 Af[M::FWD];
@@ -285,8 +272,21 @@ __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(Le
   LaneLevels<N> ll;
   lane_levels<N>(lv, g, ll);
   constexpr f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  const int region = blockIdx.x * kMixedBwdWaves + wave;
+  uint32_t* rkey = rec.key + (size_t)region * N::LPL * rec.cap;
+  float2* rval = rec.val + (size_t)region * N::LPL * rec.cap;
+  uint32_t cnt[N::LPL];
+#pragma unroll
+  for (int q = 0; q < N::LPL; ++q) cnt[q] = 0;
+  DWAcc<N::ENC, N::HD> dw0;
+  DWAcc<N::HD, 16> dw1;
+  DWAcc<N::CIN, N::HC> dw2;
+  DWAcc<N::HC, N::HC> dw3;  // second colour hidden layer (unused with one)
+  DWAcc<N::HC, 3> dwl;
+  dw0.zero(); dw1.zero(); dw2.zero(); dwl.zero();
+  if constexpr (N::NCH == 2) dw3.zero();
 
-  for (int tile = blockIdx.x * kMixedBwdWaves + wave; tile < ntiles; tile += gridDim.x * kMixedBwdWaves) {
+  for (int tile = region; tile < ntiles; tile += gridDim.x * kMixedBwdWaves) {
     const int s = tile * 16 + jc;
     const bool valid = s < S;
     float xn[3] = {0.5f, 0.5f, 0.5f}, d[3] = {0.0f, 0.0f, 1.0f};
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(Le
     stage_bf<N, N::HC / 16>(Xs, hl, g, jc);
     stage_bf<N, 1>(Ys, &dz, g, jc);
     wave_lds_fence();
-    dw_mixed<N, N::HC, 3>(Xs, Ys, dW + N::woff(N::NW - 1), lane);
+    dw_mixed<N, N::HC, 3>(Xs, Ys, dwl, lane);
     wave_lds_fence();
 
     f4 dh3[N::HC / 16];
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(Le
       stage_bf<N, N::HC / 16>(Xs, act.h3, g, jc);
       stage_bf<N, N::HC / 16>(Ys, dhl, g, jc);
       wave_lds_fence();
-      dw_mixed<N, N::HC, N::HC>(Xs, Ys, dW + N::woff(3), lane);
+      dw_mixed<N, N::HC, N::HC>(Xs, Ys, dw3, lane);
       wave_lds_fence();
     } else {
 #pragma unroll
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(Le
     for (int r = 0; r < 4; ++r) Xs[(16 + 4 * g + r) * M::SROW + jc] = (__bf16)act.sh[r];
     stage_bf<N, N::HC / 16>(Ys, dh3, g, jc);
     wave_lds_fence();
-    dw_mixed<N, N::CIN, N::HC>(Xs, Ys, dW + N::woff(2), lane);
+    dw_mixed<N, N::CIN, N::HC>(Xs, Ys, dw2, lane);
     wave_lds_fence();
     if (g == 0) dgeo[0] += expf(act.o[0]) * ds;
     f4 dh1[N::HD / 16];
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(Le
     stage_bf<N, N::HD / 16>(Xs, act.h1, g, jc);
     stage_bf<N, 1>(Ys, &dgeo, g, jc);
     wave_lds_fence();
-    dw_mixed<N, N::HD, 16>(Xs, Ys, dW + N::woff(1), lane);
+    dw_mixed<N, N::HD, 16>(Xs, Ys, dw1, lane);
     wave_lds_fence();
     constexpr int MT0 = N::bmt(0);
     f4 de[MT0];
@@ -408,27 +408,29 @@ __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(Le
     }
     stage_bf<N, N::HD / 16>(Ys, dh1, g, jc);
     wave_lds_fence();
-    dw_mixed<N, N::ENC, N::HD>(Xs, Ys, dW + N::woff(0), lane);
+    dw_mixed<N, N::ENC, N::HD>(Xs, Ys, dw0, lane);
     wave_lds_fence();
 #pragma unroll
     for (int q = 0; q < N::LPL; ++q) {
       const int k0 = 2 * q, k1 = 2 * q + 1;
       const float d0 = valid ? de[k0 >> 2][k0 & 3] : 0.0f;
       const float d1 = valid ? de[k1 >> 2][k1 & 3] : 0.0f;
-      Corner8 c;
-      corners(xn[0], xn[1], xn[2], ll.res[q], ll.dense[q], lv.table_mask, ll.off[q], c);
-      float* ptr[8];
-      bool on[8];
-      float v0[8], v1[8];
+      level_records(xn, ll.res[q], ll.dense[q], lv.table_mask, ll.off[q], valid, d0, d1, rkey + q * rec.cap,
+                    rval + q * rec.cap, cnt[q]);
+    }
+  }
+  if (lane == 0) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        v0[k] = c.w[k] * d0;
-        v1[k] = c.w[k] * d1;
-        const uint32_t key = valid ? c.idx[k] : 0xFFFFFFFFu;
-        on[k] = row_run_sums(key, v0[k], v1[k]) && valid;
-        ptr[k] = grad_table + 2 * (size_t)c.idx[k];
-      }
-      atomic_add_pairs<8>(ptr, on, v0, v1);
+    for (int q = 0; q < N::LPL; ++q) rec.count[region * N::LPL + q] = cnt[q];
+  }
+  for (int w = 0; w < kMixedBwdWaves; ++w) {
+    __syncthreads();
+    if (wave == w) {
+      dw0.flush(dW + N::woff(0), lane);
+      dw1.flush(dW + N::woff(1), lane);
+      dw2.flush(dW + N::woff(2), lane);
+      if constexpr (N::NCH == 2) dw3.flush(dW + N::woff(3), lane);
+      dwl.flush(dW + N::woff(N::NW - 1), lane);
     }
   }
   __syncthreads();
@@ -436,17 +438,6 @@ __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(Le
   for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) out[i] = dW[i];
 }
 
-template <class N>
-__global__ void mixed_dw_reduce_kernel(const float* __restrict__ partial, int nblocks, WOffsets wo,
-                                       float* __restrict__ grads) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N::NWEIGHTS) return;
-  float acc = 0.0f;
-  for (int b = 0; b < nblocks; ++b) acc += partial[(size_t)b * N::NWEIGHTS + i];
-  int j = 0;
-  while (j + 1 < N::NW && i >= N::woff(j + 1)) ++j;
-  grads[wo.off[j] + (i - N::woff(j))] += acc;
-}
 
 // ---------------------------------------------------------------------------
 // Host launchers.  Shadow buffer: BF16 operands (forward, then backward),
@@ -490,17 +481,15 @@ static hipError_t fwd_impl(const LevelInfo& lv, const void* shadow, const Sample
 
 template <class N>
 static hipError_t bwd_impl(const LevelInfo& lv, const void* shadow, const SampleSrc& src, int nblocks,
-                           const float* dsigma, const float* drgb, float* grad_table, float* partial,
+                           const float* dsigma, const float* drgb, const RecordBuffers& rec, float* partial,
                            const WOffsets& wo, float* grads, hipStream_t st) {
   const __bf16* ops = static_cast<const __bf16*>(shadow);
   const _Float16* t16 = reinterpret_cast<const _Float16*>(static_cast<const char*>(shadow) + mixed_ops_bytes<N>());
   hipLaunchKernelGGL(mixed_bwd_kernel<N>, dim3(nblocks), dim3(kMixedBwdWaves * kWave), 0, st, lv, t16, ops, src,
-                     dsigma, drgb, grad_table, partial);
+                     dsigma, drgb, rec, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(mixed_dw_reduce_kernel<N>, dim3((N::NWEIGHTS + 255) / 256), dim3(256), 0, st, partial, nblocks,
-                     wo, grads);
-  return hipGetLastError();
+  return launch_dw_reduce<N>(partial, nblocks, wo, grads, st);
 }
 
 hipError_t mixed_prepare(int shape, const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
@@ -516,11 +505,11 @@ hipError_t mixed_forward(int shape, const LevelInfo& lv, const void* shadow, con
 }
 
 hipError_t mixed_backward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int nblocks,
-                          const float* dsigma, const float* drgb, float* grad_table, float* partial,
+                          const float* dsigma, const float* drgb, const RecordBuffers& rec, float* partial,
                           const WOffsets& wo, float* grads, hipStream_t st) {
   return shape == kShapeTiny
-             ? bwd_impl<NetTiny>(lv, shadow, src, nblocks, dsigma, drgb, grad_table, partial, wo, grads, st)
-             : bwd_impl<NetFull>(lv, shadow, src, nblocks, dsigma, drgb, grad_table, partial, wo, grads, st);
+             ? bwd_impl<NetTiny>(lv, shadow, src, nblocks, dsigma, drgb, rec, partial, wo, grads, st)
+             : bwd_impl<NetFull>(lv, shadow, src, nblocks, dsigma, drgb, rec, partial, wo, grads, st);
 }
 
 }  // namespace nsl

@@ -35,14 +35,52 @@ struct SampleSrc {
   int n;
 };
 
+// scatter.hip: table-gradient records and their binned reduction.
+constexpr int kBinShift = 13;                 // 2^13 entries (64 KB of FP32 pairs) per bin
+constexpr int kBinEntries = 1 << kBinShift;
+constexpr int kMaxBins = 4096;                // bins of a table (LDS cursors of the placement)
+constexpr uint32_t kChunk = 65536;            // records per reduce workgroup
+
+// A region (one backward wave) writes the records of level group q (levels
+// 4q..4q+3, one iteration of its level loop) to sub-region q, so that a
+// stretch of records spans few bins.
+struct RecordBuffers {
+  uint32_t* key;          // [nregions][nsub][cap] global entry index (unsorted)
+  float2* val;            // [nregions][nsub][cap] gradient of the entry's two features
+  uint32_t* count;        // [nregions][nsub] records written to each sub-region
+  uint32_t cap;           // records per sub-region
+  int nsub;               // sub-regions per region (levels / 4)
+  uint32_t* hist;         // [nregions][nbins]
+  uint32_t* off;          // [nregions][nbins]
+  uint32_t* bin_total;    // [nbins]
+  uint32_t* bin_start;    // [nbins + 1]
+  uint32_t* chunk_start;  // [nbins + 1]
+  uint3* sorted;          // [all records] (entry, g0, g1) grouped by bin
+};
+
+struct BinPlan {
+  uint32_t entries;
+  int nbins, nregions, nsub, max_chunks;
+  uint32_t cap;           // records per sub-region
+};
+
+// Regions = waves of the backward grid; max_samples bounds the records.
+BinPlan bin_plan(uint32_t entries, int levels, int nregions, int64_t max_samples);
+// grad_table += sum of all records (after the backward kernel).
+hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, float* grad_table, hipStream_t st);
+
 // field.hip
 size_t field_prep_floats(int shape);
 size_t field_nweights(int shape);
 hipError_t field_prep(int shape, const float* params, const WOffsets& wo, float* out, hipStream_t st);
 hipError_t field_forward(int shape, const FieldArgs& a, const SampleSrc& src, int max_samples,
                          float* sigma, float* rgb, hipStream_t st);
+constexpr int kFieldBwdWaves = 4;             // waves per workgroup of the FP32 backward
+constexpr int kMixedBwdWaves = 4;             // waves per workgroup of the mixed backward
+// Writes the table-gradient records of every sample into rec (one region per
+// wave) and adds the weight gradients into grads.
 hipError_t field_backward(int shape, const FieldArgs& a, const SampleSrc& src, int nblocks,
-                          const float* dsigma, const float* drgb, float* grad_table,
+                          const float* dsigma, const float* drgb, const RecordBuffers& rec,
                           float* partial, const WOffsets& wo, float* grads, hipStream_t st);
 
 struct RenderParams {
@@ -64,7 +102,7 @@ hipError_t mixed_prepare(int shape, const float* params, const WOffsets& wo, int
 hipError_t mixed_forward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
                          float* sigma, float* rgb, hipStream_t st);
 hipError_t mixed_backward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int nblocks,
-                          const float* dsigma, const float* drgb, float* grad_table, float* partial,
+                          const float* dsigma, const float* drgb, const RecordBuffers& rec, float* partial,
                           const WOffsets& wo, float* grads, hipStream_t st);
 
 // march.hip
@@ -125,7 +163,8 @@ struct LossIO {
   float lambda_d;
   float loss_scale;
   const float* scale_dev;  // if set, the loss scale is read from scale_dev[0]
-  float* loss;             // [3] accumulated
+  float* loss;             // [3] written: L, L_rgb, L_D
+  float* parts;            // [R,2] per-ray L_rgb and L_D shares (workspace)
   float* ray_out;          // [R,6] z units or null
 };
 

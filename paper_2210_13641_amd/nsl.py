@@ -94,7 +94,7 @@ _sig("nsl_step_workspace_bytes", _sz, [_vp, C.POINTER(StepConfig), _i])
 _sig("nsl_train_step", _i, [_vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(StepConfig), _vp, _i, _vp, _sz, _vp,
                             _vp, _vp, _vp])
 _sig("nsl_march", _i, [_vp, _vp, C.POINTER(StepConfig), _vp, _i, _vp, _sz, _vp, _vp, _vp, _vp, _vp, _vp])
-_sig("nsl_field_workspace_bytes", _sz, [_vp])
+_sig("nsl_field_workspace_bytes", _sz, [_vp, _i])
 _sig("nsl_field_fwd", _i, [_vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _sz, _vp])
 _sig("nsl_field_bwd", _i, [_vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp])
 _sig("nsl_composite_fwd", _i, [_vp, _vp, _vp, _vp, _i, _f, _f, _vp, _vp])
@@ -211,8 +211,9 @@ class Field:
             _lib.nsl_field_destroy(self.handle)
             self.handle = None
 
-    def workspace_bytes(self):
-        return _lib.nsl_field_workspace_bytes(self.handle)
+    def workspace_bytes(self, S):
+        """Workspace of fwd/bwd (either precision) for up to S samples."""
+        return _lib.nsl_field_workspace_bytes(self.handle, S)
 
     def fwd(self, params, xn, dirs, ws):
         S = xn.shape[0]

@@ -57,8 +57,9 @@ def test_host_side_errors(nsl):
     lib = nsl._lib
     f = nsl.Field(W.C1_FIELD)
     fake = C.c_void_p(1 << 20)          # never dereferenced: validation fails first
-    need = lib.nsl_field_workspace_bytes(f.handle)
-    assert need > 0
+    need = lib.nsl_field_workspace_bytes(f.handle, 16)
+    assert need > 0 and lib.nsl_field_workspace_bytes(f.handle, 1 << 20) > need
+    assert lib.nsl_field_workspace_bytes(f.handle, 1 << 27) == 0      # records beyond 32-bit positions
     rc = lib.nsl_field_fwd(f.handle, fake, fake, fake, 16, fake, fake, fake, need - 1, None)
     assert rc == nsl.E_WORKSPACE and b"workspace" in lib.nsl_last_error()
     rc = lib.nsl_field_fwd(f.handle, None, fake, fake, 16, fake, fake, fake, need, None)

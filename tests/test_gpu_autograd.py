@@ -41,7 +41,7 @@ def test_autograd_matches_oracle_on_4096_rays(nsl, gpu):
     ts = [orays.uniform_t(sampler)] * len(ids)
     t_all, ray_of, xn = ostep.sample_positions(spec, o32, d32, ts, o["sel"])
     P = _t(torch, dev, flat).requires_grad_(True)
-    ws = torch.empty(f.workspace_bytes(), dtype=torch.uint8, device=dev)
+    ws = torch.empty(f.workspace_bytes(len(xn)), dtype=torch.uint8, device=dev)
     off = _t(torch, dev, o["offsets"].astype(np.int32))
     out = ag.render_samples(f, P, _t(torch, dev, xn), _t(torch, dev, d32[o["sel"]][ray_of]),
                             _t(torch, dev, t_all), off, sampler.dt, ws)

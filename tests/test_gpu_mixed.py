@@ -41,7 +41,7 @@ def test_mixed_field_forward_and_adjoint(nsl, gpu, spec, table_range):
     dsig = rng.normal(size=S).astype(np.float32)
     drgb = rng.normal(size=(S, 3)).astype(np.float32)
     grads = torch.zeros(lay["total"], dtype=torch.float32, device=dev)
-    ws = torch.empty(f.workspace_bytes(), dtype=torch.uint8, device=dev)
+    ws = torch.empty(f.workspace_bytes(S), dtype=torch.uint8, device=dev)
     f.bwd_mixed(shadow, _t(torch, dev, xn), _t(torch, dev, d), _t(torch, dev, dsig), _t(torch, dev, drgb), grads, ws)
     dWs, dWm, de, dem = ofield.mlp_bwd(spec, w64, cache, dsig.astype(np.float64), np.abs(dsig).astype(np.float64),
                                        drgb.astype(np.float64), np.abs(drgb).astype(np.float64), band_tol=TOL)

@@ -135,7 +135,7 @@ def test_field_forward_and_adjoint(nsl, torch_dev, spec, table_range):
                        [1, 1, 0], [0, 1, 1], [0.125, 0.375, 0.625]], np.float32)   # faces, vertices
     d = rng.normal(size=(S, 3))
     d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
-    ws = torch.empty(f.workspace_bytes(), dtype=torch.uint8, device=dev)
+    ws = torch.empty(f.workspace_bytes(S), dtype=torch.uint8, device=dev)
     P = _t(torch, dev, flat)
     sig, rgb = f.fwd(P, _t(torch, dev, xn), _t(torch, dev, d), ws)
     torch.cuda.synchronize()
@@ -177,7 +177,7 @@ def test_field_gradient_accumulates(nsl, torch_dev):
     d = _t(torch, dev, (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32))
     ds = _t(torch, dev, rng.normal(size=S).astype(np.float32))
     dc = _t(torch, dev, rng.normal(size=(S, 3)).astype(np.float32))
-    ws = torch.empty(f.workspace_bytes(), dtype=torch.uint8, device=dev)
+    ws = torch.empty(f.workspace_bytes(S), dtype=torch.uint8, device=dev)
     P = _t(torch, dev, flat)
     g1 = torch.zeros(f.layout["total"], device=dev)
     f.bwd(P, xn, d, ds, dc, g1, ws)
