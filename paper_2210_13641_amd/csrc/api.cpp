@@ -57,23 +57,17 @@ struct Carver {
 
 constexpr int kBwdBlocks = 256;  // persistent backward grid (one block per CU)
 
-int bwd_regions(bool mixed) { return kBwdBlocks * (mixed ? kMixedBwdWaves : kFieldBwdWaves); }
-
-// Table-gradient records of a backward pass over at most max_samples samples.
+// Buffers of the table-gradient reduction of at most max_samples samples.
 RecordBuffers carve_records(Carver& cv, const BinPlan& p) {
   RecordBuffers r{};
-  const size_t n = (size_t)p.cap * p.nsub * p.nregions;
-  r.key = cv.take<uint32_t>(n);
-  r.val = cv.take<float2>(n);
-  r.count = cv.take<uint32_t>((size_t)p.nregions * p.nsub);
-  r.cap = p.cap;
-  r.nsub = p.nsub;
-  r.hist = cv.take<uint32_t>((size_t)p.nregions * p.nbins);
-  r.off = cv.take<uint32_t>((size_t)p.nregions * p.nbins);
+  r.de = cv.take<float2>((size_t)p.levels * p.stride);
+  r.stride = p.stride;
+  r.hist = cv.take<uint32_t>((size_t)p.nblk * p.nbins);
+  r.off = cv.take<uint32_t>((size_t)p.nblk * p.nbins);
   r.bin_total = cv.take<uint32_t>((size_t)p.nbins);
   r.bin_start = cv.take<uint32_t>((size_t)p.nbins + 1);
   r.chunk_start = cv.take<uint32_t>((size_t)p.nbins + 1);
-  r.sorted = cv.take<uint3>(n);
+  r.sorted = cv.take<uint3>((size_t)p.max_records);
   return r;
 }
 
@@ -327,8 +321,8 @@ struct StepBuffers {
   BinPlan plan;
 };
 
-BinPlan plan_of(const nsl_field* f, bool mixed, int64_t max_samples) {
-  return bin_plan((uint32_t)(f->lay.table_floats / 2), f->cfg.levels, bwd_regions(mixed), max_samples);
+BinPlan plan_of(const nsl_field* f, int64_t max_samples) {
+  return bin_plan((uint32_t)(f->lay.table_floats / 2), f->cfg.levels, max_samples);
 }
 
 size_t step_carve(const nsl_field* f, int n, int max_samples, bool mixed, void* base, StepBuffers* b) {
@@ -351,7 +345,7 @@ size_t step_carve(const nsl_field* f, int n, int max_samples, bool mixed, void* 
   s.partial = cv.take<float>((size_t)kBwdBlocks * field_nweights(f->shape));
   s.loss_parts = cv.take<float>(2 * (size_t)n);
   s.shadow = mixed ? cv.take<char>(mixed_shadow_bytes(f->shape, f->lay.table_floats)) : nullptr;
-  s.plan = plan_of(f, mixed, max_samples);
+  s.plan = plan_of(f, max_samples);
   s.rec = carve_records(cv, s.plan);
   if (b) *b = s;
   return cv.used;
@@ -470,7 +464,7 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   else
     HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, b.dsigma, b.drgb, b.rec, b.partial, f->wo, grads, st),
             "field backward");
-  HIP_TRY(bin_scatter(b.plan, b.rec, grads, st), "table gradient");
+  HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, grads, st), "table gradient");
   if (c->scale_state) HIP_TRY(scale_check(grads, total, c->scale_state, st), "loss scale");
   HIP_TRY(mark(5), "profile event");
   if (c->do_adam)
@@ -534,7 +528,7 @@ int nsl_profile_read(double* ms, int* n_steps) {
 }
 
 // Field-level workspace: MFMA operands, per-block weight-gradient partials and
-// the table-gradient records of S samples (sized for either precision).
+// the table-gradient buffers of S samples (the same for either precision).
 struct FieldWs {
   float* wprep;
   float* partial;
@@ -542,25 +536,20 @@ struct FieldWs {
   BinPlan plan;
 };
 
-static size_t field_carve(const nsl_field* f, int S, bool mixed, void* base, FieldWs* w) {
-  size_t bytes = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    const bool m = pass == 1;
-    Carver cv(m == mixed ? base : nullptr);
-    FieldWs x{};
-    x.wprep = cv.take<float>(field_prep_floats(f->shape));
-    x.partial = cv.take<float>((size_t)kBwdBlocks * field_nweights(f->shape));
-    x.plan = plan_of(f, m, S);
-    x.rec = carve_records(cv, x.plan);
-    if (m == mixed && w) *w = x;
-    bytes = cv.used > bytes ? cv.used : bytes;
-  }
-  return bytes;
+static size_t field_carve(const nsl_field* f, int S, void* base, FieldWs* w) {
+  Carver cv(base);
+  FieldWs x{};
+  x.wprep = cv.take<float>(field_prep_floats(f->shape));
+  x.partial = cv.take<float>((size_t)kBwdBlocks * field_nweights(f->shape));
+  x.plan = plan_of(f, S);
+  x.rec = carve_records(cv, x.plan);
+  if (w) *w = x;
+  return cv.used;
 }
 
 size_t nsl_field_workspace_bytes(const nsl_field* f, int S) {
   if (!f || S < 0 || !records_fit(f->cfg.levels, S)) return 0;
-  return field_carve(f, S, false, nullptr, nullptr);
+  return field_carve(f, S, nullptr, nullptr);
 }
 
 static int field_common(const nsl_field* f, const float* params, const float* xn, const float* dirs, int S,
@@ -570,7 +559,7 @@ static int field_common(const nsl_field* f, const float* params, const float* xn
   if (S < 0) return fail(NSL_E_INVALID, "negative sample count");
   if (!records_fit(f->cfg.levels, S)) return fail(NSL_E_INVALID, "S * 8 * levels must stay below 2^32");
   if (ws_bytes < nsl_field_workspace_bytes(f, S)) return fail(NSL_E_WORKSPACE, "field workspace too small");
-  field_carve(f, S, mixed, ws, &w);
+  field_carve(f, S, ws, &w);
   src = SampleSrc{};
   src.xn = xn; src.dir = dirs; src.box = f->box; src.n = S; src.n_dev = nullptr;
   return NSL_OK;
@@ -600,7 +589,7 @@ int nsl_field_bwd(const nsl_field* f, const float* params, const float* xn, cons
   FieldArgs fa{params, w.wprep, f->lv};
   HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, dsigma, drgb, w.rec, w.partial, f->wo, grads, st),
           "field backward");
-  HIP_TRY(bin_scatter(w.plan, w.rec, grads, st), "table gradient");
+  HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, grads, st), "table gradient");
   return NSL_OK;
 }
 
@@ -634,7 +623,7 @@ int nsl_field_bwd_mixed(const nsl_field* f, const void* shadow, const float* xn,
   if (rc) return rc;
   HIP_TRY(mixed_backward(f->shape, f->lv, shadow, src, kBwdBlocks, dsigma, drgb, w.rec, w.partial, f->wo, grads, st),
           "field backward (mixed)");
-  HIP_TRY(bin_scatter(w.plan, w.rec, grads, st), "table gradient");
+  HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, grads, st), "table gradient");
   return NSL_OK;
 }
 

@@ -212,11 +212,6 @@ __global__ __launch_bounds__(kFieldBwdWaves * kWave, 1) void field_bwd_kernel(Fi
   lane_levels<N>(a.lv, g, ll);
   constexpr f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
   const int region = blockIdx.x * kFieldBwdWaves + wave;
-  uint32_t* rkey = rec.key + (size_t)region * N::LPL * rec.cap;
-  float2* rval = rec.val + (size_t)region * N::LPL * rec.cap;
-  uint32_t cnt[N::LPL];
-#pragma unroll
-  for (int q = 0; q < N::LPL; ++q) cnt[q] = 0;
   // weight gradients of the wave, summed over its tiles in registers
   DWAcc<N::ENC, N::HD> dw0;
   DWAcc<N::HD, 16> dw1;
@@ -352,18 +347,15 @@ __global__ __launch_bounds__(kFieldBwdWaves * kWave, 1) void field_bwd_kernel(Fi
     wave_lds_fence();
     dw_accumulate<N, N::ENC, N::HD>(Xs, Ys, dw0, lane);
     wave_lds_fence();
+    // dL/de of this lane's levels g + 4q, level-major: the 16 lanes of a row
+    // store 16 consecutive samples of one level
+    if (valid) {
 #pragma unroll
-    for (int q = 0; q < N::LPL; ++q) {
-      const int k0 = 2 * q, k1 = 2 * q + 1;
-      const float d0 = valid ? de[k0 >> 2][k0 & 3] : 0.0f;
-      const float d1 = valid ? de[k1 >> 2][k1 & 3] : 0.0f;
-      level_records(xn, ll.res[q], ll.dense[q], a.lv.table_mask, ll.off[q], valid, d0, d1, rkey + q * rec.cap,
-                    rval + q * rec.cap, cnt[q]);
+      for (int q = 0; q < N::LPL; ++q) {
+        const int k0 = 2 * q, k1 = 2 * q + 1;
+        rec.de[(size_t)(g + 4 * q) * rec.stride + s] = make_float2(de[k0 >> 2][k0 & 3], de[k1 >> 2][k1 & 3]);
+      }
     }
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int q = 0; q < N::LPL; ++q) rec.count[region * N::LPL + q] = cnt[q];
   }
   // workgroup sum of the weight gradients: waves add in turn (no atomics)
   for (int w = 0; w < kFieldBwdWaves; ++w) {

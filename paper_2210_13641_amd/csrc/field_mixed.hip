@@ -273,11 +273,6 @@ __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(Le
   lane_levels<N>(lv, g, ll);
   constexpr f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
   const int region = blockIdx.x * kMixedBwdWaves + wave;
-  uint32_t* rkey = rec.key + (size_t)region * N::LPL * rec.cap;
-  float2* rval = rec.val + (size_t)region * N::LPL * rec.cap;
-  uint32_t cnt[N::LPL];
-#pragma unroll
-  for (int q = 0; q < N::LPL; ++q) cnt[q] = 0;
   DWAcc<N::ENC, N::HD> dw0;
   DWAcc<N::HD, 16> dw1;
   DWAcc<N::CIN, N::HC> dw2;
@@ -410,18 +405,15 @@ __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(Le
     wave_lds_fence();
     dw_mixed<N, N::ENC, N::HD>(Xs, Ys, dw0, lane);
     wave_lds_fence();
+    // dL/de of this lane's levels g + 4q, level-major: the 16 lanes of a row
+    // store 16 consecutive samples of one level
+    if (valid) {
 #pragma unroll
-    for (int q = 0; q < N::LPL; ++q) {
-      const int k0 = 2 * q, k1 = 2 * q + 1;
-      const float d0 = valid ? de[k0 >> 2][k0 & 3] : 0.0f;
-      const float d1 = valid ? de[k1 >> 2][k1 & 3] : 0.0f;
-      level_records(xn, ll.res[q], ll.dense[q], lv.table_mask, ll.off[q], valid, d0, d1, rkey + q * rec.cap,
-                    rval + q * rec.cap, cnt[q]);
+      for (int q = 0; q < N::LPL; ++q) {
+        const int k0 = 2 * q, k1 = 2 * q + 1;
+        rec.de[(size_t)(g + 4 * q) * rec.stride + s] = make_float2(de[k0 >> 2][k0 & 3], de[k1 >> 2][k1 & 3]);
+      }
     }
-  }
-  if (lane == 0) {
-#pragma unroll
-    for (int q = 0; q < N::LPL; ++q) rec.count[region * N::LPL + q] = cnt[q];
   }
   for (int w = 0; w < kMixedBwdWaves; ++w) {
     __syncthreads();

@@ -41,33 +41,28 @@ constexpr int kBinEntries = 1 << kBinShift;
 constexpr int kMaxBins = 4096;                // bins of a table (LDS cursors of the placement)
 constexpr uint32_t kChunk = 65536;            // records per reduce workgroup
 
-// A region (one backward wave) writes the records of level group q (levels
-// 4q..4q+3, one iteration of its level loop) to sub-region q, so that a
-// stretch of records spans few bins.
 struct RecordBuffers {
-  uint32_t* key;          // [nregions][nsub][cap] global entry index (unsorted)
-  float2* val;            // [nregions][nsub][cap] gradient of the entry's two features
-  uint32_t* count;        // [nregions][nsub] records written to each sub-region
-  uint32_t cap;           // records per sub-region
-  int nsub;               // sub-regions per region (levels / 4)
-  uint32_t* hist;         // [nregions][nbins]
-  uint32_t* off;          // [nregions][nbins]
+  float2* de;             // [levels][stride] dL/de of every sample (two features per level)
+  int stride;             // samples per level row of de
+  uint32_t* hist;         // [nblk][nbins] records per block of samples and bin
+  uint32_t* off;          // [nblk][nbins]
   uint32_t* bin_total;    // [nbins]
   uint32_t* bin_start;    // [nbins + 1]
   uint32_t* chunk_start;  // [nbins + 1]
-  uint3* sorted;          // [all records] (entry, g0, g1) grouped by bin
+  uint3* sorted;          // [max_records] (entry, g0, g1) grouped by bin
 };
 
 struct BinPlan {
   uint32_t entries;
-  int nbins, nregions, nsub, max_chunks;
-  uint32_t cap;           // records per sub-region
+  int nbins, nblk, levels, stride, max_chunks;
+  int64_t max_records;
 };
 
-// Regions = waves of the backward grid; max_samples bounds the records.
-BinPlan bin_plan(uint32_t entries, int levels, int nregions, int64_t max_samples);
-// grad_table += sum of all records (after the backward kernel).
-hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, float* grad_table, hipStream_t st);
+BinPlan bin_plan(uint32_t entries, int levels, int64_t max_samples);
+// grad_table += the table gradient of the samples of src, from the dL/de
+// that the backward kernel left in rb.de.
+hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
+                       float* grad_table, hipStream_t st);
 
 // field.hip
 size_t field_prep_floats(int shape);
@@ -77,8 +72,8 @@ hipError_t field_forward(int shape, const FieldArgs& a, const SampleSrc& src, in
                          float* sigma, float* rgb, hipStream_t st);
 constexpr int kFieldBwdWaves = 4;             // waves per workgroup of the FP32 backward
 constexpr int kMixedBwdWaves = 4;             // waves per workgroup of the mixed backward
-// Writes the table-gradient records of every sample into rec (one region per
-// wave) and adds the weight gradients into grads.
+// Writes dL/de of every sample to rec.de and adds the weight gradients into
+// grads (the table gradient then comes from bin_scatter).
 hipError_t field_backward(int shape, const FieldArgs& a, const SampleSrc& src, int nblocks,
                           const float* dsigma, const float* drgb, const RecordBuffers& rec,
                           float* partial, const WOffsets& wo, float* grads, hipStream_t st);

@@ -1,70 +1,111 @@
 // Table-gradient accumulation without global atomics on the hot path.
 //
-// The backward kernels do not add w_c * dL/de into the gradient table
-// directly (the chain rule through the trilinear blend of Sec. 3.3's
-// encoding: every sample adds to the 8 corner entries of every level).
-// Device-coherent atomics on gfx950 retire at roughly one lane per clock per
-// XCD whatever the address pattern, and under contention a compare-and-swap
-// loop degrades much further, so each backward wave instead appends records
-// (entry index, two feature gradients) to a region of its own.  The records
-// are then partitioned by bin (2^13 consecutive entries) with a counting
-// sort, and each bin is reduced in LDS by a workgroup that owns it:
+// The gradient of a table entry is the sum, over every sample and every
+// corner of its cell that lands on the entry, of the corner's trilinear
+// weight times dL/de of that level (the chain rule through the encoding of
+// Sec. 3.3).  Device-coherent atomics on gfx950 retire at roughly one lane
+// per clock per XCD whatever the address pattern, and LDS float atomics at a
+// third of a lane per clock per CU, so the sum is formed by a counting sort
+// into bins of 2^13 consecutive entries and an LDS reduction per bin:
 //
-//   count   per region, records per bin (LDS histogram)       [region][bin]
-//   scan    per bin, exclusive prefix over regions; bin totals
-//   start   exclusive prefix over bins; chunks of kChunk records per bin
-//   place   records to their bin's slice (ordered by bin in LDS first)
-//   reduce  one workgroup per chunk: LDS accumulation of the bin, then
-//           grad += acc (a bin of one chunk owns its entries; chunks of a
-//           bin with several use atomics, one per touched entry)
-#include "kernels.h"
+//   (backward)  dL/de of every sample, level-major [level][sample]
+//   count       per block of samples: records per bin (LDS integer atomics)
+//   scan        per bin, exclusive prefix over blocks; bin totals
+//   start       exclusive prefix over bins; chunks of kChunk records per bin
+//   place       the block's records again, ordered by bin in LDS, stored to
+//               their bins' slices
+//   reduce      one workgroup per chunk: LDS accumulation of the bin with
+//               64-bit compare-and-swap on (g0, g1) pairs, then grad += acc
+//               (a bin of one chunk owns its entries; chunks of a bin with
+//               several add with atomics, one per touched entry)
+//
+// A record is (entry, w * dL/de_l0, w * dL/de_l1).  Count and place generate
+// the same records from the sample positions and dL/de: the 16 lanes of a
+// row hold 16 consecutive samples (mostly along one ray) at one level, equal
+// corners form runs of neighbouring lanes, and each run becomes one record
+// carrying the run's sum.
+#include "field_common.h"
 
 namespace nsl {
 
 namespace {
 
-constexpr int kCountThreads = 512;
-constexpr int kReduceThreads = 512;
+constexpr int kRecThreads = 512;                     // count and place
+constexpr int kRecWaves = kRecThreads / kWave;
+constexpr int kRecTilesPerWave = 1;
+constexpr int kRecSamples = kRecWaves * kRecTilesPerWave * 16;      // samples per block
+constexpr int kPlaceChunk = kRecWaves * kRecTilesPerWave * 64 * 8;  // records of one level group
+constexpr int kReduceThreads = 1024;
 constexpr int kReducePer = 8;                        // records in flight per thread
-constexpr int kPlaceThreads = 512;
-constexpr int kPlacePer = 8;                         // records per thread and chunk
-constexpr int kPlaceChunk = kPlaceThreads * kPlacePer;
 
-__global__ __launch_bounds__(kCountThreads) void bin_count_kernel(RecordBuffers rb, int nbins) {
+// The records of one level (l = g + 4q for lane group g) of one tile.
+struct LevelRecords {
+  uint32_t idx[8];
+  float v0[8], v1[8];
+  bool on[8];
+};
+
+// dL/de of this lane's levels g + 4q (zero for samples beyond the batch).
+__device__ __forceinline__ void load_de(const float2* __restrict__ de, int stride, int levels, int g, int s,
+                                       bool valid, float2 d[kMaxLevels / 4]) {
+#pragma unroll
+  for (int q = 0; q < kMaxLevels / 4; ++q)
+    d[q] = valid && 4 * q < levels ? de[(size_t)(g + 4 * q) * stride + s] : make_float2(0.0f, 0.0f);
+}
+
+__device__ __forceinline__ void level_records(const LevelInfo& lv, float2 d, int l, bool valid, const float xn[3],
+                                              LevelRecords& r) {
+  Corner8 c;
+  corners(xn[0], xn[1], xn[2], lv.res[l], (lv.dense_bits >> l) & 1u, lv.table_mask, lv.offset[l], c);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    r.idx[k] = c.idx[k];
+    r.v0[k] = c.w[k] * d.x;
+    r.v1[k] = c.w[k] * d.y;
+    r.on[k] = row_run_sums(valid ? c.idx[k] : 0xFFFFFFFFu, r.v0[k], r.v1[k]) && valid;
+  }
+}
+
+__device__ __forceinline__ int sample_count(const SampleSrc& src) { return src.n_dev ? (int)*src.n_dev : src.n; }
+
+__global__ __launch_bounds__(kRecThreads) void bin_count_kernel(SampleSrc src, LevelInfo lv, RecordBuffers rb,
+                                                               int nbins) {
   extern __shared__ uint32_t h[];
-  for (int i = threadIdx.x; i < nbins; i += kCountThreads) h[i] = 0u;
+  for (int i = threadIdx.x; i < nbins; i += kRecThreads) h[i] = 0u;
   __syncthreads();
-  const int r = blockIdx.x;
-  for (int q = 0; q < rb.nsub; ++q) {
-    const size_t sub = (size_t)r * rb.nsub + q;
-    const uint32_t n = rb.count[sub];
-    const uint32_t* key = rb.key + sub * rb.cap;
-    for (uint32_t base = 0; base < n; base += kCountThreads * 8) {
-      uint32_t k[8];
+  const int S = sample_count(src);
+  const int wave = threadIdx.x / kWave, lane = lane_id(), g = lane >> 4, jc = lane & 15;
+  for (int j = 0; j < kRecTilesPerWave; ++j) {
+    const int tile = (blockIdx.x * kRecWaves + wave) * kRecTilesPerWave + j;
+    if (tile * 16 >= S) break;
+    const int s = tile * 16 + jc;
+    const bool valid = s < S;
+    float xn[3] = {0.5f, 0.5f, 0.5f}, d[3];
+    if (valid) load_sample(src, s, xn, d);
+    float2 dl[kMaxLevels / 4];
+    load_de(rb.de, rb.stride, lv.levels, g, s, valid, dl);
+    for (int q = 0; q < lv.levels / 4; ++q) {
+      LevelRecords r;
+      level_records(lv, dl[q], g + 4 * q, valid, xn, r);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const uint32_t i = base + j * kCountThreads + threadIdx.x;
-        k[j] = i < n ? key[i] : 0xFFFFFFFFu;
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j)
-        if (k[j] != 0xFFFFFFFFu) atomicAdd(&h[k[j] >> kBinShift], 1u);
+      for (int k = 0; k < 8; ++k)
+        if (r.on[k]) atomicAdd(&h[r.idx[k] >> kBinShift], 1u);
     }
   }
   __syncthreads();
-  uint32_t* out = rb.hist + (size_t)r * nbins;
-  for (int i = threadIdx.x; i < nbins; i += kCountThreads) out[i] = h[i];
+  uint32_t* out = rb.hist + (size_t)blockIdx.x * nbins;
+  for (int i = threadIdx.x; i < nbins; i += kRecThreads) out[i] = h[i];
 }
 
-// off[r][b] = sum over regions r' < r of hist[r'][b]; total[b] = sum over
-// all.  A block takes 16 bins; each bin's regions are split over 16 threads
-// (partial sums, a 16-way exclusive scan, then the running prefix).
-__global__ __launch_bounds__(256) void bin_colscan_kernel(RecordBuffers rb, int nbins, int nregions) {
+// off[b'][b] = sum over blocks b'' < b' of hist[b''][b]; total[b] = sum over
+// all.  A workgroup takes 16 bins; each bin's blocks are split over 16
+// threads (partial sums, a 16-way exclusive scan, then the running prefix).
+__global__ __launch_bounds__(256) void bin_colscan_kernel(RecordBuffers rb, int nbins, int nblk) {
   __shared__ uint32_t part[16][17];
   const int bl = threadIdx.x & 15, q = threadIdx.x >> 4;
   const int b = blockIdx.x * 16 + bl;
-  const int per = (nregions + 15) / 16;
-  const int r0 = min(nregions, q * per), r1 = min(nregions, r0 + per);
+  const int per = (nblk + 15) / 16;
+  const int r0 = min(nblk, q * per), r1 = min(nblk, r0 + per);
   uint32_t sum = 0;
   if (b < nbins) {
 #pragma unroll 8
@@ -125,72 +166,83 @@ __global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int n
   }
 }
 
-// Records of one region to their bins' slices.  Chunks of kPlaceChunk
-// records are first ordered by bin in LDS (counting sort with LDS integer
-// atomics), so that the global stores of a wave cover runs of consecutive
-// slots of a few bins instead of one cache line per lane.
-__global__ __launch_bounds__(kPlaceThreads) void bin_place_kernel(RecordBuffers rb, int nbins) {
+// The block's records, one level group at a time: generated as in the
+// count, ordered by bin in LDS (counting sort with LDS integer atomics), and
+// stored so that the global stores of a wave cover runs of consecutive slots
+// of a few bins instead of one cache line per lane.
+__global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, LevelInfo lv, RecordBuffers rb,
+                                                               int nbins) {
   extern __shared__ uint32_t bins_lds[];  // gcur, cnt, lst: [nbins] each
   uint32_t* gcur = bins_lds;
   uint32_t* cnt = bins_lds + nbins;
   uint32_t* lst = bins_lds + 2 * nbins;
-  __shared__ uint32_t wsum[kPlaceThreads / kWave];
+  __shared__ uint32_t wsum[kRecWaves];
   __shared__ uint3 stage[kPlaceChunk];
-  const int r = blockIdx.x, t = threadIdx.x;
-  const uint32_t* off = rb.off + (size_t)r * nbins;
-  for (int b = t; b < nbins; b += kPlaceThreads) gcur[b] = rb.bin_start[b] + off[b];
-  const int per = (nbins + kPlaceThreads - 1) / kPlaceThreads;
+  const int t = threadIdx.x;
+  const uint32_t* off = rb.off + (size_t)blockIdx.x * nbins;
+  for (int b = t; b < nbins; b += kRecThreads) gcur[b] = rb.bin_start[b] + off[b];
+  const int S = sample_count(src);
+  const int wave = t / kWave, lane = lane_id(), g = lane >> 4, jc = lane & 15;
+  const int per = (nbins + kRecThreads - 1) / kRecThreads;
   const int b0 = min(nbins, t * per), b1 = min(nbins, b0 + per);
-  for (int q = 0; q < rb.nsub; ++q) {
-  const size_t sub = (size_t)r * rb.nsub + q;
-  const uint32_t n = rb.count[sub];
-  const uint32_t* key = rb.key + sub * rb.cap;
-  const float2* val = rb.val + sub * rb.cap;
-  for (uint32_t base = 0; base < n; base += kPlaceChunk) {
-    const uint32_t m = min((uint32_t)kPlaceChunk, n - base);
-    for (int b = t; b < nbins; b += kPlaceThreads) cnt[b] = 0u;
-    __syncthreads();
-    uint32_t k[kPlacePer], rank[kPlacePer];
-    float2 v[kPlacePer];
+  float xn[kRecTilesPerWave][3];
+  float2 dl[kRecTilesPerWave][kMaxLevels / 4];
+  bool valid[kRecTilesPerWave];
 #pragma unroll
-    for (int j = 0; j < kPlacePer; ++j) {
-      const uint32_t i = j * kPlaceThreads + t;
-      if (i < m) {
-        k[j] = key[base + i];
-        v[j] = val[base + i];
-        rank[j] = atomicAdd(&cnt[k[j] >> kBinShift], 1u);
-      }
+  for (int j = 0; j < kRecTilesPerWave; ++j) {
+    const int tile = (blockIdx.x * kRecWaves + wave) * kRecTilesPerWave + j;
+    const int s = tile * 16 + jc;
+    valid[j] = s < S;
+    float d[3];
+    xn[j][0] = xn[j][1] = xn[j][2] = 0.5f;
+    if (valid[j]) load_sample(src, s, xn[j], d);
+    load_de(rb.de, rb.stride, lv.levels, g, s, valid[j], dl[j]);
+  }
+  for (int q = 0; q < lv.levels / 4; ++q) {
+    for (int b = t; b < nbins; b += kRecThreads) cnt[b] = 0u;
+    __syncthreads();
+    LevelRecords r[kRecTilesPerWave];
+    uint32_t rank[kRecTilesPerWave][8];
+#pragma unroll
+    for (int j = 0; j < kRecTilesPerWave; ++j) {
+      level_records(lv, dl[j][q], g + 4 * q, valid[j], xn[j], r[j]);
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (r[j].on[k]) rank[j][k] = atomicAdd(&cnt[r[j].idx[k] >> kBinShift], 1u);
     }
     __syncthreads();
-    // lst = exclusive prefix of cnt: per-thread runs of bins, then a scan of
-    // the thread totals
+    // lst = exclusive prefix of cnt: per-thread runs of bins, a wave scan of
+    // the thread totals, then the totals of the waves before
     uint32_t mine = 0;
     for (int b = b0; b < b1; ++b) mine += cnt[b];
     const uint32_t incl = wave_incl_scan_u32(mine);
-    if (lane_id() == kWave - 1) wsum[t / kWave] = incl;
+    if (lane == kWave - 1) wsum[wave] = incl;
     __syncthreads();
-    uint32_t run = incl - mine;
-    for (int w = 0; w < t / kWave; ++w) run += wsum[w];
+    uint32_t run = incl - mine, m = 0;
+    for (int w = 0; w < kRecWaves; ++w) {
+      run += w < wave ? wsum[w] : 0u;
+      m += wsum[w];
+    }
     for (int b = b0; b < b1; ++b) {
       lst[b] = run;
       run += cnt[b];
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kPlacePer; ++j) {
-      const uint32_t i = j * kPlaceThreads + t;
-      if (i < m) stage[lst[k[j] >> kBinShift] + rank[j]] = make_uint3(k[j], __float_as_uint(v[j].x),
-                                                                        __float_as_uint(v[j].y));
-    }
+    for (int j = 0; j < kRecTilesPerWave; ++j)
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (r[j].on[k])
+          stage[lst[r[j].idx[k] >> kBinShift] + rank[j][k]] =
+              make_uint3(r[j].idx[k], __float_as_uint(r[j].v0[k]), __float_as_uint(r[j].v1[k]));
     __syncthreads();
-    for (uint32_t i = t; i < m; i += kPlaceThreads) {
+    for (uint32_t i = t; i < m; i += kRecThreads) {
       const uint3 rec = stage[i];
       const uint32_t b = rec.x >> kBinShift;
       rb.sorted[gcur[b] + (i - lst[b])] = rec;
     }
     __syncthreads();
-    for (int b = t; b < nbins; b += kPlaceThreads) gcur[b] += cnt[b];
-  }
+    for (int b = t; b < nbins; b += kRecThreads) gcur[b] += cnt[b];
   }
 }
 
@@ -226,10 +278,10 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
     for (int j = 0; j < kReducePer; ++j) {
       if (rec[j].x == 0xFFFFFFFFu) continue;
       const uint32_t e = rec[j].x - e0;
-      const float a = __uint_as_float(rec[j].y), c = __uint_as_float(rec[j].z);
+      const float a = __uint_as_float(rec[j].y), cc = __uint_as_float(rec[j].z);
       unsigned long long seen = acc[e];
       for (;;) {
-        const unsigned long long got = atomicCAS(&acc[e], seen, add_pair_bits(seen, a, c));
+        const unsigned long long got = atomicCAS(&acc[e], seen, add_pair_bits(seen, a, cc));
         if (got == seen) break;
         seen = got;
       }
@@ -237,46 +289,45 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
   }
   __syncthreads();
   const uint32_t ne = min((uint32_t)kBinEntries, entries - e0);
-  float2* g = reinterpret_cast<float2*>(grad_table) + e0;
+  float2* gt = reinterpret_cast<float2*>(grad_table) + e0;
   for (uint32_t e = threadIdx.x; e < ne; e += kReduceThreads) {
     const unsigned long long w = acc[e];
     const float a0 = __uint_as_float((uint32_t)w), a1 = __uint_as_float((uint32_t)(w >> 32));
     if (a0 == 0.0f && a1 == 0.0f) continue;
     if (nch == 1) {
-      float2 v = g[e];
+      float2 v = gt[e];
       v.x += a0;
       v.y += a1;
-      g[e] = v;
+      gt[e] = v;
     } else {
-      atomicAdd(&g[e].x, a0);
-      atomicAdd(&g[e].y, a1);
+      atomicAdd(&gt[e].x, a0);
+      atomicAdd(&gt[e].y, a1);
     }
   }
 }
 
 }  // namespace
 
-BinPlan bin_plan(uint32_t entries, int levels, int nregions, int64_t max_samples) {
+BinPlan bin_plan(uint32_t entries, int levels, int64_t max_samples) {
   BinPlan p;
   p.entries = entries;
   p.nbins = (int)((entries + kBinEntries - 1) / kBinEntries);
-  p.nregions = nregions;
-  p.nsub = levels / 4;
-  const int64_t tiles = (max_samples + 15) / 16;
-  const int64_t per_region = (tiles + nregions - 1) / nregions;
-  p.cap = (uint32_t)(per_region * 64 * 8);  // 64 lanes x 8 corners per tile and level group
-  const int64_t records = (int64_t)p.cap * p.nsub * nregions;
-  p.max_chunks = (int)(p.nbins + (records + kChunk - 1) / kChunk);
+  p.levels = levels;
+  p.stride = (int)max_samples;
+  p.nblk = (int)((max_samples + kRecSamples - 1) / kRecSamples);
+  p.max_records = max_samples * 8 * levels;
+  p.max_chunks = (int)(p.nbins + (p.max_records + kChunk - 1) / kChunk);
   return p;
 }
 
-hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, float* grad_table, hipStream_t st) {
-  if (p.nbins == 0) return hipSuccess;
-  const size_t hist_lds = (size_t)p.nbins * sizeof(uint32_t);
-  hipLaunchKernelGGL(bin_count_kernel, dim3(p.nregions), dim3(kCountThreads), hist_lds, st, rb, p.nbins);
-  hipLaunchKernelGGL(bin_colscan_kernel, dim3((p.nbins + 15) / 16), dim3(256), 0, st, rb, p.nbins, p.nregions);
+hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
+                       float* grad_table, hipStream_t st) {
+  if (p.nbins == 0 || p.nblk == 0) return hipSuccess;
+  const size_t bins_lds = (size_t)p.nbins * sizeof(uint32_t);
+  hipLaunchKernelGGL(bin_count_kernel, dim3(p.nblk), dim3(kRecThreads), bins_lds, st, src, lv, rb, p.nbins);
+  hipLaunchKernelGGL(bin_colscan_kernel, dim3((p.nbins + 15) / 16), dim3(256), 0, st, rb, p.nbins, p.nblk);
   hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins);
-  hipLaunchKernelGGL(bin_place_kernel, dim3(p.nregions), dim3(kPlaceThreads), 3 * hist_lds, st, rb, p.nbins);
+  hipLaunchKernelGGL(bin_place_kernel, dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb, p.nbins);
   hipLaunchKernelGGL(bin_reduce_kernel, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins, p.entries,
                      grad_table);
   return hipGetLastError();
