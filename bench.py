@@ -46,26 +46,40 @@ def mlp_macs(spec):
     return fwd, dx, fwd
 
 
-def roofline(spec, phase_ms, samples, table_bytes, mlp_peak):
-    """Roofline of the slower of the two field kernels of a step.
-    field_fwd: gather 8*L*F entries of the table and the forward MLP;
-    field_bwd: scatter of FP32 gradients (8*L*F*4 B) and the MLP adjoint
-    (the recompute of the encoding and forward MLP is not counted)."""
+def kernel_work(spec, table_bytes):
+    """Algorithmic work per sample of the single-kernel phases of a step.
+    field_fwd: gather of 8 corners x L levels x F features of the table and
+    the forward MLP; field_bwd (recompute adjoint): the same gather again, the
+    forward MLP again and its adjoint (input and weight gradients);
+    grad_reduce: the table-gradient scatter, 8 x L x F FP32 values (several
+    kernels; reported beside the dominant one)."""
     fwd_mac, dx_mac, dw_mac = mlp_macs(spec)
     n = 8 * spec.levels * spec.feat_per_level
-    work = {"field_fwd": dict(flops=2 * fwd_mac, bytes=n * table_bytes),
-            "field_bwd": dict(flops=2 * (dx_mac + dw_mac), bytes=n * 4)}
-    dom = max(work, key=lambda k: phase_ms[k])
-    w = work[dom]
-    t = phase_ms[dom] * 1e-3
-    if w["flops"] / mlp_peak >= w["bytes"] / PEAK_HBM:
-        a = w["flops"] * samples / t / 1e12
+    return {"field_fwd": dict(flops=2 * fwd_mac, bytes=n * table_bytes),
+            "field_bwd": dict(flops=2 * (fwd_mac + dx_mac + dw_mac), bytes=n * table_bytes),
+            "grad_reduce": dict(flops=0, bytes=n * 4)}
+
+
+def roofline_of(name, work, samples, ms, mlp_peak):
+    t = ms * 1e-3
+    if work["flops"] / mlp_peak >= work["bytes"] / PEAK_HBM:
+        a = work["flops"] * samples / t / 1e12
         r = dict(bound="mfma", achieved=a, peak=mlp_peak / 1e12, unit="TFLOP/s", frac=a / (mlp_peak / 1e12))
     else:
-        a = w["bytes"] * samples / t / 1e9
+        a = work["bytes"] * samples / t / 1e9
         r = dict(bound="hbm", achieved=a, peak=PEAK_HBM / 1e9, unit="GB/s", frac=a / (PEAK_HBM / 1e9))
-    r.update(traffic=None, kernel=dom, per_sample=w, samples_per_launch=samples, launch_ms=phase_ms[dom])
+    r.update(traffic=None, kernel=name, per_sample=work, samples_per_launch=samples, launch_ms=ms)
     return r
+
+
+def roofline(spec, phase_ms, samples, table_bytes, mlp_peak):
+    """Roofline of the slower single-kernel phase (field forward or field
+    backward), timed with HIP events on the step's stream, and of the
+    table-gradient reduction."""
+    work = kernel_work(spec, table_bytes)
+    dom = max(("field_fwd", "field_bwd"), key=lambda k: phase_ms[k])
+    r = roofline_of(dom, work[dom], samples, phase_ms[dom], mlp_peak)
+    return r, roofline_of("grad_reduce", work["grad_reduce"], samples, phase_ms["grad_reduce"], mlp_peak)
 
 
 def main(argv=None):
@@ -177,8 +191,9 @@ def main(argv=None):
                          full_ms=1e3 * dt_full / args.steps, phases={k: v / n_done for k, v in ph.items()},
                          S=float(np.mean([S_sets[i % N_SETS] for i in range(n_prof)])), R=st[:, 0].astype(np.int64))
     mixed, fp32 = res["mixed"], res["fp32"]
-    roof = roofline(spec, mixed["phases"], mixed["S"], 2, PEAK_BF16)
-    roof_fp32 = roofline(spec, fp32["phases"], fp32["S"], 4, PEAK_FP32)
+    spr = samples_per_ray(nsl, torch, mapper, field, cfgs["fp32"], id_sets, wsb, dev, sampler.max_samples)
+    roof, roof_grad = roofline(spec, mixed["phases"], mixed["S"], 2, PEAK_BF16)
+    roof_fp32, roof_grad_fp32 = roofline(spec, fp32["phases"], fp32["S"], 4, PEAK_FP32)
 
     out = {
         "metric": METRIC,
@@ -201,6 +216,7 @@ def main(argv=None):
             "candidates_per_step": N_CANDIDATES,
             "rays_per_step": float(mixed["R"].mean()),
             "samples_per_step": mixed["S"],
+            "samples_per_ray": spr,
             "phase": "fwd+bwd to parameter gradients (gradient clearing included)",
         },
         "fp32_samples_per_s": fp32["value"],
@@ -210,6 +226,7 @@ def main(argv=None):
         "phases_ms": {"mixed": mixed["phases"], "fp32": fp32["phases"]},
         "roofline": roof,
         "roofline_fp32": roof_fp32,
+        "roofline_grad_reduce": {"mixed": roof_grad, "fp32": roof_grad_fp32},
     }
     if args.serve_requests > 0:
         out["serving"] = serving(nsl, torch, dev, W, args.serve_requests, args.serve_warmup)
@@ -217,6 +234,26 @@ def main(argv=None):
         out["cpu_baseline"] = cpu_baseline(spec, sampler, kf, occ, table, ws, args.cpu_candidates)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def samples_per_ray(nsl, torch, mapper, field, cfg, id_sets, wsb, dev, max_samples):
+    """Histogram (power-of-two bins) and mean of the samples per ray of the
+    batches (rays: kept candidates with at least one sample)."""
+    n = []
+    for ids in id_sets:
+        cnt = torch.zeros(ids.numel(), dtype=torch.int32, device=dev)
+        off = torch.zeros(ids.numel() + 1, dtype=torch.int32, device=dev)
+        tt = torch.zeros(max_samples, dtype=torch.float32, device=dev)
+        ray = torch.zeros(max_samples, dtype=torch.int32, device=dev)
+        nsl.march(mapper, field, cfg, ids, wsb, cnt, off, tt, ray)
+        c, o = cnt.cpu().numpy().astype(np.int64), off.cpu().numpy().astype(np.int64)
+        kept = (o[1:] <= max_samples) & (c > 0)
+        n.append(c[kept])
+    n = np.concatenate(n)
+    edges = [1, 2, 4, 8, 16, 32, 64, 128, 256, 257]
+    h, _ = np.histogram(n, bins=edges)
+    return {"mean": float(n.mean()), "min": int(n.min()), "max": int(n.max()),
+            "hist": {f"{a}-{b - 1}": int(x) for a, b, x in zip(edges[:-1], edges[1:], h)}}
 
 
 def serving(nsl, torch, dev, W, n_req, warmup):

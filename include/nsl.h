@@ -251,11 +251,13 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
  * elapsed milliseconds per phase:
  *   0 gradient clearing and weight-operand preparation, 1 rays + march +
  *   batch cut, 2 field forward, 3 compositing + loss + its adjoint,
- *   4 field backward (recompute, MLP adjoint, scatter, weight reduction),
- *   5 Adam.
+ *   4 field backward kernel (recompute, MLP adjoint, weight gradients per
+ *   workgroup, dL/de), 5 gradient reductions (weights; table: bin count,
+ *   scans, placement, reduction; the overflow check of dynamic loss
+ *   scaling), 6 Adam.
  * nsl_profile_read copies the sums (ms[NSL_PHASES]) and the number of
  * profiled steps; enabling again resets them. */
-#define NSL_PHASES 6
+#define NSL_PHASES 7
 int nsl_profile_enable(int on);
 int nsl_profile_read(double* ms, int* n_steps);
 

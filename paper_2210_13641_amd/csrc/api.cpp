@@ -464,15 +464,17 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   else
     HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, b.dsigma, b.drgb, b.rec, b.partial, f->wo, grads, st),
             "field backward");
+  HIP_TRY(mark(5), "profile event");
+  HIP_TRY(field_dw_reduce(f->shape, b.partial, kBwdBlocks, f->wo, grads, st), "weight gradient");
   HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, grads, st), "table gradient");
   if (c->scale_state) HIP_TRY(scale_check(grads, total, c->scale_state, st), "loss scale");
-  HIP_TRY(mark(5), "profile event");
+  HIP_TRY(mark(6), "profile event");
   if (c->do_adam)
     HIP_TRY(adam_update(params, grads, adam_m, adam_v, total, c->lr, c->beta1, c->beta2, c->eps, c->adam_step,
                         1.0f / c->loss_scale, c->scale_state, st),
             "adam");
   if (c->scale_state) HIP_TRY(scale_end(c->scale_state, st), "loss scale");
-  HIP_TRY(mark(6), "profile event");
+  HIP_TRY(mark(7), "profile event");
   if (prof) {
     HIP_TRY(hipEventSynchronize(g_prof.ev[NSL_PHASES]), "profile sync");
     for (int i = 0; i < NSL_PHASES; ++i) {
@@ -589,6 +591,7 @@ int nsl_field_bwd(const nsl_field* f, const float* params, const float* xn, cons
   FieldArgs fa{params, w.wprep, f->lv};
   HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, dsigma, drgb, w.rec, w.partial, f->wo, grads, st),
           "field backward");
+  HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, st), "weight gradient");
   HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, grads, st), "table gradient");
   return NSL_OK;
 }
@@ -623,6 +626,7 @@ int nsl_field_bwd_mixed(const nsl_field* f, const void* shadow, const float* xn,
   if (rc) return rc;
   HIP_TRY(mixed_backward(f->shape, f->lv, shadow, src, kBwdBlocks, dsigma, drgb, w.rec, w.partial, f->wo, grads, st),
           "field backward (mixed)");
+  HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, st), "weight gradient");
   HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, grads, st), "table gradient");
   return NSL_OK;
 }

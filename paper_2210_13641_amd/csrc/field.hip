@@ -495,9 +495,7 @@ static hipError_t launch_bwd(const FieldArgs& a, const SampleSrc& src, int nbloc
                              float* partial, const WOffsets& wo, float* grads, hipStream_t st) {
   hipLaunchKernelGGL(field_bwd_kernel<N>, dim3(nblocks), dim3(kFieldBwdWaves * kWave), 0, st, a, src, dsigma, drgb,
                      rec, partial);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_dw_reduce<N>(partial, nblocks, wo, grads, st);
+  return hipGetLastError();
 }
 
 template <class N>
@@ -513,6 +511,12 @@ hipError_t render_tiles(int shape, const LevelInfo& lv, const Aabb& box, const n
                         hipStream_t st) {
   return shape == kShapeTiny ? launch_render<NetTiny>(lv, box, reqs, n_req, tiles, n_tiles, rp, st)
                              : launch_render<NetFull>(lv, box, reqs, n_req, tiles, n_tiles, rp, st);
+}
+
+hipError_t field_dw_reduce(int shape, const float* partial, int nblocks, const WOffsets& wo, float* grads,
+                           hipStream_t st) {
+  return shape == kShapeTiny ? launch_dw_reduce<NetTiny>(partial, nblocks, wo, grads, st)
+                             : launch_dw_reduce<NetFull>(partial, nblocks, wo, grads, st);
 }
 
 size_t field_fwd_floats(int shape) { return shape == kShapeTiny ? NetTiny::FWD_FLOATS : NetFull::FWD_FLOATS; }

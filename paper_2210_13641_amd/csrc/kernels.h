@@ -72,11 +72,15 @@ hipError_t field_forward(int shape, const FieldArgs& a, const SampleSrc& src, in
                          float* sigma, float* rgb, hipStream_t st);
 constexpr int kFieldBwdWaves = 4;             // waves per workgroup of the FP32 backward
 constexpr int kMixedBwdWaves = 4;             // waves per workgroup of the mixed backward
-// Writes dL/de of every sample to rec.de and adds the weight gradients into
-// grads (the table gradient then comes from bin_scatter).
+// Writes dL/de of every sample to rec.de and the weight gradients of each
+// workgroup to partial[nblocks][weights]; field_dw_reduce then adds them
+// into grads and bin_scatter the table gradient.
 hipError_t field_backward(int shape, const FieldArgs& a, const SampleSrc& src, int nblocks,
                           const float* dsigma, const float* drgb, const RecordBuffers& rec,
                           float* partial, const WOffsets& wo, float* grads, hipStream_t st);
+
+hipError_t field_dw_reduce(int shape, const float* partial, int nblocks, const WOffsets& wo, float* grads,
+                           hipStream_t st);
 
 struct RenderParams {
   float t_near, dt, stop_T;

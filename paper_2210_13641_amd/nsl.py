@@ -149,7 +149,7 @@ def _dev(t, dtype):
     return _ptr(t)
 
 
-PHASES = ("prep", "march", "field_fwd", "composite_loss", "field_bwd", "adam")
+PHASES = ("prep", "march", "field_fwd", "composite_loss", "field_bwd", "grad_reduce", "adam")
 
 
 def profile_enable(on=True):
