@@ -72,6 +72,35 @@ def roofline_of(name, work, samples, ms, mlp_peak):
     return r
 
 
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_paper_scale.md")
+PMC_SOURCES = ("field.hip", "field_mixed.hip", "field_common.h", "net.h", "common.h", "scatter.hip", "kernels.h")
+PMC_ROWS = {("field_bwd", 2): "mixed_bwd_kernel<NetFull>", ("field_bwd", 4): "nsl::field_bwd_kernel<NetFull >",
+            ("field_fwd", 2): "mixed_fwd_kernel<NetFull>", ("field_fwd", 4): "nsl::field_fwd_kernel<NetFull >"}
+
+
+def measured_traffic(kernel, table_bytes):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) of a
+    kernel from the committed counter summary, or None when the kernel
+    sources differ from those the counters were taken on."""
+    import hashlib
+    try:
+        text = open(PMC_SUMMARY).read()
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for name in PMC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2210_13641_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    if f"kernel sources sha256: {h.hexdigest()}" not in text:
+        return None
+    row = PMC_ROWS.get((kernel, table_bytes))
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if row and len(cells) >= 4 and cells[0] == f"`{row}`":
+            return (float(cells[2]) + float(cells[3])) * 1e6
+    return None
+
+
 def roofline(spec, phase_ms, samples, table_bytes, mlp_peak):
     """Roofline of the slower single-kernel phase (field forward or field
     backward), timed with HIP events on the step's stream, and of the
@@ -79,6 +108,10 @@ def roofline(spec, phase_ms, samples, table_bytes, mlp_peak):
     work = kernel_work(spec, table_bytes)
     dom = max(("field_fwd", "field_bwd"), key=lambda k: phase_ms[k])
     r = roofline_of(dom, work[dom], samples, phase_ms[dom], mlp_peak)
+    r["traffic"] = measured_traffic(dom, table_bytes)
+    if r["traffic"] is not None:
+        r["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated; profiles/pmc_traffic_paper_scale.md)"
+        r["algorithmic_bytes"] = work[dom]["bytes"] * samples
     return r, roofline_of("grad_reduce", work["grad_reduce"], samples, phase_ms["grad_reduce"], mlp_peak)
 
 

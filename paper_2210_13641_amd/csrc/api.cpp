@@ -67,6 +67,7 @@ RecordBuffers carve_records(Carver& cv, const BinPlan& p) {
   r.bin_total = cv.take<uint32_t>((size_t)p.nbins);
   r.bin_start = cv.take<uint32_t>((size_t)p.nbins + 1);
   r.chunk_start = cv.take<uint32_t>((size_t)p.nbins + 1);
+  r.chunk_bin = cv.take<uint32_t>((size_t)p.max_chunks);
   r.sorted = cv.take<uint3>((size_t)p.max_records);
   return r;
 }

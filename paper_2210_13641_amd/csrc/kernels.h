@@ -49,6 +49,7 @@ struct RecordBuffers {
   uint32_t* bin_total;    // [nbins]
   uint32_t* bin_start;    // [nbins + 1]
   uint32_t* chunk_start;  // [nbins + 1]
+  uint32_t* chunk_bin;    // [max_chunks] bin of each chunk
   uint3* sorted;          // [max_records] (entry, g0, g1) grouped by bin
 };
 

@@ -68,15 +68,26 @@ __device__ __forceinline__ void level_records(const LevelInfo& lv, float2 d, int
 
 __device__ __forceinline__ int sample_count(const SampleSrc& src) { return src.n_dev ? (int)*src.n_dev : src.n; }
 
+// Workgroups are dispatched round-robin over the 8 XCDs.  Block i runs the
+// sample range of logical block (i % 8) * (nblk / 8) + i / 8, so that each
+// XCD walks a contiguous stretch of logical blocks in order; the slices the
+// placement writes into a bin are ordered by logical block, hence the runs
+// that consecutive workgroups of one XCD store are adjacent in memory and
+// meet in that XCD's L2.  nblk is a multiple of 8.
+__device__ __forceinline__ int logical_block(int nblk) {
+  return (int)(blockIdx.x % 8u) * (nblk / 8) + (int)(blockIdx.x / 8u);
+}
+
 __global__ __launch_bounds__(kRecThreads) void bin_count_kernel(SampleSrc src, LevelInfo lv, RecordBuffers rb,
                                                                int nbins) {
   extern __shared__ uint32_t h[];
   for (int i = threadIdx.x; i < nbins; i += kRecThreads) h[i] = 0u;
   __syncthreads();
   const int S = sample_count(src);
+  const int blk = logical_block(gridDim.x);
   const int wave = threadIdx.x / kWave, lane = lane_id(), g = lane >> 4, jc = lane & 15;
   for (int j = 0; j < kRecTilesPerWave; ++j) {
-    const int tile = (blockIdx.x * kRecWaves + wave) * kRecTilesPerWave + j;
+    const int tile = (blk * kRecWaves + wave) * kRecTilesPerWave + j;
     if (tile * 16 >= S) break;
     const int s = tile * 16 + jc;
     const bool valid = s < S;
@@ -93,18 +104,19 @@ __global__ __launch_bounds__(kRecThreads) void bin_count_kernel(SampleSrc src, L
     }
   }
   __syncthreads();
-  uint32_t* out = rb.hist + (size_t)blockIdx.x * nbins;
+  uint32_t* out = rb.hist + (size_t)blk * nbins;
   for (int i = threadIdx.x; i < nbins; i += kRecThreads) out[i] = h[i];
 }
 
 // off[b'][b] = sum over blocks b'' < b' of hist[b''][b]; total[b] = sum over
-// all.  A workgroup takes 16 bins; each bin's blocks are split over 16
-// threads (partial sums, a 16-way exclusive scan, then the running prefix).
-__global__ __launch_bounds__(256) void bin_colscan_kernel(RecordBuffers rb, int nbins, int nblk) {
-  __shared__ uint32_t part[16][17];
+// all.  A workgroup takes 16 bins; each bin's blocks are split over 64
+// threads (partial sums, a 64-way exclusive scan, then the running prefix).
+constexpr int kScanGroups = 64;
+__global__ __launch_bounds__(16 * kScanGroups) void bin_colscan_kernel(RecordBuffers rb, int nbins, int nblk) {
+  __shared__ uint32_t part[kScanGroups][17];
   const int bl = threadIdx.x & 15, q = threadIdx.x >> 4;
   const int b = blockIdx.x * 16 + bl;
-  const int per = (nblk + 15) / 16;
+  const int per = (nblk + kScanGroups - 1) / kScanGroups;
   const int r0 = min(nblk, q * per), r1 = min(nblk, r0 + per);
   uint32_t sum = 0;
   if (b < nbins) {
@@ -115,7 +127,7 @@ __global__ __launch_bounds__(256) void bin_colscan_kernel(RecordBuffers rb, int 
   __syncthreads();
   if (b >= nbins) return;
   uint32_t run = 0, total = 0;
-  for (int k = 0; k < 16; ++k) {
+  for (int k = 0; k < kScanGroups; ++k) {
     const uint32_t x = part[k][bl];
     run += k < q ? x : 0u;
     total += x;
@@ -157,8 +169,10 @@ __global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int n
     const uint32_t n = rb.bin_total[b];
     rb.bin_start[b] = run_r;
     rb.chunk_start[b] = run_c;
+    const uint32_t nc = (n + kChunk - 1) / kChunk;
+    for (uint32_t k = 0; k < nc; ++k) rb.chunk_bin[run_c + k] = (uint32_t)b;
     run_r += n;
-    run_c += (n + kChunk - 1) / kChunk;
+    run_c += nc;
   }
   if (t == 1023) {
     rb.bin_start[nbins] = s_rec[1023];
@@ -179,7 +193,8 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
   __shared__ uint32_t wsum[kRecWaves];
   __shared__ uint3 stage[kPlaceChunk];
   const int t = threadIdx.x;
-  const uint32_t* off = rb.off + (size_t)blockIdx.x * nbins;
+  const int blk = logical_block(gridDim.x);
+  const uint32_t* off = rb.off + (size_t)blk * nbins;
   for (int b = t; b < nbins; b += kRecThreads) gcur[b] = rb.bin_start[b] + off[b];
   const int S = sample_count(src);
   const int wave = t / kWave, lane = lane_id(), g = lane >> 4, jc = lane & 15;
@@ -190,7 +205,7 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
   bool valid[kRecTilesPerWave];
 #pragma unroll
   for (int j = 0; j < kRecTilesPerWave; ++j) {
-    const int tile = (blockIdx.x * kRecWaves + wave) * kRecTilesPerWave + j;
+    const int tile = (blk * kRecWaves + wave) * kRecTilesPerWave + j;
     const int s = tile * 16 + jc;
     valid[j] = s < S;
     float d[3];
@@ -254,13 +269,7 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
   __shared__ unsigned long long acc[kBinEntries];
   const uint32_t c = blockIdx.x;
   if (c >= rb.chunk_start[nbins]) return;
-  // bin b: chunk_start[b] <= c < chunk_start[b + 1]
-  int lo = 0, hi = nbins;  // invariant: chunk_start[lo] <= c < chunk_start[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (rb.chunk_start[mid] <= c) lo = mid; else hi = mid;
-  }
-  const int b = lo;
+  const int b = (int)rb.chunk_bin[c];
   const uint32_t nch = rb.chunk_start[b + 1] - rb.chunk_start[b];
   const uint32_t first = rb.bin_start[b] + (c - rb.chunk_start[b]) * kChunk;
   const uint32_t last = min(rb.bin_start[b + 1], first + kChunk);
@@ -314,7 +323,7 @@ BinPlan bin_plan(uint32_t entries, int levels, int64_t max_samples) {
   p.nbins = (int)((entries + kBinEntries - 1) / kBinEntries);
   p.levels = levels;
   p.stride = (int)max_samples;
-  p.nblk = (int)((max_samples + kRecSamples - 1) / kRecSamples);
+  p.nblk = (int)((max_samples + kRecSamples - 1) / kRecSamples + 7) / 8 * 8;  // whole rounds over the XCDs
   p.max_records = max_samples * 8 * levels;
   p.max_chunks = (int)(p.nbins + (p.max_records + kChunk - 1) / kChunk);
   return p;
@@ -325,7 +334,8 @@ hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSr
   if (p.nbins == 0 || p.nblk == 0) return hipSuccess;
   const size_t bins_lds = (size_t)p.nbins * sizeof(uint32_t);
   hipLaunchKernelGGL(bin_count_kernel, dim3(p.nblk), dim3(kRecThreads), bins_lds, st, src, lv, rb, p.nbins);
-  hipLaunchKernelGGL(bin_colscan_kernel, dim3((p.nbins + 15) / 16), dim3(256), 0, st, rb, p.nbins, p.nblk);
+  hipLaunchKernelGGL(bin_colscan_kernel, dim3((p.nbins + 15) / 16), dim3(16 * kScanGroups), 0, st, rb, p.nbins,
+                     p.nblk);
   hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins);
   hipLaunchKernelGGL(bin_place_kernel, dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb, p.nbins);
   hipLaunchKernelGGL(bin_reduce_kernel, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins, p.entries,
