@@ -4,11 +4,13 @@ Training workload: the paper-scale step -- 16-level hash grid with 2^19
 entries per level, density net 32->64->16, colour net 32->64->64->3, 128^3
 occupancy grid of a 64-blob scene, 8 keyframes of 640x480, 4096 pixel
 candidates per step cut at 2^18 samples (1..256 samples per ray).  A step is
-nsl_train_step: rays + march + field forward + compositing/loss + recompute
-backward to parameter gradients (the headline; gradient clearing included),
-and the full step adds Adam.  It runs in mixed precision (FP16 tables, BF16
-MLP on MFMA, FP32 accumulation and masters; the headline value) and in plain
-FP32.  Inputs are resident in device memory before timing starts.
+nsl_train_step: rays + march + field forward + compositing/loss + backward to
+parameter gradients (the headline; gradient clearing included), and the full
+step adds Adam.  The backward recomputes the MLP; the headline keeps the
+encoding from the forward (keep_encoding = 1), and the variant that gathers
+it again is reported beside it.  It runs in mixed precision (FP16 tables,
+BF16 MLP on MFMA, FP32 accumulation and masters; the headline value) and in
+plain FP32.  Inputs are resident in device memory before timing starts.
 
 Serving workload: render requests (Poisson arrivals at 200/s, image sizes
 160x120 .. 1280x960, 32 samples, early termination at T < 1e-4) against the
@@ -164,17 +166,16 @@ def main(argv=None):
     V = torch.zeros_like(P)
     id_sets = [t(W.c2_candidates(N_CANDIDATES, seed=3 + i).view(np.int32)) for i in range(N_SETS)]
     scale = t(np.array([2.0 ** 15, 0, 0, 0], np.float32))
-    cfgs = {
-        "mixed": nsl.step_config(sampler, zero_grads=True, precision=nsl.PRECISION_MIXED, scale_state=scale),
-        "fp32": nsl.step_config(sampler, zero_grads=True),
-    }
-    full = {
-        "mixed": nsl.step_config(sampler, zero_grads=False, do_adam=True, lr=W.ADAM_LR, betas=W.ADAM_BETAS,
-                                 eps=W.ADAM_EPS, precision=nsl.PRECISION_MIXED, scale_state=scale),
-        "fp32": nsl.step_config(sampler, zero_grads=False, do_adam=True, lr=W.ADAM_LR, betas=W.ADAM_BETAS,
-                                eps=W.ADAM_EPS),
-    }
-    wsb = torch.empty(nsl.step_workspace_bytes(field, cfgs["mixed"], N_CANDIDATES), dtype=torch.uint8, device=dev)
+    variants = {"fp32": (False, False), "mixed": (True, False), "fp32_keep_encoding": (False, True),
+                "mixed_keep_encoding": (True, True)}
+    cfgs, full = {}, {}
+    for name, (mx, keep) in variants.items():
+        prec = dict(precision=nsl.PRECISION_MIXED, scale_state=scale) if mx else {}
+        cfgs[name] = nsl.step_config(sampler, zero_grads=True, keep_encoding=keep, **prec)
+        full[name] = nsl.step_config(sampler, zero_grads=False, do_adam=True, lr=W.ADAM_LR, betas=W.ADAM_BETAS,
+                                     eps=W.ADAM_EPS, keep_encoding=keep, **prec)
+    wsb = torch.empty(max(nsl.step_workspace_bytes(field, c, N_CANDIDATES) for c in cfgs.values()),
+                      dtype=torch.uint8, device=dev)
     loss = torch.zeros(3, device=dev)
     stats = torch.zeros(N_SETS, 4, dtype=torch.int32, device=dev)
 
@@ -205,7 +206,7 @@ def main(argv=None):
         return time.perf_counter() - t0
 
     res = {}
-    for name in ("fp32", "mixed"):
+    for name in variants:
         dt = timed(cfgs[name], False)
         st = stats.cpu().numpy()
         S_sets = st[:, 1].astype(np.int64)
@@ -223,7 +224,10 @@ def main(argv=None):
         res[name] = dict(value=samples / dt, ms=1e3 * dt / args.steps, full_value=samples / dt_full,
                          full_ms=1e3 * dt_full / args.steps, phases={k: v / n_done for k, v in ph.items()},
                          S=float(np.mean([S_sets[i % N_SETS] for i in range(n_prof)])), R=st[:, 0].astype(np.int64))
-    mixed, fp32 = res["mixed"], res["fp32"]
+    # headline: the forward keeps the encoding for the backward (the MLP is
+    # recomputed in the backward either way); the recompute-only variants are
+    # reported beside it
+    mixed, fp32 = res["mixed_keep_encoding"], res["fp32_keep_encoding"]
     spr = samples_per_ray(nsl, torch, mapper, field, cfgs["fp32"], id_sets, wsb, dev, sampler.max_samples)
     roof, roof_grad = roofline(spec, mixed["phases"], mixed["S"], 2, PEAK_BF16)
     roof_fp32, roof_grad_fp32 = roofline(spec, fp32["phases"], fp32["S"], 4, PEAK_FP32)
@@ -251,6 +255,7 @@ def main(argv=None):
             "samples_per_step": mixed["S"],
             "samples_per_ray": spr,
             "phase": "fwd+bwd to parameter gradients (gradient clearing included)",
+            "backward": "recompute adjoint of the MLP; the encoding kept from the forward (keep_encoding = 1)",
         },
         "fp32_samples_per_s": fp32["value"],
         "fp32_ms_per_step": fp32["ms"],
@@ -260,6 +265,14 @@ def main(argv=None):
         "roofline": roof,
         "roofline_fp32": roof_fp32,
         "roofline_grad_reduce": {"mixed": roof_grad, "fp32": roof_grad_fp32},
+        "recompute_encoding": {
+            "note": "keep_encoding = 0: the backward gathers the table again instead of reading the encoding "
+                    "the forward kept",
+            "mixed_samples_per_s": res["mixed"]["value"],
+            "fp32_samples_per_s": res["fp32"]["value"],
+            "full_step_samples_per_s": {"mixed": res["mixed"]["full_value"], "fp32": res["fp32"]["full_value"]},
+            "phases_ms": {"mixed": res["mixed"]["phases"], "fp32": res["fp32"]["phases"]},
+        },
     }
     if args.serve_requests > 0:
         out["serving"] = serving(nsl, torch, dev, W, args.serve_requests, args.serve_warmup)

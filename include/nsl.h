@@ -197,6 +197,14 @@ int nsl_occupancy_set(nsl_mapper* m, const uint32_t* bits, int src_on_host,
  * applies bias-corrected Adam at step adam_step (>= 1) to every parameter
  * with gradient grads / loss scale and clears grads afterwards.
  *
+ * keep_encoding: the backward needs the encoding e of every sample.  With 0
+ * it gathers the table again (no per-sample activations are kept between the
+ * forward and the backward; the MLP is always recomputed).  With 1 the
+ * forward stores e in the workspace (2*levels values per sample, FP32, or
+ * BF16 in mixed precision, exactly as the MLP consumes it) and the backward
+ * reads it: the same results, about 128 (64) bytes per sample of traffic
+ * instead of a second gather, whose random reads move whole cache lines.
+ *
  * precision: NSL_PRECISION_FP32, or NSL_PRECISION_MIXED: the step converts
  * the FP32 master parameters to an FP16 table copy and BF16 MLP operands,
  * evaluates and differentiates the field with BF16 MFMA and FP32
@@ -228,6 +236,8 @@ typedef struct nsl_step_config {
   float loss_scale;
   int32_t precision;     /* NSL_PRECISION_FP32 or NSL_PRECISION_MIXED */
   float* scale_state;    /* device float[4] or NULL (static loss_scale) */
+  int32_t keep_encoding; /* 0: the backward recomputes the encoding from the table; 1: the
+                            forward keeps it in the workspace for the backward */
 } nsl_step_config;
 
 typedef struct nsl_step_stats {

@@ -318,6 +318,7 @@ struct StepBuffers {
   float* drgb;
   float* partial;
   float* loss_parts;
+  void* ecache;
   RecordBuffers rec;
   BinPlan plan;
 };
@@ -326,7 +327,7 @@ BinPlan plan_of(const nsl_field* f, int64_t max_samples) {
   return bin_plan((uint32_t)(f->lay.table_floats / 2), f->cfg.levels, max_samples);
 }
 
-size_t step_carve(const nsl_field* f, int n, int max_samples, bool mixed, void* base, StepBuffers* b) {
+size_t step_carve(const nsl_field* f, int n, int max_samples, bool mixed, bool keep_e, void* base, StepBuffers* b) {
   Carver cv(base);
   StepBuffers s{};
   s.rb.rays = cv.take<float4>(2 * (size_t)n);
@@ -345,6 +346,9 @@ size_t step_carve(const nsl_field* f, int n, int max_samples, bool mixed, void* 
   s.drgb = cv.take<float>(3 * (size_t)max_samples);
   s.partial = cv.take<float>((size_t)kBwdBlocks * field_nweights(f->shape));
   s.loss_parts = cv.take<float>(2 * (size_t)n);
+  // encoding cache: 2*levels values per sample over whole 16-sample tiles
+  const size_t e_vals = ((size_t)max_samples + 15) / 16 * 16 * 2 * f->cfg.levels;
+  s.ecache = keep_e ? (mixed ? (void*)cv.take<uint16_t>(e_vals) : (void*)cv.take<float>(e_vals)) : nullptr;
   s.shadow = mixed ? cv.take<char>(mixed_shadow_bytes(f->shape, f->lay.table_floats)) : nullptr;
   s.plan = plan_of(f, max_samples);
   s.rec = carve_records(cv, s.plan);
@@ -367,6 +371,7 @@ int check_step_cfg(const nsl_step_config* c, const nsl_field* f) {
   if (c->do_adam && c->adam_step < 1) return fail(NSL_E_INVALID, "adam_step must be >= 1");
   if (!(c->loss_scale > 0.0f)) return fail(NSL_E_INVALID, "loss_scale must be > 0");
   if (c->precision != NSL_PRECISION_FP32 && c->precision != NSL_PRECISION_MIXED) return fail(NSL_E_INVALID, "bad precision");
+  if (c->keep_encoding != 0 && c->keep_encoding != 1) return fail(NSL_E_INVALID, "keep_encoding must be 0 or 1");
   return NSL_OK;
 }
 
@@ -398,7 +403,8 @@ int check_ids_range(const nsl_mapper* m, int n) {
 
 size_t nsl_step_workspace_bytes(const nsl_field* f, const nsl_step_config* c, int n) {
   if (!f || !c || n < 0 || c->max_samples < 1 || !records_fit(f->cfg.levels, c->max_samples)) return 0;
-  return step_carve(f, n, c->max_samples, c->precision == NSL_PRECISION_MIXED, nullptr, nullptr);
+  return step_carve(f, n, c->max_samples, c->precision == NSL_PRECISION_MIXED, c->keep_encoding != 0, nullptr,
+                    nullptr);
 }
 
 static int run_march(nsl_mapper* m, const nsl_field* f, const nsl_step_config* c, const uint32_t* ids, int n,
@@ -422,7 +428,7 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   if (ws_bytes < nsl_step_workspace_bytes(f, c, n)) return fail(NSL_E_WORKSPACE, "step workspace too small");
   StepBuffers b;
   const bool mixed = c->precision == NSL_PRECISION_MIXED;
-  step_carve(f, n, c->max_samples, mixed, ws, &b);
+  step_carve(f, n, c->max_samples, mixed, c->keep_encoding != 0, ws, &b);
   if (stats_out) b.rb.stats = reinterpret_cast<uint32_t*>(stats_out);
   b.rb.loss = loss_out;
   const int64_t total = f->lay.total_floats;
@@ -442,6 +448,7 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   FieldArgs fa{params, b.wprep, f->lv};
   SampleSrc src{};
   src.t = b.t; src.ray = b.ray; src.rays = b.rb.rays; src.box = f->box; src.n_dev = b.rb.stats + 1; src.n = 0;
+  src.ecache = b.ecache;
   if (mixed)
     HIP_TRY(mixed_forward(f->shape, f->lv, b.shadow, src, c->max_samples, b.sigma, b.rgb, st), "field forward");
   else
@@ -497,7 +504,7 @@ int nsl_march(nsl_mapper* m, const nsl_field* f, const nsl_step_config* c, const
   if ((rc = check_ids_range(m, n))) return rc;
   if (ws_bytes < nsl_step_workspace_bytes(f, c, n)) return fail(NSL_E_WORKSPACE, "march workspace too small");
   StepBuffers b;
-  step_carve(f, n, c->max_samples, c->precision == NSL_PRECISION_MIXED, ws, &b);
+  step_carve(f, n, c->max_samples, c->precision == NSL_PRECISION_MIXED, c->keep_encoding != 0, ws, &b);
   b.rb.counts = counts;
   b.rb.offsets = offsets;
   b.t = t;

@@ -146,6 +146,11 @@ __global__ __launch_bounds__(256) void field_fwd_kernel(FieldArgs a, SampleSrc s
   float xn[3] = {0.5f, 0.5f, 0.5f}, d[3] = {0.0f, 0.0f, 1.0f};
   if (valid) load_sample(src, s, xn, d);
   encode<N>(a.table, a.lv.table_mask, ll, xn, act.e);
+  if (src.ecache) {
+    float* ec = static_cast<float*>(src.ecache) + ((size_t)tile * kWave + lane) * N::NSLOT;
+#pragma unroll
+    for (int k = 0; k < N::NSLOT; ++k) ec[k] = act.e[k];
+  }
   sh_lane<N>(d, g, act.sh);
   mlp_fwd<N>(Af, lane, act);
   if (g == 0 && valid) {
@@ -227,10 +232,16 @@ __global__ __launch_bounds__(kFieldBwdWaves * kWave, 1) void field_bwd_kernel(Fi
     float xn[3] = {0.5f, 0.5f, 0.5f}, d[3] = {0.0f, 0.0f, 1.0f};
     if (valid) load_sample(src, s, xn, d);
     Acts<N> act;
-    encode<N>(a.table, a.lv.table_mask, ll, xn, act.e);
-    if (!valid) {
+    if (src.ecache) {
+      const float* ec = static_cast<const float*>(src.ecache) + ((size_t)tile * kWave + lane) * N::NSLOT;
 #pragma unroll
-      for (int k = 0; k < N::NSLOT; ++k) act.e[k] = 0.0f;
+      for (int k = 0; k < N::NSLOT; ++k) act.e[k] = valid ? ec[k] : 0.0f;
+    } else {
+      encode<N>(a.table, a.lv.table_mask, ll, xn, act.e);
+      if (!valid) {
+#pragma unroll
+        for (int k = 0; k < N::NSLOT; ++k) act.e[k] = 0.0f;
+      }
     }
     sh_lane<N>(d, g, act.sh);
     mlp_fwd<N>(Af, lane, act);

@@ -211,6 +211,13 @@ __global__ __launch_bounds__(256) void mixed_fwd_kernel(LevelInfo lv, const _Flo
   float xn[3] = {0.5f, 0.5f, 0.5f}, d[3] = {0.0f, 0.0f, 1.0f};
   if (valid) load_sample(src, s, xn, d);
   encode<N>(table, lv.table_mask, ll, xn, act.e);
+  if (src.ecache) {
+    // the encoding as the MFMA consumes it (BF16), so that the backward
+    // reproduces the forward exactly
+    __bf16* ec = static_cast<__bf16*>(src.ecache) + ((size_t)tile * kWave + lane) * N::NSLOT;
+#pragma unroll
+    for (int k = 0; k < N::NSLOT; ++k) ec[k] = (__bf16)act.e[k];
+  }
   sh_lane<N>(d, g, act.sh);
   mlp_fwd_mixed<N>(Af, lane, act);
   if (g == 0 && valid) {
@@ -287,10 +294,16 @@ __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(Le
     float xn[3] = {0.5f, 0.5f, 0.5f}, d[3] = {0.0f, 0.0f, 1.0f};
     if (valid) load_sample(src, s, xn, d);
     MActs<N> act;
-    encode<N>(table, lv.table_mask, ll, xn, act.e);
-    if (!valid) {
+    if (src.ecache) {
+      const __bf16* ec = static_cast<const __bf16*>(src.ecache) + ((size_t)tile * kWave + lane) * N::NSLOT;
 #pragma unroll
-      for (int k = 0; k < N::NSLOT; ++k) act.e[k] = 0.0f;
+      for (int k = 0; k < N::NSLOT; ++k) act.e[k] = valid ? (float)ec[k] : 0.0f;
+    } else {
+      encode<N>(table, lv.table_mask, ll, xn, act.e);
+      if (!valid) {
+#pragma unroll
+        for (int k = 0; k < N::NSLOT; ++k) act.e[k] = 0.0f;
+      }
     }
     sh_lane<N>(d, g, act.sh);
     mlp_fwd_mixed<N>(Af, lane, act);

@@ -33,6 +33,10 @@ struct SampleSrc {
   Aabb box;
   const uint32_t* n_dev;
   int n;
+  // Optional encoding cache, [tile][lane][slot] in the MFMA B-operand lane
+  // layout (FP32, or BF16 in mixed precision): the forward writes it and the
+  // backward reads it instead of gathering the table again.
+  void* ecache;
 };
 
 // scatter.hip: table-gradient records and their binned reduction.

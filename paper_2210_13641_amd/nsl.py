@@ -47,7 +47,7 @@ class StepConfig(C.Structure):
                 ("lambda_d", C.c_float), ("zero_grads", C.c_int32), ("do_adam", C.c_int32),
                 ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
                 ("adam_step", C.c_int32), ("loss_scale", C.c_float), ("precision", C.c_int32),
-                ("scale_state", C.c_void_p)]
+                ("scale_state", C.c_void_p), ("keep_encoding", C.c_int32)]
 
 
 class RenderConfig(C.Structure):
@@ -299,7 +299,8 @@ class Mapper:
 # ---------------------------------------------------------------------------
 
 def step_config(sampler_spec, lambda_d=1.0, zero_grads=True, do_adam=False, lr=1e-2, betas=(0.9, 0.99),
-                eps=1e-15, adam_step=1, loss_scale=1.0, precision=PRECISION_FP32, scale_state=None) -> StepConfig:
+                eps=1e-15, adam_step=1, loss_scale=1.0, precision=PRECISION_FP32, scale_state=None,
+                keep_encoding=False) -> StepConfig:
     c = StepConfig()
     c.sampler = SAMPLER_UNIFORM if sampler_spec.mode == "uniform" else SAMPLER_OCCUPANCY
     c.t_near, c.t_far, c.dt = sampler_spec.t_near, sampler_spec.t_far, sampler_spec.dt
@@ -309,6 +310,7 @@ def step_config(sampler_spec, lambda_d=1.0, zero_grads=True, do_adam=False, lr=1
     c.adam_step, c.loss_scale = adam_step, loss_scale
     c.precision = precision
     c.scale_state = scale_state.data_ptr() if scale_state is not None else None
+    c.keep_encoding = int(keep_encoding)
     return c
 
 

@@ -103,15 +103,18 @@ def test_workspace_queries_scale(nsl):
     assert a > 40 * W.C2_SAMPLER.max_samples
 
 
-def test_render_records_match_c_layout(nsl, tmp_path):
-    """The binding's ctypes mirrors of the render records have the C sizes
-    and offsets (checked with the host C compiler)."""
+def test_records_match_c_layout(nsl, tmp_path):
+    """The binding's ctypes mirrors of the render records and the step
+    configuration have the C sizes and offsets (checked with the host C
+    compiler)."""
     import ctypes as C
     import subprocess
     src = tmp_path / "lay.c"
     src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "nsl.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(nsl_render_request), '
-                   'offsetof(nsl_render_request, rgb), offsetof(nsl_render_request, H), sizeof(nsl_render_tile));return 0;}\n')
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(nsl_render_request), '
+                   'offsetof(nsl_render_request, rgb), offsetof(nsl_render_request, H), sizeof(nsl_render_tile), '
+                   'sizeof(nsl_step_config), offsetof(nsl_step_config, precision), '
+                   'offsetof(nsl_step_config, scale_state), offsetof(nsl_step_config, keep_encoding));return 0;}\n')
     exe = tmp_path / "lay"
     inc = os.path.join(os.path.dirname(HEADER))
     r = subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", inc, "-I", "/opt/rocm/include", str(src), "-o", str(exe)],
@@ -120,4 +123,5 @@ def test_render_records_match_c_layout(nsl, tmp_path):
         pytest.skip("host C compiler cannot build against the HIP headers: " + r.stderr[-200:])
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     assert got == [C.sizeof(nsl.RenderRequest), nsl.RenderRequest.rgb.offset, nsl.RenderRequest.H.offset,
-                   C.sizeof(nsl.RenderTile)]
+                   C.sizeof(nsl.RenderTile), C.sizeof(nsl.StepConfig), nsl.StepConfig.precision.offset,
+                   nsl.StepConfig.scale_state.offset, nsl.StepConfig.keep_encoding.offset]

@@ -246,12 +246,16 @@ def test_march_uniform_and_bad_ids(nsl, torch_dev):
 # Whole step
 # ----------------------------------------------------------------------------
 
-def _step_gpu(nsl, torch, dev, spec, sampler, kf, ids, flat, occ=None, grid_res=1, adam=None, lam=1.0):
+def _step_gpu(nsl, torch, dev, spec, sampler, kf, ids, flat, occ=None, grid_res=1, adam=None, lam=1.0,
+              keep_encoding=False, mixed=False):
     f = nsl.Field(spec)
     m = upload_keyframes(nsl, torch, kf, dev, grid_res=grid_res, occ=occ)
-    kw = dict(lambda_d=lam, zero_grads=True)
+    kw = dict(lambda_d=lam, zero_grads=True, keep_encoding=keep_encoding)
     if adam:
         kw.update(do_adam=True, lr=adam["lr"], betas=adam["betas"], eps=adam["eps"], adam_step=adam["step"])
+    if mixed:
+        kw.update(precision=nsl.PRECISION_MIXED,
+                  scale_state=torch.tensor([2.0 ** 15, 0.0, 0.0, 0.0], dtype=torch.float32, device=dev))
     cfg = nsl.step_config(sampler, **kw)
     n = len(ids)
     ws = torch.empty(nsl.step_workspace_bytes(f, cfg, n), dtype=torch.uint8, device=dev)
@@ -334,6 +338,30 @@ def test_step_paper_scale(nsl, torch_dev):
     o = ostep.train_step(spec, sampler, kf, t64, w64, ids, occupancy=occ)
     report(f"  R={o['R']} S={o['S']} ambiguous ReLU units={o['n_amb']}")
     _compare_step(spec, g, o, f.layout)
+
+
+@pytest.mark.parametrize("mixed", [False, True], ids=["fp32", "mixed"])
+def test_step_keep_encoding_matches_recompute(nsl, torch_dev, mixed):
+    """With the encoding kept from the forward instead of gathered again, the
+    paper-scale step gives the same forward results, loss and weight
+    gradients bit for bit, and the same table gradient up to the summation
+    order of its reduction."""
+    torch, dev = torch_dev
+    scene, occ, kf = c2_inputs()
+    report(f"step: keep_encoding vs recompute, paper scale, {'mixed' if mixed else 'fp32'}")
+    spec, sampler = W.C2_FIELD, W.C2_SAMPLER
+    ids = W.c2_candidates(4096)
+    f = nsl.Field(spec)
+    flat, _, _ = params_for(spec, f.layout, seed=0, table_range=0.3)
+    a, b = [_step_gpu(nsl, torch, dev, spec, sampler, kf, ids, flat, occ=occ, grid_res=128, keep_encoding=k,
+                      mixed=mixed) for k in (False, True)]
+    assert np.array_equal(a["stats"], b["stats"])
+    assert np.array_equal(a["rays"], b["rays"]) and np.array_equal(a["loss"], b["loss"])
+    nt = f.layout["table_floats"]
+    assert np.array_equal(a["grads"][nt:], b["grads"][nt:])      # fixed-order weight-gradient sums
+    ga, gb = a["grads"][:nt].astype(np.float64), b["grads"][:nt].astype(np.float64)
+    assert np.count_nonzero(ga) > 0.1 * nt
+    assert np.allclose(ga, gb, rtol=1e-5, atol=1e-6 * np.abs(ga).max())
 
 
 def test_step_with_adam(nsl, torch_dev):
