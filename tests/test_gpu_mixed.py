@@ -114,3 +114,104 @@ def test_dynamic_loss_scale_skips_overflow(nsl, gpu):
     ok = _mixed_step(nsl, torch, dev, spec, sampler, kf, ids, flat, [2.0 ** 15, 1999, 0, 0], adam=True)
     assert ok["state"].tolist() == [2.0 ** 16, 0.0, 0.0, 0.0]   # 2000 clean steps: scale doubles
     assert not np.array_equal(ok["params"], flat)
+
+
+def _err(a, b, mag):
+    """relative L2 error / largest error in units of the element's running-
+    error magnitude (the quantity the tolerances bound)"""
+    a, b = np.asarray(a, np.float64).ravel(), np.asarray(b, np.float64).ravel()
+    mag = np.abs(np.asarray(mag, np.float64).ravel())
+    rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+    top = mag.max() if mag.size else 0.0
+    nrm = np.max(np.abs(a - b) / np.maximum(mag, max(1e-6 * top, 1e-300))) if mag.size else 0.0
+    return f"{rel:.1e}/{nrm:.1e}"
+
+
+@pytest.mark.parametrize("n_cams", [8, 32], ids=["2^18", "2^20"])
+def test_mixed_error_along_training(nsl, gpu, n_cams):
+    """Mixed-precision training of the tiny field on n_cams 32x32 cameras
+    (2^18 or 2^20 samples per step) for 100 Adam steps with dynamic loss
+    scaling.  At steps 1, 10 and 100 every output and gradient of the mixed
+    step -- and of the plain FP32 step at the same parameters -- is compared
+    with the FP64 oracle evaluated at the FP32 master parameters.
+
+    Reported errors are relative L2 errors against the exact oracle.  The
+    FP32 step must match it at 1e-5; the mixed step must match, at 2e-2, the
+    oracle whose ReLU units within 2e-2 of their own magnitude of zero may
+    take either side (checked at every report step for 2^18 samples and at
+    step 1 for 2^20, where each oracle evaluation takes tens of seconds)."""
+    import dataclasses
+    import torch
+    dev = gpu
+    spec = W.C1_FIELD
+    kf = W.c4_keyframes(n_cams)
+    ids = W.c1_pixels(K=n_cams)
+    sampler = dataclasses.replace(W.C1_SAMPLER, max_samples=n_cams * 1024 * 32)
+    f = nsl.Field(spec)
+    lay = f.layout
+    flat, _, _ = params_for(spec, lay, seed=0)
+    m = upload_keyframes(nsl, torch, kf, dev)
+    idt = _t(torch, dev, ids.view(np.int32))
+    P = _t(torch, dev, flat)
+    G = torch.zeros_like(P)
+    M, V = torch.zeros_like(P), torch.zeros_like(P)
+    state = torch.tensor([2.0 ** 15, 0.0, 0.0, 0.0], device=dev)
+    train = nsl.step_config(sampler, precision=nsl.PRECISION_MIXED, scale_state=state, zero_grads=False,
+                            do_adam=True, lr=W.ADAM_LR, betas=W.ADAM_BETAS, eps=W.ADAM_EPS)
+    ws = torch.empty(nsl.step_workspace_bytes(f, train, len(ids)), dtype=torch.uint8, device=dev)
+    loss = torch.zeros(3, device=dev)
+    n = len(ids)
+    report(f"mixed training: {n_cams} cameras, {n * 32} samples per step, 100 Adam steps, scale 2^15; "
+           "errors against the exact FP64 oracle as relative L2 / max |error| per running-error magnitude")
+
+    def probe(precision):
+        st = state.clone()
+        scale = float(st[0].item()) if precision == nsl.PRECISION_MIXED else 1.0
+        cfg = nsl.step_config(sampler, precision=precision, scale_state=st if precision == nsl.PRECISION_MIXED
+                              else None, zero_grads=True)
+        g = torch.zeros_like(P)
+        lo = torch.zeros(3, device=dev)
+        rays = torch.zeros(n, 6, device=dev)
+        nsl.train_step(m, f, P, g, None, None, cfg, idt, ws, lo, None, rays)
+        torch.cuda.synchronize()
+        return dict(loss=lo.cpu().numpy(), rays=rays.cpu().numpy(), grads=g.cpu().numpy() / scale)
+
+    for step in range(1, 101):
+        if step in (1, 10, 100):
+            gm, g32 = probe(nsl.PRECISION_MIXED), probe(nsl.PRECISION_FP32)
+            pv = P.cpu().numpy()
+            t64 = pv[:lay["table_floats"]].astype(np.float64)
+            w64 = [pv[o:o + a * b].astype(np.float64).reshape(a, b)
+                   for o, (a, b) in zip(lay["w_offsets"], spec.mlp_dims())]
+            o = ostep.train_step(spec, sampler, kf, t64, w64, ids)
+            ob = ostep.train_step(spec, sampler, kf, t64, w64, ids, band=TOL) if n_cams == 8 or step == 1 else None
+            sel = o["sel"]
+            def outs(o):
+                return [("rgb", o["rgb"], np.abs(o["rgb"]) + 1e-7, lambda r: r[sel, :3]),
+                        ("depth", o["depth_z"], np.abs(o["depth_z"]) + 1e-7, lambda r: r[sel, 3]),
+                        ("var", o["var_z"], o["var_z_mag"], lambda r: r[sel, 4]),
+                        ("opacity", o["opacity"], o["opacity"] + 1e-7, lambda r: r[sel, 5])]
+
+            def grads(o):
+                return [("table", o["grad_table"], o["grad_table_mag"])] + \
+                    [(f"W{j}", o["grad_w"][j], o["grad_w_mag"][j]) for j in range(len(o["grad_w"]))]
+
+            for name, g, tol, oc in (("mixed", gm, TOL, ob), ("fp32", g32, 1e-5, o)):
+                gtab, gws = split_grads(g["grads"], lay, spec)
+                got = [gtab] + list(gws)
+                if oc is not None:              # the assertion
+                    assert g["loss"][0] == pytest.approx(oc["loss"], rel=tol)
+                    for nm, ref, mag, pick in outs(oc):
+                        check_mag(f"{name} step {step} {nm}", pick(g["rays"]), ref, mag, tol)
+                    for (nm, ref, mag), a in zip(grads(oc), got):
+                        check_mag(f"{name} step {step} grad {nm}", a, ref, mag, tol)
+                line = [f"step {step:3d} {name:5s} loss {abs(g['loss'][0] / o['loss'] - 1):.1e}"]
+                line += [f"{nm} {_err(pick(g['rays']), ref, mag)}" for nm, ref, mag, pick in outs(o)]
+                line += [f"d{nm} {_err(a, ref, mag)}" for (nm, ref, mag), a in zip(grads(o), got)]
+                report("  " + " ".join(line))
+        cfg = train
+        cfg.adam_step = step
+        nsl.train_step(m, f, P, G, M, V, cfg, idt, ws, loss)
+    torch.cuda.synchronize()
+    st = state.cpu().numpy()
+    report(f"  final loss scale {st[0]:.0f}, skipped steps {st[2]:.0f}")
