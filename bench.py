@@ -49,17 +49,21 @@ def mlp_macs(spec):
 
 
 def kernel_work(spec, table_bytes):
-    """Algorithmic work per sample of the single-kernel phases of a step.
-    field_fwd: gather of 8 corners x L levels x F features of the table and
-    the forward MLP; field_bwd (recompute adjoint): the same gather again, the
-    forward MLP again and its adjoint (input and weight gradients);
-    grad_reduce: the table-gradient scatter, 8 x L x F FP32 values (several
-    kernels; reported beside the dominant one)."""
+    """Algorithmic work per sample of the steps of the path, as the profiler
+    phases time them (the encoding kept from the forward, keep_encoding = 1):
+      encode      the table gather, 8 corners x L levels x F features;
+      field_fwd   the forward MLP;
+      field_bwd   the MLP recomputed and its adjoint (input and weight
+                  gradients);
+      table_grad  the table-gradient scatter, 8 x L x F FP32 values (five
+                  kernels: bin count, column scan, bin starts, placement,
+                  reduction)."""
     fwd_mac, dx_mac, dw_mac = mlp_macs(spec)
     n = 8 * spec.levels * spec.feat_per_level
-    return {"field_fwd": dict(flops=2 * fwd_mac, bytes=n * table_bytes),
-            "field_bwd": dict(flops=2 * (fwd_mac + dx_mac + dw_mac), bytes=n * table_bytes),
-            "grad_reduce": dict(flops=0, bytes=n * 4)}
+    return {"encode": dict(flops=0, bytes=n * table_bytes),
+            "field_fwd": dict(flops=2 * fwd_mac, bytes=0),
+            "field_bwd": dict(flops=2 * (fwd_mac + dx_mac + dw_mac), bytes=0),
+            "table_grad": dict(flops=0, bytes=n * 4)}
 
 
 def roofline_of(name, work, samples, ms, mlp_peak):
@@ -76,15 +80,23 @@ def roofline_of(name, work, samples, ms, mlp_peak):
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_paper_scale.md")
 PMC_SOURCES = ("field.hip", "field_mixed.hip", "field_common.h", "net.h", "common.h", "scatter.hip", "kernels.h")
-PMC_ROWS = {("field_bwd", 2): "mixed_bwd_kernel<NetFull>", ("field_bwd", 4): "nsl::field_bwd_kernel<NetFull >",
-            ("field_fwd", 2): "mixed_fwd_kernel<NetFull>", ("field_fwd", 4): "nsl::field_fwd_kernel<NetFull >"}
+BIN_KERNELS = ["nsl::bin_count_kernel", "nsl::bin_colscan_kernel", "nsl::bin_start_kernel", "nsl::bin_place_kernel",
+               "nsl::bin_reduce_kernel"]
+PMC_ROWS = {("table_grad", 2): BIN_KERNELS, ("table_grad", 4): BIN_KERNELS,
+            ("field_bwd", 2): ["mixed_bwd_kernel<NetFull>"], ("field_bwd", 4): ["nsl::field_bwd_kernel<NetFull >"],
+            ("field_fwd", 2): ["mixed_fwd_kernel<NetFull>"], ("field_fwd", 4): ["nsl::field_fwd_kernel<NetFull >"],
+            ("encode", 2): ["encode_levels_kernel<NetFull, _Float16, unsigned int>"],
+            ("encode", 4): ["nsl::encode_levels_kernel<NetFull, float, HIP_vector_type<float, 2u> >"]}
 
 
-def measured_traffic(kernel, table_bytes):
-    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) of a
-    kernel from the committed counter summary, or None when the kernel
-    sources differ from those the counters were taken on."""
+def measured_traffic(phase, table_bytes):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated) of the
+    kernels of a phase, from the committed counter summary of the mixed
+    headline step, or None when the kernel sources differ from those the
+    counters were taken on (or the summary lacks a kernel)."""
     import hashlib
+    if table_bytes != 2:
+        return None
     try:
         text = open(PMC_SUMMARY).read()
     except OSError:
@@ -95,26 +107,37 @@ def measured_traffic(kernel, table_bytes):
             h.update(fh.read())
     if f"kernel sources sha256: {h.hexdigest()}" not in text:
         return None
-    row = PMC_ROWS.get((kernel, table_bytes))
+    rows = {}
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if row and len(cells) >= 4 and cells[0] == f"`{row}`":
-            return (float(cells[2]) + float(cells[3])) * 1e6
-    return None
+        if len(cells) >= 4 and cells[0].startswith("`"):
+            try:
+                rows[cells[0].strip("`")] = (float(cells[2]) + float(cells[3])) * 1e6
+            except ValueError:
+                pass
+    want = PMC_ROWS.get((phase, table_bytes), [])
+    if not want or any(k not in rows for k in want):
+        return None
+    return sum(rows[k] for k in want)
 
 
 def roofline(spec, phase_ms, samples, table_bytes, mlp_peak):
-    """Roofline of the slower single-kernel phase (field forward or field
-    backward), timed with HIP events on the step's stream, and of the
-    table-gradient reduction."""
+    """Rooflines of the steps of the path (HIP events on the step's stream)
+    and the dominant one (the slowest)."""
     work = kernel_work(spec, table_bytes)
-    dom = max(("field_fwd", "field_bwd"), key=lambda k: phase_ms[k])
-    r = roofline_of(dom, work[dom], samples, phase_ms[dom], mlp_peak)
-    r["traffic"] = measured_traffic(dom, table_bytes)
-    if r["traffic"] is not None:
-        r["traffic_unit"] = "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated; profiles/pmc_traffic_paper_scale.md)"
-        r["algorithmic_bytes"] = work[dom]["bytes"] * samples
-    return r, roofline_of("grad_reduce", work["grad_reduce"], samples, phase_ms["grad_reduce"], mlp_peak)
+    all_r = {}
+    for k in work:
+        r = roofline_of(k, work[k], samples, phase_ms[k], mlp_peak)
+        r["traffic"] = measured_traffic(k, table_bytes)
+        if r["traffic"] is not None:
+            r["traffic_unit"] = ("HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated; "
+                                 "profiles/pmc_traffic_paper_scale.md)")
+            r["algorithmic_bytes"] = work[k]["bytes"] * samples
+        if k == "table_grad":
+            r["kernels"] = "bin_count, bin_colscan, bin_start, bin_place, bin_reduce"
+        all_r[k] = r
+    dom = max(work, key=lambda k: phase_ms[k])
+    return all_r[dom], all_r
 
 
 def main(argv=None):
@@ -127,6 +150,8 @@ def main(argv=None):
     ap.add_argument("--serve-requests", type=int, default=2200)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-only", action="store_true", help="only the serving workload")
+    ap.add_argument("--only", default="", help="comma-separated step variants to time (counter runs); the JSON "
+                    "line needs all four")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy first (reference kernel for HBM counters)")
     args = ap.parse_args(argv)
@@ -206,7 +231,8 @@ def main(argv=None):
         return time.perf_counter() - t0
 
     res = {}
-    for name in variants:
+    names = [v for v in args.only.split(",") if v] or list(variants)
+    for name in names:
         dt = timed(cfgs[name], False)
         st = stats.cpu().numpy()
         S_sets = st[:, 1].astype(np.int64)
@@ -224,13 +250,16 @@ def main(argv=None):
         res[name] = dict(value=samples / dt, ms=1e3 * dt / args.steps, full_value=samples / dt_full,
                          full_ms=1e3 * dt_full / args.steps, phases={k: v / n_done for k, v in ph.items()},
                          S=float(np.mean([S_sets[i % N_SETS] for i in range(n_prof)])), R=st[:, 0].astype(np.int64))
+    if args.only:
+        print(json.dumps({k: {"samples_per_s": v["value"], "phases_ms": v["phases"]} for k, v in res.items()}))
+        return 0
     # headline: the forward keeps the encoding for the backward (the MLP is
     # recomputed in the backward either way); the recompute-only variants are
     # reported beside it
     mixed, fp32 = res["mixed_keep_encoding"], res["fp32_keep_encoding"]
     spr = samples_per_ray(nsl, torch, mapper, field, cfgs["fp32"], id_sets, wsb, dev, sampler.max_samples)
-    roof, roof_grad = roofline(spec, mixed["phases"], mixed["S"], 2, PEAK_BF16)
-    roof_fp32, roof_grad_fp32 = roofline(spec, fp32["phases"], fp32["S"], 4, PEAK_FP32)
+    roof, roofs = roofline(spec, mixed["phases"], mixed["S"], 2, PEAK_BF16)
+    roof_fp32, roofs_fp32 = roofline(spec, fp32["phases"], fp32["S"], 4, PEAK_FP32)
 
     out = {
         "metric": METRIC,
@@ -264,7 +293,7 @@ def main(argv=None):
         "phases_ms": {"mixed": mixed["phases"], "fp32": fp32["phases"]},
         "roofline": roof,
         "roofline_fp32": roof_fp32,
-        "roofline_grad_reduce": {"mixed": roof_grad, "fp32": roof_grad_fp32},
+        "rooflines": {"mixed": roofs, "fp32": roofs_fp32},
         "recompute_encoding": {
             "note": "keep_encoding = 0: the backward gathers the table again instead of reading the encoding "
                     "the forward kept",

@@ -260,14 +260,16 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
  * event (so profiled steps synchronise the host), and accumulates the
  * elapsed milliseconds per phase:
  *   0 gradient clearing and weight-operand preparation, 1 rays + march +
- *   batch cut, 2 field forward, 3 compositing + loss + its adjoint,
- *   4 field backward kernel (recompute, MLP adjoint, weight gradients per
- *   workgroup, dL/de), 5 gradient reductions (weights; table: bin count,
- *   scans, placement, reduction; the overflow check of dynamic loss
- *   scaling), 6 Adam.
+ *   batch cut, 2 encoding of every sample (keep_encoding = 1 only),
+ *   3 field forward (MLP; with keep_encoding = 0 also the table gather),
+ *   4 compositing + loss + its adjoint, 5 field backward kernel (MLP
+ *   recompute and adjoint, weight gradients per workgroup, dL/de),
+ *   6 table gradient (bin count, scans, placement, reduction), 7 weight-
+ *   gradient reduction and the overflow check of dynamic loss scaling,
+ *   8 Adam.
  * nsl_profile_read copies the sums (ms[NSL_PHASES]) and the number of
  * profiled steps; enabling again resets them. */
-#define NSL_PHASES 7
+#define NSL_PHASES 9
 int nsl_profile_enable(int on);
 int nsl_profile_read(double* ms, int* n_steps);
 

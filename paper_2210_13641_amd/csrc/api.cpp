@@ -346,9 +346,9 @@ size_t step_carve(const nsl_field* f, int n, int max_samples, bool mixed, bool k
   s.drgb = cv.take<float>(3 * (size_t)max_samples);
   s.partial = cv.take<float>((size_t)kBwdBlocks * field_nweights(f->shape));
   s.loss_parts = cv.take<float>(2 * (size_t)n);
-  // encoding cache: 2*levels values per sample over whole 16-sample tiles
-  const size_t e_vals = ((size_t)max_samples + 15) / 16 * 16 * 2 * f->cfg.levels;
-  s.ecache = keep_e ? (mixed ? (void*)cv.take<uint16_t>(e_vals) : (void*)cv.take<float>(e_vals)) : nullptr;
+  // kept encoding: [levels][max_samples] FP32 or packed BF16 pairs
+  const size_t e_pairs = (size_t)max_samples * f->cfg.levels;
+  s.ecache = keep_e ? (mixed ? (void*)cv.take<uint32_t>(e_pairs) : (void*)cv.take<float2>(e_pairs)) : nullptr;
   s.shadow = mixed ? cv.take<char>(mixed_shadow_bytes(f->shape, f->lay.table_floats)) : nullptr;
   s.plan = plan_of(f, max_samples);
   s.rec = carve_records(cv, s.plan);
@@ -449,11 +449,19 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   SampleSrc src{};
   src.t = b.t; src.ray = b.ray; src.rays = b.rb.rays; src.box = f->box; src.n_dev = b.rb.stats + 1; src.n = 0;
   src.ecache = b.ecache;
+  src.ecache_stride = c->max_samples;
+  if (src.ecache) {
+    if (mixed)
+      HIP_TRY(mixed_encode(f->shape, f->lv, b.shadow, src, c->max_samples, st), "encoding");
+    else
+      HIP_TRY(field_encode(f->shape, fa, src, c->max_samples, st), "encoding");
+  }
+  HIP_TRY(mark(3), "profile event");
   if (mixed)
     HIP_TRY(mixed_forward(f->shape, f->lv, b.shadow, src, c->max_samples, b.sigma, b.rgb, st), "field forward");
   else
     HIP_TRY(field_forward(f->shape, fa, src, c->max_samples, b.sigma, b.rgb, st), "field forward");
-  HIP_TRY(mark(3), "profile event");
+  HIP_TRY(mark(4), "profile event");
 
   CompositeIO io{};
   io.sigma = b.sigma; io.rgb = b.rgb; io.t = b.t; io.off = b.rb.offsets; io.counts = b.rb.counts;
@@ -463,7 +471,7 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   lo.lambda_d = c->lambda_d; lo.loss_scale = c->loss_scale; lo.scale_dev = c->scale_state;
   lo.loss = loss_out; lo.parts = b.loss_parts; lo.ray_out = ray_out;
   HIP_TRY(composite_loss_backward(io, lo, b.dsigma, b.drgb, st), "composite");
-  HIP_TRY(mark(4), "profile event");
+  HIP_TRY(mark(5), "profile event");
 
   if (mixed)
     HIP_TRY(mixed_backward(f->shape, f->lv, b.shadow, src, kBwdBlocks, b.dsigma, b.drgb, b.rec, b.partial, f->wo,
@@ -472,17 +480,18 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   else
     HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, b.dsigma, b.drgb, b.rec, b.partial, f->wo, grads, st),
             "field backward");
-  HIP_TRY(mark(5), "profile event");
-  HIP_TRY(field_dw_reduce(f->shape, b.partial, kBwdBlocks, f->wo, grads, st), "weight gradient");
-  HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, grads, st), "table gradient");
-  if (c->scale_state) HIP_TRY(scale_check(grads, total, c->scale_state, st), "loss scale");
   HIP_TRY(mark(6), "profile event");
+  HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, grads, st), "table gradient");
+  HIP_TRY(mark(7), "profile event");
+  HIP_TRY(field_dw_reduce(f->shape, b.partial, kBwdBlocks, f->wo, grads, st), "weight gradient");
+  if (c->scale_state) HIP_TRY(scale_check(grads, total, c->scale_state, st), "loss scale");
+  HIP_TRY(mark(8), "profile event");
   if (c->do_adam)
     HIP_TRY(adam_update(params, grads, adam_m, adam_v, total, c->lr, c->beta1, c->beta2, c->eps, c->adam_step,
                         1.0f / c->loss_scale, c->scale_state, st),
             "adam");
   if (c->scale_state) HIP_TRY(scale_end(c->scale_state, st), "loss scale");
-  HIP_TRY(mark(7), "profile event");
+  HIP_TRY(mark(9), "profile event");
   if (prof) {
     HIP_TRY(hipEventSynchronize(g_prof.ev[NSL_PHASES]), "profile sync");
     for (int i = 0; i < NSL_PHASES; ++i) {

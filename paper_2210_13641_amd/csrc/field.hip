@@ -145,12 +145,10 @@ __global__ __launch_bounds__(256) void field_fwd_kernel(FieldArgs a, SampleSrc s
   Acts<N> act;
   float xn[3] = {0.5f, 0.5f, 0.5f}, d[3] = {0.0f, 0.0f, 1.0f};
   if (valid) load_sample(src, s, xn, d);
-  encode<N>(a.table, a.lv.table_mask, ll, xn, act.e);
-  if (src.ecache) {
-    float* ec = static_cast<float*>(src.ecache) + ((size_t)tile * kWave + lane) * N::NSLOT;
-#pragma unroll
-    for (int k = 0; k < N::NSLOT; ++k) ec[k] = act.e[k];
-  }
+  if (src.ecache)
+    read_encoding<N>(static_cast<const float2*>(src.ecache), src.ecache_stride, g, s, valid, act.e);
+  else
+    encode<N>(a.table, a.lv.table_mask, ll, xn, act.e);
   sh_lane<N>(d, g, act.sh);
   mlp_fwd<N>(Af, lane, act);
   if (g == 0 && valid) {
@@ -233,9 +231,7 @@ __global__ __launch_bounds__(kFieldBwdWaves * kWave, 1) void field_bwd_kernel(Fi
     if (valid) load_sample(src, s, xn, d);
     Acts<N> act;
     if (src.ecache) {
-      const float* ec = static_cast<const float*>(src.ecache) + ((size_t)tile * kWave + lane) * N::NSLOT;
-#pragma unroll
-      for (int k = 0; k < N::NSLOT; ++k) act.e[k] = valid ? ec[k] : 0.0f;
+      read_encoding<N>(static_cast<const float2*>(src.ecache), src.ecache_stride, g, s, valid, act.e);
     } else {
       encode<N>(a.table, a.lv.table_mask, ll, xn, act.e);
       if (!valid) {
@@ -522,6 +518,20 @@ hipError_t render_tiles(int shape, const LevelInfo& lv, const Aabb& box, const n
                         hipStream_t st) {
   return shape == kShapeTiny ? launch_render<NetTiny>(lv, box, reqs, n_req, tiles, n_tiles, rp, st)
                              : launch_render<NetFull>(lv, box, reqs, n_req, tiles, n_tiles, rp, st);
+}
+
+template <class N>
+static hipError_t launch_encode(const FieldArgs& a, const SampleSrc& src, int max_samples, hipStream_t st) {
+  const int grid = encode_grid<N>(max_samples);
+  if (grid > 0)
+    hipLaunchKernelGGL((encode_levels_kernel<N, float, float2>), dim3(grid), dim3(256), 0, st, a.lv, a.table, src,
+                       static_cast<float2*>(src.ecache), src.ecache_stride);
+  return hipGetLastError();
+}
+
+hipError_t field_encode(int shape, const FieldArgs& a, const SampleSrc& src, int max_samples, hipStream_t st) {
+  return shape == kShapeTiny ? launch_encode<NetTiny>(a, src, max_samples, st)
+                             : launch_encode<NetFull>(a, src, max_samples, st);
 }
 
 hipError_t field_dw_reduce(int shape, const float* partial, int nblocks, const WOffsets& wo, float* grads,

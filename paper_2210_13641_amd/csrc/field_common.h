@@ -80,26 +80,95 @@ __device__ __forceinline__ float2 load_entry(const _Float16* __restrict__ t, uin
   return make_float2((float)v[0], (float)v[1]);
 }
 
+// Trilinear blend of one level's two features at xn.
+template <class T>
+__device__ __forceinline__ float2 encode_level(const T* __restrict__ table, uint32_t mask, int res, bool dense,
+                                               uint32_t off, const float xn[3]) {
+  Corner8 c;
+  corners(xn[0], xn[1], xn[2], res, dense, mask, off, c);
+  float2 v[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = load_entry(table, c.idx[k]);
+  float a0 = 0.0f, a1 = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    a0 += c.w[k] * v[k].x;
+    a1 += c.w[k] * v[k].y;
+  }
+  return make_float2(a0, a1);
+}
+
 template <class N, class T>
 __device__ __forceinline__ void encode(const T* __restrict__ table, uint32_t mask,
                                        const LaneLevels<N>& ll, const float xn[3],
                                        float e[N::NSLOT]) {
 #pragma unroll
   for (int q = 0; q < N::LPL; ++q) {
-    Corner8 c;
-    corners(xn[0], xn[1], xn[2], ll.res[q], ll.dense[q], mask, ll.off[q], c);
-    float2 v[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = load_entry(table, c.idx[k]);
-    float a0 = 0.0f, a1 = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      a0 += c.w[k] * v[k].x;
-      a1 += c.w[k] * v[k].y;
-    }
-    e[2 * q] = a0;
-    e[2 * q + 1] = a1;
+    const float2 v = encode_level(table, mask, ll.res[q], ll.dense[q], ll.off[q], xn);
+    e[2 * q] = v.x;
+    e[2 * q + 1] = v.y;
   }
+}
+
+// The kept encoding, level-major [level][ecache_stride]: FP32 pairs, or BF16
+// pairs (as the mixed-precision MLP consumes them) packed in 32 bits.
+__device__ __forceinline__ void store_encoding(float2* out, float2 v) { *out = v; }
+__device__ __forceinline__ void store_encoding(uint32_t* out, float2 v) {
+  const __bf16 a = (__bf16)v.x, b = (__bf16)v.y;
+  *out = (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+}
+__device__ __forceinline__ float2 load_encoding(const float2* in) { return *in; }
+__device__ __forceinline__ float2 load_encoding(const uint32_t* in) {
+  const uint32_t w = *in;
+  return make_float2((float)__builtin_bit_cast(__bf16, (uint16_t)(w & 0xFFFFu)),
+                     (float)__builtin_bit_cast(__bf16, (uint16_t)(w >> 16)));
+}
+
+// This lane's encoding slots (levels g + 4q of sample s) from the kept
+// encoding; zero for samples beyond the batch.
+template <class N, class E>
+__device__ __forceinline__ void read_encoding(const E* __restrict__ ec, int stride, int g, int s, bool valid,
+                                              float e[N::NSLOT]) {
+#pragma unroll
+  for (int q = 0; q < N::LPL; ++q) {
+    const float2 v = valid ? load_encoding(ec + (size_t)(g + 4 * q) * stride + s) : make_float2(0.0f, 0.0f);
+    e[2 * q] = v.x;
+    e[2 * q + 1] = v.y;
+  }
+}
+
+// The encoding of every sample, written level-major for the MLP kernels.
+// Workgroups are dispatched round-robin over the 8 XCDs, in order; with 16
+// levels, the workgroups of XCD x evaluate level x for every sample and then
+// level x + 8, so at any time each XCD's L2 holds the table slice of one
+// level (2 MB in FP16) instead of seeing the whole table, and the random
+// corner reads hit in L2.  One thread per (sample, level); with fewer
+// levels, threads take (sample, level) pairs in order.
+template <class N>
+__host__ __device__ constexpr int encode_grid(int max_samples) {
+  return N::L >= 8 ? 16 * ((max_samples + 255) / 256) : (max_samples * N::L + 255) / 256;
+}
+
+template <class N, class T, class E>
+__global__ __launch_bounds__(256) void encode_levels_kernel(LevelInfo lv, const T* __restrict__ table, SampleSrc src,
+                                                            E* __restrict__ out, int stride) {
+  const int S = src.n_dev ? (int)*src.n_dev : src.n;
+  int l, s;
+  if constexpr (N::L == 16) {
+    const int per_level = (int)(gridDim.x / 16u);  // workgroups per XCD and level
+    const int x = blockIdx.x % 8u, j = blockIdx.x / 8u;
+    l = x + 8 * (j / per_level);
+    s = (j % per_level) * 256 + threadIdx.x;
+  } else {
+    const int gid = blockIdx.x * 256 + threadIdx.x;
+    l = gid % N::L;
+    s = gid / N::L;
+  }
+  if (s >= S) return;
+  float xn[3], d[3];
+  load_sample(src, s, xn, d);
+  const float2 v = encode_level(table, lv.table_mask, lv.res[l], (lv.dense_bits >> l) & 1u, lv.offset[l], xn);
+  store_encoding(out + (size_t)l * stride + s, v);
 }
 
 // Real orthonormal SH coefficients 4g..4g+3 of direction d (0 beyond NSH).

@@ -210,14 +210,10 @@ __global__ __launch_bounds__(256) void mixed_fwd_kernel(LevelInfo lv, const _Flo
   MActs<N> act;
   float xn[3] = {0.5f, 0.5f, 0.5f}, d[3] = {0.0f, 0.0f, 1.0f};
   if (valid) load_sample(src, s, xn, d);
-  encode<N>(table, lv.table_mask, ll, xn, act.e);
-  if (src.ecache) {
-    // the encoding as the MFMA consumes it (BF16), so that the backward
-    // reproduces the forward exactly
-    __bf16* ec = static_cast<__bf16*>(src.ecache) + ((size_t)tile * kWave + lane) * N::NSLOT;
-#pragma unroll
-    for (int k = 0; k < N::NSLOT; ++k) ec[k] = (__bf16)act.e[k];
-  }
+  if (src.ecache)
+    read_encoding<N>(static_cast<const uint32_t*>(src.ecache), src.ecache_stride, g, s, valid, act.e);
+  else
+    encode<N>(table, lv.table_mask, ll, xn, act.e);
   sh_lane<N>(d, g, act.sh);
   mlp_fwd_mixed<N>(Af, lane, act);
   if (g == 0 && valid) {
@@ -295,9 +291,7 @@ __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(Le
     if (valid) load_sample(src, s, xn, d);
     MActs<N> act;
     if (src.ecache) {
-      const __bf16* ec = static_cast<const __bf16*>(src.ecache) + ((size_t)tile * kWave + lane) * N::NSLOT;
-#pragma unroll
-      for (int k = 0; k < N::NSLOT; ++k) act.e[k] = valid ? (float)ec[k] : 0.0f;
+      read_encoding<N>(static_cast<const uint32_t*>(src.ecache), src.ecache_stride, g, s, valid, act.e);
     } else {
       encode<N>(table, lv.table_mask, ll, xn, act.e);
       if (!valid) {
@@ -493,6 +487,23 @@ static hipError_t bwd_impl(const LevelInfo& lv, const void* shadow, const Sample
   hipLaunchKernelGGL(mixed_bwd_kernel<N>, dim3(nblocks), dim3(kMixedBwdWaves * kWave), 0, st, lv, t16, ops, src,
                      dsigma, drgb, rec, partial);
   return hipGetLastError();
+}
+
+template <class N>
+static hipError_t encode_impl(const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
+                              hipStream_t st) {
+  const _Float16* t16 = reinterpret_cast<const _Float16*>(static_cast<const char*>(shadow) + mixed_ops_bytes<N>());
+  const int grid = encode_grid<N>(max_samples);
+  if (grid > 0)
+    hipLaunchKernelGGL((encode_levels_kernel<N, _Float16, uint32_t>), dim3(grid), dim3(256), 0, st, lv, t16, src,
+                       static_cast<uint32_t*>(src.ecache), src.ecache_stride);
+  return hipGetLastError();
+}
+
+hipError_t mixed_encode(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
+                        hipStream_t st) {
+  return shape == kShapeTiny ? encode_impl<NetTiny>(lv, shadow, src, max_samples, st)
+                             : encode_impl<NetFull>(lv, shadow, src, max_samples, st);
 }
 
 hipError_t mixed_prepare(int shape, const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,

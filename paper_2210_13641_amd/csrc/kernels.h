@@ -33,10 +33,12 @@ struct SampleSrc {
   Aabb box;
   const uint32_t* n_dev;
   int n;
-  // Optional encoding cache, [tile][lane][slot] in the MFMA B-operand lane
-  // layout (FP32, or BF16 in mixed precision): the forward writes it and the
-  // backward reads it instead of gathering the table again.
+  // Optional kept encoding, level-major [level][ecache_stride]: FP32 pairs
+  // (float2), or BF16 pairs packed in 32 bits in mixed precision.  When set,
+  // the forward and backward MLP kernels read it instead of gathering the
+  // table (it is written by field_encode / mixed_encode).
   void* ecache;
+  int ecache_stride;
 };
 
 // scatter.hip: table-gradient records and their binned reduction.
@@ -86,6 +88,8 @@ hipError_t field_backward(int shape, const FieldArgs& a, const SampleSrc& src, i
 
 hipError_t field_dw_reduce(int shape, const float* partial, int nblocks, const WOffsets& wo, float* grads,
                            hipStream_t st);
+// The encoding of every sample of src into src.ecache (FP32 table).
+hipError_t field_encode(int shape, const FieldArgs& a, const SampleSrc& src, int max_samples, hipStream_t st);
 
 struct RenderParams {
   float t_near, dt, stop_T;
@@ -105,6 +109,9 @@ hipError_t mixed_prepare(int shape, const float* params, const WOffsets& wo, int
                          hipStream_t st);
 hipError_t mixed_forward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
                          float* sigma, float* rgb, hipStream_t st);
+// The encoding of every sample of src into src.ecache (FP16 table, BF16 out).
+hipError_t mixed_encode(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
+                        hipStream_t st);
 hipError_t mixed_backward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int nblocks,
                           const float* dsigma, const float* drgb, const RecordBuffers& rec, float* partial,
                           const WOffsets& wo, float* grads, hipStream_t st);

@@ -149,7 +149,8 @@ def _dev(t, dtype):
     return _ptr(t)
 
 
-PHASES = ("prep", "march", "field_fwd", "composite_loss", "field_bwd", "grad_reduce", "adam")
+PHASES = ("prep", "march", "encode", "field_fwd", "composite_loss", "field_bwd", "table_grad", "weight_grad",
+          "adam")
 
 
 def profile_enable(on=True):

@@ -250,8 +250,10 @@ def serve(field, cfg, device, requests, params, train_fn=None, train_period=5e-3
             next_train += train_period
             srv.publish(params, train_stream)
         srv.pump()
-        if not srv.active and srv.pending and srv.pending[0].arrival > srv.now():
-            time.sleep(min(srv.pending[0].arrival - srv.now(), 2e-4))
+        if not srv.active and srv.pending:
+            wait = srv.pending[0].arrival - srv.now()      # read the clock once
+            if wait > 0:
+                time.sleep(min(wait, 2e-4))
     torch.cuda.synchronize(device)
     wall = srv.now() - t_start
     done = sorted(srv.finished, key=lambda r: r.rid)
