@@ -68,7 +68,7 @@ RecordBuffers carve_records(Carver& cv, const BinPlan& p) {
   r.bin_start = cv.take<uint32_t>((size_t)p.nbins + 1);
   r.chunk_start = cv.take<uint32_t>((size_t)p.nbins + 1);
   r.chunk_bin = cv.take<uint32_t>((size_t)p.max_chunks);
-  r.sorted = cv.take<uint3>((size_t)p.max_records);
+  r.sorted = cv.take<uint3>((size_t)p.max_records);  // room for either record format
   return r;
 }
 
@@ -481,7 +481,7 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
     HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, b.dsigma, b.drgb, b.rec, b.partial, f->wo, grads, st),
             "field backward");
   HIP_TRY(mark(6), "profile event");
-  HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, grads, st), "table gradient");
+  HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, mixed, grads, st), "table gradient");
   HIP_TRY(mark(7), "profile event");
   HIP_TRY(field_dw_reduce(f->shape, b.partial, kBwdBlocks, f->wo, grads, st), "weight gradient");
   if (c->scale_state) HIP_TRY(scale_check(grads, total, c->scale_state, st), "loss scale");
@@ -609,7 +609,7 @@ int nsl_field_bwd(const nsl_field* f, const float* params, const float* xn, cons
   HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, dsigma, drgb, w.rec, w.partial, f->wo, grads, st),
           "field backward");
   HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, st), "weight gradient");
-  HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, grads, st), "table gradient");
+  HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, false, grads, st), "table gradient");
   return NSL_OK;
 }
 
@@ -644,7 +644,7 @@ int nsl_field_bwd_mixed(const nsl_field* f, const void* shadow, const float* xn,
   HIP_TRY(mixed_backward(f->shape, f->lv, shadow, src, kBwdBlocks, dsigma, drgb, w.rec, w.partial, f->wo, grads, st),
           "field backward (mixed)");
   HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, st), "weight gradient");
-  HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, grads, st), "table gradient");
+  HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, true, grads, st), "table gradient");
   return NSL_OK;
 }
 

@@ -56,7 +56,8 @@ struct RecordBuffers {
   uint32_t* bin_start;    // [nbins + 1]
   uint32_t* chunk_start;  // [nbins + 1]
   uint32_t* chunk_bin;    // [max_chunks] bin of each chunk
-  uint3* sorted;          // [max_records] (entry, g0, g1) grouped by bin
+  void* sorted;           // [max_records] records grouped by bin: (entry, g0, g1) as uint3, or
+                          // (entry, g0 | g1 << 16 in BF16) as uint2
 };
 
 struct BinPlan {
@@ -69,7 +70,7 @@ BinPlan bin_plan(uint32_t entries, int levels, int64_t max_samples);
 // grad_table += the table gradient of the samples of src, from the dL/de
 // that the backward kernel left in rb.de.
 hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
-                       float* grad_table, hipStream_t st);
+                       bool bf16_values, float* grad_table, hipStream_t st);
 
 // field.hip
 size_t field_prep_floats(int shape);

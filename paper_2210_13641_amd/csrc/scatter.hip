@@ -19,7 +19,9 @@
 //               (a bin of one chunk owns its entries; chunks of a bin with
 //               several add with atomics, one per touched entry)
 //
-// A record is (entry, w * dL/de_l0, w * dL/de_l1).  Count and place generate
+// A record is (entry, w * dL/de_l0, w * dL/de_l1), the values in FP32, or in
+// BF16 for the mixed-precision step (accumulated in FP32 all the same).
+// Count and place generate
 // the same records from the sample positions and dL/de: the 16 lanes of a
 // row hold 16 consecutive samples (mostly along one ray) at one level, equal
 // corners form runs of neighbouring lanes, and each run becomes one record
@@ -37,6 +39,34 @@ constexpr int kRecSamples = kRecWaves * kRecTilesPerWave * 16;      // samples p
 constexpr int kPlaceChunk = kRecWaves * kRecTilesPerWave * 64 * 8;  // records of one level group
 constexpr int kReduceThreads = 1024;
 constexpr int kReducePer = 8;                        // records in flight per thread
+
+// Record formats in the sorted array: FP32 values (entry, g0, g1), or, for
+// mixed precision, BF16 values (entry, g0 | g1 << 16).  Either way the
+// reduction accumulates in FP32.
+struct RecF32 {
+  typedef uint3 T;
+  static __device__ __forceinline__ T pack(uint32_t e, float a, float b) {
+    return make_uint3(e, __float_as_uint(a), __float_as_uint(b));
+  }
+  static __device__ __forceinline__ uint32_t key(const T& r) { return r.x; }
+  static __device__ __forceinline__ float2 val(const T& r) {
+    return make_float2(__uint_as_float(r.y), __uint_as_float(r.z));
+  }
+  static __device__ __forceinline__ T none() { return make_uint3(0xFFFFFFFFu, 0u, 0u); }
+};
+struct RecBF16 {
+  typedef uint2 T;
+  static __device__ __forceinline__ T pack(uint32_t e, float a, float b) {
+    const __bf16 x = (__bf16)a, y = (__bf16)b;
+    return make_uint2(e, (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16));
+  }
+  static __device__ __forceinline__ uint32_t key(const T& r) { return r.x; }
+  static __device__ __forceinline__ float2 val(const T& r) {
+    return make_float2((float)__builtin_bit_cast(__bf16, (uint16_t)(r.y & 0xFFFFu)),
+                       (float)__builtin_bit_cast(__bf16, (uint16_t)(r.y >> 16)));
+  }
+  static __device__ __forceinline__ T none() { return make_uint2(0xFFFFFFFFu, 0u); }
+};
 
 // The records of one level (l = g + 4q for lane group g) of one tile.
 struct LevelRecords {
@@ -184,14 +214,17 @@ __global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int n
 // count, ordered by bin in LDS (counting sort with LDS integer atomics), and
 // stored so that the global stores of a wave cover runs of consecutive slots
 // of a few bins instead of one cache line per lane.
+template <class R>
 __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, LevelInfo lv, RecordBuffers rb,
                                                                int nbins) {
+  typedef typename R::T Rec;
+  Rec* __restrict__ sorted = reinterpret_cast<Rec*>(rb.sorted);
   extern __shared__ uint32_t bins_lds[];  // gcur, cnt, lst: [nbins] each
   uint32_t* gcur = bins_lds;
   uint32_t* cnt = bins_lds + nbins;
   uint32_t* lst = bins_lds + 2 * nbins;
   __shared__ uint32_t wsum[kRecWaves];
-  __shared__ uint3 stage[kPlaceChunk];
+  __shared__ Rec stage[kPlaceChunk];
   const int t = threadIdx.x;
   const int blk = logical_block(gridDim.x);
   const uint32_t* off = rb.off + (size_t)blk * nbins;
@@ -248,21 +281,23 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
 #pragma unroll
       for (int k = 0; k < 8; ++k)
         if (r[j].on[k])
-          stage[lst[r[j].idx[k] >> kBinShift] + rank[j][k]] =
-              make_uint3(r[j].idx[k], __float_as_uint(r[j].v0[k]), __float_as_uint(r[j].v1[k]));
+          stage[lst[r[j].idx[k] >> kBinShift] + rank[j][k]] = R::pack(r[j].idx[k], r[j].v0[k], r[j].v1[k]);
     __syncthreads();
     for (uint32_t i = t; i < m; i += kRecThreads) {
-      const uint3 rec = stage[i];
-      const uint32_t b = rec.x >> kBinShift;
-      rb.sorted[gcur[b] + (i - lst[b])] = rec;
+      const Rec rec = stage[i];
+      const uint32_t b = R::key(rec) >> kBinShift;
+      sorted[gcur[b] + (i - lst[b])] = rec;
     }
     __syncthreads();
     for (int b = t; b < nbins; b += kRecThreads) gcur[b] += cnt[b];
   }
 }
 
+template <class R>
 __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffers rb, int nbins, uint32_t entries,
                                                                     float* __restrict__ grad_table) {
+  typedef typename R::T Rec;
+  const Rec* __restrict__ sorted = reinterpret_cast<const Rec*>(rb.sorted);
   // (g0, g1) of each entry as one 64-bit word: float pairs are added with
   // LDS 64-bit compare-and-swap, which retires far faster than LDS float
   // atomics on this architecture
@@ -277,17 +312,18 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
   __syncthreads();
   const uint32_t e0 = (uint32_t)b << kBinShift;
   for (uint32_t base = first; base < last; base += kReduceThreads * kReducePer) {
-    uint3 rec[kReducePer];
+    Rec rec[kReducePer];
 #pragma unroll
     for (int j = 0; j < kReducePer; ++j) {
       const uint32_t i = base + j * kReduceThreads + threadIdx.x;
-      rec[j] = i < last ? rb.sorted[i] : make_uint3(0xFFFFFFFFu, 0u, 0u);
+      rec[j] = i < last ? sorted[i] : R::none();
     }
 #pragma unroll
     for (int j = 0; j < kReducePer; ++j) {
-      if (rec[j].x == 0xFFFFFFFFu) continue;
-      const uint32_t e = rec[j].x - e0;
-      const float a = __uint_as_float(rec[j].y), cc = __uint_as_float(rec[j].z);
+      if (R::key(rec[j]) == 0xFFFFFFFFu) continue;
+      const uint32_t e = R::key(rec[j]) - e0;
+      const float2 v = R::val(rec[j]);
+      const float a = v.x, cc = v.y;
       unsigned long long seen = acc[e];
       for (;;) {
         const unsigned long long got = atomicCAS(&acc[e], seen, add_pair_bits(seen, a, cc));
@@ -330,16 +366,24 @@ BinPlan bin_plan(uint32_t entries, int levels, int64_t max_samples) {
 }
 
 hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
-                       float* grad_table, hipStream_t st) {
+                       bool bf16_values, float* grad_table, hipStream_t st) {
   if (p.nbins == 0 || p.nblk == 0) return hipSuccess;
   const size_t bins_lds = (size_t)p.nbins * sizeof(uint32_t);
   hipLaunchKernelGGL(bin_count_kernel, dim3(p.nblk), dim3(kRecThreads), bins_lds, st, src, lv, rb, p.nbins);
   hipLaunchKernelGGL(bin_colscan_kernel, dim3((p.nbins + 15) / 16), dim3(16 * kScanGroups), 0, st, rb, p.nbins,
                      p.nblk);
   hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins);
-  hipLaunchKernelGGL(bin_place_kernel, dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb, p.nbins);
-  hipLaunchKernelGGL(bin_reduce_kernel, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins, p.entries,
-                     grad_table);
+  if (bf16_values) {
+    hipLaunchKernelGGL(bin_place_kernel<RecBF16>, dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb,
+                       p.nbins);
+    hipLaunchKernelGGL(bin_reduce_kernel<RecBF16>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins,
+                       p.entries, grad_table);
+  } else {
+    hipLaunchKernelGGL(bin_place_kernel<RecF32>, dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb,
+                       p.nbins);
+    hipLaunchKernelGGL(bin_reduce_kernel<RecF32>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins,
+                       p.entries, grad_table);
+  }
   return hipGetLastError();
 }
 
