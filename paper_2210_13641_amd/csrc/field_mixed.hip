@@ -1,6 +1,6 @@
 // Mixed-precision hash-grid field on gfx950: FP16 tables, BF16 weights and
-// activations on v_mfma_f32_16x16x32_bf16 with FP32 accumulation, weight
-// gradients on v_mfma_f32_16x16x16_bf16 (samples on the contraction axis),
+// activations on v_mfma_f32_16x16x32_bf16 with FP32 accumulation (weight
+// gradients too, with samples on the contraction axis),
 // FP32 trilinear blending, FP32 table-gradient accumulation.
 //
 // Operand layouts follow the FP32 kernels (features as rows, 16 samples as
@@ -12,25 +12,31 @@
 namespace nsl {
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef short s4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f4 mfma32(bf8 a, bf8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
-__device__ __forceinline__ f4 mfma16(s4 a, s4 b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef short s8v __attribute__((ext_vector_type(8)));
+
+// Two floats as BF16 (round to nearest even), a in the low half; one
+// v_cvt_pk_bf16_f32.
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+  const bf2 v = {(__bf16)a, (__bf16)b};
+  return __builtin_bit_cast(uint32_t, v);
 }
 
 __device__ __forceinline__ bf8 pack8(f4 lo, f4 hi) {
-  bf8 r;
-  r[0] = (__bf16)lo[0]; r[1] = (__bf16)lo[1]; r[2] = (__bf16)lo[2]; r[3] = (__bf16)lo[3];
-  r[4] = (__bf16)hi[0]; r[5] = (__bf16)hi[1]; r[6] = (__bf16)hi[2]; r[7] = (__bf16)hi[3];
-  return r;
+  return __builtin_bit_cast(bf8, make_uint4(bf16_pair(lo[0], lo[1]), bf16_pair(lo[2], lo[3]),
+                                            bf16_pair(hi[0], hi[1]), bf16_pair(hi[2], hi[3])));
 }
 
-__device__ __forceinline__ short bf16_bits(float x) {
-  const __bf16 b = (__bf16)x;
-  return __builtin_bit_cast(short, b);
+// Element u of a as 16 bits.  The whole vector is reinterpreted first: the
+// gfx950 compiler lowers a bit cast of one extracted __bf16 element to
+// element 0 whatever the index.
+__device__ __forceinline__ uint32_t bf_bits(bf8 a, int u) {
+  return (uint32_t)(uint16_t)__builtin_bit_cast(s8v, a)[u];
 }
 
 // Layout of the BF16 operands (one block = 64 lanes x 8 values per (m, k-step)).
@@ -54,8 +60,6 @@ struct Mixed {
     return o;
   }
   static constexpr int BWD = boff(N::NW);
-  static constexpr int SROW = 20;  // bf16 per staged row (16 samples + pad)
-  static constexpr int STAGE = (N::XROWS + N::YROWS) * SROW;
 };
 
 // Input feature of forward k-slot (s, lane group g, value u) of layer j; -1 = pad.
@@ -224,28 +228,482 @@ __global__ __launch_bounds__(256) void mixed_fwd_kernel(LevelInfo lv, const _Flo
   }
 }
 
-// Stage a D-layout block as bf16 rows [feature][sample].
-template <class N, int TILES>
-__device__ __forceinline__ void stage_bf(__bf16* S, const f4* v, int g, int jc) {
+// ---------------------------------------------------------------------------
+// Backward: two 16-sample tiles per wave step.  Each weight operand read from
+// LDS feeds both tiles' MFMAs, so the two dependency chains overlap on the
+// one wave a SIMD holds.  Activations the backward needs are kept as the BF16
+// operands the next layer consumed; the weight-gradient products contract
+// over the 32 samples of the pair on v_mfma_f32_16x16x32_bf16, staged
+// [feature][sample] with the two tiles interleaved (column 2j + t), so every
+// staging store writes both tiles' values as one 32-bit word.
+// ---------------------------------------------------------------------------
+
+constexpr int kPairRow = 40;        // bf16 per staged row: 32 samples + pad
+constexpr int kPairRowW = kPairRow / 2;
+
+template <class N>
+struct PActs {
+  bf8 e;                   // layer-0 operand: encoding slots (zero beyond NSLOT)
+  bf8 h1[N::HD / 32];      // ReLU outputs of layer 0, as layer-1 operands
+  f4 o;                    // geometry output, FP32
+  bf8 osh;                 // layer-2 operand: geometry rows 4g.., SH 4g..
+  bf8 h3[N::HC / 32];
+  bf8 h4[N::HC / 32];      // second colour hidden layer (NCH == 2)
+  f4 z;                    // colour logits (rows 0..2 in lane group 0)
+};
+
+// Inputs of one tile: encoding slots, view direction, upstream gradients.
+template <class N>
+struct TileIn {
+  uint32_t e[N::LPL];      // BF16 pairs of levels g + 4q
+  float d[3];
+  float ds, dr[3];
+};
+
+// acc[r] where the ReLU output (element 4*half + r of p) is positive, else 0.
+__device__ __forceinline__ f4 relu_grad(f4 acc, bf8 p, int half) {
+  const s8v q = __builtin_bit_cast(s8v, p);
 #pragma unroll
-  for (int m = 0; m < TILES; ++m)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) S[(16 * m + 4 * g + r) * Mixed<N>::SROW + jc] = (__bf16)v[m][r];
+  for (int r = 0; r < 4; ++r) acc[r] = q[4 * half + r] > 0 ? acc[r] : 0.0f;
+  return acc;
 }
 
-template <class N, int KIN, int KOUT>
-__device__ __forceinline__ void dw_mixed(const __bf16* Xs, const __bf16* Ys, DWAcc<KIN, KOUT>& acc, int lane) {
-  constexpr int MI = DWAcc<KIN, KOUT>::MI, NJ = DWAcc<KIN, KOUT>::NJ, SR = Mixed<N>::SROW;
+template <class N, bool KEEP>
+__device__ __forceinline__ void fetch_tile(const SampleSrc& src, const _Float16* __restrict__ table,
+                                           const LevelInfo& lv, const LaneLevels<N>& ll,
+                                           const float* __restrict__ dsigma, const float* __restrict__ drgb, int s,
+                                           bool valid, int g, uint32_t ridx, TileIn<N>& in) {
+  in.d[0] = 0.0f; in.d[1] = 0.0f; in.d[2] = 1.0f;
+  if constexpr (KEEP) {
+    const uint32_t* ec = static_cast<const uint32_t*>(src.ecache);
+#pragma unroll
+    for (int q = 0; q < N::LPL; ++q) in.e[q] = valid ? ec[(size_t)(g + 4 * q) * src.ecache_stride + s] : 0u;
+    if (valid) {
+      if (src.t) {
+        const float4 dd = src.rays[2 * ridx + 1];
+        in.d[0] = dd.x; in.d[1] = dd.y; in.d[2] = dd.z;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) in.d[i] = src.dir[3 * s + i];
+      }
+    }
+  } else {
+    float xn[3] = {0.5f, 0.5f, 0.5f};
+    if (valid) load_sample(src, s, xn, in.d);
+    float e[N::NSLOT];
+    encode<N>(table, lv.table_mask, ll, xn, e);
+#pragma unroll
+    for (int q = 0; q < N::LPL; ++q) in.e[q] = valid ? bf16_pair(e[2 * q], e[2 * q + 1]) : 0u;
+  }
+  in.ds = 0.0f;
+  in.dr[0] = in.dr[1] = in.dr[2] = 0.0f;
+  if (g == 0 && valid) {
+    in.ds = dsigma[s];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) in.dr[r] = drgb[3 * s + r];
+  }
+}
+
+template <class N>
+__device__ __forceinline__ uint32_t ray_of(const SampleSrc& src, int s, int S) {
+  return src.t && s < S ? src.ray[s] : 0u;
+}
+
+// Forward of T tiles, interleaved layer by layer.
+template <class N, int T>
+__device__ __forceinline__ void fwd_tiles(const __bf16* __restrict__ Af, int lane, const f4 (&sh)[T],
+                                          PActs<N> (&a)[T]) {
+  using M = Mixed<N>;
+  constexpr f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  {
+    const __bf16* A = Af + M::foff(0);
+    f4 h[T][N::HD / 16];
+#pragma unroll
+    for (int m = 0; m < N::HD / 16; ++m) {
+      const bf8 w = lds_bf8<N>(A, m, lane);
+#pragma unroll
+      for (int t = 0; t < T; ++t) h[t][m] = relu4(mfma32(w, a[t].e, zero));
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int s = 0; s < N::HD / 32; ++s) a[t].h1[s] = pack8(h[t][2 * s], h[t][2 * s + 1]);
+  }
+  {
+    const __bf16* A = Af + M::foff(1);
+    f4 acc[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] = zero;
+#pragma unroll
+    for (int s = 0; s < N::HD / 32; ++s) {
+      const bf8 w = lds_bf8<N>(A, s, lane);
+#pragma unroll
+      for (int t = 0; t < T; ++t) acc[t] = mfma32(w, a[t].h1[s], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      a[t].o = acc[t];
+      a[t].osh = pack8(acc[t], sh[t]);
+    }
+  }
+  {
+    const __bf16* A = Af + M::foff(2);
+    f4 h[T][N::HC / 16];
+#pragma unroll
+    for (int m = 0; m < N::HC / 16; ++m) {
+      const bf8 w = lds_bf8<N>(A, m, lane);
+#pragma unroll
+      for (int t = 0; t < T; ++t) h[t][m] = relu4(mfma32(w, a[t].osh, zero));
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int s = 0; s < N::HC / 32; ++s) a[t].h3[s] = pack8(h[t][2 * s], h[t][2 * s + 1]);
+  }
+  if constexpr (N::NCH == 2) {
+    const __bf16* A = Af + M::foff(3);
+    f4 acc[T][N::HC / 16];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int m = 0; m < N::HC / 16; ++m) acc[t][m] = zero;
+#pragma unroll
+    for (int s = 0; s < N::HC / 32; ++s)
+#pragma unroll
+      for (int m = 0; m < N::HC / 16; ++m) {
+        const bf8 w = lds_bf8<N>(A, m * (N::HC / 32) + s, lane);
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[t][m] = mfma32(w, a[t].h3[s], acc[t][m]);
+      }
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int s = 0; s < N::HC / 32; ++s) a[t].h4[s] = pack8(relu4(acc[t][2 * s]), relu4(acc[t][2 * s + 1]));
+  }
+  {
+    const __bf16* A = Af + M::foff(N::NW - 1);
+    f4 acc[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) acc[t] = zero;
+#pragma unroll
+    for (int s = 0; s < N::HC / 32; ++s) {
+      const bf8 w = lds_bf8<N>(A, s, lane);
+#pragma unroll
+      for (int t = 0; t < T; ++t) acc[t] = mfma32(w, N::NCH == 2 ? a[t].h4[s] : a[t].h3[s], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t) a[t].z = acc[t];
+  }
+}
+
+// Staging rows (u32 words: column pair j of row f at f * kPairRowW + j).
+// MB 16-row blocks of a packed activation of the two tiles.
+template <int MB>
+__device__ __forceinline__ void stage_packed(uint32_t* S, const bf8* a0, const bf8* a1, int g, int jc) {
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int u = 4 * (m & 1) + r;
+      S[(16 * m + 4 * g + r) * kPairRowW + jc] = bf_bits(a0[m >> 1], u) | (bf_bits(a1[m >> 1], u) << 16);
+    }
+}
+template <int MB>
+__device__ __forceinline__ void stage_f32(uint32_t* S, const f4* v0, const f4* v1, int g, int jc) {
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) S[(16 * m + 4 * g + r) * kPairRowW + jc] = bf16_pair(v0[m][r], v1[m][r]);
+}
+
+// acc += X^T dY over the 32 staged samples.
+template <int KIN, int KOUT>
+__device__ __forceinline__ void dw_pair(const __bf16* Xs, const __bf16* Ys, DWAcc<KIN, KOUT>& acc, int lane) {
+  constexpr int MI = DWAcc<KIN, KOUT>::MI, NJ = DWAcc<KIN, KOUT>::NJ;
   const int gk = lane >> 4, i = lane & 15;
-  s4 xa[MI], yb[NJ];
+  bf8 xa[MI], yb[NJ];
 #pragma unroll
-  for (int m = 0; m < MI; ++m) xa[m] = *reinterpret_cast<const s4*>(Xs + (16 * m + i) * SR + 4 * gk);
+  for (int m = 0; m < MI; ++m) xa[m] = *reinterpret_cast<const bf8*>(Xs + (16 * m + i) * kPairRow + 8 * gk);
 #pragma unroll
-  for (int n = 0; n < NJ; ++n) yb[n] = *reinterpret_cast<const s4*>(Ys + (16 * n + i) * SR + 4 * gk);
+  for (int n = 0; n < NJ; ++n) yb[n] = *reinterpret_cast<const bf8*>(Ys + (16 * n + i) * kPairRow + 8 * gk);
 #pragma unroll
   for (int m = 0; m < MI; ++m)
 #pragma unroll
-    for (int n = 0; n < NJ; ++n) acc.v[m * NJ + n] = mfma16(xa[m], yb[n], acc.v[m * NJ + n]);
+    for (int n = 0; n < NJ; ++n) acc.v[m * NJ + n] = mfma32(xa[m], yb[n], acc.v[m * NJ + n]);
+}
+
+template <class N>
+struct PairAcc {
+  DWAcc<N::ENC, N::HD> w0;
+  DWAcc<N::HD, 16> w1;
+  DWAcc<N::CIN, N::HC> w2;
+  DWAcc<N::HC, N::HC> w3;  // second colour hidden layer (unused with one)
+  DWAcc<N::HC, 3> wl;
+};
+
+// dL/de of a tile pair held back one pair: stored after the next pair's
+// forward, so the stores are in flight while that pair computes instead of
+// being waited for with the next pair's prefetched inputs.
+template <class N>
+struct PendingDe {
+  f4 de[2][N::bmt(0)];
+  int s[2];
+  bool valid[2];
+  // this lane's levels g + 4q, level-major: the 16 lanes of a row store 16
+  // consecutive samples of one level
+  __device__ __forceinline__ void store(const RecordBuffers& rec, int g) const {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      if (valid[t]) {
+#pragma unroll
+        for (int q = 0; q < N::LPL; ++q) {
+          const int k0 = 2 * q, k1 = 2 * q + 1;
+          rec.de[(size_t)(g + 4 * q) * rec.stride + s[t]] =
+              make_float2(de[t][k0 >> 2][k0 & 3], de[t][k1 >> 2][k1 & 3]);
+        }
+      }
+    }
+  }
+};
+
+// Forward recompute, backward chain, weight-gradient products and dL/de of
+// one tile pair (tiles t: samples 32p + 16t + jc); the previous pair's
+// dL/de (pend) is stored after the forward and replaced by this pair's.
+template <class N>
+__device__ __forceinline__ void bwd_pair(const __bf16* __restrict__ Af, const __bf16* __restrict__ Ab,
+                                         __bf16* Xs, __bf16* Ys, const TileIn<N> (&in)[2], const int (&s)[2],
+                                         const bool (&valid)[2], const RecordBuffers& rec, PairAcc<N>& dw,
+                                         PendingDe<N>& pend, int lane) {
+  using M = Mixed<N>;
+  constexpr int T = 2;
+  constexpr f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  const int g = lane >> 4, jc = lane & 15;
+  uint32_t* Xw = reinterpret_cast<uint32_t*>(Xs);
+  uint32_t* Yw = reinterpret_cast<uint32_t*>(Ys);
+  PActs<N> a[T];
+  f4 sh[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w[q] = q < N::LPL ? in[t].e[q < N::LPL ? q : 0] : 0u;
+    a[t].e = __builtin_bit_cast(bf8, make_uint4(w[0], w[1], w[2], w[3]));
+    float shv[4];
+    sh_lane<N>(in[t].d, g, shv);
+    sh[t] = f4{shv[0], shv[1], shv[2], shv[3]};
+  }
+  fwd_tiles<N, T>(Af, lane, sh, a);
+  pend.store(rec, g);
+
+  f4 dz[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    dz[t] = zero;
+    if (g == 0) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const float c = sigmoidf(a[t].z[r]);
+        dz[t][r] = in[t].dr[r] * c * (1.0f - c);
+      }
+    }
+  }
+  // last colour layer
+  f4 dhl[T][N::HC / 16];
+  {
+    const __bf16* A = Ab + M::boff(N::NW - 1);
+    bf8 b[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) b[t] = pack8(dz[t], zero);
+#pragma unroll
+    for (int m = 0; m < N::HC / 16; ++m) {
+      const bf8 w = lds_bf8<N>(A, m, lane);
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+        dhl[t][m] = relu_grad(mfma32(w, b[t], zero), N::NCH == 2 ? a[t].h4[m >> 1] : a[t].h3[m >> 1], m & 1);
+    }
+  }
+  stage_packed<N::HC / 16>(Xw, N::NCH == 2 ? a[0].h4 : a[0].h3, N::NCH == 2 ? a[1].h4 : a[1].h3, g, jc);
+  stage_f32<1>(Yw, &dz[0], &dz[1], g, jc);
+  wave_lds_fence();
+  dw_pair(Xs, Ys, dw.wl, lane);
+  wave_lds_fence();
+
+  f4 dh3[T][N::HC / 16];
+  if constexpr (N::NCH == 2) {
+    const __bf16* A = Ab + M::boff(3);
+    f4 acc[T][N::HC / 16];
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int m = 0; m < N::HC / 16; ++m) acc[t][m] = zero;
+#pragma unroll
+    for (int k = 0; k < N::HC / 32; ++k) {
+      bf8 b[T];
+#pragma unroll
+      for (int t = 0; t < T; ++t) b[t] = pack8(dhl[t][2 * k], dhl[t][2 * k + 1]);
+#pragma unroll
+      for (int m = 0; m < N::HC / 16; ++m) {
+        const bf8 w = lds_bf8<N>(A, m * (N::HC / 32) + k, lane);
+#pragma unroll
+        for (int t = 0; t < T; ++t) acc[t][m] = mfma32(w, b[t], acc[t][m]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int m = 0; m < N::HC / 16; ++m) dh3[t][m] = relu_grad(acc[t][m], a[t].h3[m >> 1], m & 1);
+    stage_packed<N::HC / 16>(Xw, a[0].h3, a[1].h3, g, jc);
+    stage_f32<N::HC / 16>(Yw, dhl[0], dhl[1], g, jc);
+    wave_lds_fence();
+    dw_pair(Xs, Ys, dw.w3, lane);
+    wave_lds_fence();
+  } else {
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int m = 0; m < N::HC / 16; ++m) dh3[t][m] = dhl[t][m];
+  }
+  // first colour layer: gradient of the geometry features
+  f4 dgeo[T];
+  {
+    const __bf16* A = Ab + M::boff(2);
+#pragma unroll
+    for (int t = 0; t < T; ++t) dgeo[t] = zero;
+#pragma unroll
+    for (int k = 0; k < N::HC / 32; ++k) {
+      const bf8 w = lds_bf8<N>(A, k, lane);
+#pragma unroll
+      for (int t = 0; t < T; ++t) dgeo[t] = mfma32(w, pack8(dh3[t][2 * k], dh3[t][2 * k + 1]), dgeo[t]);
+    }
+  }
+  stage_packed<2>(Xw, &a[0].osh, &a[1].osh, g, jc);
+  stage_f32<N::HC / 16>(Yw, dh3[0], dh3[1], g, jc);
+  wave_lds_fence();
+  dw_pair(Xs, Ys, dw.w2, lane);
+  wave_lds_fence();
+  if (g == 0) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) dgeo[t][0] += expf(a[t].o[0]) * in[t].ds;
+  }
+  // second density layer
+  f4 dh1[T][N::HD / 16];
+  {
+    const __bf16* A = Ab + M::boff(1);
+    bf8 b[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) b[t] = pack8(dgeo[t], zero);
+#pragma unroll
+    for (int m = 0; m < N::HD / 16; ++m) {
+      const bf8 w = lds_bf8<N>(A, m, lane);
+#pragma unroll
+      for (int t = 0; t < T; ++t) dh1[t][m] = relu_grad(mfma32(w, b[t], zero), a[t].h1[m >> 1], m & 1);
+    }
+  }
+  stage_packed<N::HD / 16>(Xw, a[0].h1, a[1].h1, g, jc);
+  stage_f32<1>(Yw, &dgeo[0], &dgeo[1], g, jc);
+  wave_lds_fence();
+  dw_pair(Xs, Ys, dw.w1, lane);
+  wave_lds_fence();
+  // first density layer: dL/de
+  constexpr int MT0 = N::bmt(0);
+  f4 de[T][MT0];
+  {
+    const __bf16* A = Ab + M::boff(0);
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+#pragma unroll
+      for (int m = 0; m < MT0; ++m) de[t][m] = zero;
+#pragma unroll
+    for (int k = 0; k < N::HD / 32; ++k) {
+      bf8 b[T];
+#pragma unroll
+      for (int t = 0; t < T; ++t) b[t] = pack8(dh1[t][2 * k], dh1[t][2 * k + 1]);
+#pragma unroll
+      for (int m = 0; m < MT0; ++m) {
+        const bf8 w = lds_bf8<N>(A, m * (N::HD / 32) + k, lane);
+#pragma unroll
+        for (int t = 0; t < T; ++t) de[t][m] = mfma32(w, b[t], de[t][m]);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < N::NSLOT; ++k)
+    Xw[fwd_in_feature<N>(0, k, g) * kPairRowW + jc] = bf_bits(a[0].e, k) | (bf_bits(a[1].e, k) << 16);
+  if constexpr (N::ENC < 16) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) Xw[(N::ENC + 2 * g + k) * kPairRowW + jc] = 0u;
+  }
+  stage_f32<N::HD / 16>(Yw, dh1[0], dh1[1], g, jc);
+  wave_lds_fence();
+  dw_pair(Xs, Ys, dw.w0, lane);
+  wave_lds_fence();
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    pend.s[t] = s[t];
+    pend.valid[t] = valid[t];
+#pragma unroll
+    for (int m = 0; m < MT0; ++m) pend.de[t][m] = de[t][m];
+  }
+}
+
+// Tile pairs of a wave: pair p, p + step, ...  With the kept encoding, the
+// next pair's inputs are fetched while this pair computes (ray indices two
+// pairs ahead, so the dependent direction load has its index in hand).
+template <class N, bool KEEP>
+__device__ __forceinline__ void bwd_pairs(const __bf16* __restrict__ Af, const __bf16* __restrict__ Ab,
+                                          const _Float16* __restrict__ table, const LevelInfo& lv,
+                                          const SampleSrc& src, const float* __restrict__ dsigma,
+                                          const float* __restrict__ drgb, const RecordBuffers& rec, __bf16* Xs,
+                                          __bf16* Ys, PairAcc<N>& dw, int first, int step, int S, int lane) {
+  const int g = lane >> 4, jc = lane & 15;
+  const int npairs = (S + 31) / 32;
+  LaneLevels<N> ll;
+  lane_levels<N>(lv, g, ll);
+  TileIn<N> cur[2];
+  uint32_t rid1[2] = {0u, 0u};
+  PendingDe<N> pend;
+  pend.valid[0] = pend.valid[1] = false;
+  pend.s[0] = pend.s[1] = 0;
+  if constexpr (KEEP) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int s0 = 32 * first + 16 * t + jc;
+      fetch_tile<N, true>(src, table, lv, ll, dsigma, drgb, s0, s0 < S, g, ray_of<N>(src, s0, S), cur[t]);
+      rid1[t] = ray_of<N>(src, 32 * (first + step) + 16 * t + jc, S);
+    }
+  }
+  for (int p = first; p < npairs; p += step) {
+    int s[2];
+    bool valid[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      s[t] = 32 * p + 16 * t + jc;
+      valid[t] = s[t] < S;
+    }
+    TileIn<N> nxt[2];
+    uint32_t rid2[2];
+    if constexpr (KEEP) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int s1 = 32 * (p + step) + 16 * t + jc;
+        fetch_tile<N, true>(src, table, lv, ll, dsigma, drgb, s1, s1 < S, g, rid1[t], nxt[t]);
+        rid2[t] = ray_of<N>(src, 32 * (p + 2 * step) + 16 * t + jc, S);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+        fetch_tile<N, false>(src, table, lv, ll, dsigma, drgb, s[t], valid[t], g, 0u, cur[t]);
+    }
+    bwd_pair<N>(Af, Ab, Xs, Ys, cur, s, valid, rec, dw, pend, lane);
+    if constexpr (KEEP) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        cur[t] = nxt[t];
+        rid1[t] = rid2[t];
+      }
+    }
+  }
+  pend.store(rec, g);
 }
 
 // kMixedBwdWaves waves per workgroup, one per SIMD: the weight-gradient
@@ -257,186 +715,43 @@ __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(Le
                                                            const float* __restrict__ drgb, RecordBuffers rec,
                                                            float* __restrict__ dw_partial) {
   using M = Mixed<N>;
+  constexpr int STAGE = (N::XROWS + N::YROWS) * kPairRow;
   __shared__ __attribute__((aligned(16))) __bf16 Af[M::FWD];
   __shared__ __attribute__((aligned(16))) __bf16 Ab[M::BWD];
   __shared__ __attribute__((aligned(16))) float dW[N::NWEIGHTS];
-  __shared__ __attribute__((aligned(16))) __bf16 stage_all[kMixedBwdWaves * M::STAGE];
+  __shared__ __attribute__((aligned(16))) __bf16 stage_all[kMixedBwdWaves * STAGE];
   load_bf16<N>(Af, prep, M::FWD);
   load_bf16<N>(Ab, prep + M::FWD, M::BWD);
   for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) dW[i] = 0.0f;
   __syncthreads();
 
   const int S = src.n_dev ? (int)*src.n_dev : src.n;
-  const int ntiles = (S + 15) / 16;
   const int wave = threadIdx.x / kWave;
-  const int lane = lane_id(), g = lane >> 4, jc = lane & 15;
-  __bf16* Xs = stage_all + wave * M::STAGE;
-  __bf16* Ys = Xs + N::XROWS * M::SROW;
-  LaneLevels<N> ll;
-  lane_levels<N>(lv, g, ll);
-  constexpr f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-  const int region = blockIdx.x * kMixedBwdWaves + wave;
-  DWAcc<N::ENC, N::HD> dw0;
-  DWAcc<N::HD, 16> dw1;
-  DWAcc<N::CIN, N::HC> dw2;
-  DWAcc<N::HC, N::HC> dw3;  // second colour hidden layer (unused with one)
-  DWAcc<N::HC, 3> dwl;
-  dw0.zero(); dw1.zero(); dw2.zero(); dwl.zero();
-  if constexpr (N::NCH == 2) dw3.zero();
-
-  for (int tile = region; tile < ntiles; tile += gridDim.x * kMixedBwdWaves) {
-    const int s = tile * 16 + jc;
-    const bool valid = s < S;
-    float xn[3] = {0.5f, 0.5f, 0.5f}, d[3] = {0.0f, 0.0f, 1.0f};
-    if (valid) load_sample(src, s, xn, d);
-    MActs<N> act;
-    if (src.ecache) {
-      read_encoding<N>(static_cast<const uint32_t*>(src.ecache), src.ecache_stride, g, s, valid, act.e);
-    } else {
-      encode<N>(table, lv.table_mask, ll, xn, act.e);
-      if (!valid) {
-#pragma unroll
-        for (int k = 0; k < N::NSLOT; ++k) act.e[k] = 0.0f;
-      }
-    }
-    sh_lane<N>(d, g, act.sh);
-    mlp_fwd_mixed<N>(Af, lane, act);
-
-    float ds = 0.0f;
-    f4 dz = zero;
-    if (g == 0 && valid) {
-      ds = dsigma[s];
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const float c = sigmoidf(act.z[r]);
-        dz[r] = drgb[3 * s + r] * c * (1.0f - c);
-      }
-    }
-    const f4* hl = (N::NCH == 2) ? act.h4 : act.h3;
-    f4 dhl[N::HC / 16];
-    {
-      const bf8 b = pack8(dz, zero);
-      const __bf16* A = Ab + M::boff(N::NW - 1);
-#pragma unroll
-      for (int m = 0; m < N::HC / 16; ++m) {
-        f4 acc = mfma32(lds_bf8<N>(A, m, lane), b, zero);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = hl[m][r] > 0.0f ? acc[r] : 0.0f;
-        dhl[m] = acc;
-      }
-    }
-    stage_bf<N, N::HC / 16>(Xs, hl, g, jc);
-    stage_bf<N, 1>(Ys, &dz, g, jc);
-    wave_lds_fence();
-    dw_mixed<N, N::HC, 3>(Xs, Ys, dwl, lane);
-    wave_lds_fence();
-
-    f4 dh3[N::HC / 16];
-    if constexpr (N::NCH == 2) {
-      const __bf16* A = Ab + M::boff(3);
-      f4 acc[N::HC / 16];
-#pragma unroll
-      for (int m = 0; m < N::HC / 16; ++m) acc[m] = zero;
-#pragma unroll
-      for (int k = 0; k < N::HC / 32; ++k) {
-        const bf8 b = pack8(dhl[2 * k], dhl[2 * k + 1]);
-#pragma unroll
-        for (int m = 0; m < N::HC / 16; ++m) acc[m] = mfma32(lds_bf8<N>(A, m * (N::HC / 32) + k, lane), b, acc[m]);
-      }
-#pragma unroll
-      for (int m = 0; m < N::HC / 16; ++m) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[m][r] = act.h3[m][r] > 0.0f ? acc[m][r] : 0.0f;
-        dh3[m] = acc[m];
-      }
-      stage_bf<N, N::HC / 16>(Xs, act.h3, g, jc);
-      stage_bf<N, N::HC / 16>(Ys, dhl, g, jc);
-      wave_lds_fence();
-      dw_mixed<N, N::HC, N::HC>(Xs, Ys, dw3, lane);
-      wave_lds_fence();
-    } else {
-#pragma unroll
-      for (int m = 0; m < N::HC / 16; ++m) dh3[m] = dhl[m];
-    }
-    f4 dgeo = zero;
-    {
-      const __bf16* A = Ab + M::boff(2);
-#pragma unroll
-      for (int k = 0; k < N::HC / 32; ++k) dgeo = mfma32(lds_bf8<N>(A, k, lane), pack8(dh3[2 * k], dh3[2 * k + 1]), dgeo);
-    }
-    stage_bf<N, 1>(Xs, &act.o, g, jc);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Xs[(16 + 4 * g + r) * M::SROW + jc] = (__bf16)act.sh[r];
-    stage_bf<N, N::HC / 16>(Ys, dh3, g, jc);
-    wave_lds_fence();
-    dw_mixed<N, N::CIN, N::HC>(Xs, Ys, dw2, lane);
-    wave_lds_fence();
-    if (g == 0) dgeo[0] += expf(act.o[0]) * ds;
-    f4 dh1[N::HD / 16];
-    {
-      const bf8 b = pack8(dgeo, zero);
-      const __bf16* A = Ab + M::boff(1);
-#pragma unroll
-      for (int m = 0; m < N::HD / 16; ++m) {
-        f4 acc = mfma32(lds_bf8<N>(A, m, lane), b, zero);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = act.h1[m][r] > 0.0f ? acc[r] : 0.0f;
-        dh1[m] = acc;
-      }
-    }
-    stage_bf<N, N::HD / 16>(Xs, act.h1, g, jc);
-    stage_bf<N, 1>(Ys, &dgeo, g, jc);
-    wave_lds_fence();
-    dw_mixed<N, N::HD, 16>(Xs, Ys, dw1, lane);
-    wave_lds_fence();
-    constexpr int MT0 = N::bmt(0);
-    f4 de[MT0];
-    {
-      const __bf16* A = Ab + M::boff(0);
-#pragma unroll
-      for (int m = 0; m < MT0; ++m) de[m] = zero;
-#pragma unroll
-      for (int k = 0; k < N::HD / 32; ++k) {
-        const bf8 b = pack8(dh1[2 * k], dh1[2 * k + 1]);
-#pragma unroll
-        for (int m = 0; m < MT0; ++m) de[m] = mfma32(lds_bf8<N>(A, m * (N::HD / 32) + k, lane), b, de[m]);
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < N::NSLOT; ++k) Xs[fwd_in_feature<N>(0, k, g) * M::SROW + jc] = (__bf16)act.e[k];
-    if constexpr (N::ENC < 16) {
-#pragma unroll
-      for (int k = 0; k < 2; ++k) Xs[(N::ENC + 2 * g + k) * M::SROW + jc] = (__bf16)0.0f;
-    }
-    stage_bf<N, N::HD / 16>(Ys, dh1, g, jc);
-    wave_lds_fence();
-    dw_mixed<N, N::ENC, N::HD>(Xs, Ys, dw0, lane);
-    wave_lds_fence();
-    // dL/de of this lane's levels g + 4q, level-major: the 16 lanes of a row
-    // store 16 consecutive samples of one level
-    if (valid) {
-#pragma unroll
-      for (int q = 0; q < N::LPL; ++q) {
-        const int k0 = 2 * q, k1 = 2 * q + 1;
-        rec.de[(size_t)(g + 4 * q) * rec.stride + s] = make_float2(de[k0 >> 2][k0 & 3], de[k1 >> 2][k1 & 3]);
-      }
-    }
-  }
+  const int lane = lane_id();
+  __bf16* Xs = stage_all + wave * STAGE;
+  __bf16* Ys = Xs + N::XROWS * kPairRow;
+  PairAcc<N> dw;
+  dw.w0.zero(); dw.w1.zero(); dw.w2.zero(); dw.wl.zero();
+  if constexpr (N::NCH == 2) dw.w3.zero();
+  const int first = blockIdx.x * kMixedBwdWaves + wave, step = gridDim.x * kMixedBwdWaves;
+  if (src.ecache)
+    bwd_pairs<N, true>(Af, Ab, table, lv, src, dsigma, drgb, rec, Xs, Ys, dw, first, step, S, lane);
+  else
+    bwd_pairs<N, false>(Af, Ab, table, lv, src, dsigma, drgb, rec, Xs, Ys, dw, first, step, S, lane);
   for (int w = 0; w < kMixedBwdWaves; ++w) {
     __syncthreads();
     if (wave == w) {
-      dw0.flush(dW + N::woff(0), lane);
-      dw1.flush(dW + N::woff(1), lane);
-      dw2.flush(dW + N::woff(2), lane);
-      if constexpr (N::NCH == 2) dw3.flush(dW + N::woff(3), lane);
-      dwl.flush(dW + N::woff(N::NW - 1), lane);
+      dw.w0.flush(dW + N::woff(0), lane);
+      dw.w1.flush(dW + N::woff(1), lane);
+      dw.w2.flush(dW + N::woff(2), lane);
+      if constexpr (N::NCH == 2) dw.w3.flush(dW + N::woff(3), lane);
+      dw.wl.flush(dW + N::woff(N::NW - 1), lane);
     }
   }
   __syncthreads();
   float* out = dw_partial + (size_t)blockIdx.x * N::NWEIGHTS;
   for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) out[i] = dW[i];
 }
-
 
 // ---------------------------------------------------------------------------
 // Host launchers.  Shadow buffer: BF16 operands (forward, then backward),
