@@ -23,6 +23,11 @@
  *    (nsl_field, nsl_mapper) are small host allocations.
  *  - Calls are asynchronous on the given stream; results are valid after the
  *    stream is synchronised.  Pointers must stay valid until then.
+ *  - Parameter vectors (params, grads, Adam moments, the params of render
+ *    requests) and mixed-precision shadows are 16-byte aligned: the kernels
+ *    read them with 16-byte loads.  Calls that receive them reject other
+ *    addresses with NSL_E_INVALID (render requests are device records and
+ *    are not checked).
  *  - Camera model: pinhole, OpenCV axes (x right, y down, z forward);
  *    pose = camera-to-world [R | t], 3x4 row-major float; intrinsics
  *    (fx, fy, cx, cy); pixel (u, v) has its centre at (u+1/2, v+1/2).

@@ -42,6 +42,9 @@ int hip_fail(hipError_t e, const char* what) {
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
+// Parameter vectors and shadows are read with 16-byte loads.
+bool misaligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) != 0; }
+
 // Sequential carving of a caller buffer into 256-byte aligned pieces.
 struct Carver {
   char* base;
@@ -424,6 +427,8 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   if (rc) return rc;
   if ((rc = check_ids_range(m, n))) return rc;
   if (c->do_adam && (!adam_m || !adam_v)) return fail(NSL_E_INVALID, "adam needs m and v");
+  if (misaligned(params) || misaligned(grads) || (c->do_adam && (misaligned(adam_m) || misaligned(adam_v))))
+    return fail(NSL_E_INVALID, "params, grads and Adam moments must be 16-byte aligned");
   if (c->sampler == NSL_SAMPLER_OCCUPANCY && m->grid_res < 1) return fail(NSL_E_INVALID, "no occupancy grid");
   if (ws_bytes < nsl_step_workspace_bytes(f, c, n)) return fail(NSL_E_WORKSPACE, "step workspace too small");
   StepBuffers b;
@@ -587,6 +592,7 @@ static int field_common(const nsl_field* f, const float* params, const float* xn
 int nsl_field_fwd(const nsl_field* f, const float* params, const float* xn, const float* dirs, int S, float* sigma,
                   float* rgb, void* ws, size_t ws_bytes, hipStream_t st) {
   if (!sigma || !rgb) return fail(NSL_E_INVALID, "null output");
+  if (misaligned(params)) return fail(NSL_E_INVALID, "params must be 16-byte aligned");
   FieldWs w;
   SampleSrc src;
   int rc = field_common(f, params, xn, dirs, S, ws, ws_bytes, false, w, src);
@@ -600,6 +606,7 @@ int nsl_field_fwd(const nsl_field* f, const float* params, const float* xn, cons
 int nsl_field_bwd(const nsl_field* f, const float* params, const float* xn, const float* dirs, int S,
                   const float* dsigma, const float* drgb, float* grads, void* ws, size_t ws_bytes, hipStream_t st) {
   if (!dsigma || !drgb || !grads) return fail(NSL_E_INVALID, "null argument");
+  if (misaligned(params) || misaligned(grads)) return fail(NSL_E_INVALID, "params and grads must be 16-byte aligned");
   FieldWs w;
   SampleSrc src;
   int rc = field_common(f, params, xn, dirs, S, ws, ws_bytes, false, w, src);
@@ -619,6 +626,7 @@ size_t nsl_mixed_shadow_bytes(const nsl_field* f) {
 
 int nsl_field_prepare_mixed(const nsl_field* f, const float* params, void* shadow, hipStream_t st) {
   if (!f || !params || !shadow) return fail(NSL_E_INVALID, "null argument");
+  if (misaligned(params) || misaligned(shadow)) return fail(NSL_E_INVALID, "params and shadow must be 16-byte aligned");
   HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, shadow, st), "prepare mixed");
   return NSL_OK;
 }
@@ -626,6 +634,7 @@ int nsl_field_prepare_mixed(const nsl_field* f, const float* params, void* shado
 int nsl_field_fwd_mixed(const nsl_field* f, const void* shadow, const float* xn, const float* dirs, int S,
                         float* sigma, float* rgb, hipStream_t st) {
   if (!f || !shadow || !xn || !dirs || !sigma || !rgb) return fail(NSL_E_INVALID, "null argument");
+  if (misaligned(shadow)) return fail(NSL_E_INVALID, "shadow must be 16-byte aligned");
   if (S < 0) return fail(NSL_E_INVALID, "negative sample count");
   SampleSrc src{};
   src.xn = xn; src.dir = dirs; src.box = f->box; src.n = S;
@@ -637,6 +646,7 @@ int nsl_field_bwd_mixed(const nsl_field* f, const void* shadow, const float* xn,
                         const float* dsigma, const float* drgb, float* grads, void* ws, size_t ws_bytes,
                         hipStream_t st) {
   if (!f || !shadow || !dsigma || !drgb || !grads) return fail(NSL_E_INVALID, "null argument");
+  if (misaligned(shadow) || misaligned(grads)) return fail(NSL_E_INVALID, "shadow and grads must be 16-byte aligned");
   FieldWs w;
   SampleSrc src;
   int rc = field_common(f, nullptr, xn, dirs, S, ws, ws_bytes, true, w, src);
@@ -676,6 +686,8 @@ int nsl_composite_bwd(const float* sigma, const float* rgb, const float* t, cons
 int nsl_adam(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps, int step,
              float grad_scale, hipStream_t st) {
   if (!p || !g || !m || !v) return fail(NSL_E_INVALID, "null argument");
+  if (misaligned(p) || misaligned(g) || misaligned(m) || misaligned(v))
+    return fail(NSL_E_INVALID, "params, grads and moments must be 16-byte aligned");
   if (n < 0 || step < 1) return fail(NSL_E_INVALID, "bad count or step");
   HIP_TRY(adam_update(p, g, m, v, n, lr, b1, b2, eps, step, grad_scale, nullptr, st), "adam");
   return NSL_OK;
@@ -707,6 +719,7 @@ size_t nsl_field_prepared_bytes(const nsl_field* f) {
 
 int nsl_field_prepare(const nsl_field* f, const float* params, void* prepared, hipStream_t st) {
   if (!f || !params || !prepared) return fail(NSL_E_INVALID, "null argument");
+  if (misaligned(params)) return fail(NSL_E_INVALID, "params must be 16-byte aligned");
   HIP_TRY(field_prep(f->shape, params, f->wo, static_cast<float*>(prepared), st), "prepare");
   return NSL_OK;
 }

@@ -112,26 +112,27 @@ __global__ void mixed_prep_kernel(const float* __restrict__ params, WOffsets wo,
   out[idx] = (__bf16)v;
 }
 
-__global__ void table_to_half_kernel(const float* __restrict__ t, _Float16* __restrict__ h, int64_t n2) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n2) return;
-  const float2 v = reinterpret_cast<const float2*>(t)[i];
-  h2 o;
-  o[0] = (_Float16)v.x;
-  o[1] = (_Float16)v.y;
-  reinterpret_cast<h2*>(h)[i] = o;
+// FP16 copy of the FP32 table, four entries (eight values) per thread.
+__global__ __launch_bounds__(256) void table_to_half_kernel(const float* __restrict__ t, _Float16* __restrict__ h,
+                                                            int64_t n2) {
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i + 4 <= n2) {
+    const float4 a = reinterpret_cast<const float4*>(t)[i / 2];
+    const float4 b = reinterpret_cast<const float4*>(t)[i / 2 + 1];
+    typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+    const h8 o = {(_Float16)a.x, (_Float16)a.y, (_Float16)a.z, (_Float16)a.w,
+                  (_Float16)b.x, (_Float16)b.y, (_Float16)b.z, (_Float16)b.w};
+    *reinterpret_cast<h8*>(h + 2 * i) = o;
+  } else {
+    for (int64_t k = i; k < n2; ++k) {
+      const float2 v = reinterpret_cast<const float2*>(t)[k];
+      h2 o;
+      o[0] = (_Float16)v.x;
+      o[1] = (_Float16)v.y;
+      reinterpret_cast<h2*>(h)[k] = o;
+    }
+  }
 }
-
-template <class N>
-struct MActs {
-  float e[N::NSLOT];
-  f4 h1[N::HD / 16];
-  f4 o;
-  float sh[4];
-  f4 h3[N::HC / 16];
-  f4 h4[N::HC / 16];
-  f4 z;
-};
 
 template <class N>
 __device__ __forceinline__ bf8 lds_bf8(const __bf16* A, int block, int lane) {
@@ -139,93 +140,9 @@ __device__ __forceinline__ bf8 lds_bf8(const __bf16* A, int block, int lane) {
 }
 
 template <class N>
-__device__ __forceinline__ void mlp_fwd_mixed(const __bf16* __restrict__ Af, int lane, MActs<N>& a) {
-  using M = Mixed<N>;
-  constexpr f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-  {
-    bf8 b;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) b[u] = (__bf16)(u < N::NSLOT ? a.e[u < N::NSLOT ? u : 0] : 0.0f);
-    const __bf16* A = Af + M::foff(0);
-#pragma unroll
-    for (int m = 0; m < N::HD / 16; ++m) a.h1[m] = relu4(mfma32(lds_bf8<N>(A, m, lane), b, zero));
-  }
-  {
-    const __bf16* A = Af + M::foff(1);
-    f4 acc = zero;
-#pragma unroll
-    for (int s = 0; s < N::HD / 32; ++s) acc = mfma32(lds_bf8<N>(A, s, lane), pack8(a.h1[2 * s], a.h1[2 * s + 1]), acc);
-    a.o = acc;
-  }
-  {
-    const f4 shv = {a.sh[0], a.sh[1], a.sh[2], a.sh[3]};
-    const bf8 b = pack8(a.o, shv);
-    const __bf16* A = Af + M::foff(2);
-#pragma unroll
-    for (int m = 0; m < N::HC / 16; ++m) a.h3[m] = relu4(mfma32(lds_bf8<N>(A, m, lane), b, zero));
-  }
-  const f4* hl = a.h3;
-  if constexpr (N::NCH == 2) {
-    const __bf16* A = Af + M::foff(3);
-    f4 acc[N::HC / 16];
-#pragma unroll
-    for (int m = 0; m < N::HC / 16; ++m) acc[m] = zero;
-#pragma unroll
-    for (int s = 0; s < N::HC / 32; ++s) {
-      const bf8 b = pack8(a.h3[2 * s], a.h3[2 * s + 1]);
-#pragma unroll
-      for (int m = 0; m < N::HC / 16; ++m) acc[m] = mfma32(lds_bf8<N>(A, m * (N::HC / 32) + s, lane), b, acc[m]);
-    }
-#pragma unroll
-    for (int m = 0; m < N::HC / 16; ++m) a.h4[m] = relu4(acc[m]);
-    hl = a.h4;
-  }
-  {
-    const __bf16* A = Af + M::foff(N::NW - 1);
-    f4 acc = zero;
-#pragma unroll
-    for (int s = 0; s < N::HC / 32; ++s) acc = mfma32(lds_bf8<N>(A, s, lane), pack8(hl[2 * s], hl[2 * s + 1]), acc);
-    a.z = acc;
-  }
-}
-
-template <class N>
 __device__ __forceinline__ void load_bf16(__bf16* dst, const __bf16* __restrict__ src, int n) {
   for (int i = threadIdx.x * 8; i < n; i += blockDim.x * 8)
     *reinterpret_cast<float4*>(dst + i) = *reinterpret_cast<const float4*>(src + i);
-}
-
-template <class N>
-__global__ __launch_bounds__(256) void mixed_fwd_kernel(LevelInfo lv, const _Float16* __restrict__ table,
-                                                        const __bf16* __restrict__ prep, SampleSrc src,
-                                                        float* __restrict__ sigma_out, float* __restrict__ rgb_out) {
-  using M = Mixed<N>;
-  __shared__ __attribute__((aligned(16))) __bf16 Af[M::FWD];
-  load_bf16<N>(Af, prep, M::FWD);
-  __syncthreads();
-  const int S = src.n_dev ? (int)*src.n_dev : src.n;
-  const int lane = lane_id(), g = lane >> 4, jc = lane & 15;
-  const int tile = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-  const int s = tile * 16 + jc;
-  if (tile * 16 >= S) return;
-  const bool valid = s < S;
-  LaneLevels<N> ll;
-  lane_levels<N>(lv, g, ll);
-  MActs<N> act;
-  float xn[3] = {0.5f, 0.5f, 0.5f}, d[3] = {0.0f, 0.0f, 1.0f};
-  if (valid) load_sample(src, s, xn, d);
-  if (src.ecache)
-    read_encoding<N>(static_cast<const uint32_t*>(src.ecache), src.ecache_stride, g, s, valid, act.e);
-  else
-    encode<N>(table, lv.table_mask, ll, xn, act.e);
-  sh_lane<N>(d, g, act.sh);
-  mlp_fwd_mixed<N>(Af, lane, act);
-  if (g == 0 && valid) {
-    sigma_out[s] = expf(act.o[0]);
-    rgb_out[3 * s + 0] = sigmoidf(act.z[0]);
-    rgb_out[3 * s + 1] = sigmoidf(act.z[1]);
-    rgb_out[3 * s + 2] = sigmoidf(act.z[2]);
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -297,7 +214,7 @@ __device__ __forceinline__ void fetch_tile(const SampleSrc& src, const _Float16*
   }
   in.ds = 0.0f;
   in.dr[0] = in.dr[1] = in.dr[2] = 0.0f;
-  if (g == 0 && valid) {
+  if (dsigma && g == 0 && valid) {
     in.ds = dsigma[s];
 #pragma unroll
     for (int r = 0; r < 3; ++r) in.dr[r] = drgb[3 * s + r];
@@ -396,6 +313,19 @@ __device__ __forceinline__ void fwd_tiles(const __bf16* __restrict__ Af, int lan
   }
 }
 
+// Layer-0 operand (encoding slots, zero beyond NSLOT) and SH coefficients of
+// one tile.
+template <class N>
+__device__ __forceinline__ void tile_operands(const TileIn<N>& in, int g, PActs<N>& a, f4& sh) {
+  uint32_t w[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) w[q] = q < N::LPL ? in.e[q < N::LPL ? q : 0] : 0u;
+  a.e = __builtin_bit_cast(bf8, make_uint4(w[0], w[1], w[2], w[3]));
+  float shv[4];
+  sh_lane<N>(in.d, g, shv);
+  sh = f4{shv[0], shv[1], shv[2], shv[3]};
+}
+
 // Staging rows (u32 words: column pair j of row f at f * kPairRowW + j).
 // MB 16-row blocks of a packed activation of the two tiles.
 template <int MB>
@@ -483,15 +413,7 @@ __device__ __forceinline__ void bwd_pair(const __bf16* __restrict__ Af, const __
   PActs<N> a[T];
   f4 sh[T];
 #pragma unroll
-  for (int t = 0; t < T; ++t) {
-    uint32_t w[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) w[q] = q < N::LPL ? in[t].e[q < N::LPL ? q : 0] : 0u;
-    a[t].e = __builtin_bit_cast(bf8, make_uint4(w[0], w[1], w[2], w[3]));
-    float shv[4];
-    sh_lane<N>(in[t].d, g, shv);
-    sh[t] = f4{shv[0], shv[1], shv[2], shv[3]};
-  }
+  for (int t = 0; t < T; ++t) tile_operands<N>(in[t], g, a[t], sh[t]);
   fwd_tiles<N, T>(Af, lane, sh, a);
   pend.store(rec, g);
 
@@ -753,6 +675,42 @@ __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(Le
   for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) out[i] = dW[i];
 }
 
+// Forward: density and colour of one 16-sample tile per wave, as the backward
+// recomputes them (one tile per wave keeps four waves per SIMD resident,
+// which hides the input loads better than pairing tiles here).
+template <class N>
+__global__ __launch_bounds__(256) void mixed_fwd_kernel(LevelInfo lv, const _Float16* __restrict__ table,
+                                                        const __bf16* __restrict__ prep, SampleSrc src,
+                                                        float* __restrict__ sigma_out, float* __restrict__ rgb_out) {
+  using M = Mixed<N>;
+  __shared__ __attribute__((aligned(16))) __bf16 Af[M::FWD];
+  load_bf16<N>(Af, prep, M::FWD);
+  __syncthreads();
+  const int S = src.n_dev ? (int)*src.n_dev : src.n;
+  const int lane = lane_id(), g = lane >> 4, jc = lane & 15;
+  const int tile = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  if (tile * 16 >= S) return;
+  LaneLevels<N> ll;
+  lane_levels<N>(lv, g, ll);
+  const int s = tile * 16 + jc;
+  const bool valid = s < S;
+  TileIn<N> in;
+  if (src.ecache)
+    fetch_tile<N, true>(src, table, lv, ll, nullptr, nullptr, s, valid, g, ray_of<N>(src, s, S), in);
+  else
+    fetch_tile<N, false>(src, table, lv, ll, nullptr, nullptr, s, valid, g, 0u, in);
+  PActs<N> a[1];
+  f4 sh[1];
+  tile_operands<N>(in, g, a[0], sh[0]);
+  fwd_tiles<N, 1>(Af, lane, sh, a);
+  if (g == 0 && valid) {
+    sigma_out[s] = expf(a[0].o[0]);
+    rgb_out[3 * s + 0] = sigmoidf(a[0].z[0]);
+    rgb_out[3 * s + 1] = sigmoidf(a[0].z[1]);
+    rgb_out[3 * s + 2] = sigmoidf(a[0].z[2]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers.  Shadow buffer: BF16 operands (forward, then backward),
 // padded to 256 bytes, then the FP16 table (same entry layout as FP32).
@@ -778,7 +736,7 @@ static hipError_t prep_impl(const float* params, const WOffsets& wo, int64_t tab
   _Float16* t16 = reinterpret_cast<_Float16*>(static_cast<char*>(shadow) + mixed_ops_bytes<N>());
   const int64_t n2 = table_floats / 2;
   if (n2 > 0)
-    hipLaunchKernelGGL(table_to_half_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, params, t16, n2);
+    hipLaunchKernelGGL(table_to_half_kernel, dim3((unsigned)((n2 + 1023) / 1024)), dim3(256), 0, st, params, t16, n2);
   return hipGetLastError();
 }
 

@@ -91,6 +91,13 @@ def test_host_side_errors(nsl):
     lib.nsl_mapper_destroy(m)
     assert lib.nsl_composite_fwd(None, fake, fake, fake, 1, 0.1, 0.0, fake, None) == nsl.E_INVALID
     assert lib.nsl_adam(fake, fake, fake, fake, 10, 1e-2, 0.9, 0.99, 1e-15, 0, 1.0, None) == nsl.E_INVALID
+    # parameter vectors and shadows are read with 16-byte loads
+    odd = C.c_void_p((1 << 20) + 8)
+    assert lib.nsl_adam(odd, fake, fake, fake, 10, 1e-2, 0.9, 0.99, 1e-15, 1, 1.0, None) == nsl.E_INVALID
+    assert b"16-byte" in lib.nsl_last_error()
+    rc = lib.nsl_field_fwd(f.handle, odd, fake, fake, 16, fake, fake, fake, need, None)
+    assert rc == nsl.E_INVALID and b"16-byte" in lib.nsl_last_error()
+    assert lib.nsl_field_prepare_mixed(f.handle, fake, odd, None) == nsl.E_INVALID
 
 
 def test_workspace_queries_scale(nsl):
