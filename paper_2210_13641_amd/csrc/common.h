@@ -63,6 +63,9 @@ __device__ __forceinline__ float normalise_axis(float x, float lo, float inv) {
 // floor(xn*N) taken on the exact product (TwoProduct: xn*N = ph + pl exactly),
 // clamped to N-1; f = xn*N - i0 rounded once.
 __device__ __forceinline__ int cell_floor(float xn, int n, float& f) {
+  // no contraction: fused, xn*N - i would be rounded once with the product's
+  // error inside it, and adding pl would count that error twice
+#pragma clang fp contract(off)
   const float nf = (float)n;
   const float ph = xn * nf;
   const float pl = __builtin_fmaf(xn, nf, -ph);
@@ -131,65 +134,59 @@ __device__ __forceinline__ int row_from_below(int v) {
   return __builtin_amdgcn_update_dpp(0, v, 0x110 + N, 0xF, 0xF, true);
 }
 
-// Runs of equal keys among consecutive lanes of each 16-lane row: the first
-// lane of every run gets the sums of a and b over the run (segmented suffix
-// scan); returns whether this lane starts a run.
-__device__ __forceinline__ bool row_run_sums(uint32_t key, float& a, float& b) {
+// Runs of consecutive valid lanes of each 16-lane row whose samples lie in
+// the same grid cell (equal cell coordinates).  Such lanes share all eight
+// corner entries, so one run structure serves every value: a segmented
+// suffix sum gives the first lane of each run the sums of v[0..K) over the
+// run.  Returns whether this lane starts a run.  When no lane of the wave
+// shares its cell with the lane below, the scan is skipped (every lane is
+// its own run and keeps its values).
+template <int K>
+__device__ __forceinline__ bool row_cell_runs(const uint32_t cell[3], bool valid, float (&v)[K]) {
   const int r = threadIdx.x & 15;
-  const uint32_t above = (uint32_t)row_from_above<1>((int)key);
-  const uint32_t below = (uint32_t)row_from_below<1>((int)key);
-  const bool head = r == 0 || below != key;
-  int tail = (r == 15 || above != key) ? 1 : 0;  // a run ends within [r, r + span)
-#define NSL_RUN_STEP(N)                               \
-  {                                                   \
-    const float na = row_from_above<N>(a);            \
-    const float nb = row_from_above<N>(b);            \
-    const int nt = row_from_above<N>(tail);           \
-    if (!tail) {                                      \
-      a += na;                                        \
-      b += nb;                                        \
-      tail = nt;                                      \
-    }                                                 \
+  // every neighbour read first, with all lanes active: a DPP read under a
+  // partial exec mask (a short-circuit && would make it one) sees inactive
+  // lanes as zero
+  const int vb = row_from_below<1>((int)valid), va = row_from_above<1>((int)valid);
+  uint32_t cb[3], ca[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    cb[i] = (uint32_t)row_from_below<1>((int)cell[i]);
+    ca[i] = (uint32_t)row_from_above<1>((int)cell[i]);
+  }
+  bool same_below = valid & (r != 0) & (vb != 0);
+  bool same_above = valid & (r != 15) & (va != 0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    same_below &= cb[i] == cell[i];
+    same_above &= ca[i] == cell[i];
+  }
+  if (__ballot(same_below) == 0ull) return true;
+  int tail = same_above ? 0 : 1;  // the run continues above this lane
+#define NSL_RUN_STEP(N)                                               \
+  {                                                                   \
+    const int nt = row_from_above<N>(tail);                           \
+    float nv[K];                                                      \
+    _Pragma("unroll") for (int k = 0; k < K; ++k) nv[k] = row_from_above<N>(v[k]); \
+    if (!tail) {                                                      \
+      _Pragma("unroll") for (int k = 0; k < K; ++k) v[k] += nv[k];    \
+      tail = nt;                                                      \
+    }                                                                 \
   }
   NSL_RUN_STEP(1)
   NSL_RUN_STEP(2)
   NSL_RUN_STEP(4)
   NSL_RUN_STEP(8)
 #undef NSL_RUN_STEP
-  return head;
+  return !same_below;
 }
 
-// p_k[0] += a_k, p_k[1] += b_k for K table entries, each as one 64-bit
-// compare-and-swap (one memory-side atomic per entry instead of two: the two
-// features of an entry share 8 aligned bytes).  All K reads, then all K
-// swaps are issued before any result is awaited; only swaps that lost a race
-// (or started from a stale read) go round again.
+// The 64-bit word of a (g0, g1) float pair after adding (a, b): the step of
+// a compare-and-swap accumulation of both features at once.
 __device__ __forceinline__ unsigned long long add_pair_bits(unsigned long long v, float a, float b) {
   const float x = __uint_as_float((unsigned)(v & 0xFFFFFFFFull)) + a;
   const float y = __uint_as_float((unsigned)(v >> 32)) + b;
   return (unsigned long long)__float_as_uint(x) | ((unsigned long long)__float_as_uint(y) << 32);
-}
-
-template <int K>
-__device__ __forceinline__ void atomic_add_pairs(float* const p[K], const bool on[K], const float a[K],
-                                                 const float b[K]) {
-  unsigned long long seen[K], got[K];
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-    seen[k] = on[k] ? __hip_atomic_load(reinterpret_cast<unsigned long long*>(p[k]), __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT)
-                    : 0ull;
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-    got[k] = on[k] ? atomicCAS(reinterpret_cast<unsigned long long*>(p[k]), seen[k], add_pair_bits(seen[k], a[k], b[k]))
-                   : seen[k];
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    while (got[k] != seen[k]) {
-      seen[k] = got[k];
-      got[k] = atomicCAS(reinterpret_cast<unsigned long long*>(p[k]), seen[k], add_pair_bits(seen[k], a[k], b[k]));
-    }
-  }
 }
 
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {

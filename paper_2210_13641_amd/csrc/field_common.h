@@ -54,6 +54,7 @@ __device__ __forceinline__ void lane_levels(const LevelInfo& lv, int g, LaneLeve
 struct Corner8 {
   uint32_t idx[8];
   float w[8];
+  uint32_t cell[3];  // integer coordinates of the cell's lower corner
 };
 
 __device__ __forceinline__ void corners(float x, float y, float z, int n, bool dense,
@@ -62,6 +63,9 @@ __device__ __forceinline__ void corners(float x, float y, float z, int n, bool d
   const uint32_t ix = (uint32_t)cell_floor(x, n, fx);
   const uint32_t iy = (uint32_t)cell_floor(y, n, fy);
   const uint32_t iz = (uint32_t)cell_floor(z, n, fz);
+  c.cell[0] = ix;
+  c.cell[1] = iy;
+  c.cell[2] = iz;
   const float gx[2] = {1.0f - fx, fx}, gy[2] = {1.0f - fy, fy}, gz[2] = {1.0f - fz, fz};
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -256,45 +260,6 @@ struct DWAcc {
       }
   }
 };
-
-// Appends the records of the lanes with on[k] to the wave's region,
-// compacted in lane order; cnt (wave-uniform) counts the records so far.
-template <int K>
-__device__ __forceinline__ void emit_records(uint32_t* __restrict__ key, float2* __restrict__ val, uint32_t& cnt,
-                                             const bool on[K], const uint32_t idx[K], const float v0[K],
-                                             const float v1[K]) {
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const uint64_t m = __ballot(on[k]);
-    const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    if (on[k]) {
-      key[cnt + below] = idx[k];
-      val[cnt + below] = make_float2(v0[k], v1[k]);
-    }
-    cnt += (uint32_t)__popcll(m);
-  }
-}
-
-// Table-gradient records of one level group: the 16 lanes of a row hold 16
-// consecutive samples (mostly along one ray) at the same level, so equal
-// corners form runs of neighbouring lanes; each run is summed in registers
-// and only its first lane writes a record.
-__device__ __forceinline__ void level_records(const float xn[3], int res, bool dense, uint32_t mask, uint32_t off,
-                                              bool valid, float d0, float d1, uint32_t* __restrict__ key,
-                                              float2* __restrict__ val, uint32_t& cnt) {
-  Corner8 c;
-  corners(xn[0], xn[1], xn[2], res, dense, mask, off, c);
-  bool on[8];
-  float v0[8], v1[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    v0[k] = c.w[k] * d0;
-    v1[k] = c.w[k] * d1;
-    const uint32_t rk = valid ? c.idx[k] : 0xFFFFFFFFu;
-    on[k] = row_run_sums(rk, v0[k], v1[k]) && valid;
-  }
-  emit_records<8>(key, val, cnt, on, c.idx, v0, v1);
-}
 
 // grads[weights] += sum over blocks of the per-block weight gradients, in a
 // fixed order: a block takes 64 weights, its four waves sum every fourth

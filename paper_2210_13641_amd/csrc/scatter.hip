@@ -23,9 +23,9 @@
 // BF16 for the mixed-precision step (accumulated in FP32 all the same).
 // Count and place generate
 // the same records from the sample positions and dL/de: the 16 lanes of a
-// row hold 16 consecutive samples (mostly along one ray) at one level, equal
-// corners form runs of neighbouring lanes, and each run becomes one record
-// carrying the run's sum.
+// row hold 16 consecutive samples (mostly along one ray) at one level;
+// neighbouring lanes in the same cell form a run, and each run gives eight
+// records (one per corner) carrying the run's sums.
 #include "field_common.h"
 
 namespace nsl {
@@ -68,11 +68,13 @@ struct RecBF16 {
   static __device__ __forceinline__ T none() { return make_uint2(0xFFFFFFFFu, 0u); }
 };
 
-// The records of one level (l = g + 4q for lane group g) of one tile.
+// The records of one level (l = g + 4q for lane group g) of one tile: the
+// eight corners of this lane's cell with their run sums; on = this lane
+// starts a run of samples in one cell (and is valid).
 struct LevelRecords {
   uint32_t idx[8];
   float v0[8], v1[8];
-  bool on[8];
+  bool on;
 };
 
 // dL/de of this lane's levels g + 4q (zero for samples beyond the batch).
@@ -87,12 +89,18 @@ __device__ __forceinline__ void level_records(const LevelInfo& lv, float2 d, int
                                               LevelRecords& r) {
   Corner8 c;
   corners(xn[0], xn[1], xn[2], lv.res[l], (lv.dense_bits >> l) & 1u, lv.table_mask, lv.offset[l], c);
+  float v[16];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    v[2 * k] = c.w[k] * d.x;
+    v[2 * k + 1] = c.w[k] * d.y;
+  }
+  r.on = row_cell_runs<16>(c.cell, valid, v) && valid;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     r.idx[k] = c.idx[k];
-    r.v0[k] = c.w[k] * d.x;
-    r.v1[k] = c.w[k] * d.y;
-    r.on[k] = row_run_sums(valid ? c.idx[k] : 0xFFFFFFFFu, r.v0[k], r.v1[k]) && valid;
+    r.v0[k] = v[2 * k];
+    r.v1[k] = v[2 * k + 1];
   }
 }
 
@@ -128,9 +136,10 @@ __global__ __launch_bounds__(kRecThreads) void bin_count_kernel(SampleSrc src, L
     for (int q = 0; q < lv.levels / 4; ++q) {
       LevelRecords r;
       level_records(lv, dl[q], g + 4 * q, valid, xn, r);
+      if (r.on) {
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (r.on[k]) atomicAdd(&h[r.idx[k] >> kBinShift], 1u);
+        for (int k = 0; k < 8; ++k) atomicAdd(&h[r.idx[k] >> kBinShift], 1u);
+      }
     }
   }
   __syncthreads();
@@ -214,9 +223,10 @@ __global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int n
 // count, ordered by bin in LDS (counting sort with LDS integer atomics), and
 // stored so that the global stores of a wave cover runs of consecutive slots
 // of a few bins instead of one cache line per lane.
-template <class R>
+template <class R, int G>
 __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, LevelInfo lv, RecordBuffers rb,
                                                                int nbins) {
+  static_assert(kRecTilesPerWave == 1, "one tile per wave");
   typedef typename R::T Rec;
   Rec* __restrict__ sorted = reinterpret_cast<Rec*>(rb.sorted);
   extern __shared__ uint32_t bins_lds[];  // gcur, cnt, lst: [nbins] each
@@ -224,39 +234,49 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
   uint32_t* cnt = bins_lds + nbins;
   uint32_t* lst = bins_lds + 2 * nbins;
   __shared__ uint32_t wsum[kRecWaves];
-  __shared__ Rec stage[kPlaceChunk];
+  __shared__ Rec stage[kPlaceChunk * G];
   const int t = threadIdx.x;
   const int blk = logical_block(gridDim.x);
   const uint32_t* off = rb.off + (size_t)blk * nbins;
-  for (int b = t; b < nbins; b += kRecThreads) gcur[b] = rb.bin_start[b] + off[b];
+  for (int b = t; b < nbins; b += kRecThreads) {
+    gcur[b] = rb.bin_start[b] + off[b];
+    cnt[b] = 0u;
+  }
   const int S = sample_count(src);
   const int wave = t / kWave, lane = lane_id(), g = lane >> 4, jc = lane & 15;
   const int per = (nbins + kRecThreads - 1) / kRecThreads;
   const int b0 = min(nbins, t * per), b1 = min(nbins, b0 + per);
-  float xn[kRecTilesPerWave][3];
-  float2 dl[kRecTilesPerWave][kMaxLevels / 4];
-  bool valid[kRecTilesPerWave];
-#pragma unroll
-  for (int j = 0; j < kRecTilesPerWave; ++j) {
-    const int tile = (blk * kRecWaves + wave) * kRecTilesPerWave + j;
-    const int s = tile * 16 + jc;
-    valid[j] = s < S;
+  const int s = (blk * kRecWaves + wave) * 16 + jc;
+  const bool valid = s < S;
+  float xn[3] = {0.5f, 0.5f, 0.5f};
+  {
     float d[3];
-    xn[j][0] = xn[j][1] = xn[j][2] = 0.5f;
-    if (valid[j]) load_sample(src, s, xn[j], d);
-    load_de(rb.de, rb.stride, lv.levels, g, s, valid[j], dl[j]);
+    if (valid) load_sample(src, s, xn, d);
   }
-  for (int q = 0; q < lv.levels / 4; ++q) {
-    for (int b = t; b < nbins; b += kRecThreads) cnt[b] = 0u;
-    __syncthreads();
-    LevelRecords r[kRecTilesPerWave];
-    uint32_t rank[kRecTilesPerWave][8];
+  float2 dl[kMaxLevels / 4];
+  load_de(rb.de, rb.stride, lv.levels, g, s, valid, dl);
+  __syncthreads();
+  const int groups = lv.levels / 4;
+  for (int q0 = 0; q0 < groups; q0 += G) {
+    // G level groups per round: the records in their stored format, off
+    // lanes (and groups beyond the last) holding R::none()
+    Rec rec[G][8];
+    uint32_t rank[G][8];
 #pragma unroll
-    for (int j = 0; j < kRecTilesPerWave; ++j) {
-      level_records(lv, dl[j][q], g + 4 * q, valid[j], xn[j], r[j]);
+    for (int h = 0; h < G; ++h) {
+      const int q = q0 + h;
+      if (q < groups) {
+        LevelRecords r;
+        level_records(lv, dl[q], g + 4 * q, valid, xn, r);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) rec[h][k] = r.on ? R::pack(r.idx[k], r.v0[k], r.v1[k]) : R::none();
+      } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) rec[h][k] = R::none();
+      }
 #pragma unroll
       for (int k = 0; k < 8; ++k)
-        if (r[j].on[k]) rank[j][k] = atomicAdd(&cnt[r[j].idx[k] >> kBinShift], 1u);
+        if (R::key(rec[h][k]) != 0xFFFFFFFFu) rank[h][k] = atomicAdd(&cnt[R::key(rec[h][k]) >> kBinShift], 1u);
     }
     __syncthreads();
     // lst = exclusive prefix of cnt: per-thread runs of bins, a wave scan of
@@ -277,19 +297,23 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kRecTilesPerWave; ++j)
+    for (int h = 0; h < G; ++h)
 #pragma unroll
       for (int k = 0; k < 8; ++k)
-        if (r[j].on[k])
-          stage[lst[r[j].idx[k] >> kBinShift] + rank[j][k]] = R::pack(r[j].idx[k], r[j].v0[k], r[j].v1[k]);
+        if (R::key(rec[h][k]) != 0xFFFFFFFFu) stage[lst[R::key(rec[h][k]) >> kBinShift] + rank[h][k]] = rec[h][k];
     __syncthreads();
     for (uint32_t i = t; i < m; i += kRecThreads) {
-      const Rec rec = stage[i];
-      const uint32_t b = R::key(rec) >> kBinShift;
-      sorted[gcur[b] + (i - lst[b])] = rec;
+      const Rec r = stage[i];
+      const uint32_t b = R::key(r) >> kBinShift;
+      sorted[gcur[b] + (i - lst[b])] = r;
     }
     __syncthreads();
-    for (int b = t; b < nbins; b += kRecThreads) gcur[b] += cnt[b];
+    // advance the bin cursors; clear the counts for the next round
+    for (int b = t; b < nbins; b += kRecThreads) {
+      gcur[b] += cnt[b];
+      cnt[b] = 0u;
+    }
+    __syncthreads();
   }
 }
 
@@ -374,12 +398,12 @@ hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSr
                      p.nblk);
   hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins);
   if (bf16_values) {
-    hipLaunchKernelGGL(bin_place_kernel<RecBF16>, dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb,
+    hipLaunchKernelGGL((bin_place_kernel<RecBF16, 2>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb,
                        p.nbins);
     hipLaunchKernelGGL(bin_reduce_kernel<RecBF16>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins,
                        p.entries, grad_table);
   } else {
-    hipLaunchKernelGGL(bin_place_kernel<RecF32>, dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb,
+    hipLaunchKernelGGL((bin_place_kernel<RecF32, 1>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb,
                        p.nbins);
     hipLaunchKernelGGL(bin_reduce_kernel<RecF32>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins,
                        p.entries, grad_table);
