@@ -216,11 +216,14 @@ int nsl_occupancy_set(nsl_mapper* m, const uint32_t* bits, int src_on_host,
  * accumulation, and accumulates every gradient in FP32; transmittance, the
  * depth-variance reduction and the Sigma_D-weighted loss stay FP32.
  * scale_state (device float[4], may be NULL): dynamic loss scaling.  The
- * scale is read from scale_state[0] (loss_scale is then ignored); after the
- * backward pass a non-finite gradient sets scale_state[3] = 1, Adam skips the
- * update (gradients are cleared), the scale is halved and scale_state[2]
- * counts the skip; otherwise scale_state[1] counts clean steps and the scale
- * doubles after 2000 of them.
+ * scale is read from scale_state[0] (loss_scale is then ignored); a
+ * non-finite value among the gradients the step writes (every MLP weight
+ * gradient and the table entries its samples touch, checked as they are
+ * written) sets scale_state[3] = 1, Adam skips the update (gradients are
+ * cleared), the scale is halved and scale_state[2] counts the skip; otherwise
+ * scale_state[1] counts clean steps and the scale doubles after 2000 of them.
+ * Gradients carried over from earlier steps (zero_grads = 0 without Adam)
+ * were checked by the step that wrote them.
  *
  * loss_out (device, 3 floats): L, L_rgb, L_D.  stats_out (device, may be
  * NULL).  ray_out (device, may be NULL): [n_candidates, 6] per candidate:
@@ -270,8 +273,7 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
  *   4 compositing + loss + its adjoint, 5 field backward kernel (MLP
  *   recompute and adjoint, weight gradients per workgroup, dL/de),
  *   6 table gradient (bin count, scans, placement, reduction), 7 weight-
- *   gradient reduction and the overflow check of dynamic loss scaling,
- *   8 Adam.
+ *   gradient reduction, 8 Adam (and the loss-scale update).
  * nsl_profile_read copies the sums (ms[NSL_PHASES]) and the number of
  * profiled steps; enabling again resets them. */
 #define NSL_PHASES 9

@@ -486,10 +486,10 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
     HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, b.dsigma, b.drgb, b.rec, b.partial, f->wo, grads, st),
             "field backward");
   HIP_TRY(mark(6), "profile event");
-  HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, mixed, grads, st), "table gradient");
+  float* overflow = c->scale_state ? c->scale_state + 3 : nullptr;  // set by the two gradient writers
+  HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, mixed, grads, overflow, st), "table gradient");
   HIP_TRY(mark(7), "profile event");
-  HIP_TRY(field_dw_reduce(f->shape, b.partial, kBwdBlocks, f->wo, grads, st), "weight gradient");
-  if (c->scale_state) HIP_TRY(scale_check(grads, total, c->scale_state, st), "loss scale");
+  HIP_TRY(field_dw_reduce(f->shape, b.partial, kBwdBlocks, f->wo, grads, overflow, st), "weight gradient");
   HIP_TRY(mark(8), "profile event");
   if (c->do_adam)
     HIP_TRY(adam_update(params, grads, adam_m, adam_v, total, c->lr, c->beta1, c->beta2, c->eps, c->adam_step,
@@ -615,8 +615,8 @@ int nsl_field_bwd(const nsl_field* f, const float* params, const float* xn, cons
   FieldArgs fa{params, w.wprep, f->lv};
   HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, dsigma, drgb, w.rec, w.partial, f->wo, grads, st),
           "field backward");
-  HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, st), "weight gradient");
-  HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, false, grads, st), "table gradient");
+  HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, nullptr, st), "weight gradient");
+  HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, false, grads, nullptr, st), "table gradient");
   return NSL_OK;
 }
 
@@ -653,8 +653,8 @@ int nsl_field_bwd_mixed(const nsl_field* f, const void* shadow, const float* xn,
   if (rc) return rc;
   HIP_TRY(mixed_backward(f->shape, f->lv, shadow, src, kBwdBlocks, dsigma, drgb, w.rec, w.partial, f->wo, grads, st),
           "field backward (mixed)");
-  HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, st), "weight gradient");
-  HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, true, grads, st), "table gradient");
+  HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, nullptr, st), "weight gradient");
+  HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, true, grads, nullptr, st), "table gradient");
   return NSL_OK;
 }
 

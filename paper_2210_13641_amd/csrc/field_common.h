@@ -266,7 +266,7 @@ struct DWAcc {
 // partial, and the four sums are added in LDS.
 template <class N>
 __global__ __launch_bounds__(256) void dw_reduce_kernel(const float* __restrict__ partial, int nblocks, WOffsets wo,
-                                                        float* __restrict__ grads) {
+                                                        float* __restrict__ grads, float* __restrict__ overflow) {
   __shared__ float red[4][64];
   const int wl = threadIdx.x & 63, pg = threadIdx.x >> 6;
   const int i = blockIdx.x * 64 + wl;
@@ -281,14 +281,17 @@ __global__ __launch_bounds__(256) void dw_reduce_kernel(const float* __restrict_
   const float sum = (red[0][wl] + red[1][wl]) + (red[2][wl] + red[3][wl]);
   int j = 0;
   while (j + 1 < N::NW && i >= N::woff(j + 1)) ++j;
-  grads[wo.off[j] + (i - N::woff(j))] += sum;
+  float* g = grads + wo.off[j] + (i - N::woff(j));
+  const float r = *g + sum;
+  *g = r;
+  if (overflow && !isfinite(r)) *overflow = 1.0f;
 }
 
 template <class N>
 __host__ inline hipError_t launch_dw_reduce(const float* partial, int nblocks, const WOffsets& wo, float* grads,
-                                           hipStream_t st) {
+                                           float* overflow, hipStream_t st) {
   hipLaunchKernelGGL(dw_reduce_kernel<N>, dim3((N::NWEIGHTS + 63) / 64), dim3(256), 0, st, partial, nblocks, wo,
-                     grads);
+                     grads, overflow);
   return hipGetLastError();
 }
 

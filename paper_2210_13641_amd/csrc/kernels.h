@@ -69,8 +69,10 @@ struct BinPlan {
 BinPlan bin_plan(uint32_t entries, int levels, int64_t max_samples);
 // grad_table += the table gradient of the samples of src, from the dL/de
 // that the backward kernel left in rb.de.
+// overflow (may be null): set to 1.0f when a gradient value the call writes
+// is not finite (the loss-scale overflow flag).
 hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
-                       bool bf16_values, float* grad_table, hipStream_t st);
+                       bool bf16_values, float* grad_table, float* overflow, hipStream_t st);
 
 // field.hip
 size_t field_prep_floats(int shape);
@@ -88,7 +90,7 @@ hipError_t field_backward(int shape, const FieldArgs& a, const SampleSrc& src, i
                           float* partial, const WOffsets& wo, float* grads, hipStream_t st);
 
 hipError_t field_dw_reduce(int shape, const float* partial, int nblocks, const WOffsets& wo, float* grads,
-                           hipStream_t st);
+                           float* overflow, hipStream_t st);
 // The encoding of every sample of src into src.ecache (FP32 table).
 hipError_t field_encode(int shape, const FieldArgs& a, const SampleSrc& src, int max_samples, hipStream_t st);
 
@@ -201,7 +203,6 @@ hipError_t adam_update(float* p, float* g, float* m, float* v, int64_t n, float 
 // Dynamic loss scaling: clear the overflow flag, flag non-finite gradients,
 // then halve (overflow) or count clean steps and double after 2000.
 hipError_t scale_begin(float* state, hipStream_t st);
-hipError_t scale_check(const float* g, int64_t n, float* state, hipStream_t st);
 hipError_t scale_end(float* state, hipStream_t st);
 hipError_t fill_zero(float* p, int64_t n, hipStream_t st);
 // Writes one request record to device memory (taken by value at launch),

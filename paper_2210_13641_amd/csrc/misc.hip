@@ -62,23 +62,6 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(float* __restrict__ p, i
 
 __global__ void scale_begin_kernel(float* state) { state[3] = 0.0f; }
 
-__global__ __launch_bounds__(256) void scale_check_kernel(const float* __restrict__ g, int64_t n,
-                                                          float* __restrict__ state) {
-  // four float4 loads in flight per thread, then the scalar tail
-  bool bad = false;
-  const int64_t n4 = n / 4, stride = (int64_t)gridDim.x * blockDim.x;
-  const float4* g4 = reinterpret_cast<const float4*>(g);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += 4 * stride) {
-    float4 v[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] = i + k * stride < n4 ? g4[i + k * stride] : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) bad |= !isfinite(v[k].x) || !isfinite(v[k].y) || !isfinite(v[k].z) || !isfinite(v[k].w);
-  }
-  for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) bad |= !isfinite(g[i]);
-  if (__ballot(bad) != 0ull && lane_id() == 0) state[3] = 1.0f;
-}
-
 __global__ void scale_end_kernel(float* state) {
   if (state[3] != 0.0f) {
     state[0] *= 0.5f;
@@ -123,11 +106,6 @@ hipError_t fill_zero(float* p, int64_t n, hipStream_t st) {
 
 hipError_t scale_begin(float* state, hipStream_t st) {
   hipLaunchKernelGGL(scale_begin_kernel, dim3(1), dim3(1), 0, st, state);
-  return hipGetLastError();
-}
-
-hipError_t scale_check(const float* g, int64_t n, float* state, hipStream_t st) {
-  if (n > 0) hipLaunchKernelGGL(scale_check_kernel, dim3(2048), dim3(256), 0, st, g, n, state);
   return hipGetLastError();
 }
 

@@ -319,7 +319,8 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
 
 template <class R>
 __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffers rb, int nbins, uint32_t entries,
-                                                                    float* __restrict__ grad_table) {
+                                                                    float* __restrict__ grad_table,
+                                                                    float* __restrict__ overflow) {
   typedef typename R::T Rec;
   const Rec* __restrict__ sorted = reinterpret_cast<const Rec*>(rb.sorted);
   // (g0, g1) of each entry as one 64-bit word: float pairs are added with
@@ -357,8 +358,11 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
     }
   }
   __syncthreads();
+  // every gradient value written is checked for the loss-scale overflow flag
+  // (for the atomic adds, the value each add leaves)
   const uint32_t ne = min((uint32_t)kBinEntries, entries - e0);
   float2* gt = reinterpret_cast<float2*>(grad_table) + e0;
+  bool bad = false;
   for (uint32_t e = threadIdx.x; e < ne; e += kReduceThreads) {
     const unsigned long long w = acc[e];
     const float a0 = __uint_as_float((uint32_t)w), a1 = __uint_as_float((uint32_t)(w >> 32));
@@ -368,11 +372,14 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
       v.x += a0;
       v.y += a1;
       gt[e] = v;
+      bad |= !isfinite(v.x) || !isfinite(v.y);
     } else {
-      atomicAdd(&gt[e].x, a0);
-      atomicAdd(&gt[e].y, a1);
+      const float o0 = atomicAdd(&gt[e].x, a0);
+      const float o1 = atomicAdd(&gt[e].y, a1);
+      bad |= !isfinite(o0 + a0) || !isfinite(o1 + a1);
     }
   }
+  if (overflow && bad) *overflow = 1.0f;
 }
 
 }  // namespace
@@ -390,7 +397,7 @@ BinPlan bin_plan(uint32_t entries, int levels, int64_t max_samples) {
 }
 
 hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
-                       bool bf16_values, float* grad_table, hipStream_t st) {
+                       bool bf16_values, float* grad_table, float* overflow, hipStream_t st) {
   if (p.nbins == 0 || p.nblk == 0) return hipSuccess;
   const size_t bins_lds = (size_t)p.nbins * sizeof(uint32_t);
   hipLaunchKernelGGL(bin_count_kernel, dim3(p.nblk), dim3(kRecThreads), bins_lds, st, src, lv, rb, p.nbins);
@@ -401,12 +408,12 @@ hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSr
     hipLaunchKernelGGL((bin_place_kernel<RecBF16, 2>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb,
                        p.nbins);
     hipLaunchKernelGGL(bin_reduce_kernel<RecBF16>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins,
-                       p.entries, grad_table);
+                       p.entries, grad_table, overflow);
   } else {
     hipLaunchKernelGGL((bin_place_kernel<RecF32, 1>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb,
                        p.nbins);
     hipLaunchKernelGGL(bin_reduce_kernel<RecF32>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins,
-                       p.entries, grad_table);
+                       p.entries, grad_table, overflow);
   }
   return hipGetLastError();
 }
