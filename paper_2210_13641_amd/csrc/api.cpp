@@ -441,11 +441,15 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   auto mark = [&](int i) -> hipError_t { return prof ? hipEventRecord(g_prof.ev[i], st) : hipSuccess; };
   HIP_TRY(mark(0), "profile event");
   if (c->scale_state) HIP_TRY(scale_begin(c->scale_state, st), "loss scale");
-  if (c->zero_grads) HIP_TRY(fill_zero(grads, total, st), "zero grads");
-  if (mixed)
-    HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, b.shadow, st), "prep mixed");
-  else
+  if (mixed) {
+    // the gradient clearing rides along the FP16 table copy
+    HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, b.shadow, c->zero_grads ? grads : nullptr,
+                          total, st),
+            "prep mixed");
+  } else {
+    if (c->zero_grads) HIP_TRY(fill_zero(grads, total, st), "zero grads");
     HIP_TRY(field_prep(f->shape, params, f->wo, b.wprep, st), "prep weights");
+  }
   HIP_TRY(mark(1), "profile event");
   if ((rc = run_march(m, f, c, ids, n, b, st))) return rc;
   HIP_TRY(mark(2), "profile event");
@@ -627,7 +631,7 @@ size_t nsl_mixed_shadow_bytes(const nsl_field* f) {
 int nsl_field_prepare_mixed(const nsl_field* f, const float* params, void* shadow, hipStream_t st) {
   if (!f || !params || !shadow) return fail(NSL_E_INVALID, "null argument");
   if (misaligned(params) || misaligned(shadow)) return fail(NSL_E_INVALID, "params and shadow must be 16-byte aligned");
-  HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, shadow, st), "prepare mixed");
+  HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, shadow, nullptr, 0, st), "prepare mixed");
   return NSL_OK;
 }
 

@@ -112,24 +112,28 @@ __global__ void mixed_prep_kernel(const float* __restrict__ params, WOffsets wo,
   out[idx] = (__bf16)v;
 }
 
-// FP16 copy of the FP32 table, four entries (eight values) per thread.
+// FP16 copy of the FP32 table (tf floats), eight values per thread; with g
+// set, the same pass clears the gradient vector (total floats), which the
+// step needs anyway when it starts from zero gradients.
 __global__ __launch_bounds__(256) void table_to_half_kernel(const float* __restrict__ t, _Float16* __restrict__ h,
-                                                            int64_t n2) {
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  if (i + 4 <= n2) {
-    const float4 a = reinterpret_cast<const float4*>(t)[i / 2];
-    const float4 b = reinterpret_cast<const float4*>(t)[i / 2 + 1];
-    typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+                                                            int64_t tf, float* __restrict__ g, int64_t total) {
+  typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
+  if (i + 8 <= tf) {
+    const float4 a = reinterpret_cast<const float4*>(t + i)[0];
+    const float4 b = reinterpret_cast<const float4*>(t + i)[1];
     const h8 o = {(_Float16)a.x, (_Float16)a.y, (_Float16)a.z, (_Float16)a.w,
                   (_Float16)b.x, (_Float16)b.y, (_Float16)b.z, (_Float16)b.w};
-    *reinterpret_cast<h8*>(h + 2 * i) = o;
+    *reinterpret_cast<h8*>(h + i) = o;
   } else {
-    for (int64_t k = i; k < n2; ++k) {
-      const float2 v = reinterpret_cast<const float2*>(t)[k];
-      h2 o;
-      o[0] = (_Float16)v.x;
-      o[1] = (_Float16)v.y;
-      reinterpret_cast<h2*>(h)[k] = o;
+    for (int64_t k = i; k < tf; ++k) h[k] = (_Float16)t[k];
+  }
+  if (g) {
+    if (i + 8 <= total) {
+      reinterpret_cast<float4*>(g + i)[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      reinterpret_cast<float4*>(g + i)[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    } else {
+      for (int64_t k = i; k < total; ++k) g[k] = 0.0f;
     }
   }
 }
@@ -728,15 +732,16 @@ size_t mixed_shadow_bytes(int shape, int64_t table_floats) {
 
 template <class N>
 static hipError_t prep_impl(const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
-                            hipStream_t st) {
+                            float* zero_grads, int64_t total, hipStream_t st) {
   using M = Mixed<N>;
   const int n = M::FWD + M::BWD;
   hipLaunchKernelGGL(mixed_prep_kernel<N>, dim3((n + 255) / 256), dim3(256), 0, st, params, wo,
                      static_cast<__bf16*>(shadow));
   _Float16* t16 = reinterpret_cast<_Float16*>(static_cast<char*>(shadow) + mixed_ops_bytes<N>());
-  const int64_t n2 = table_floats / 2;
-  if (n2 > 0)
-    hipLaunchKernelGGL(table_to_half_kernel, dim3((unsigned)((n2 + 1023) / 1024)), dim3(256), 0, st, params, t16, n2);
+  const int64_t span = zero_grads ? (total > table_floats ? total : table_floats) : table_floats;
+  if (span > 0)
+    hipLaunchKernelGGL(table_to_half_kernel, dim3((unsigned)((span + 2047) / 2048)), dim3(256), 0, st, params, t16,
+                       table_floats, zero_grads, total);
   return hipGetLastError();
 }
 
@@ -780,9 +785,9 @@ hipError_t mixed_encode(int shape, const LevelInfo& lv, const void* shadow, cons
 }
 
 hipError_t mixed_prepare(int shape, const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
-                         hipStream_t st) {
-  return shape == kShapeTiny ? prep_impl<NetTiny>(params, wo, table_floats, shadow, st)
-                             : prep_impl<NetFull>(params, wo, table_floats, shadow, st);
+                         float* zero_grads, int64_t total, hipStream_t st) {
+  return shape == kShapeTiny ? prep_impl<NetTiny>(params, wo, table_floats, shadow, zero_grads, total, st)
+                             : prep_impl<NetFull>(params, wo, table_floats, shadow, zero_grads, total, st);
 }
 
 hipError_t mixed_forward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,

@@ -108,8 +108,10 @@ size_t field_fwd_floats(int shape);
 // field_mixed.hip: FP16 table, BF16 MLP on MFMA, FP32 accumulation.  The
 // shadow buffer holds the BF16 operands and the FP16 table copy.
 size_t mixed_shadow_bytes(int shape, int64_t table_floats);
+// zero_grads (may be null): a gradient vector of total floats cleared in the
+// same pass as the FP16 table copy.
 hipError_t mixed_prepare(int shape, const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
-                         hipStream_t st);
+                         float* zero_grads, int64_t total, hipStream_t st);
 hipError_t mixed_forward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
                          float* sigma, float* rgb, hipStream_t st);
 // The encoding of every sample of src into src.ecache (FP16 table, BF16 out).
