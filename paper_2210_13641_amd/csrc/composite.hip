@@ -170,6 +170,80 @@ __global__ __launch_bounds__(256) void composite_bwd_kernel(CompositeIO io, cons
                g_opacity ? g_opacity[r] : 0.0f, g_sigma, g_rgb_s);
 }
 
+// Rays of at most kCacheChunks * 64 samples (every training ray: the march
+// caps them at 256) keep their chunks in registers, so the V* pass and the
+// adjoint reuse the loads and the transmittance of the forward pass.
+constexpr int kCacheChunks = 4;
+
+__device__ __forceinline__ RaySums ray_forward_cached(const CompositeIO& io, uint32_t b, uint32_t n,
+                                                      Chunk (&cc)[kCacheChunks]) {
+  RaySums r{};
+  float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f, A = 0.0f;
+  float carry = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kCacheChunks; ++k) {
+    const uint32_t i0 = (uint32_t)k * kWave;
+    if (i0 < n) {
+      carry += load_chunk(io, b, n, i0, carry, cc[k]);
+      C0 += cc[k].w * cc[k].c[0];
+      C1 += cc[k].w * cc[k].c[1];
+      C2 += cc[k].w * cc[k].c[2];
+      D += cc[k].w * cc[k].t;
+      A += cc[k].w;
+    }
+  }
+  r.C[0] = wave_sum(C0);
+  r.C[1] = wave_sum(C1);
+  r.C[2] = wave_sum(C2);
+  r.D = wave_sum(D);
+  r.A = wave_sum(A);
+  float V = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kCacheChunks; ++k) {
+    if ((uint32_t)k * kWave < n) {
+      const float e = cc[k].t - r.D;
+      V += cc[k].w * e * e;
+    }
+  }
+  r.V = wave_sum(V);
+  return r;
+}
+
+__device__ __forceinline__ void ray_backward_cached(uint32_t b, uint32_t n, const RaySums& r,
+                                                    const Chunk (&cc)[kCacheChunks], const float gC[3], float gD,
+                                                    float delta, float* __restrict__ g_sigma,
+                                                    float* __restrict__ g_rgb) {
+  float p0 = 0.0f, p1 = 0.0f, p2 = 0.0f, pD = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kCacheChunks; ++k) {
+    const uint32_t i0 = (uint32_t)k * kWave;
+    if (i0 < n) {
+      const Chunk& c = cc[k];
+      const float q0 = wave_incl_scan(c.w * c.c[0]) + p0;
+      const float q1 = wave_incl_scan(c.w * c.c[1]) + p1;
+      const float q2 = wave_incl_scan(c.w * c.c[2]) + p2;
+      const float qD = wave_incl_scan(c.w * c.t) + pD;
+      const float dC0 = c.Tn * c.c[0] - (r.C[0] - q0);
+      const float dC1 = c.Tn * c.c[1] - (r.C[1] - q1);
+      const float dC2 = c.Tn * c.c[2] - (r.C[2] - q2);
+      const float dD = c.Tn * c.t - (r.D - qD);
+      const float dtau = gC[0] * dC0 + gC[1] * dC1 + gC[2] * dC2 + gD * dD;
+      const uint32_t i = i0 + lane_id();
+      if (i < n) {
+        const uint32_t s = b + i;
+        g_sigma[s] = delta * dtau;
+        g_rgb[3 * s] = gC[0] * c.w;
+        g_rgb[3 * s + 1] = gC[1] * c.w;
+        g_rgb[3 * s + 2] = gC[2] * c.w;
+      }
+      p0 = __shfl(q0, kWave - 1, kWave);
+      p1 = __shfl(q1, kWave - 1, kWave);
+      p2 = __shfl(q2, kWave - 1, kWave);
+      pD = __shfl(qD, kWave - 1, kWave);
+    }
+  }
+}
+
 // Train step: forward sums, loss terms and seeds, adjoint.
 __global__ __launch_bounds__(256) void composite_loss_kernel(CompositeIO io, LossIO lo,
                                                              float* __restrict__ g_sigma,
@@ -188,7 +262,10 @@ __global__ __launch_bounds__(256) void composite_loss_kernel(CompositeIO io, Los
     }
     return;
   }
-  const RaySums s = ray_forward(io, b, n);
+  // no early termination in training (stop_T = 0): the cached path holds
+  const bool cached = n <= (uint32_t)(kCacheChunks * kWave) && !(io.stop_T > 0.0f);
+  Chunk cc[kCacheChunks];
+  const RaySums s = cached ? ray_forward_cached(io, b, n, cc) : ray_forward(io, b, n);
   const float Rf = (float)lo.stats[0];
   const float4 tg = lo.target[r];
   const float pi = lo.prec[r];
@@ -209,7 +286,10 @@ __global__ __launch_bounds__(256) void composite_loss_kernel(CompositeIO io, Los
       o[3] = s.D / sc; o[4] = s.V / (sc * sc); o[5] = s.A;
     }
   }
-  ray_backward(io, b, n, s, gC, gD, 0.0f, 0.0f, g_sigma, g_rgb_s);
+  if (cached)
+    ray_backward_cached(b, n, s, cc, gC, gD, io.delta, g_sigma, g_rgb_s);
+  else
+    ray_backward(io, b, n, s, gC, gD, 0.0f, 0.0f, g_sigma, g_rgb_s);
 }
 
 // loss = (L_rgb + lambda_d L_D, L_rgb, L_D): sums of the per-ray parts in a
