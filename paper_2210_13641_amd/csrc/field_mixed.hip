@@ -230,59 +230,66 @@ __device__ __forceinline__ uint32_t ray_of(const SampleSrc& src, int s, int S) {
   return src.t && s < S ? src.ray[s] : 0u;
 }
 
-// Forward of T tiles, interleaved layer by layer.
+// K consecutive weight-operand blocks of one layer.
+template <class N, int K>
+__device__ __forceinline__ void load_ops(const __bf16* A, int lane, bf8 (&w)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) w[k] = lds_bf8<N>(A, k, lane);
+}
+
+// Forward of T tiles, interleaved layer by layer; each layer's weight
+// operands are read from LDS one layer ahead, so the reads overlap the
+// previous layer's MFMAs instead of each waiting in front of its own.
 template <class N, int T>
 __device__ __forceinline__ void fwd_tiles(const __bf16* __restrict__ Af, int lane, const f4 (&sh)[T],
                                           PActs<N> (&a)[T]) {
   using M = Mixed<N>;
   constexpr f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  constexpr int K3 = N::NCH == 2 ? (N::HC / 16) * (N::HC / 32) : 1;
+  bf8 w0[N::HD / 16], w1[N::HD / 32], w2[N::HC / 16], w3[K3], w4[N::HC / 32];
+  load_ops<N>(Af + M::foff(0), lane, w0);
+  load_ops<N>(Af + M::foff(1), lane, w1);
   {
-    const __bf16* A = Af + M::foff(0);
     f4 h[T][N::HD / 16];
 #pragma unroll
-    for (int m = 0; m < N::HD / 16; ++m) {
-      const bf8 w = lds_bf8<N>(A, m, lane);
+    for (int m = 0; m < N::HD / 16; ++m)
 #pragma unroll
-      for (int t = 0; t < T; ++t) h[t][m] = relu4(mfma32(w, a[t].e, zero));
-    }
+      for (int t = 0; t < T; ++t) h[t][m] = relu4(mfma32(w0[m], a[t].e, zero));
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
       for (int s = 0; s < N::HD / 32; ++s) a[t].h1[s] = pack8(h[t][2 * s], h[t][2 * s + 1]);
   }
+  load_ops<N>(Af + M::foff(2), lane, w2);
   {
-    const __bf16* A = Af + M::foff(1);
     f4 acc[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) acc[t] = zero;
 #pragma unroll
-    for (int s = 0; s < N::HD / 32; ++s) {
-      const bf8 w = lds_bf8<N>(A, s, lane);
+    for (int s = 0; s < N::HD / 32; ++s)
 #pragma unroll
-      for (int t = 0; t < T; ++t) acc[t] = mfma32(w, a[t].h1[s], acc[t]);
-    }
+      for (int t = 0; t < T; ++t) acc[t] = mfma32(w1[s], a[t].h1[s], acc[t]);
 #pragma unroll
     for (int t = 0; t < T; ++t) {
       a[t].o = acc[t];
       a[t].osh = pack8(acc[t], sh[t]);
     }
   }
+  if constexpr (N::NCH == 2) load_ops<N>(Af + M::foff(3), lane, w3);
+  else load_ops<N>(Af + M::foff(N::NW - 1), lane, w4);
   {
-    const __bf16* A = Af + M::foff(2);
     f4 h[T][N::HC / 16];
 #pragma unroll
-    for (int m = 0; m < N::HC / 16; ++m) {
-      const bf8 w = lds_bf8<N>(A, m, lane);
+    for (int m = 0; m < N::HC / 16; ++m)
 #pragma unroll
-      for (int t = 0; t < T; ++t) h[t][m] = relu4(mfma32(w, a[t].osh, zero));
-    }
+      for (int t = 0; t < T; ++t) h[t][m] = relu4(mfma32(w2[m], a[t].osh, zero));
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
       for (int s = 0; s < N::HC / 32; ++s) a[t].h3[s] = pack8(h[t][2 * s], h[t][2 * s + 1]);
   }
   if constexpr (N::NCH == 2) {
-    const __bf16* A = Af + M::foff(3);
+    load_ops<N>(Af + M::foff(N::NW - 1), lane, w4);
     f4 acc[T][N::HC / 16];
 #pragma unroll
     for (int t = 0; t < T; ++t)
@@ -291,27 +298,22 @@ __device__ __forceinline__ void fwd_tiles(const __bf16* __restrict__ Af, int lan
 #pragma unroll
     for (int s = 0; s < N::HC / 32; ++s)
 #pragma unroll
-      for (int m = 0; m < N::HC / 16; ++m) {
-        const bf8 w = lds_bf8<N>(A, m * (N::HC / 32) + s, lane);
+      for (int m = 0; m < N::HC / 16; ++m)
 #pragma unroll
-        for (int t = 0; t < T; ++t) acc[t][m] = mfma32(w, a[t].h3[s], acc[t][m]);
-      }
+        for (int t = 0; t < T; ++t) acc[t][m] = mfma32(w3[m * (N::HC / 32) + s], a[t].h3[s], acc[t][m]);
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
       for (int s = 0; s < N::HC / 32; ++s) a[t].h4[s] = pack8(relu4(acc[t][2 * s]), relu4(acc[t][2 * s + 1]));
   }
   {
-    const __bf16* A = Af + M::foff(N::NW - 1);
     f4 acc[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) acc[t] = zero;
 #pragma unroll
-    for (int s = 0; s < N::HC / 32; ++s) {
-      const bf8 w = lds_bf8<N>(A, s, lane);
+    for (int s = 0; s < N::HC / 32; ++s)
 #pragma unroll
-      for (int t = 0; t < T; ++t) acc[t] = mfma32(w, N::NCH == 2 ? a[t].h4[s] : a[t].h3[s], acc[t]);
-    }
+      for (int t = 0; t < T; ++t) acc[t] = mfma32(w4[s], N::NCH == 2 ? a[t].h4[s] : a[t].h3[s], acc[t]);
 #pragma unroll
     for (int t = 0; t < T; ++t) a[t].z = acc[t];
   }
@@ -433,21 +435,27 @@ __device__ __forceinline__ void bwd_pair(const __bf16* __restrict__ Af, const __
       }
     }
   }
+  // Each layer's transposed weight operands are read from LDS before the
+  // previous layer's weight-gradient product, whose LDS fences would
+  // otherwise keep the reads waiting in front of the layer's MFMAs.
+  constexpr int K3 = N::NCH == 2 ? (N::HC / 16) * (N::HC / 32) : 1;
+  constexpr int MT0 = N::bmt(0);
+  bf8 w4[N::HC / 16], w3[K3], w2[N::HC / 32], w1[N::HD / 16], w0[MT0 * (N::HD / 32)];
+  load_ops<N>(Ab + M::boff(N::NW - 1), lane, w4);
   // last colour layer
   f4 dhl[T][N::HC / 16];
   {
-    const __bf16* A = Ab + M::boff(N::NW - 1);
     bf8 b[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) b[t] = pack8(dz[t], zero);
 #pragma unroll
-    for (int m = 0; m < N::HC / 16; ++m) {
-      const bf8 w = lds_bf8<N>(A, m, lane);
+    for (int m = 0; m < N::HC / 16; ++m)
 #pragma unroll
       for (int t = 0; t < T; ++t)
-        dhl[t][m] = relu_grad(mfma32(w, b[t], zero), N::NCH == 2 ? a[t].h4[m >> 1] : a[t].h3[m >> 1], m & 1);
-    }
+        dhl[t][m] = relu_grad(mfma32(w4[m], b[t], zero), N::NCH == 2 ? a[t].h4[m >> 1] : a[t].h3[m >> 1], m & 1);
   }
+  if constexpr (N::NCH == 2) load_ops<N>(Ab + M::boff(3), lane, w3);
+  else load_ops<N>(Ab + M::boff(2), lane, w2);
   stage_packed<N::HC / 16>(Xw, N::NCH == 2 ? a[0].h4 : a[0].h3, N::NCH == 2 ? a[1].h4 : a[1].h3, g, jc);
   stage_f32<1>(Yw, &dz[0], &dz[1], g, jc);
   wave_lds_fence();
@@ -456,7 +464,6 @@ __device__ __forceinline__ void bwd_pair(const __bf16* __restrict__ Af, const __
 
   f4 dh3[T][N::HC / 16];
   if constexpr (N::NCH == 2) {
-    const __bf16* A = Ab + M::boff(3);
     f4 acc[T][N::HC / 16];
 #pragma unroll
     for (int t = 0; t < T; ++t)
@@ -468,16 +475,15 @@ __device__ __forceinline__ void bwd_pair(const __bf16* __restrict__ Af, const __
 #pragma unroll
       for (int t = 0; t < T; ++t) b[t] = pack8(dhl[t][2 * k], dhl[t][2 * k + 1]);
 #pragma unroll
-      for (int m = 0; m < N::HC / 16; ++m) {
-        const bf8 w = lds_bf8<N>(A, m * (N::HC / 32) + k, lane);
+      for (int m = 0; m < N::HC / 16; ++m)
 #pragma unroll
-        for (int t = 0; t < T; ++t) acc[t][m] = mfma32(w, b[t], acc[t][m]);
-      }
+        for (int t = 0; t < T; ++t) acc[t][m] = mfma32(w3[m * (N::HC / 32) + k], b[t], acc[t][m]);
     }
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
       for (int m = 0; m < N::HC / 16; ++m) dh3[t][m] = relu_grad(acc[t][m], a[t].h3[m >> 1], m & 1);
+    load_ops<N>(Ab + M::boff(2), lane, w2);
     stage_packed<N::HC / 16>(Xw, a[0].h3, a[1].h3, g, jc);
     stage_f32<N::HC / 16>(Yw, dhl[0], dhl[1], g, jc);
     wave_lds_fence();
@@ -492,16 +498,14 @@ __device__ __forceinline__ void bwd_pair(const __bf16* __restrict__ Af, const __
   // first colour layer: gradient of the geometry features
   f4 dgeo[T];
   {
-    const __bf16* A = Ab + M::boff(2);
 #pragma unroll
     for (int t = 0; t < T; ++t) dgeo[t] = zero;
 #pragma unroll
-    for (int k = 0; k < N::HC / 32; ++k) {
-      const bf8 w = lds_bf8<N>(A, k, lane);
+    for (int k = 0; k < N::HC / 32; ++k)
 #pragma unroll
-      for (int t = 0; t < T; ++t) dgeo[t] = mfma32(w, pack8(dh3[t][2 * k], dh3[t][2 * k + 1]), dgeo[t]);
-    }
+      for (int t = 0; t < T; ++t) dgeo[t] = mfma32(w2[k], pack8(dh3[t][2 * k], dh3[t][2 * k + 1]), dgeo[t]);
   }
+  load_ops<N>(Ab + M::boff(1), lane, w1);
   stage_packed<2>(Xw, &a[0].osh, &a[1].osh, g, jc);
   stage_f32<N::HC / 16>(Yw, dh3[0], dh3[1], g, jc);
   wave_lds_fence();
@@ -514,27 +518,23 @@ __device__ __forceinline__ void bwd_pair(const __bf16* __restrict__ Af, const __
   // second density layer
   f4 dh1[T][N::HD / 16];
   {
-    const __bf16* A = Ab + M::boff(1);
     bf8 b[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) b[t] = pack8(dgeo[t], zero);
 #pragma unroll
-    for (int m = 0; m < N::HD / 16; ++m) {
-      const bf8 w = lds_bf8<N>(A, m, lane);
+    for (int m = 0; m < N::HD / 16; ++m)
 #pragma unroll
-      for (int t = 0; t < T; ++t) dh1[t][m] = relu_grad(mfma32(w, b[t], zero), a[t].h1[m >> 1], m & 1);
-    }
+      for (int t = 0; t < T; ++t) dh1[t][m] = relu_grad(mfma32(w1[m], b[t], zero), a[t].h1[m >> 1], m & 1);
   }
+  load_ops<N>(Ab + M::boff(0), lane, w0);
   stage_packed<N::HD / 16>(Xw, a[0].h1, a[1].h1, g, jc);
   stage_f32<1>(Yw, &dgeo[0], &dgeo[1], g, jc);
   wave_lds_fence();
   dw_pair(Xs, Ys, dw.w1, lane);
   wave_lds_fence();
   // first density layer: dL/de
-  constexpr int MT0 = N::bmt(0);
   f4 de[T][MT0];
   {
-    const __bf16* A = Ab + M::boff(0);
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
@@ -545,11 +545,9 @@ __device__ __forceinline__ void bwd_pair(const __bf16* __restrict__ Af, const __
 #pragma unroll
       for (int t = 0; t < T; ++t) b[t] = pack8(dh1[t][2 * k], dh1[t][2 * k + 1]);
 #pragma unroll
-      for (int m = 0; m < MT0; ++m) {
-        const bf8 w = lds_bf8<N>(A, m * (N::HD / 32) + k, lane);
+      for (int m = 0; m < MT0; ++m)
 #pragma unroll
-        for (int t = 0; t < T; ++t) de[t][m] = mfma32(w, b[t], de[t][m]);
-      }
+        for (int t = 0; t < T; ++t) de[t][m] = mfma32(w0[m * (N::HD / 32) + k], b[t], de[t][m]);
     }
   }
 #pragma unroll
