@@ -447,7 +447,9 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
                           total, st),
             "prep mixed");
   } else {
-    if (c->zero_grads) HIP_TRY(fill_zero(grads, total, st), "zero grads");
+    // the table part is overwritten by the table-gradient reduction
+    const int64_t z0 = f->lay.table_floats & ~(int64_t)3;
+    if (c->zero_grads) HIP_TRY(fill_zero(grads + z0, total - z0, st), "zero grads");
     HIP_TRY(field_prep(f->shape, params, f->wo, b.wprep, st), "prep weights");
   }
   HIP_TRY(mark(1), "profile event");
@@ -491,7 +493,7 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
             "field backward");
   HIP_TRY(mark(6), "profile event");
   float* overflow = c->scale_state ? c->scale_state + 3 : nullptr;  // set by the two gradient writers
-  HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, mixed, grads, overflow, st), "table gradient");
+  HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, mixed, c->zero_grads != 0, grads, overflow, st), "table gradient");
   HIP_TRY(mark(7), "profile event");
   HIP_TRY(field_dw_reduce(f->shape, b.partial, kBwdBlocks, f->wo, grads, overflow, st), "weight gradient");
   HIP_TRY(mark(8), "profile event");
@@ -620,7 +622,7 @@ int nsl_field_bwd(const nsl_field* f, const float* params, const float* xn, cons
   HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, dsigma, drgb, w.rec, w.partial, f->wo, grads, st),
           "field backward");
   HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, nullptr, st), "weight gradient");
-  HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, false, grads, nullptr, st), "table gradient");
+  HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, false, false, grads, nullptr, st), "table gradient");
   return NSL_OK;
 }
 
@@ -658,7 +660,7 @@ int nsl_field_bwd_mixed(const nsl_field* f, const void* shadow, const float* xn,
   HIP_TRY(mixed_backward(f->shape, f->lv, shadow, src, kBwdBlocks, dsigma, drgb, w.rec, w.partial, f->wo, grads, st),
           "field backward (mixed)");
   HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, nullptr, st), "weight gradient");
-  HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, true, grads, nullptr, st), "table gradient");
+  HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, true, false, grads, nullptr, st), "table gradient");
   return NSL_OK;
 }
 

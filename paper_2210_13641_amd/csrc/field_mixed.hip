@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void table_to_half_kernel(const float* __restr
   } else {
     for (int64_t k = i; k < tf; ++k) h[k] = (_Float16)t[k];
   }
-  if (g) {
+  if (g && i >= (tf & ~(int64_t)7)) {
     if (i + 8 <= total) {
       reinterpret_cast<float4*>(g + i)[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       reinterpret_cast<float4*>(g + i)[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -677,9 +677,25 @@ __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(Le
   for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) out[i] = dW[i];
 }
 
-// Forward: density and colour of one 16-sample tile per wave, as the backward
-// recomputes them (one tile per wave keeps four waves per SIMD resident,
-// which hides the input loads better than pairing tiles here).
+// Forward: density and colour of 16-sample tiles, one tile per wave at a
+// time (four waves per SIMD stay resident, which hides latency better than
+// pairing tiles here).  The grid is a fixed number of workgroups, so the
+// weight operands are staged into LDS once per workgroup rather than once per
+// four tiles; with the kept encoding, a wave fetches its next tile's inputs
+// while it computes the current one (ray indices two tiles ahead).
+constexpr int kMixedFwdGrid = 1024;
+
+template <class N>
+__device__ __forceinline__ void fwd_store(const PActs<N>& a, int g, int s, bool valid, float* __restrict__ sigma_out,
+                                          float* __restrict__ rgb_out) {
+  if (g == 0 && valid) {
+    sigma_out[s] = expf(a.o[0]);
+    rgb_out[3 * s + 0] = sigmoidf(a.z[0]);
+    rgb_out[3 * s + 1] = sigmoidf(a.z[1]);
+    rgb_out[3 * s + 2] = sigmoidf(a.z[2]);
+  }
+}
+
 template <class N>
 __global__ __launch_bounds__(256) void mixed_fwd_kernel(LevelInfo lv, const _Float16* __restrict__ table,
                                                         const __bf16* __restrict__ prep, SampleSrc src,
@@ -689,27 +705,41 @@ __global__ __launch_bounds__(256) void mixed_fwd_kernel(LevelInfo lv, const _Flo
   load_bf16<N>(Af, prep, M::FWD);
   __syncthreads();
   const int S = src.n_dev ? (int)*src.n_dev : src.n;
+  const int ntiles = (S + 15) / 16;
   const int lane = lane_id(), g = lane >> 4, jc = lane & 15;
-  const int tile = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-  if (tile * 16 >= S) return;
+  const int first = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int step = gridDim.x * (blockDim.x / kWave);
+  if (first >= ntiles) return;
   LaneLevels<N> ll;
   lane_levels<N>(lv, g, ll);
-  const int s = tile * 16 + jc;
-  const bool valid = s < S;
-  TileIn<N> in;
-  if (src.ecache)
-    fetch_tile<N, true>(src, table, lv, ll, nullptr, nullptr, s, valid, g, ray_of<N>(src, s, S), in);
-  else
-    fetch_tile<N, false>(src, table, lv, ll, nullptr, nullptr, s, valid, g, 0u, in);
-  PActs<N> a[1];
-  f4 sh[1];
-  tile_operands<N>(in, g, a[0], sh[0]);
-  fwd_tiles<N, 1>(Af, lane, sh, a);
-  if (g == 0 && valid) {
-    sigma_out[s] = expf(a[0].o[0]);
-    rgb_out[3 * s + 0] = sigmoidf(a[0].z[0]);
-    rgb_out[3 * s + 1] = sigmoidf(a[0].z[1]);
-    rgb_out[3 * s + 2] = sigmoidf(a[0].z[2]);
+  if (src.ecache) {
+    TileIn<N> cur;
+    const int s0 = 16 * first + jc;
+    fetch_tile<N, true>(src, table, lv, ll, nullptr, nullptr, s0, s0 < S, g, ray_of<N>(src, s0, S), cur);
+    uint32_t rid1 = ray_of<N>(src, 16 * (first + step) + jc, S);
+    for (int tile = first; tile < ntiles; tile += step) {
+      const int s = 16 * tile + jc, s1 = s + 16 * step;
+      TileIn<N> nxt;
+      fetch_tile<N, true>(src, table, lv, ll, nullptr, nullptr, s1, s1 < S, g, rid1, nxt);
+      rid1 = ray_of<N>(src, s1 + 16 * step, S);
+      PActs<N> a[1];
+      f4 sh[1];
+      tile_operands<N>(cur, g, a[0], sh[0]);
+      fwd_tiles<N, 1>(Af, lane, sh, a);
+      fwd_store<N>(a[0], g, s, s < S, sigma_out, rgb_out);
+      cur = nxt;
+    }
+  } else {
+    for (int tile = first; tile < ntiles; tile += step) {
+      const int s = 16 * tile + jc;
+      TileIn<N> in;
+      fetch_tile<N, false>(src, table, lv, ll, nullptr, nullptr, s, s < S, g, 0u, in);
+      PActs<N> a[1];
+      f4 sh[1];
+      tile_operands<N>(in, g, a[0], sh[0]);
+      fwd_tiles<N, 1>(Af, lane, sh, a);
+      fwd_store<N>(a[0], g, s, s < S, sigma_out, rgb_out);
+    }
   }
 }
 
@@ -736,7 +766,7 @@ static hipError_t prep_impl(const float* params, const WOffsets& wo, int64_t tab
   hipLaunchKernelGGL(mixed_prep_kernel<N>, dim3((n + 255) / 256), dim3(256), 0, st, params, wo,
                      static_cast<__bf16*>(shadow));
   _Float16* t16 = reinterpret_cast<_Float16*>(static_cast<char*>(shadow) + mixed_ops_bytes<N>());
-  const int64_t span = zero_grads ? (total > table_floats ? total : table_floats) : table_floats;
+  const int64_t span = zero_grads && total > table_floats ? total : table_floats;
   if (span > 0)
     hipLaunchKernelGGL(table_to_half_kernel, dim3((unsigned)((span + 2047) / 2048)), dim3(256), 0, st, params, t16,
                        table_floats, zero_grads, total);
@@ -750,7 +780,8 @@ static hipError_t fwd_impl(const LevelInfo& lv, const void* shadow, const Sample
   if (tiles == 0) return hipSuccess;
   const __bf16* ops = static_cast<const __bf16*>(shadow);
   const _Float16* t16 = reinterpret_cast<const _Float16*>(static_cast<const char*>(shadow) + mixed_ops_bytes<N>());
-  hipLaunchKernelGGL(mixed_fwd_kernel<N>, dim3((tiles + 3) / 4), dim3(256), 0, st, lv, t16, ops, src, sigma, rgb);
+  const int grid = (tiles + 3) / 4 < kMixedFwdGrid ? (tiles + 3) / 4 : kMixedFwdGrid;
+  hipLaunchKernelGGL(mixed_fwd_kernel<N>, dim3(grid), dim3(256), 0, st, lv, t16, ops, src, sigma, rgb);
   return hipGetLastError();
 }
 

@@ -68,11 +68,12 @@ struct BinPlan {
 
 BinPlan bin_plan(uint32_t entries, int levels, int64_t max_samples);
 // grad_table += the table gradient of the samples of src, from the dL/de
-// that the backward kernel left in rb.de.
+// that the backward kernel left in rb.de; with overwrite, grad_table = that
+// gradient (every entry is written, so the caller need not clear it first).
 // overflow (may be null): set to 1.0f when a gradient value the call writes
 // is not finite (the loss-scale overflow flag).
 hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
-                       bool bf16_values, float* grad_table, float* overflow, hipStream_t st);
+                       bool bf16_values, bool overwrite, float* grad_table, float* overflow, hipStream_t st);
 
 // field.hip
 size_t field_prep_floats(int shape);
@@ -108,8 +109,10 @@ size_t field_fwd_floats(int shape);
 // field_mixed.hip: FP16 table, BF16 MLP on MFMA, FP32 accumulation.  The
 // shadow buffer holds the BF16 operands and the FP16 table copy.
 size_t mixed_shadow_bytes(int shape, int64_t table_floats);
-// zero_grads (may be null): a gradient vector of total floats cleared in the
-// same pass as the FP16 table copy.
+// zero_grads (may be null): a gradient vector of total floats whose entries
+// from table_floats rounded down to a multiple of 8 onwards (the MLP weights
+// and padding) are cleared in the same pass as the FP16 table copy; the table
+// part is left to bin_scatter's overwrite.
 hipError_t mixed_prepare(int shape, const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
                          float* zero_grads, int64_t total, hipStream_t st);
 hipError_t mixed_forward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,

@@ -223,9 +223,14 @@ __global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int n
 // count, ordered by bin in LDS (counting sort with LDS integer atomics), and
 // stored so that the global stores of a wave cover runs of consecutive slots
 // of a few bins instead of one cache line per lane.
+//
+// zero_table (overwriting reductions only, else null): the gradient entries of
+// the bins that the reduction will not overwrite (bins with no records, or
+// with several chunks, which add with atomics) are cleared here first.
 template <class R, int G>
 __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, LevelInfo lv, RecordBuffers rb,
-                                                               int nbins) {
+                                                               int nbins, float* __restrict__ zero_table,
+                                                               uint32_t entries) {
   static_assert(kRecTilesPerWave == 1, "one tile per wave");
   typedef typename R::T Rec;
   Rec* __restrict__ sorted = reinterpret_cast<Rec*>(rb.sorted);
@@ -241,6 +246,19 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
   for (int b = t; b < nbins; b += kRecThreads) {
     gcur[b] = rb.bin_start[b] + off[b];
     cnt[b] = 0u;
+  }
+  if (zero_table) {
+    // two entries (one float4) per thread and step; the table is 16-byte
+    // aligned, an odd last entry is cleared on its own
+    const uint32_t units = (entries + 1) / 2;
+    for (uint32_t u = blockIdx.x * kRecThreads + t; u < units; u += gridDim.x * kRecThreads) {
+      const uint32_t e = 2 * u, bin = e >> kBinShift;
+      if (rb.chunk_start[bin + 1] - rb.chunk_start[bin] == 1u) continue;
+      if (e + 1 < entries)
+        reinterpret_cast<float4*>(zero_table)[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      else
+        reinterpret_cast<float2*>(zero_table)[e] = make_float2(0.0f, 0.0f);
+    }
   }
   const int S = sample_count(src);
   const int wave = t / kWave, lane = lane_id(), g = lane >> 4, jc = lane & 15;
@@ -317,10 +335,12 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
   }
 }
 
+// overwrite: a bin of one chunk stores its sums over every entry (zeros
+// included) instead of adding them to the gradient.
 template <class R>
 __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffers rb, int nbins, uint32_t entries,
                                                                     float* __restrict__ grad_table,
-                                                                    float* __restrict__ overflow) {
+                                                                    float* __restrict__ overflow, bool overwrite) {
   typedef typename R::T Rec;
   const Rec* __restrict__ sorted = reinterpret_cast<const Rec*>(rb.sorted);
   // (g0, g1) of each entry as one 64-bit word: float pairs are added with
@@ -366,6 +386,11 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
   for (uint32_t e = threadIdx.x; e < ne; e += kReduceThreads) {
     const unsigned long long w = acc[e];
     const float a0 = __uint_as_float((uint32_t)w), a1 = __uint_as_float((uint32_t)(w >> 32));
+    if (nch == 1 && overwrite) {
+      gt[e] = make_float2(a0, a1);
+      bad |= !isfinite(a0) || !isfinite(a1);
+      continue;
+    }
     if (a0 == 0.0f && a1 == 0.0f) continue;
     if (nch == 1) {
       float2 v = gt[e];
@@ -397,8 +422,9 @@ BinPlan bin_plan(uint32_t entries, int levels, int64_t max_samples) {
 }
 
 hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
-                       bool bf16_values, float* grad_table, float* overflow, hipStream_t st) {
+                       bool bf16_values, bool overwrite, float* grad_table, float* overflow, hipStream_t st) {
   if (p.nbins == 0 || p.nblk == 0) return hipSuccess;
+  float* zero_table = overwrite ? grad_table : nullptr;
   const size_t bins_lds = (size_t)p.nbins * sizeof(uint32_t);
   hipLaunchKernelGGL(bin_count_kernel, dim3(p.nblk), dim3(kRecThreads), bins_lds, st, src, lv, rb, p.nbins);
   hipLaunchKernelGGL(bin_colscan_kernel, dim3((p.nbins + 15) / 16), dim3(16 * kScanGroups), 0, st, rb, p.nbins,
@@ -406,14 +432,14 @@ hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSr
   hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins);
   if (bf16_values) {
     hipLaunchKernelGGL((bin_place_kernel<RecBF16, 2>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb,
-                       p.nbins);
+                       p.nbins, zero_table, p.entries);
     hipLaunchKernelGGL(bin_reduce_kernel<RecBF16>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins,
-                       p.entries, grad_table, overflow);
+                       p.entries, grad_table, overflow, overwrite);
   } else {
     hipLaunchKernelGGL((bin_place_kernel<RecF32, 1>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb,
-                       p.nbins);
+                       p.nbins, zero_table, p.entries);
     hipLaunchKernelGGL(bin_reduce_kernel<RecF32>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins,
-                       p.entries, grad_table, overflow);
+                       p.entries, grad_table, overflow, overwrite);
   }
   return hipGetLastError();
 }

@@ -291,6 +291,11 @@ def _compare_step(spec, g, o, lay, tol=TOL):
     assert g["loss"][1] == pytest.approx(o["loss_rgb"], rel=tol)
     assert g["loss"][2] == pytest.approx(o["loss_d"], rel=tol)
     gtab, gws = split_grads(g["grads"], lay, spec)
+    covered = np.zeros(len(g["grads"]), bool)
+    covered[:lay["table_floats"]] = True
+    for off, (a, b) in zip(lay["w_offsets"], spec.mlp_dims()):
+        covered[off:off + a * b] = True
+    assert np.all(g["grads"][~covered] == 0)        # the padding between blocks is cleared as well
     check_mag("grad table", gtab, o["grad_table"], o["grad_table_mag"], tol)
     for j in range(len(gws)):
         check_mag(f"grad W{j}", gws[j], o["grad_w"][j], o["grad_w_mag"][j], tol)
