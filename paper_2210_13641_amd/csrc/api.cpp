@@ -440,13 +440,14 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   const bool prof = g_prof.on;
   auto mark = [&](int i) -> hipError_t { return prof ? hipEventRecord(g_prof.ev[i], st) : hipSuccess; };
   HIP_TRY(mark(0), "profile event");
-  if (c->scale_state) HIP_TRY(scale_begin(c->scale_state, st), "loss scale");
   if (mixed) {
-    // the gradient clearing rides along the FP16 table copy
+    // the gradient clearing and the overflow-flag reset ride along the FP16
+    // table copy
     HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, b.shadow, c->zero_grads ? grads : nullptr,
-                          total, st),
+                          total, c->scale_state ? c->scale_state + 3 : nullptr, st),
             "prep mixed");
   } else {
+    if (c->scale_state) HIP_TRY(scale_begin(c->scale_state, st), "loss scale");
     // the table part is overwritten by the table-gradient reduction
     const int64_t z0 = f->lay.table_floats & ~(int64_t)3;
     if (c->zero_grads) HIP_TRY(fill_zero(grads + z0, total - z0, st), "zero grads");
@@ -495,7 +496,9 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   float* overflow = c->scale_state ? c->scale_state + 3 : nullptr;  // set by the two gradient writers
   HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, mixed, c->zero_grads != 0, grads, overflow, st), "table gradient");
   HIP_TRY(mark(7), "profile event");
-  HIP_TRY(field_dw_reduce(f->shape, b.partial, kBwdBlocks, f->wo, grads, overflow, st), "weight gradient");
+  const LossSum ls{b.loss_parts, n, c->lambda_d, loss_out};
+  HIP_TRY(field_dw_reduce(f->shape, b.partial, kBwdBlocks, f->wo, grads, overflow, &ls, st),
+          "weight gradient and loss");
   HIP_TRY(mark(8), "profile event");
   if (c->do_adam)
     HIP_TRY(adam_update(params, grads, adam_m, adam_v, total, c->lr, c->beta1, c->beta2, c->eps, c->adam_step,
@@ -621,7 +624,7 @@ int nsl_field_bwd(const nsl_field* f, const float* params, const float* xn, cons
   FieldArgs fa{params, w.wprep, f->lv};
   HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, dsigma, drgb, w.rec, w.partial, f->wo, grads, st),
           "field backward");
-  HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, nullptr, st), "weight gradient");
+  HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, nullptr, nullptr, st), "weight gradient");
   HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, false, false, grads, nullptr, st), "table gradient");
   return NSL_OK;
 }
@@ -633,7 +636,8 @@ size_t nsl_mixed_shadow_bytes(const nsl_field* f) {
 int nsl_field_prepare_mixed(const nsl_field* f, const float* params, void* shadow, hipStream_t st) {
   if (!f || !params || !shadow) return fail(NSL_E_INVALID, "null argument");
   if (misaligned(params) || misaligned(shadow)) return fail(NSL_E_INVALID, "params and shadow must be 16-byte aligned");
-  HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, shadow, nullptr, 0, st), "prepare mixed");
+  HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, shadow, nullptr, 0, nullptr, st),
+          "prepare mixed");
   return NSL_OK;
 }
 
@@ -659,7 +663,7 @@ int nsl_field_bwd_mixed(const nsl_field* f, const void* shadow, const float* xn,
   if (rc) return rc;
   HIP_TRY(mixed_backward(f->shape, f->lv, shadow, src, kBwdBlocks, dsigma, drgb, w.rec, w.partial, f->wo, grads, st),
           "field backward (mixed)");
-  HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, nullptr, st), "weight gradient");
+  HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, nullptr, nullptr, st), "weight gradient");
   HIP_TRY(bin_scatter(w.plan, w.rec, src, f->lv, true, false, grads, nullptr, st), "table gradient");
   return NSL_OK;
 }

@@ -292,34 +292,6 @@ __global__ __launch_bounds__(256) void composite_loss_kernel(CompositeIO io, Los
     ray_backward(io, b, n, s, gC, gD, 0.0f, 0.0f, g_sigma, g_rgb_s);
 }
 
-// loss = (L_rgb + lambda_d L_D, L_rgb, L_D): sums of the per-ray parts in a
-// fixed order (strided per-thread sums, then a tree in LDS).
-__global__ __launch_bounds__(1024) void loss_reduce_kernel(const float* __restrict__ parts, int R, float lambda_d,
-                                                           float* __restrict__ loss) {
-  __shared__ float s0[1024], s1[1024];
-  const int t = threadIdx.x;
-  float a = 0.0f, b = 0.0f;
-  for (int r = t; r < R; r += 1024) {
-    a += parts[2 * r];
-    b += parts[2 * r + 1];
-  }
-  s0[t] = a;
-  s1[t] = b;
-  __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
-    if (t < o) {
-      s0[t] += s0[t + o];
-      s1[t] += s1[t + o];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    loss[0] = s0[0] + lambda_d * s1[0];
-    loss[1] = s0[0];
-    loss[2] = s1[0];
-  }
-}
-
 dim3 grid_for(int R) { return dim3((R + kWavesPerBlock - 1) / kWavesPerBlock); }
 
 }  // namespace
@@ -342,7 +314,6 @@ hipError_t composite_loss_backward(const CompositeIO& io, const LossIO& lo, floa
                                    float* g_rgb_s, hipStream_t st) {
   if (io.R > 0) {
     hipLaunchKernelGGL(composite_loss_kernel, grid_for(io.R), dim3(256), 0, st, io, lo, g_sigma, g_rgb_s);
-    hipLaunchKernelGGL(loss_reduce_kernel, dim3(1), dim3(1024), 0, st, lo.parts, io.R, lo.lambda_d, lo.loss);
   }
   return hipGetLastError();
 }

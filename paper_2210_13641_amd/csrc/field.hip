@@ -535,9 +535,9 @@ hipError_t field_encode(int shape, const FieldArgs& a, const SampleSrc& src, int
 }
 
 hipError_t field_dw_reduce(int shape, const float* partial, int nblocks, const WOffsets& wo, float* grads,
-                           float* overflow, hipStream_t st) {
-  return shape == kShapeTiny ? launch_dw_reduce<NetTiny>(partial, nblocks, wo, grads, overflow, st)
-                             : launch_dw_reduce<NetFull>(partial, nblocks, wo, grads, overflow, st);
+                           float* overflow, const LossSum* ls, hipStream_t st) {
+  return shape == kShapeTiny ? launch_dw_reduce<NetTiny>(partial, nblocks, wo, grads, overflow, ls, st)
+                             : launch_dw_reduce<NetFull>(partial, nblocks, wo, grads, overflow, ls, st);
 }
 
 size_t field_fwd_floats(int shape) { return shape == kShapeTiny ? NetTiny::FWD_FLOATS : NetFull::FWD_FLOATS; }

@@ -261,24 +261,78 @@ struct DWAcc {
   }
 };
 
+// The loss of a step from its per-ray shares, summed in a fixed order by one
+// 256-thread workgroup: loss = (L_rgb + lambda_d L_D, L_rgb, L_D).
+__device__ __forceinline__ void loss_sum_block(const LossSum& ls) {
+  __shared__ float s0[256], s1[256];
+  const int t = threadIdx.x;
+  const float2* __restrict__ p2 = reinterpret_cast<const float2*>(ls.parts);
+  float a = 0.0f, b = 0.0f;
+  for (int r0 = 0; r0 < ls.R; r0 += 256 * 16) {
+    float2 v[16];  // sixteen loads in flight, added in ray order
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int r = r0 + 256 * k + t;
+      v[k] = r < ls.R ? p2[r] : make_float2(0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      a += v[k].x;
+      b += v[k].y;
+    }
+  }
+  s0[t] = a;
+  s1[t] = b;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      s0[t] += s0[t + o];
+      s1[t] += s1[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    ls.loss[0] = s0[0] + ls.lambda_d * s1[0];
+    ls.loss[1] = s0[0];
+    ls.loss[2] = s1[0];
+  }
+}
+
 // grads[weights] += sum over blocks of the per-block weight gradients, in a
-// fixed order: a block takes 64 weights, its four waves sum every fourth
-// partial, and the four sums are added in LDS.
+// fixed order: a workgroup takes 16 weights, each of its 16 thread groups
+// sums every 16th partial (all loads of a thread in flight at once), and the
+// 16 sums are added in LDS.  With ls.loss set, one more workgroup sums the
+// loss of the step.
 template <class N>
 __global__ __launch_bounds__(256) void dw_reduce_kernel(const float* __restrict__ partial, int nblocks, WOffsets wo,
-                                                        float* __restrict__ grads, float* __restrict__ overflow) {
-  __shared__ float red[4][64];
-  const int wl = threadIdx.x & 63, pg = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + wl;
+                                                        float* __restrict__ grads, float* __restrict__ overflow,
+                                                        LossSum ls) {
+  if (ls.loss && blockIdx.x == gridDim.x - 1) {
+    loss_sum_block(ls);
+    return;
+  }
+  __shared__ float red[16][16];
+  const int wl = threadIdx.x & 15, pg = threadIdx.x >> 4;
+  const int i = blockIdx.x * 16 + wl;
   float acc = 0.0f;
   if (i < N::NWEIGHTS) {
-#pragma unroll 8
-    for (int b = pg; b < nblocks; b += 4) acc += partial[(size_t)b * N::NWEIGHTS + i];
+    for (int b0 = pg; b0 < nblocks; b0 += 256) {
+      float v[16];  // sixteen loads in flight, added in block order
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int b = b0 + 16 * k;
+        v[k] = b < nblocks ? partial[(size_t)b * N::NWEIGHTS + i] : 0.0f;
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc += v[k];
+    }
   }
   red[pg][wl] = acc;
   __syncthreads();
   if (pg != 0 || i >= N::NWEIGHTS) return;
-  const float sum = (red[0][wl] + red[1][wl]) + (red[2][wl] + red[3][wl]);
+  float sum = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) sum += red[k][wl];
   int j = 0;
   while (j + 1 < N::NW && i >= N::woff(j + 1)) ++j;
   float* g = grads + wo.off[j] + (i - N::woff(j));
@@ -289,9 +343,10 @@ __global__ __launch_bounds__(256) void dw_reduce_kernel(const float* __restrict_
 
 template <class N>
 __host__ inline hipError_t launch_dw_reduce(const float* partial, int nblocks, const WOffsets& wo, float* grads,
-                                           float* overflow, hipStream_t st) {
-  hipLaunchKernelGGL(dw_reduce_kernel<N>, dim3((N::NWEIGHTS + 63) / 64), dim3(256), 0, st, partial, nblocks, wo,
-                     grads, overflow);
+                                           float* overflow, const LossSum* ls, hipStream_t st) {
+  const LossSum none{};
+  hipLaunchKernelGGL(dw_reduce_kernel<N>, dim3((N::NWEIGHTS + 15) / 16 + (ls ? 1 : 0)), dim3(256), 0, st, partial,
+                     nblocks, wo, grads, overflow, ls ? *ls : none);
   return hipGetLastError();
 }
 

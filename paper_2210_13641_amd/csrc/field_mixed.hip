@@ -81,10 +81,11 @@ __host__ __device__ constexpr int mixed_bwd_kfeature(int j, int s, int g, int u)
   return 32 * s + 16 * (u >> 2) + 4 * g + (u & 3);
 }
 
+// Element idx of the BF16 operand arrays (forward, then backward).
 template <class N>
-__global__ void mixed_prep_kernel(const float* __restrict__ params, WOffsets wo, __bf16* __restrict__ out) {
+__device__ __forceinline__ void prep_operand(const float* __restrict__ params, const WOffsets& wo,
+                                             __bf16* __restrict__ out, int idx) {
   using M = Mixed<N>;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= M::FWD + M::BWD) return;
   float v = 0.0f;
   const bool fwd = idx < M::FWD;
@@ -112,13 +113,12 @@ __global__ void mixed_prep_kernel(const float* __restrict__ params, WOffsets wo,
   out[idx] = (__bf16)v;
 }
 
-// FP16 copy of the FP32 table (tf floats), eight values per thread; with g
-// set, the same pass clears the gradient vector (total floats), which the
-// step needs anyway when it starts from zero gradients.
-__global__ __launch_bounds__(256) void table_to_half_kernel(const float* __restrict__ t, _Float16* __restrict__ h,
-                                                            int64_t tf, float* __restrict__ g, int64_t total) {
+// FP16 copy of the FP32 table (tf floats), eight values [i, i + 8) per
+// thread; with g set, the same pass clears the gradient vector from tf
+// rounded down to a multiple of 8 up to total.
+__device__ __forceinline__ void table_to_half(const float* __restrict__ t, _Float16* __restrict__ h, int64_t tf,
+                                              float* __restrict__ g, int64_t total, int64_t i) {
   typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-  const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
   if (i + 8 <= tf) {
     const float4 a = reinterpret_cast<const float4*>(t + i)[0];
     const float4 b = reinterpret_cast<const float4*>(t + i)[1];
@@ -136,6 +136,22 @@ __global__ __launch_bounds__(256) void table_to_half_kernel(const float* __restr
       for (int64_t k = i; k < total; ++k) g[k] = 0.0f;
     }
   }
+}
+
+// One launch prepares a mixed-precision step: workgroups [0, tblocks) copy
+// the table to FP16 (and clear the gradient tail), the rest lay out the BF16
+// weight operands; clear_flag (may be null), the loss-scale overflow flag, is
+// reset by the first thread.
+template <class N>
+__global__ __launch_bounds__(256) void mixed_prepare_kernel(const float* __restrict__ params, WOffsets wo,
+                                                            __bf16* __restrict__ ops, _Float16* __restrict__ t16,
+                                                            int64_t tf, float* __restrict__ g, int64_t total,
+                                                            int tblocks, float* __restrict__ clear_flag) {
+  if (clear_flag && blockIdx.x == 0 && threadIdx.x == 0) *clear_flag = 0.0f;
+  if ((int)blockIdx.x < tblocks)
+    table_to_half(params, t16, tf, g, total, ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8);
+  else
+    prep_operand<N>(params, wo, ops, ((int)blockIdx.x - tblocks) * 256 + (int)threadIdx.x);
 }
 
 template <class N>
@@ -760,16 +776,14 @@ size_t mixed_shadow_bytes(int shape, int64_t table_floats) {
 
 template <class N>
 static hipError_t prep_impl(const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
-                            float* zero_grads, int64_t total, hipStream_t st) {
+                            float* zero_grads, int64_t total, float* clear_flag, hipStream_t st) {
   using M = Mixed<N>;
   const int n = M::FWD + M::BWD;
-  hipLaunchKernelGGL(mixed_prep_kernel<N>, dim3((n + 255) / 256), dim3(256), 0, st, params, wo,
-                     static_cast<__bf16*>(shadow));
   _Float16* t16 = reinterpret_cast<_Float16*>(static_cast<char*>(shadow) + mixed_ops_bytes<N>());
   const int64_t span = zero_grads && total > table_floats ? total : table_floats;
-  if (span > 0)
-    hipLaunchKernelGGL(table_to_half_kernel, dim3((unsigned)((span + 2047) / 2048)), dim3(256), 0, st, params, t16,
-                       table_floats, zero_grads, total);
+  const int tblocks = (int)((span + 2047) / 2048);
+  hipLaunchKernelGGL(mixed_prepare_kernel<N>, dim3(tblocks + (n + 255) / 256), dim3(256), 0, st, params, wo,
+                     static_cast<__bf16*>(shadow), t16, table_floats, zero_grads, total, tblocks, clear_flag);
   return hipGetLastError();
 }
 
@@ -814,9 +828,9 @@ hipError_t mixed_encode(int shape, const LevelInfo& lv, const void* shadow, cons
 }
 
 hipError_t mixed_prepare(int shape, const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
-                         float* zero_grads, int64_t total, hipStream_t st) {
-  return shape == kShapeTiny ? prep_impl<NetTiny>(params, wo, table_floats, shadow, zero_grads, total, st)
-                             : prep_impl<NetFull>(params, wo, table_floats, shadow, zero_grads, total, st);
+                         float* zero_grads, int64_t total, float* clear_flag, hipStream_t st) {
+  return shape == kShapeTiny ? prep_impl<NetTiny>(params, wo, table_floats, shadow, zero_grads, total, clear_flag, st)
+                             : prep_impl<NetFull>(params, wo, table_floats, shadow, zero_grads, total, clear_flag, st);
 }
 
 hipError_t mixed_forward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,

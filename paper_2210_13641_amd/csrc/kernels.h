@@ -90,8 +90,18 @@ hipError_t field_backward(int shape, const FieldArgs& a, const SampleSrc& src, i
                           const float* dsigma, const float* drgb, const RecordBuffers& rec,
                           float* partial, const WOffsets& wo, float* grads, hipStream_t st);
 
+// The loss of a step from the per-ray shares parts[R][2] (L_rgb, L_D) that
+// composite_loss_backward leaves: loss[0..2] = (L_rgb + lambda_d L_D, L_rgb,
+// L_D), summed in a fixed order.
+struct LossSum {
+  const float* parts;
+  int R;
+  float lambda_d;
+  float* loss;
+};
+// ls (may be null): the step's loss is summed by the same launch.
 hipError_t field_dw_reduce(int shape, const float* partial, int nblocks, const WOffsets& wo, float* grads,
-                           float* overflow, hipStream_t st);
+                           float* overflow, const LossSum* ls, hipStream_t st);
 // The encoding of every sample of src into src.ecache (FP32 table).
 hipError_t field_encode(int shape, const FieldArgs& a, const SampleSrc& src, int max_samples, hipStream_t st);
 
@@ -112,9 +122,11 @@ size_t mixed_shadow_bytes(int shape, int64_t table_floats);
 // zero_grads (may be null): a gradient vector of total floats whose entries
 // from table_floats rounded down to a multiple of 8 onwards (the MLP weights
 // and padding) are cleared in the same pass as the FP16 table copy; the table
-// part is left to bin_scatter's overwrite.
+// part is left to bin_scatter's overwrite.  clear_flag (may be null) is set
+// to 0 by the same launch (the loss-scale overflow flag at the start of a
+// step).
 hipError_t mixed_prepare(int shape, const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
-                         float* zero_grads, int64_t total, hipStream_t st);
+                         float* zero_grads, int64_t total, float* clear_flag, hipStream_t st);
 hipError_t mixed_forward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
                          float* sigma, float* rgb, hipStream_t st);
 // The encoding of every sample of src into src.ecache (FP16 table, BF16 out).
@@ -191,6 +203,8 @@ hipError_t composite_forward(const CompositeIO& io, hipStream_t st);
 hipError_t composite_backward(const CompositeIO& io, const float* g_rgb, const float* g_depth,
                               const float* g_var, const float* g_opacity, float* g_sigma, float* g_rgb_s,
                               hipStream_t st);
+// Writes the per-ray loss shares to lo.parts; their sum into lo.loss is
+// left to a LossSum (the step's last reduction launch).
 hipError_t composite_loss_backward(const CompositeIO& io, const LossIO& lo, float* g_sigma,
                                    float* g_rgb_s, hipStream_t st);
 

@@ -118,24 +118,22 @@ __global__ __launch_bounds__(256) void rays_count_kernel(KeyframeStore kf, March
 
 constexpr int kScanThreads = 1024;
 
-// Single-block exclusive scan of the counts, batch cut and statistics.
+// Single-block exclusive scan of the counts, batch cut and statistics: each
+// thread sums a run of consecutive rays, a wave scan (DPP) and the totals of
+// the waves before give its exclusive offset.
 __global__ __launch_bounds__(kScanThreads) void scan_cut_kernel(RayBuffers rb, int n, int max_samples) {
-  __shared__ uint32_t part[kScanThreads];
+  __shared__ uint32_t wtot[kScanThreads / kWave];
   __shared__ uint32_t red[3][kScanThreads / kWave];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid / kWave;
   const int per = (n + kScanThreads - 1) / kScanThreads;
   const int b = tid * per, e = min(n, b + per);
   uint32_t sum = 0;
   for (int i = b; i < e; ++i) sum += rb.counts[i];
-  part[tid] = sum;
+  const uint32_t incl = wave_incl_scan_u32(sum);
+  if (lane_id() == kWave - 1) wtot[wave] = incl;
   __syncthreads();
-  for (int o = 1; o < kScanThreads; o <<= 1) {
-    const uint32_t v = tid >= o ? part[tid - o] : 0u;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  uint32_t run = part[tid] - sum;  // exclusive
+  uint32_t run = incl - sum;  // exclusive
+  for (int w = 0; w < wave; ++w) run += wtot[w];
   uint32_t nr = 0, nk = 0, nm = 0;
   for (int i = b; i < e; ++i) {
     rb.offsets[i] = run;

@@ -148,36 +148,46 @@ __global__ __launch_bounds__(kRecThreads) void bin_count_kernel(SampleSrc src, L
 }
 
 // off[b'][b] = sum over blocks b'' < b' of hist[b''][b]; total[b] = sum over
-// all.  A workgroup takes 16 bins; each bin's blocks are split over 64
-// threads (partial sums, a 64-way exclusive scan, then the running prefix).
+// all.  A workgroup takes 16 bins; the blocks are taken in segments of
+// 64 x kColRows, thread group q owning kColRows consecutive blocks of a
+// segment, whose counts it loads at once and keeps in registers: group sums,
+// a 64-way exclusive scan in LDS, then the running prefix over the group's
+// blocks.
 constexpr int kScanGroups = 64;
+constexpr int kColRows = 32;
 __global__ __launch_bounds__(16 * kScanGroups) void bin_colscan_kernel(RecordBuffers rb, int nbins, int nblk) {
   __shared__ uint32_t part[kScanGroups][17];
   const int bl = threadIdx.x & 15, q = threadIdx.x >> 4;
   const int b = blockIdx.x * 16 + bl;
-  const int per = (nblk + kScanGroups - 1) / kScanGroups;
-  const int r0 = min(nblk, q * per), r1 = min(nblk, r0 + per);
-  uint32_t sum = 0;
-  if (b < nbins) {
+  const bool on = b < nbins;
+  uint32_t carry = 0;
+  for (int seg = 0; seg < nblk; seg += kScanGroups * kColRows) {
+    const int r0 = seg + q * kColRows;
+    uint32_t v[kColRows], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kColRows; ++k) v[k] = on && r0 + k < nblk ? rb.hist[(size_t)(r0 + k) * nbins + b] : 0u;
+#pragma unroll
+    for (int k = 0; k < kColRows; ++k) sum += v[k];
+    part[q][bl] = sum;
+    __syncthreads();
+    uint32_t run = carry, total = 0;
 #pragma unroll 8
-    for (int r = r0; r < r1; ++r) sum += rb.hist[(size_t)r * nbins + b];
+    for (int k = 0; k < kScanGroups; ++k) {
+      const uint32_t x = part[k][bl];
+      run += k < q ? x : 0u;
+      total += x;
+    }
+    if (on) {
+#pragma unroll
+      for (int k = 0; k < kColRows; ++k) {
+        if (r0 + k < nblk) rb.off[(size_t)(r0 + k) * nbins + b] = run;
+        run += v[k];
+      }
+    }
+    carry += total;
+    __syncthreads();
   }
-  part[q][bl] = sum;
-  __syncthreads();
-  if (b >= nbins) return;
-  uint32_t run = 0, total = 0;
-  for (int k = 0; k < kScanGroups; ++k) {
-    const uint32_t x = part[k][bl];
-    run += k < q ? x : 0u;
-    total += x;
-  }
-  if (q == 0) rb.bin_total[b] = total;
-#pragma unroll 8
-  for (int r = r0; r < r1; ++r) {
-    const uint32_t h = rb.hist[(size_t)r * nbins + b];
-    rb.off[(size_t)r * nbins + b] = run;
-    run += h;
-  }
+  if (on && q == 0) rb.bin_total[b] = carry;
 }
 
 // bin_start = exclusive prefix of the totals, chunk_start = exclusive prefix
