@@ -148,20 +148,32 @@ __global__ __launch_bounds__(kRecThreads) void bin_count_kernel(SampleSrc src, L
 }
 
 // off[b'][b] = sum over blocks b'' < b' of hist[b''][b]; total[b] = sum over
-// all.  A workgroup takes 16 bins; the blocks are taken in segments of
-// 64 x kColRows, thread group q owning kColRows consecutive blocks of a
-// segment, whose counts it loads at once and keeps in registers: group sums,
-// a 64-way exclusive scan in LDS, then the running prefix over the group's
-// blocks.
-constexpr int kScanGroups = 64;
-constexpr int kColRows = 32;
-__global__ __launch_bounds__(16 * kScanGroups) void bin_colscan_kernel(RecordBuffers rb, int nbins, int nblk) {
-  __shared__ uint32_t part[kScanGroups][17];
-  const int bl = threadIdx.x & 15, q = threadIdx.x >> 4;
-  const int b = blockIdx.x * 16 + bl;
+// all.  A workgroup takes 4 bins and splits the blocks into segments of
+// 256 x kColRows: thread group q (4 threads, one per bin) owns kColRows
+// consecutive blocks of a segment, loads their counts at once and keeps them
+// in registers; the 256 group sums of a bin are scanned by one wave (4 per
+// lane, then a DPP scan), and each thread writes the running prefix over its
+// blocks.  A 128-byte row segment holds 32 bins, read by 8 workgroups: those
+// are placed on one XCD (workgroups go round-robin over the 8 XCDs), so the
+// segment is fetched into one L2 only.
+constexpr int kColBins = 4;
+constexpr int kColGroups = 256;
+constexpr int kColRows = 8;
+__device__ __forceinline__ int colscan_first_bin() {
+  const int x = (int)(blockIdx.x % 8u), j = (int)(blockIdx.x / 8u);
+  return ((j / 8) * 8 + x) * 32 + (j % 8) * kColBins;
+}
+int colscan_grid(int nbins) { return 64 * ((nbins + 255) / 256); }
+
+__global__ __launch_bounds__(kColBins * kColGroups) void bin_colscan_kernel(RecordBuffers rb, int nbins, int nblk) {
+  __shared__ uint32_t part[kColGroups][kColBins];
+  __shared__ uint32_t tot[kColBins];
+  const int bl = threadIdx.x & (kColBins - 1), q = threadIdx.x / kColBins;
+  const int b = colscan_first_bin() + bl;
   const bool on = b < nbins;
+  const int wave = threadIdx.x / kWave, lane = lane_id();
   uint32_t carry = 0;
-  for (int seg = 0; seg < nblk; seg += kScanGroups * kColRows) {
+  for (int seg = 0; seg < nblk; seg += kColGroups * kColRows) {
     const int r0 = seg + q * kColRows;
     uint32_t v[kColRows], sum = 0;
 #pragma unroll
@@ -170,13 +182,25 @@ __global__ __launch_bounds__(16 * kScanGroups) void bin_colscan_kernel(RecordBuf
     for (int k = 0; k < kColRows; ++k) sum += v[k];
     part[q][bl] = sum;
     __syncthreads();
-    uint32_t run = carry, total = 0;
-#pragma unroll 8
-    for (int k = 0; k < kScanGroups; ++k) {
-      const uint32_t x = part[k][bl];
-      run += k < q ? x : 0u;
-      total += x;
+    if (wave < kColBins) {
+      // wave w scans bin w: lane l holds groups 4l .. 4l + 3
+      uint32_t g[4], x = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        g[k] = part[4 * lane + k][wave];
+        x += g[k];
+      }
+      const uint32_t incl = wave_incl_scan_u32(x);
+      uint32_t run = incl - x;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        part[4 * lane + k][wave] = run;
+        run += g[k];
+      }
+      if (lane == kWave - 1) tot[wave] = incl;
     }
+    __syncthreads();
+    uint32_t run = carry + part[q][bl];
     if (on) {
 #pragma unroll
       for (int k = 0; k < kColRows; ++k) {
@@ -184,7 +208,7 @@ __global__ __launch_bounds__(16 * kScanGroups) void bin_colscan_kernel(RecordBuf
         run += v[k];
       }
     }
-    carry += total;
+    carry += tot[bl];
     __syncthreads();
   }
   if (on && q == 0) rb.bin_total[b] = carry;
@@ -193,7 +217,7 @@ __global__ __launch_bounds__(16 * kScanGroups) void bin_colscan_kernel(RecordBuf
 // bin_start = exclusive prefix of the totals, chunk_start = exclusive prefix
 // of ceil(total / kChunk); both with the grand total at [nbins].
 __global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int nbins) {
-  __shared__ uint32_t s_rec[1024], s_chk[1024];
+  __shared__ uint32_t w_rec[1024 / kWave], w_chk[1024 / kWave];
   const int t = threadIdx.x;
   const int per = (nbins + 1023) / 1024;
   const int b0 = min(nbins, t * per), b1 = min(nbins, b0 + per);
@@ -203,17 +227,21 @@ __global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int n
     rec += n;
     chk += (n + kChunk - 1) / kChunk;
   }
-  s_rec[t] = rec;
-  s_chk[t] = chk;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const uint32_t a = t >= o ? s_rec[t - o] : 0u, c = t >= o ? s_chk[t - o] : 0u;
-    __syncthreads();
-    s_rec[t] += a;
-    s_chk[t] += c;
-    __syncthreads();
+  // wave scans, then the totals of the waves before
+  const int wave = t / kWave;
+  const uint32_t ir = wave_incl_scan_u32(rec), ic = wave_incl_scan_u32(chk);
+  if (lane_id() == kWave - 1) {
+    w_rec[wave] = ir;
+    w_chk[wave] = ic;
   }
-  uint32_t run_r = s_rec[t] - rec, run_c = s_chk[t] - chk;
+  __syncthreads();
+  uint32_t run_r = ir - rec, run_c = ic - chk, all_r = 0, all_c = 0;
+  for (int w = 0; w < 1024 / kWave; ++w) {
+    run_r += w < wave ? w_rec[w] : 0u;
+    run_c += w < wave ? w_chk[w] : 0u;
+    all_r += w_rec[w];
+    all_c += w_chk[w];
+  }
   for (int b = b0; b < b1; ++b) {
     const uint32_t n = rb.bin_total[b];
     rb.bin_start[b] = run_r;
@@ -224,8 +252,8 @@ __global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int n
     run_c += nc;
   }
   if (t == 1023) {
-    rb.bin_start[nbins] = s_rec[1023];
-    rb.chunk_start[nbins] = s_chk[1023];
+    rb.bin_start[nbins] = all_r;
+    rb.chunk_start[nbins] = all_c;
   }
 }
 
@@ -437,8 +465,8 @@ hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSr
   float* zero_table = overwrite ? grad_table : nullptr;
   const size_t bins_lds = (size_t)p.nbins * sizeof(uint32_t);
   hipLaunchKernelGGL(bin_count_kernel, dim3(p.nblk), dim3(kRecThreads), bins_lds, st, src, lv, rb, p.nbins);
-  hipLaunchKernelGGL(bin_colscan_kernel, dim3((p.nbins + 15) / 16), dim3(16 * kScanGroups), 0, st, rb, p.nbins,
-                     p.nblk);
+  hipLaunchKernelGGL(bin_colscan_kernel, dim3(colscan_grid(p.nbins)), dim3(kColBins * kColGroups), 0, st, rb,
+                     p.nbins, p.nblk);
   hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins);
   if (bf16_values) {
     hipLaunchKernelGGL((bin_place_kernel<RecBF16, 2>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb,
