@@ -127,28 +127,28 @@ __global__ void prep_weights_kernel(const float* __restrict__ params, WOffsets w
 // Forward: sigma and colour per sample
 // ---------------------------------------------------------------------------
 
+// Inputs of one sample for the MLP from the kept encoding: this lane's
+// encoding slots and the ray direction (ray index ridx, fetched earlier).
 template <class N>
-__global__ __launch_bounds__(256) void field_fwd_kernel(FieldArgs a, SampleSrc src,
-                                                        float* __restrict__ sigma_out,
-                                                        float* __restrict__ rgb_out) {
-  __shared__ __attribute__((aligned(16))) float Af[N::FWD_FLOATS];
-  load_operands<N>(Af, a.wprep, N::FWD_FLOATS);
-  __syncthreads();
-  const int S = src.n_dev ? (int)*src.n_dev : src.n;
-  const int lane = lane_id(), g = lane >> 4, jc = lane & 15;
-  const int tile = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-  const int s = tile * 16 + jc;
-  if (tile * 16 >= S) return;
-  const bool valid = s < S;
-  LaneLevels<N> ll;
-  lane_levels<N>(a.lv, g, ll);
-  Acts<N> act;
-  float xn[3] = {0.5f, 0.5f, 0.5f}, d[3] = {0.0f, 0.0f, 1.0f};
-  if (valid) load_sample(src, s, xn, d);
-  if (src.ecache)
-    read_encoding<N>(static_cast<const float2*>(src.ecache), src.ecache_stride, g, s, valid, act.e);
-  else
-    encode<N>(a.table, a.lv.table_mask, ll, xn, act.e);
+__device__ __forceinline__ void fetch_kept(const SampleSrc& src, int g, int s, bool valid, uint32_t ridx,
+                                           float e[N::NSLOT], float d[3]) {
+  read_encoding<N>(static_cast<const float2*>(src.ecache), src.ecache_stride, g, s, valid, e);
+  d[0] = 0.0f; d[1] = 0.0f; d[2] = 1.0f;
+  if (valid) {
+    if (src.t) {
+      const float4 dd = src.rays[2 * ridx + 1];
+      d[0] = dd.x; d[1] = dd.y; d[2] = dd.z;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) d[i] = src.dir[3 * s + i];
+    }
+  }
+}
+
+template <class N>
+__device__ __forceinline__ void fwd_tile_out(const float* Af, int lane, int g, int s, bool valid, Acts<N>& act,
+                                             const float d[3], float* __restrict__ sigma_out,
+                                             float* __restrict__ rgb_out) {
   sh_lane<N>(d, g, act.sh);
   mlp_fwd<N>(Af, lane, act);
   if (g == 0 && valid) {
@@ -156,6 +156,64 @@ __global__ __launch_bounds__(256) void field_fwd_kernel(FieldArgs a, SampleSrc s
     rgb_out[3 * s + 0] = sigmoidf(act.z[0]);
     rgb_out[3 * s + 1] = sigmoidf(act.z[1]);
     rgb_out[3 * s + 2] = sigmoidf(act.z[2]);
+  }
+}
+
+// Forward of 16-sample tiles, one per wave at a time, on a fixed grid (the
+// weight operands are staged into LDS once per workgroup); with the kept
+// encoding a wave fetches its next tile's inputs while it computes the
+// current one (ray indices two tiles ahead).
+constexpr int kFieldFwdGrid = 768;
+constexpr bool kFieldFwdPrefetch = true;
+
+template <class N>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void field_fwd_kernel(FieldArgs a, SampleSrc src,
+                                                        float* __restrict__ sigma_out,
+                                                        float* __restrict__ rgb_out) {
+  __shared__ __attribute__((aligned(16))) float Af[N::FWD_FLOATS];
+  load_operands<N>(Af, a.wprep, N::FWD_FLOATS);
+  __syncthreads();
+  const int S = src.n_dev ? (int)*src.n_dev : src.n;
+  const int ntiles = (S + 15) / 16;
+  const int lane = lane_id(), g = lane >> 4, jc = lane & 15;
+  const int first = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
+  const int step = gridDim.x * (blockDim.x / kWave);
+  if (first >= ntiles) return;
+  if (kFieldFwdPrefetch && src.ecache) {
+    auto rid = [&](int s) -> uint32_t { return src.t && s < S ? src.ray[s] : 0u; };
+    float e[N::NSLOT], d[3];
+    const int s0 = 16 * first + jc;
+    fetch_kept<N>(src, g, s0, s0 < S, rid(s0), e, d);
+    uint32_t rid1 = rid(s0 + 16 * step);
+    for (int tile = first; tile < ntiles; tile += step) {
+      const int s = 16 * tile + jc, s1 = s + 16 * step;
+      float en[N::NSLOT], dn[3];
+      fetch_kept<N>(src, g, s1, s1 < S, rid1, en, dn);
+      rid1 = rid(s1 + 16 * step);
+      Acts<N> act;
+#pragma unroll
+      for (int k = 0; k < N::NSLOT; ++k) act.e[k] = e[k];
+      fwd_tile_out<N>(Af, lane, g, s, s < S, act, d, sigma_out, rgb_out);
+#pragma unroll
+      for (int k = 0; k < N::NSLOT; ++k) e[k] = en[k];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) d[i] = dn[i];
+    }
+  } else {
+    LaneLevels<N> ll;
+    lane_levels<N>(a.lv, g, ll);
+    for (int tile = first; tile < ntiles; tile += step) {
+      const int s = 16 * tile + jc;
+      const bool valid = s < S;
+      Acts<N> act;
+      float xn[3] = {0.5f, 0.5f, 0.5f}, d[3] = {0.0f, 0.0f, 1.0f};
+      if (valid) load_sample(src, s, xn, d);
+      if (src.ecache)
+        read_encoding<N>(static_cast<const float2*>(src.ecache), src.ecache_stride, g, s, valid, act.e);
+      else
+        encode<N>(a.table, a.lv.table_mask, ll, xn, act.e);
+      fwd_tile_out<N>(Af, lane, g, s, valid, act, d, sigma_out, rgb_out);
+    }
   }
 }
 
@@ -492,7 +550,8 @@ static hipError_t launch_fwd(const FieldArgs& a, const SampleSrc& src, int max_s
                              float* sigma, float* rgb, hipStream_t st) {
   const int tiles = (max_samples + 15) / 16;
   if (tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(field_fwd_kernel<N>, dim3((tiles + 3) / 4), dim3(256), 0, st, a, src, sigma, rgb);
+  const int grid = (tiles + 3) / 4 < kFieldFwdGrid ? (tiles + 3) / 4 : kFieldFwdGrid;
+  hipLaunchKernelGGL(field_fwd_kernel<N>, dim3(grid), dim3(256), 0, st, a, src, sigma, rgb);
   return hipGetLastError();
 }
 
