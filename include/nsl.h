@@ -267,13 +267,16 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
  * its stream before each phase and after the last one, waits for the last
  * event (so profiled steps synchronise the host), and accumulates the
  * elapsed milliseconds per phase:
- *   0 gradient clearing and weight-operand preparation, 1 rays + march +
+ *   0 gradient clearing (the MLP weights and padding; the table part is
+ *   overwritten by the reduction of phase 6) and weight-operand preparation,
+ *   1 rays + march +
  *   batch cut, 2 encoding of every sample (keep_encoding = 1 only),
  *   3 field forward (MLP; with keep_encoding = 0 also the table gather),
  *   4 compositing + loss + its adjoint, 5 field backward kernel (MLP
  *   recompute and adjoint, weight gradients per workgroup, dL/de),
  *   6 table gradient (bin count, scans, placement, reduction), 7 weight-
- *   gradient reduction, 8 Adam (and the loss-scale update).
+ *   gradient reduction and the sum of the loss, 8 Adam (and the loss-scale
+ *   update).
  * nsl_profile_read copies the sums (ms[NSL_PHASES]) and the number of
  * profiled steps; enabling again resets them. */
 #define NSL_PHASES 9
