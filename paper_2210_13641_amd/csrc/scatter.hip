@@ -469,7 +469,7 @@ hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSr
                      p.nbins, p.nblk);
   hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins);
   if (bf16_values) {
-    hipLaunchKernelGGL((bin_place_kernel<RecBF16, 2>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb,
+    hipLaunchKernelGGL((bin_place_kernel<RecBF16, 1>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb,
                        p.nbins, zero_table, p.entries);
     hipLaunchKernelGGL(bin_reduce_kernel<RecBF16>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins,
                        p.entries, grad_table, overflow, overwrite);

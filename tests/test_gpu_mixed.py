@@ -61,7 +61,7 @@ def _mixed_step(nsl, torch, dev, spec, sampler, kf, ids, flat, state, adam=False
                           lr=W.ADAM_LR, betas=W.ADAM_BETAS, eps=W.ADAM_EPS, adam_step=1)
     ws = torch.empty(nsl.step_workspace_bytes(f, cfg, len(ids)), dtype=torch.uint8, device=dev)
     P = _t(torch, dev, flat)
-    G = torch.zeros_like(P)
+    G = torch.full_like(P, 7.0)                                       # zero_grads must clear this
     M, V = torch.zeros_like(P), torch.zeros_like(P)
     loss = torch.zeros(3, device=dev)
     rays = torch.zeros(len(ids), 6, device=dev)

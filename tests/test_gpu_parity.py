@@ -247,10 +247,10 @@ def test_march_uniform_and_bad_ids(nsl, torch_dev):
 # ----------------------------------------------------------------------------
 
 def _step_gpu(nsl, torch, dev, spec, sampler, kf, ids, flat, occ=None, grid_res=1, adam=None, lam=1.0,
-              keep_encoding=False, mixed=False):
+              keep_encoding=False, mixed=False, zero_grads=True):
     f = nsl.Field(spec)
     m = upload_keyframes(nsl, torch, kf, dev, grid_res=grid_res, occ=occ)
-    kw = dict(lambda_d=lam, zero_grads=True, keep_encoding=keep_encoding)
+    kw = dict(lambda_d=lam, zero_grads=zero_grads, keep_encoding=keep_encoding)
     if adam:
         kw.update(do_adam=True, lr=adam["lr"], betas=adam["betas"], eps=adam["eps"], adam_step=adam["step"])
     if mixed:
@@ -260,7 +260,7 @@ def _step_gpu(nsl, torch, dev, spec, sampler, kf, ids, flat, occ=None, grid_res=
     n = len(ids)
     ws = torch.empty(nsl.step_workspace_bytes(f, cfg, n), dtype=torch.uint8, device=dev)
     P = _t(torch, dev, flat)
-    G = torch.full((f.layout["total"],), 7.0, device=dev)          # zero_grads must clear this
+    G = torch.full((f.layout["total"],), 7.0 if zero_grads else 0.0, device=dev)  # zero_grads must clear this
     M = torch.zeros_like(P) if adam else None
     V = torch.zeros_like(P) if adam else None
     loss = torch.zeros(3, device=dev)
@@ -343,6 +343,31 @@ def test_step_paper_scale(nsl, torch_dev):
     o = ostep.train_step(spec, sampler, kf, t64, w64, ids, occupancy=occ)
     report(f"  R={o['R']} S={o['S']} ambiguous ReLU units={o['n_amb']}")
     _compare_step(spec, g, o, f.layout)
+
+
+@pytest.mark.parametrize("mixed", [False, True], ids=["fp32", "mixed"])
+def test_step_overwrite_matches_accumulate(nsl, torch_dev, mixed):
+    """A step that clears its gradients has the table-gradient reduction
+    overwrite them (bins of one chunk store every entry, the others are
+    cleared during placement); at paper scale, with bins of one chunk, of
+    several and of none, it gives what accumulating onto a zero gradient
+    gives, every entry included, up to the summation order of the
+    multi-chunk bins."""
+    torch, dev = torch_dev
+    scene, occ, kf = c2_inputs()
+    report(f"step: overwrite vs accumulate onto zeros, paper scale, {'mixed' if mixed else 'fp32'}")
+    spec, sampler = W.C2_FIELD, W.C2_SAMPLER
+    ids = W.c2_candidates(4096)
+    f = nsl.Field(spec)
+    flat, _, _ = params_for(spec, f.layout, seed=0, table_range=0.3)
+    a, b = [_step_gpu(nsl, torch, dev, spec, sampler, kf, ids, flat, occ=occ, grid_res=128, keep_encoding=True,
+                      mixed=mixed, zero_grads=z) for z in (True, False)]
+    nt = f.layout["table_floats"]
+    assert np.array_equal(a["grads"][nt:], b["grads"][nt:])
+    ga, gb = a["grads"][:nt].astype(np.float64), b["grads"][:nt].astype(np.float64)
+    assert np.array_equal(ga == 0, gb == 0)                       # the same entries untouched
+    assert np.count_nonzero(ga) > 0.1 * nt
+    assert np.allclose(ga, gb, rtol=1e-5, atol=1e-6 * np.abs(ga).max())
 
 
 @pytest.mark.parametrize("mixed", [False, True], ids=["fp32", "mixed"])
