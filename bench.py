@@ -81,7 +81,7 @@ def roofline_of(name, work, samples, ms, mlp_peak):
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_paper_scale.md")
 PMC_SOURCES = ("field.hip", "field_mixed.hip", "field_common.h", "net.h", "common.h", "scatter.hip", "kernels.h")
 BIN_KERNELS = ["nsl::bin_count_kernel", "nsl::bin_colscan_kernel", "nsl::bin_start_kernel",
-               "nsl::bin_place_kernel<nsl::RecBF16, 2>", "nsl::bin_reduce_kernel<nsl::RecBF16>"]
+               "nsl::bin_place_kernel<nsl::RecBF16, 1, 2>", "nsl::bin_reduce_kernel<nsl::RecBF16>"]
 PMC_ROWS = {("table_grad", 2): BIN_KERNELS,
             ("field_bwd", 2): ["mixed_bwd_kernel<NetFull>"], ("field_bwd", 4): ["nsl::field_bwd_kernel<NetFull >"],
             ("field_fwd", 2): ["mixed_fwd_kernel<NetFull>"], ("field_fwd", 4): ["nsl::field_fwd_kernel<NetFull >"],

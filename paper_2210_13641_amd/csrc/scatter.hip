@@ -37,6 +37,7 @@ constexpr int kRecWaves = kRecThreads / kWave;
 constexpr int kRecTilesPerWave = 1;
 constexpr int kRecSamples = kRecWaves * kRecTilesPerWave * 16;      // samples per block
 constexpr int kPlaceChunk = kRecWaves * kRecTilesPerWave * 64 * 8;  // records of one level group
+constexpr int kMaxPer = (kMaxBins + kRecThreads - 1) / kRecThreads;  // bins per thread in the placement scan
 constexpr int kReduceThreads = 1024;
 constexpr int kReducePer = 8;                        // records in flight per thread
 
@@ -265,15 +266,18 @@ __global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int n
 // zero_table (overwriting reductions only, else null): the gradient entries of
 // the bins that the reduction will not overwrite (bins with no records, or
 // with several chunks, which add with atomics) are cleared here first.
-template <class R, int G>
+template <class R, int G, int PER>
 __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, LevelInfo lv, RecordBuffers rb,
                                                                int nbins, float* __restrict__ zero_table,
                                                                uint32_t entries) {
   static_assert(kRecTilesPerWave == 1, "one tile per wave");
   typedef typename R::T Rec;
   Rec* __restrict__ sorted = reinterpret_cast<Rec*>(rb.sorted);
-  extern __shared__ uint32_t bins_lds[];  // gcur, cnt, lst: [nbins] each
-  uint32_t* gcur = bins_lds;
+  // base: slot of the round's record i of bin b is base[b] + i; cnt: the
+  // round's count per bin; lst: its exclusive prefix.  Thread t owns bins
+  // [b0, b1) (at most PER) and keeps their global cursors in registers.
+  extern __shared__ uint32_t bins_lds[];
+  uint32_t* base = bins_lds;
   uint32_t* cnt = bins_lds + nbins;
   uint32_t* lst = bins_lds + 2 * nbins;
   __shared__ uint32_t wsum[kRecWaves];
@@ -281,10 +285,12 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
   const int t = threadIdx.x;
   const int blk = logical_block(gridDim.x);
   const uint32_t* off = rb.off + (size_t)blk * nbins;
-  for (int b = t; b < nbins; b += kRecThreads) {
-    gcur[b] = rb.bin_start[b] + off[b];
-    cnt[b] = 0u;
-  }
+  for (int b = t; b < nbins; b += kRecThreads) cnt[b] = 0u;
+  const int per = (nbins + kRecThreads - 1) / kRecThreads;  // at most PER
+  const int b0 = min(nbins, t * per), b1 = min(nbins, b0 + per);
+  uint32_t cur[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) cur[k] = b0 + k < b1 ? rb.bin_start[b0 + k] + off[b0 + k] : 0u;
   if (zero_table) {
     // two entries (one float4) per thread and step; the table is 16-byte
     // aligned, an odd last entry is cleared on its own
@@ -300,8 +306,6 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
   }
   const int S = sample_count(src);
   const int wave = t / kWave, lane = lane_id(), g = lane >> 4, jc = lane & 15;
-  const int per = (nbins + kRecThreads - 1) / kRecThreads;
-  const int b0 = min(nbins, t * per), b1 = min(nbins, b0 + per);
   const int s = (blk * kRecWaves + wave) * 16 + jc;
   const bool valid = s < S;
   float xn[3] = {0.5f, 0.5f, 0.5f};
@@ -335,10 +339,16 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
         if (R::key(rec[h][k]) != 0xFFFFFFFFu) rank[h][k] = atomicAdd(&cnt[R::key(rec[h][k]) >> kBinShift], 1u);
     }
     __syncthreads();
-    // lst = exclusive prefix of cnt: per-thread runs of bins, a wave scan of
-    // the thread totals, then the totals of the waves before
-    uint32_t mine = 0;
-    for (int b = b0; b < b1; ++b) mine += cnt[b];
+    // lst = exclusive prefix of cnt (per-thread runs of bins, a wave scan of
+    // the thread totals, then the totals of the waves before); the owners
+    // of the bins also set base, advance their cursors and clear the counts
+    // for the next round
+    uint32_t c[PER], mine = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      c[k] = b0 + k < b1 ? cnt[b0 + k] : 0u;
+      mine += c[k];
+    }
     const uint32_t incl = wave_incl_scan_u32(mine);
     if (lane == kWave - 1) wsum[wave] = incl;
     __syncthreads();
@@ -347,9 +357,15 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
       run += w < wave ? wsum[w] : 0u;
       m += wsum[w];
     }
-    for (int b = b0; b < b1; ++b) {
-      lst[b] = run;
-      run += cnt[b];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      if (b0 + k < b1) {
+        lst[b0 + k] = run;
+        base[b0 + k] = cur[k] - run;
+        cnt[b0 + k] = 0u;
+        cur[k] += c[k];
+      }
+      run += c[k];
     }
     __syncthreads();
 #pragma unroll
@@ -360,14 +376,7 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
     __syncthreads();
     for (uint32_t i = t; i < m; i += kRecThreads) {
       const Rec r = stage[i];
-      const uint32_t b = R::key(r) >> kBinShift;
-      sorted[gcur[b] + (i - lst[b])] = r;
-    }
-    __syncthreads();
-    // advance the bin cursors; clear the counts for the next round
-    for (int b = t; b < nbins; b += kRecThreads) {
-      gcur[b] += cnt[b];
-      cnt[b] = 0u;
+      sorted[base[R::key(r) >> kBinShift] + i] = r;
     }
     __syncthreads();
   }
@@ -469,13 +478,21 @@ hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSr
                      p.nbins, p.nblk);
   hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins);
   if (bf16_values) {
-    hipLaunchKernelGGL((bin_place_kernel<RecBF16, 1>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb,
-                       p.nbins, zero_table, p.entries);
+    if (p.nbins <= 2 * kRecThreads)
+      hipLaunchKernelGGL((bin_place_kernel<RecBF16, 1, 2>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv,
+                         rb, p.nbins, zero_table, p.entries);
+    else
+      hipLaunchKernelGGL((bin_place_kernel<RecBF16, 1, kMaxPer>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src,
+                         lv, rb, p.nbins, zero_table, p.entries);
     hipLaunchKernelGGL(bin_reduce_kernel<RecBF16>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins,
                        p.entries, grad_table, overflow, overwrite);
   } else {
-    hipLaunchKernelGGL((bin_place_kernel<RecF32, 1>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv, rb,
-                       p.nbins, zero_table, p.entries);
+    if (p.nbins <= 2 * kRecThreads)
+      hipLaunchKernelGGL((bin_place_kernel<RecF32, 1, 2>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv,
+                         rb, p.nbins, zero_table, p.entries);
+    else
+      hipLaunchKernelGGL((bin_place_kernel<RecF32, 1, kMaxPer>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src,
+                         lv, rb, p.nbins, zero_table, p.entries);
     hipLaunchKernelGGL(bin_reduce_kernel<RecF32>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins,
                        p.entries, grad_table, overflow, overwrite);
   }
