@@ -72,6 +72,7 @@ RecordBuffers carve_records(Carver& cv, const BinPlan& p) {
   r.chunk_start = cv.take<uint32_t>((size_t)p.nbins + 1);
   r.chunk_bin = cv.take<uint32_t>((size_t)p.max_chunks);
   r.sorted = cv.take<uint3>((size_t)p.max_records);  // room for either record format
+  r.sorted_vals = reinterpret_cast<uint32_t*>(static_cast<char*>(r.sorted) + align256((size_t)p.max_records * 2));
   return r;
 }
 

@@ -57,7 +57,9 @@ struct RecordBuffers {
   uint32_t* chunk_start;  // [nbins + 1]
   uint32_t* chunk_bin;    // [max_chunks] bin of each chunk
   void* sorted;           // [max_records] records grouped by bin: (entry, g0, g1) as uint3, or
-                          // (entry, g0 | g1 << 16 in BF16) as uint2
+                          // for BF16 values the entry's offset in its bin as uint16_t ...
+  uint32_t* sorted_vals;  // ... and (g0 | g1 << 16) in BF16 here, [max_records] (inside the
+                          // space of sorted)
 };
 
 struct BinPlan {

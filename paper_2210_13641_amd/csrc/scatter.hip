@@ -41,13 +41,22 @@ constexpr int kMaxPer = (kMaxBins + kRecThreads - 1) / kRecThreads;  // bins per
 constexpr int kReduceThreads = 1024;
 constexpr int kReducePer = 8;                        // records in flight per thread
 
-// Record formats in the sorted array: FP32 values (entry, g0, g1), or, for
-// mixed precision, BF16 values (entry, g0 | g1 << 16).  Either way the
-// reduction accumulates in FP32.
+// Record formats: FP32 values (entry, g0, g1), or, for mixed precision,
+// BF16 values (entry, g0 | g1 << 16); in the sorted array the latter keep
+// only the entry's 16-bit offset in its bin (6 bytes a record).  Either way
+// the reduction accumulates in FP32.
 struct RecF32 {
   typedef uint3 T;
+  static constexpr bool kSplit = false;  // one 12-byte record per slot
   static __device__ __forceinline__ T pack(uint32_t e, float a, float b) {
     return make_uint3(e, __float_as_uint(a), __float_as_uint(b));
+  }
+  // slot pos of the sorted array (e0: first entry of the slot's bin)
+  static __device__ __forceinline__ void store(const RecordBuffers& rb, uint32_t pos, const T& r) {
+    reinterpret_cast<uint3*>(rb.sorted)[pos] = r;
+  }
+  static __device__ __forceinline__ T load(const RecordBuffers& rb, uint32_t pos, uint32_t) {
+    return reinterpret_cast<const uint3*>(rb.sorted)[pos];
   }
   static __device__ __forceinline__ uint32_t key(const T& r) { return r.x; }
   static __device__ __forceinline__ float2 val(const T& r) {
@@ -57,9 +66,20 @@ struct RecF32 {
 };
 struct RecBF16 {
   typedef uint2 T;
+  static constexpr bool kSplit = true;   // offsets and values in separate arrays
   static __device__ __forceinline__ T pack(uint32_t e, float a, float b) {
     const __bf16 x = (__bf16)a, y = (__bf16)b;
     return make_uint2(e, (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16));
+  }
+  // In the sorted array a record takes 6 bytes: the entry's offset in its
+  // bin (the bin is implied by the slot) and the two BF16 values.
+  static __device__ __forceinline__ void store(const RecordBuffers& rb, uint32_t pos, const T& r) {
+    static_assert(kBinShift <= 16, "in-bin offsets are 16-bit");
+    static_cast<uint16_t*>(rb.sorted)[pos] = (uint16_t)(r.x & (uint32_t)(kBinEntries - 1));
+    rb.sorted_vals[pos] = r.y;
+  }
+  static __device__ __forceinline__ T load(const RecordBuffers& rb, uint32_t pos, uint32_t e0) {
+    return make_uint2(e0 + static_cast<const uint16_t*>(rb.sorted)[pos], rb.sorted_vals[pos]);
   }
   static __device__ __forceinline__ uint32_t key(const T& r) { return r.x; }
   static __device__ __forceinline__ float2 val(const T& r) {
@@ -272,7 +292,6 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
                                                                uint32_t entries) {
   static_assert(kRecTilesPerWave == 1, "one tile per wave");
   typedef typename R::T Rec;
-  Rec* __restrict__ sorted = reinterpret_cast<Rec*>(rb.sorted);
   // base: slot of the round's record i of bin b is base[b] + i; cnt: the
   // round's count per bin; lst: its exclusive prefix.  Thread t owns bins
   // [b0, b1) (at most PER) and keeps their global cursors in registers.
@@ -376,7 +395,7 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
     __syncthreads();
     for (uint32_t i = t; i < m; i += kRecThreads) {
       const Rec r = stage[i];
-      sorted[base[R::key(r) >> kBinShift] + i] = r;
+      R::store(rb, base[R::key(r) >> kBinShift] + i, r);
     }
     __syncthreads();
   }
@@ -389,7 +408,6 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
                                                                     float* __restrict__ grad_table,
                                                                     float* __restrict__ overflow, bool overwrite) {
   typedef typename R::T Rec;
-  const Rec* __restrict__ sorted = reinterpret_cast<const Rec*>(rb.sorted);
   // (g0, g1) of each entry as one 64-bit word: float pairs are added with
   // LDS 64-bit compare-and-swap, which retires far faster than LDS float
   // atomics on this architecture
@@ -403,24 +421,58 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
   for (int i = threadIdx.x; i < kBinEntries; i += kReduceThreads) acc[i] = 0ull;
   __syncthreads();
   const uint32_t e0 = (uint32_t)b << kBinShift;
-  for (uint32_t base = first; base < last; base += kReduceThreads * kReducePer) {
-    Rec rec[kReducePer];
-#pragma unroll
-    for (int j = 0; j < kReducePer; ++j) {
-      const uint32_t i = base + j * kReduceThreads + threadIdx.x;
-      rec[j] = i < last ? sorted[i] : R::none();
+  // adds (a, cc) to entry e of the bin
+  auto add = [&](uint32_t e, float a, float cc) {
+    unsigned long long seen = acc[e];
+    for (;;) {
+      const unsigned long long got = atomicCAS(&acc[e], seen, add_pair_bits(seen, a, cc));
+      if (got == seen) break;
+      seen = got;
     }
+  };
+  if constexpr (R::kSplit) {
+    // 6-byte records: a lane reads four consecutive ones at a time, their
+    // offsets as one 8-byte load and their values as one 16-byte load
+    // (groups of four slots are aligned; slots outside [first, last) are
+    // skipped)
+    const uint32_t g0 = first / 4, g1 = (last + 3) / 4;
+    const uint2* __restrict__ keys = static_cast<const uint2*>(rb.sorted);
+    const uint4* __restrict__ vals = reinterpret_cast<const uint4*>(rb.sorted_vals);
+    for (uint32_t gb = g0; gb < g1; gb += kReduceThreads * 2) {
+      uint2 kk[2];
+      uint4 vv[2];
 #pragma unroll
-    for (int j = 0; j < kReducePer; ++j) {
-      if (R::key(rec[j]) == 0xFFFFFFFFu) continue;
-      const uint32_t e = R::key(rec[j]) - e0;
-      const float2 v = R::val(rec[j]);
-      const float a = v.x, cc = v.y;
-      unsigned long long seen = acc[e];
-      for (;;) {
-        const unsigned long long got = atomicCAS(&acc[e], seen, add_pair_bits(seen, a, cc));
-        if (got == seen) break;
-        seen = got;
+      for (int j = 0; j < 2; ++j) {
+        const uint32_t gi = gb + j * kReduceThreads + threadIdx.x;
+        kk[j] = gi < g1 ? keys[gi] : make_uint2(0u, 0u);
+        vv[j] = gi < g1 ? vals[gi] : make_uint4(0u, 0u, 0u, 0u);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const uint32_t p0 = 4 * (gb + j * kReduceThreads + threadIdx.x);
+        const uint32_t k4[4] = {kk[j].x & 0xFFFFu, kk[j].x >> 16, kk[j].y & 0xFFFFu, kk[j].y >> 16};
+        const uint32_t v4[4] = {vv[j].x, vv[j].y, vv[j].z, vv[j].w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (p0 + u < first || p0 + u >= last) continue;
+          const float2 v = R::val(make_uint2(0u, v4[u]));
+          add(k4[u], v.x, v.y);
+        }
+      }
+    }
+  } else {
+    for (uint32_t base = first; base < last; base += kReduceThreads * kReducePer) {
+      Rec rec[kReducePer];
+#pragma unroll
+      for (int j = 0; j < kReducePer; ++j) {
+        const uint32_t i = base + j * kReduceThreads + threadIdx.x;
+        rec[j] = i < last ? R::load(rb, i, e0) : R::none();
+      }
+#pragma unroll
+      for (int j = 0; j < kReducePer; ++j) {
+        if (R::key(rec[j]) == 0xFFFFFFFFu) continue;
+        const float2 v = R::val(rec[j]);
+        add(R::key(rec[j]) - e0, v.x, v.y);
       }
     }
   }
