@@ -71,8 +71,10 @@ RecordBuffers carve_records(Carver& cv, const BinPlan& p) {
   r.bin_start = cv.take<uint32_t>((size_t)p.nbins + 1);
   r.chunk_start = cv.take<uint32_t>((size_t)p.nbins + 1);
   r.chunk_bin = cv.take<uint32_t>((size_t)p.max_chunks);
-  r.sorted = cv.take<uint3>((size_t)p.max_records);  // room for either record format
-  r.sorted_vals = reinterpret_cast<uint32_t*>(static_cast<char*>(r.sorted) + align256((size_t)p.max_records * 2));
+  // in-bin offsets (2 bytes a record), then values (8 bytes: room for FP32 or BF16 pairs)
+  const size_t key_bytes = align256((size_t)p.max_records * 2);
+  r.sorted = cv.take<char>(key_bytes + (size_t)p.max_records * 8);
+  r.sorted_vals = reinterpret_cast<uint32_t*>(static_cast<char*>(r.sorted) + key_bytes);
   return r;
 }
 

@@ -56,10 +56,11 @@ struct RecordBuffers {
   uint32_t* bin_start;    // [nbins + 1]
   uint32_t* chunk_start;  // [nbins + 1]
   uint32_t* chunk_bin;    // [max_chunks] bin of each chunk
-  void* sorted;           // [max_records] records grouped by bin: (entry, g0, g1) as uint3, or
-                          // for BF16 values the entry's offset in its bin as uint16_t ...
-  uint32_t* sorted_vals;  // ... and (g0 | g1 << 16) in BF16 here, [max_records] (inside the
-                          // space of sorted)
+  void* sorted;           // [max_records] records grouped by bin: each entry's offset in its
+                          // bin as uint16_t (the bin is implied by the slot) ...
+  uint32_t* sorted_vals;  // ... and its values here: (g0, g1) in FP32 as uint2, or
+                          // g0 | g1 << 16 in BF16 as uint32_t ([max_records], inside the
+                          // space reserved for sorted)
 };
 
 struct BinPlan {

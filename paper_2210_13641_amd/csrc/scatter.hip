@@ -39,24 +39,31 @@ constexpr int kRecSamples = kRecWaves * kRecTilesPerWave * 16;      // samples p
 constexpr int kPlaceChunk = kRecWaves * kRecTilesPerWave * 64 * 8;  // records of one level group
 constexpr int kMaxPer = (kMaxBins + kRecThreads - 1) / kRecThreads;  // bins per thread in the placement scan
 constexpr int kReduceThreads = 1024;
-constexpr int kReducePer = 8;                        // records in flight per thread
 
 // Record formats: FP32 values (entry, g0, g1), or, for mixed precision,
-// BF16 values (entry, g0 | g1 << 16); in the sorted array the latter keep
-// only the entry's 16-bit offset in its bin (6 bytes a record).  Either way
-// the reduction accumulates in FP32.
+// BF16 values (entry, g0 | g1 << 16).  In the sorted array a record keeps
+// only the entry's 16-bit offset in its bin (10 or 6 bytes a record).  Either
+// way the reduction accumulates in FP32.
 struct RecF32 {
   typedef uint3 T;
-  static constexpr bool kSplit = false;  // one 12-byte record per slot
   static __device__ __forceinline__ T pack(uint32_t e, float a, float b) {
     return make_uint3(e, __float_as_uint(a), __float_as_uint(b));
   }
-  // slot pos of the sorted array (e0: first entry of the slot's bin)
+  // In the sorted array a record takes 10 bytes: the entry's 16-bit offset
+  // in its bin (the bin is implied by the slot) and the two FP32 values.
   static __device__ __forceinline__ void store(const RecordBuffers& rb, uint32_t pos, const T& r) {
-    reinterpret_cast<uint3*>(rb.sorted)[pos] = r;
+    static_assert(kBinShift <= 16, "in-bin offsets are 16-bit");
+    static_cast<uint16_t*>(rb.sorted)[pos] = (uint16_t)(r.x & (uint32_t)(kBinEntries - 1));
+    reinterpret_cast<uint2*>(rb.sorted_vals)[pos] = make_uint2(r.y, r.z);
   }
-  static __device__ __forceinline__ T load(const RecordBuffers& rb, uint32_t pos, uint32_t) {
-    return reinterpret_cast<const uint3*>(rb.sorted)[pos];
+  // the values of the four slots 4 gi .. 4 gi + 3
+  static __device__ __forceinline__ void vals4(const RecordBuffers& rb, uint32_t gi, float2 (&v)[4]) {
+    const uint4* p = reinterpret_cast<const uint4*>(rb.sorted_vals) + 2 * (size_t)gi;
+    const uint4 a = p[0], b = p[1];
+    v[0] = make_float2(__uint_as_float(a.x), __uint_as_float(a.y));
+    v[1] = make_float2(__uint_as_float(a.z), __uint_as_float(a.w));
+    v[2] = make_float2(__uint_as_float(b.x), __uint_as_float(b.y));
+    v[3] = make_float2(__uint_as_float(b.z), __uint_as_float(b.w));
   }
   static __device__ __forceinline__ uint32_t key(const T& r) { return r.x; }
   static __device__ __forceinline__ float2 val(const T& r) {
@@ -66,7 +73,6 @@ struct RecF32 {
 };
 struct RecBF16 {
   typedef uint2 T;
-  static constexpr bool kSplit = true;   // offsets and values in separate arrays
   static __device__ __forceinline__ T pack(uint32_t e, float a, float b) {
     const __bf16 x = (__bf16)a, y = (__bf16)b;
     return make_uint2(e, (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16));
@@ -78,15 +84,20 @@ struct RecBF16 {
     static_cast<uint16_t*>(rb.sorted)[pos] = (uint16_t)(r.x & (uint32_t)(kBinEntries - 1));
     rb.sorted_vals[pos] = r.y;
   }
-  static __device__ __forceinline__ T load(const RecordBuffers& rb, uint32_t pos, uint32_t e0) {
-    return make_uint2(e0 + static_cast<const uint16_t*>(rb.sorted)[pos], rb.sorted_vals[pos]);
-  }
   static __device__ __forceinline__ uint32_t key(const T& r) { return r.x; }
   static __device__ __forceinline__ float2 val(const T& r) {
     return make_float2((float)__builtin_bit_cast(__bf16, (uint16_t)(r.y & 0xFFFFu)),
                        (float)__builtin_bit_cast(__bf16, (uint16_t)(r.y >> 16)));
   }
   static __device__ __forceinline__ T none() { return make_uint2(0xFFFFFFFFu, 0u); }
+  // the values of the four slots 4 gi .. 4 gi + 3
+  static __device__ __forceinline__ void vals4(const RecordBuffers& rb, uint32_t gi, float2 (&v)[4]) {
+    const uint4 w = reinterpret_cast<const uint4*>(rb.sorted_vals)[gi];
+    v[0] = val(make_uint2(0u, w.x));
+    v[1] = val(make_uint2(0u, w.y));
+    v[2] = val(make_uint2(0u, w.z));
+    v[3] = val(make_uint2(0u, w.w));
+  }
 };
 
 // The records of one level (l = g + 4q for lane group g) of one tile: the
@@ -430,49 +441,30 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
       seen = got;
     }
   };
-  if constexpr (R::kSplit) {
-    // 6-byte records: a lane reads four consecutive ones at a time, their
-    // offsets as one 8-byte load and their values as one 16-byte load
-    // (groups of four slots are aligned; slots outside [first, last) are
-    // skipped)
-    const uint32_t g0 = first / 4, g1 = (last + 3) / 4;
-    const uint2* __restrict__ keys = static_cast<const uint2*>(rb.sorted);
-    const uint4* __restrict__ vals = reinterpret_cast<const uint4*>(rb.sorted_vals);
-    for (uint32_t gb = g0; gb < g1; gb += kReduceThreads * 2) {
-      uint2 kk[2];
-      uint4 vv[2];
+  // A lane reads four consecutive records at a time: their in-bin offsets
+  // with one 8-byte load and their values with one (BF16) or two (FP32)
+  // 16-byte loads.  Groups of four slots are aligned; slots outside
+  // [first, last) are skipped.
+  const uint32_t g0 = first / 4, g1 = (last + 3) / 4;
+  const uint2* __restrict__ keys = static_cast<const uint2*>(rb.sorted);
+  for (uint32_t gb = g0; gb < g1; gb += kReduceThreads * 2) {
+    uint2 kk[2];
+    float2 vv[2][4];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const uint32_t gi = gb + j * kReduceThreads + threadIdx.x;
-        kk[j] = gi < g1 ? keys[gi] : make_uint2(0u, 0u);
-        vv[j] = gi < g1 ? vals[gi] : make_uint4(0u, 0u, 0u, 0u);
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const uint32_t p0 = 4 * (gb + j * kReduceThreads + threadIdx.x);
-        const uint32_t k4[4] = {kk[j].x & 0xFFFFu, kk[j].x >> 16, kk[j].y & 0xFFFFu, kk[j].y >> 16};
-        const uint32_t v4[4] = {vv[j].x, vv[j].y, vv[j].z, vv[j].w};
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (p0 + u < first || p0 + u >= last) continue;
-          const float2 v = R::val(make_uint2(0u, v4[u]));
-          add(k4[u], v.x, v.y);
-        }
-      }
+    for (int j = 0; j < 2; ++j) {
+      const uint32_t gi = gb + j * kReduceThreads + threadIdx.x;
+      const uint32_t gc = gi < g1 ? gi : g0;  // a group of this chunk either way
+      kk[j] = keys[gc];
+      R::vals4(rb, gc, vv[j]);
     }
-  } else {
-    for (uint32_t base = first; base < last; base += kReduceThreads * kReducePer) {
-      Rec rec[kReducePer];
 #pragma unroll
-      for (int j = 0; j < kReducePer; ++j) {
-        const uint32_t i = base + j * kReduceThreads + threadIdx.x;
-        rec[j] = i < last ? R::load(rb, i, e0) : R::none();
-      }
+    for (int j = 0; j < 2; ++j) {
+      const uint32_t p0 = 4 * (gb + j * kReduceThreads + threadIdx.x);
+      const uint32_t k4[4] = {kk[j].x & 0xFFFFu, kk[j].x >> 16, kk[j].y & 0xFFFFu, kk[j].y >> 16};
 #pragma unroll
-      for (int j = 0; j < kReducePer; ++j) {
-        if (R::key(rec[j]) == 0xFFFFFFFFu) continue;
-        const float2 v = R::val(rec[j]);
-        add(R::key(rec[j]) - e0, v.x, v.y);
+      for (int u = 0; u < 4; ++u) {
+        if (p0 + u < first || p0 + u >= last) continue;
+        add(k4[u], vv[j][u].x, vv[j][u].y);
       }
     }
   }
