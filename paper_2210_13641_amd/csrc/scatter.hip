@@ -169,8 +169,18 @@ __global__ __launch_bounds__(kRecThreads) void bin_count_kernel(SampleSrc src, L
       LevelRecords r;
       level_records(lv, dl[q], g + 4 * q, valid, xn, r);
       if (r.on) {
+        // the two x-neighbour corners (k, k + 1) nearly always share a bin:
+        // one atomic counts both
 #pragma unroll
-        for (int k = 0; k < 8; ++k) atomicAdd(&h[r.idx[k] >> kBinShift], 1u);
+        for (int k = 0; k < 8; k += 2) {
+          const uint32_t ba = r.idx[k] >> kBinShift, bb = r.idx[k + 1] >> kBinShift;
+          if (ba == bb) {
+            atomicAdd(&h[ba], 2u);
+          } else {
+            atomicAdd(&h[ba], 1u);
+            atomicAdd(&h[bb], 1u);
+          }
+        }
       }
     }
   }
@@ -364,9 +374,22 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
 #pragma unroll
         for (int k = 0; k < 8; ++k) rec[h][k] = R::none();
       }
+      // ranks in the bins; the two x-neighbour corners (k, k + 1) nearly
+      // always share a bin and then take two consecutive ranks from one
+      // atomic (a lane's records are all present or all absent)
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (R::key(rec[h][k]) != 0xFFFFFFFFu) rank[h][k] = atomicAdd(&cnt[R::key(rec[h][k]) >> kBinShift], 1u);
+      for (int k = 0; k < 8; k += 2) {
+        if (R::key(rec[h][k]) != 0xFFFFFFFFu) {
+          const uint32_t ba = R::key(rec[h][k]) >> kBinShift, bb = R::key(rec[h][k + 1]) >> kBinShift;
+          if (ba == bb) {
+            rank[h][k] = atomicAdd(&cnt[ba], 2u);
+            rank[h][k + 1] = rank[h][k] + 1u;
+          } else {
+            rank[h][k] = atomicAdd(&cnt[ba], 1u);
+            rank[h][k + 1] = atomicAdd(&cnt[bb], 1u);
+          }
+        }
+      }
     }
     __syncthreads();
     // lst = exclusive prefix of cnt (per-thread runs of bins, a wave scan of
