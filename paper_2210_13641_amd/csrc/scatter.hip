@@ -15,9 +15,10 @@
 //   place       the block's records again, ordered by bin in LDS, stored to
 //               their bins' slices
 //   reduce      one workgroup per chunk: LDS accumulation of the bin with
-//               64-bit compare-and-swap on (g0, g1) pairs, then grad += acc
-//               (a bin of one chunk owns its entries; chunks of a bin with
-//               several add with atomics, one per touched entry)
+//               64-bit compare-and-swap on (g0, g1) pairs, then grad += acc,
+//               or grad = acc when the step clears its gradients (a bin of
+//               one chunk owns its entries; chunks of a bin with several add
+//               with atomics, one per touched entry)
 //
 // A record is (entry, w * dL/de_l0, w * dL/de_l1), the values in FP32, or in
 // BF16 for the mixed-precision step (accumulated in FP32 all the same).
