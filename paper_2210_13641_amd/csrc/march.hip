@@ -127,25 +127,45 @@ __global__ __launch_bounds__(kScanThreads) void scan_cut_kernel(RayBuffers rb, i
   const int tid = threadIdx.x, wave = tid / kWave;
   const int per = (n + kScanThreads - 1) / kScanThreads;
   const int b = tid * per, e = min(n, b + per);
+  // up to kCutRegs rays per thread (n <= 4096) are loaded once, counts and
+  // precisions together, and kept in registers for the second pass
+  constexpr int kCutRegs = 4;
+  uint32_t cr[kCutRegs];
+  bool pz[kCutRegs];
   uint32_t sum = 0;
-  for (int i = b; i < e; ++i) sum += rb.counts[i];
+  if (per <= kCutRegs) {
+#pragma unroll
+    for (int k = 0; k < kCutRegs; ++k) {
+      cr[k] = b + k < e ? rb.counts[b + k] : 0u;
+      pz[k] = b + k < e && rb.prec[b + k] == 0.0f;
+      sum += cr[k];
+    }
+  } else {
+    for (int i = b; i < e; ++i) sum += rb.counts[i];
+  }
   const uint32_t incl = wave_incl_scan_u32(sum);
   if (lane_id() == kWave - 1) wtot[wave] = incl;
   __syncthreads();
   uint32_t run = incl - sum;  // exclusive
   for (int w = 0; w < wave; ++w) run += wtot[w];
   uint32_t nr = 0, nk = 0, nm = 0;
-  for (int i = b; i < e; ++i) {
+  auto cut = [&](int i, uint32_t c, bool masked) {
     rb.offsets[i] = run;
-    const uint32_t c = rb.counts[i];
     run += c;
     if (run <= (uint32_t)max_samples) {
       ++nk;
       if (c > 0) {
         ++nr;
-        if (rb.prec[i] == 0.0f) ++nm;
+        if (masked) ++nm;
       }
     }
+  };
+  if (per <= kCutRegs) {
+#pragma unroll
+    for (int k = 0; k < kCutRegs; ++k)
+      if (b + k < e) cut(b + k, cr[k], pz[k]);
+  } else {
+    for (int i = b; i < e; ++i) cut(i, rb.counts[i], rb.prec[i] == 0.0f);
   }
   if (tid == kScanThreads - 1) rb.offsets[n] = run;
   // reductions
