@@ -212,8 +212,11 @@ __global__ __launch_bounds__(256) void emit_kernel(KeyframeStore kf, MarchParams
     }
     return;
   }
-  int k, pix;
-  const Ray ray = make_ray(kf, ids[r], k, pix);
+  // the ray as the counting pass stored it (the same values make_ray gives)
+  const float4 ro = rb.rays[2 * r], rd = rb.rays[2 * r + 1];
+  Ray ray;
+  ray.o[0] = ro.x; ray.o[1] = ro.y; ray.o[2] = ro.z; ray.s = ro.w;
+  ray.d[0] = rd.x; ray.d[1] = rd.y; ray.d[2] = rd.z;
   int k0, k1;
   if (!lattice_range(ray, mp, k0, k1)) return;
   uint32_t done = 0;
