@@ -195,8 +195,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_cut_kernel(RayBuffers rb, i
   }
 }
 
-__global__ __launch_bounds__(256) void emit_kernel(KeyframeStore kf, MarchParams mp,
-                                                   const uint32_t* __restrict__ ids, int n,
+__global__ __launch_bounds__(256) void emit_kernel(KeyframeStore kf, MarchParams mp, int n,
                                                    RayBuffers rb, float* __restrict__ t_out,
                                                    uint32_t* __restrict__ ray_out) {
   const int r = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
@@ -246,11 +245,11 @@ hipError_t march_rays(const KeyframeStore& kf, const MarchParams& mp, const uint
   return hipGetLastError();
 }
 
-hipError_t march_emit(const KeyframeStore& kf, const MarchParams& mp, const uint32_t* ids, int n,
+hipError_t march_emit(const KeyframeStore& kf, const MarchParams& mp, const uint32_t* /*ids*/, int n,
                       const RayBuffers& rb, float* t_out, uint32_t* ray_out, hipStream_t st) {
   if (n > 0)
-    hipLaunchKernelGGL(emit_kernel, dim3(march_block_count(n)), dim3(256), 0, st, kf, mp, ids, n, rb,
-                       t_out, ray_out);
+    hipLaunchKernelGGL(emit_kernel, dim3(march_block_count(n)), dim3(256), 0, st, kf, mp, n, rb, t_out,
+                       ray_out);  // the rays come from rb, stored by the counting pass from ids
   return hipGetLastError();
 }
 

@@ -442,7 +442,6 @@ template <class R>
 __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffers rb, int nbins, uint32_t entries,
                                                                     float* __restrict__ grad_table,
                                                                     float* __restrict__ overflow, bool overwrite) {
-  typedef typename R::T Rec;
   // (g0, g1) of each entry as one 64-bit word: float pairs are added with
   // LDS 64-bit compare-and-swap, which retires far faster than LDS float
   // atomics on this architecture
