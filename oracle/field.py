@@ -219,29 +219,34 @@ def mlp_fwd(spec, ws, e, e_mag, sh, band=1e-5):
     """Density and colour nets.  Returns a cache dict with sigma [S],
     colour [S,3] and every activation needed by ``mlp_bwd``.
 
-    Forward magnitudes (abs-propagated inputs times |W|) only serve to find
-    ambiguous ReLU units; a unit that is off passes no magnitude on.
+    Forward magnitudes (abs-propagated inputs times |W|) find the ambiguous
+    ReLU units and bound the activations' errors.  A unit that is off passes
+    no magnitude on; an ambiguous unit passes on twice its pre-activation's
+    magnitude, since a float value within tol * magnitude of a pre-activation
+    itself within tol * magnitude of zero may be up to twice that far from
+    the exact ReLU output.
     """
     W = ws
     a = dict(e=e, e_mag=e_mag, sh=sh, band=band)
     pre1 = e @ W[0]
     pre1_m = e_mag @ np.abs(W[0])
     h1, m1, amb1 = _relu_with_band(pre1, pre1_m, band)
-    h1_m = pre1_m * np.where(amb1, 1.0, m1)
+    h1_m = pre1_m * np.where(amb1, 2.0, m1)
     o = h1 @ W[1]
     o_m = h1_m @ np.abs(W[1])
     sigma = np.exp(o[:, 0])
     cur = np.concatenate([o, sh], 1)
     cur_m = np.concatenate([o_m, np.abs(sh)], 1)
-    hs, ms, ambs = [], [], []
+    hs, hms, ms, ambs = [], [], [], []
     for Wl in W[2:-1]:
         pre = cur @ Wl
         pre_m = cur_m @ np.abs(Wl)
         h, mk, amb = _relu_with_band(pre, pre_m, band)
         hs.append(cur)
+        hms.append(cur_m)
         ms.append(mk)
         ambs.append(amb)
-        cur, cur_m = h, pre_m * np.where(amb, 1.0, mk)
+        cur, cur_m = h, pre_m * np.where(amb, 2.0, mk)
     z = cur @ W[-1]
     z_m = cur_m @ np.abs(W[-1])
     colour = 1.0 / (1.0 + np.exp(-z))
@@ -249,9 +254,9 @@ def mlp_fwd(spec, ws, e, e_mag, sh, band=1e-5):
     # error of o_0 as a relative error; sigmoid damps it by c(1-c).
     sigma_mag = sigma * (1.0 + o_m[:, 0])
     colour_mag = colour + colour * (1.0 - colour) * z_m
-    a.update(pre1=pre1, h1=h1, mask1=m1, amb1=amb1, o=o, sigma=sigma, hidden_in=hs,
-             masks=ms, ambs=ambs, last_in=cur, z=z, colour=colour, sigma_mag=sigma_mag,
-             colour_mag=colour_mag)
+    a.update(pre1=pre1, h1=h1, h1_mag=h1_m, mask1=m1, amb1=amb1, o=o, sigma=sigma, hidden_in=hs,
+             hidden_in_mag=hms, masks=ms, ambs=ambs, last_in=cur, last_in_mag=cur_m, z=z,
+             colour=colour, sigma_mag=sigma_mag, colour_mag=colour_mag)
     return a
 
 
@@ -270,16 +275,21 @@ def mlp_bwd(spec, ws, cache, dsigma, dsigma_mag, dcol, dcol_mag, band_tol=1e-5):
     Returns (dW list, dW magnitude list, de [S, L*F], de magnitude).
     Ambiguous ReLU units carry half the gradient (midpoint of {0, g}) and a
     magnitude widened by |g| / (2 tol) so that either float32 choice passes.
+
+    Magnitudes are first-order running-error bounds: a product x*y carries
+    |x| y_mag + x_mag |y|, so the error of the forward activations (x_mag, the
+    forward magnitudes) enters the weight gradients, the sigmoid derivative
+    (through the colour's magnitude) and the density term (through sigma's).
     """
     W = ws
     c = cache["colour"]
     dz = dcol * c * (1.0 - c)
-    dz_m = dcol_mag * c * (1.0 - c)
+    dz_m = dcol_mag * c * (1.0 - c) + np.abs(dcol) * np.abs(1.0 - 2.0 * c) * cache["colour_mag"]
     dWs = [None] * len(W)
     dWm = [None] * len(W)
     x_last = cache["last_in"]
     dWs[-1] = x_last.T @ dz
-    dWm[-1] = np.abs(x_last).T @ dz_m
+    dWm[-1] = np.abs(x_last).T @ dz_m + cache["last_in_mag"].T @ np.abs(dz)
     g = dz @ W[-1].T
     g_m = dz_m @ np.abs(W[-1]).T
     for li in range(len(W) - 2, 1, -1):       # colour hidden layers, backwards
@@ -290,7 +300,7 @@ def mlp_bwd(spec, ws, cache, dsigma, dsigma_mag, dcol, dcol_mag, band_tol=1e-5):
         g = g * mk
         xin = cache["hidden_in"][j]
         dWs[li] = xin.T @ g
-        dWm[li] = np.abs(xin).T @ g_m
+        dWm[li] = np.abs(xin).T @ g_m + cache["hidden_in_mag"][j].T @ np.abs(g)
         g_next = g @ W[li].T
         g_m = g_m @ np.abs(W[li]).T
         g = g_next
@@ -299,10 +309,10 @@ def mlp_bwd(spec, ws, cache, dsigma, dsigma_mag, dcol, dcol_mag, band_tol=1e-5):
     do_m = g_m[:, :spec.geo_dim].copy()
     sig = cache["sigma"]
     do[:, 0] += dsigma * sig
-    do_m[:, 0] += dsigma_mag * sig
+    do_m[:, 0] += dsigma_mag * sig + np.abs(dsigma) * cache["sigma_mag"]
     h1 = cache["h1"]
     dWs[1] = h1.T @ do
-    dWm[1] = np.abs(h1).T @ do_m
+    dWm[1] = np.abs(h1).T @ do_m + cache["h1_mag"].T @ np.abs(do)
     g = do @ W[1].T
     g_m = do_m @ np.abs(W[1]).T
     mk, amb = cache["mask1"], cache["amb1"]
@@ -310,7 +320,7 @@ def mlp_bwd(spec, ws, cache, dsigma, dsigma_mag, dcol, dcol_mag, band_tol=1e-5):
     g = g * mk
     e = cache["e"]
     dWs[0] = e.T @ g
-    dWm[0] = np.abs(e).T @ g_m
+    dWm[0] = np.abs(e).T @ g_m + cache["e_mag"].T @ np.abs(g)
     de = g @ W[0].T
     de_m = g_m @ np.abs(W[0]).T
     return dWs, dWm, de, de_m

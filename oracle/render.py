@@ -61,10 +61,52 @@ def composite_ray(sigma, colour, t, delta, stop_T=0.0):
     return dict(tau=tau, T=T, w=w, C=C, D=D, A=A, V=V, n_used=n_used)
 
 
-def composite_ray_bwd(fw, colour, t, delta, gC, gD, gV, gC_m=None, gD_m=None, gV_m=None, gA=0.0):
+def composite_magnitudes(fw, t, delta, sigma_mag, colour, colour_mag, tol):
+    """Running-error magnitudes of the rendered outputs of one ray, to first
+    order: a float evaluation whose densities and colours are within tol
+    times ``sigma_mag`` and ``colour_mag`` of the exact ones, and that rounds
+    each step, lands within tol times these magnitudes of the exact outputs.
+
+    Each quantity's magnitude is the same expression with every factor
+    replaced by its magnitude:
+      tau_m = delta sigma_mag;  P_i = sum_{j<i} tau_j, P_m likewise;
+      T_m   = T (1 + P + P_m)              (dT = -T dP, plus the rounding);
+      alpha_m = alpha + e^{-tau} tau_m;    w_m = T_m alpha + T alpha_m;
+      C_m = sum w_m |c| + w c_m;  D_m = sum w_m |t|;  A_m = sum w_m.
+    V* is evaluated in two passes (d* first).  Its terms are non-negative,
+    and an error e of d* enters through the identity
+      sum_i w_i (t_i - d* - e)^2 = V* - 2 e d* (1 - A) + A e^2,
+    which holds because sum_i w_i (t_i - d*) = d* (1 - A) (Eq. 5, A = sum w),
+    so V_m = sum w_m (t - d*)^2 + 2 |d*| |1 - A| D_m + tol A D_m^2.
+    Samples past the early-termination stop carry no weight."""
+    tau = fw["tau"]
+    n = len(tau)
+    tau_m = np.asarray(delta, np.float64) * np.asarray(sigma_mag, np.float64)
+    P = np.concatenate([[0.0], np.cumsum(tau)])
+    Pm = np.concatenate([[0.0], np.cumsum(tau_m)])
+    T_m = fw["T"] * (1.0 + P + Pm)
+    alpha = -np.expm1(-tau)
+    alpha_m = alpha + np.exp(-tau) * tau_m
+    w_m = T_m[:n] * alpha + fw["T"][:n] * alpha_m
+    w_m[fw["n_used"]:] = 0.0
+    w = fw["w"]
+    tt = np.abs(np.asarray(t, np.float64))
+    c = np.abs(np.asarray(colour, np.float64))
+    cm = np.abs(np.asarray(colour_mag, np.float64))
+    C_m = (w_m[:, None] * c + w[:, None] * cm).sum(0) if n else np.zeros(3)
+    D_m = float((w_m * tt).sum())
+    A_m = float(w_m.sum())
+    u = (np.asarray(t, np.float64) - fw["D"]) ** 2
+    V_m = float((w_m * u).sum()) + 2.0 * abs(fw["D"]) * abs(1.0 - fw["A"]) * D_m + tol * fw["A"] * D_m * D_m
+    return dict(C=C_m, D=D_m, A=A_m, V=V_m, T=T_m, w=w_m, c=cm)
+
+
+def composite_ray_bwd(fw, colour, t, delta, gC, gD, gV, gC_m=None, gD_m=None, gV_m=None, gA=0.0, mag=None):
     """Adjoint of ``composite_ray``: (dsigma, dcolour, magnitudes).
 
-    Magnitudes evaluate the same formulas with |.|, with each suffix sum
+    Magnitudes evaluate the same formulas with every factor replaced by its
+    magnitude (``mag`` from ``composite_magnitudes``; without it, the values
+    themselves, i.e. exact densities and colours), with each suffix sum
     sum_{i>k} counted as |Q| + |Q_{<=k}| (a float32 kernel may form it as
     total minus prefix)."""
     gC = np.asarray(gC, np.float64)
@@ -77,6 +119,8 @@ def composite_ray_bwd(fw, colour, t, delta, gC, gD, gV, gC_m=None, gD_m=None, gV
     tt = np.asarray(t, np.float64)
     dl = np.asarray(delta, np.float64)
     D, A, V = fw["D"], fw["A"], fw["V"]
+    if mag is None:
+        mag = dict(C=np.abs(fw["C"]), D=abs(D), A=A, V=abs(V), T=T, w=w, c=np.abs(c))
     u = (tt - D) ** 2
     Tn = T[1:]
     act = np.arange(n) < n_used
@@ -91,22 +135,29 @@ def composite_ray_bwd(fw, colour, t, delta, gC, gD, gV, gC_m=None, gD_m=None, gV
     Ap = np.cumsum(w)
     dA = Tn - (A - Ap)
     dtau = dC @ gC + gD * dD + gV * dV + gA * dA
-    mC = Tn[:, None] * np.abs(c) + np.abs(fw["C"])[None, :] + np.abs(Cp)
-    mD = Tn * tt + abs(D) + np.abs(Dp)
-    mV = Tn * u + abs(V) + np.abs(Vp) + 2.0 * abs(D) * (1.0 + A) * mD
-    dtau_m = mC @ gC_m + gD_m * mD + gV_m * mV + abs(gA) * (Tn + A + Ap)
+    Tm, wm, cm = mag["T"][1:], mag["w"], mag["c"]
+    ac, at = np.abs(c), np.abs(tt)
+    um = u + 2.0 * np.abs(tt - D) * mag["D"]            # (t - d*)^2 with d* in error
+    mC = Tm[:, None] * ac + Tn[:, None] * cm + mag["C"][None, :] + np.cumsum(wm[:, None] * ac + w[:, None] * cm, 0)
+    mD = Tm * at + mag["D"] + np.cumsum(wm * at)
+    mV = Tm * u + Tn * um + mag["V"] + np.cumsum(wm * u + w * um) \
+        + 2.0 * (abs(D) * (1.0 + A) * mD + (mag["D"] * (1.0 + A) + abs(D) * mag["A"]) * np.abs(dD))
+    mA = Tm + mag["A"] + np.cumsum(wm)
+    dtau_m = mC @ gC_m + gD_m * mD + gV_m * mV + abs(gA) * mA
     dtau = np.where(act, dtau, 0.0)
     dtau_m = np.where(act, dtau_m, 0.0)
     dsig = dl * dtau
     dsig_m = dl * dtau_m
     dcol = w[:, None] * gC[None, :]
-    dcol_m = w[:, None] * gC_m[None, :]
+    dcol_m = wm[:, None] * np.abs(gC)[None, :] + w[:, None] * gC_m[None, :]
     return dsig, dcol, dsig_m, dcol_m
 
 
-def loss_seeds(C, D, I, Dt, prec, R, lam):
+def loss_seeds(C, D, I, Dt, prec, R, lam, C_m=None, D_m=None):
     """Per-ray loss terms and seeds for rays with rendered (C, D) and targets
-    (I, Dt, precision).  Returns (l_rgb, l_d, gC, gD, gC_mag, gD_mag)."""
+    (I, Dt, precision).  Returns (l_rgb, l_d, gC, gD, gC_mag, gD_mag); the
+    seed magnitudes use the magnitudes C_m, D_m of the rendered values when
+    given (else their absolute values)."""
     C = np.asarray(C, np.float64)
     I = np.asarray(I, np.float64)
     er = C - I
@@ -115,8 +166,10 @@ def loss_seeds(C, D, I, Dt, prec, R, lam):
     l_d = prec * ed * ed
     gC = 2.0 * er / R
     gD = 2.0 * lam * prec * ed / R
-    gC_m = 2.0 * (np.abs(C) + np.abs(I)) / R
-    gD_m = 2.0 * lam * prec * (np.abs(D) + np.abs(Dt)) / R
+    C_m = np.abs(C) if C_m is None else np.asarray(C_m, np.float64)
+    D_m = np.abs(D) if D_m is None else np.asarray(D_m, np.float64)
+    gC_m = 2.0 * (C_m + np.abs(I)) / R
+    gD_m = 2.0 * lam * prec * (D_m + np.abs(Dt)) / R
     return l_rgb, l_d, gC, gD, gC_m, gD_m
 
 

@@ -70,19 +70,20 @@ def train_step(spec, sampler, kf, table, ws, pixel_ids, occupancy=None, lam=1.0,
     out_d = np.zeros(R)
     out_v = np.zeros(R)
     out_a = np.zeros(R)
-    var_mag = np.zeros(R)
-    fws = []
+    mags = np.zeros((R, 6))                     # magnitudes of rgb, d*, V*, A
+    fws, fms = [], []
     for i in range(R):
         a, b = offs[i], offs[i + 1]
-        fw = render.composite_ray(sigma[a:b], colour[a:b], t_all[a:b],
-                                  np.full(b - a, sampler.dt))
+        dl = np.full(b - a, sampler.dt)
+        fw = render.composite_ray(sigma[a:b], colour[a:b], t_all[a:b], dl)
+        fm = render.composite_magnitudes(fw, t_all[a:b], dl, cache["sigma_mag"][a:b], colour[a:b],
+                                         cache["colour_mag"][a:b], band)
         fws.append(fw)
+        fms.append(fm)
         out_rgb[i], out_d[i], out_v[i], out_a[i] = fw["C"], fw["D"], fw["V"], fw["A"]
-        # magnitude of V*: sum of w (|t| + |d*|)^2 bounds the rounding of the
-        # differences t - d* as well as of the sum itself
-        var_mag[i] = float((fw["w"] * (np.abs(t_all[a:b]) + abs(fw["D"])) ** 2).sum())
+        mags[i] = [*fm["C"], fm["D"], fm["V"], fm["A"]]
     l_rgb, l_d, gC, gD, gC_m, gD_m = render.loss_seeds(out_rgb, out_d, I[sel], Dray[sel],
-                                                       prec[sel], R, lam)
+                                                       prec[sel], R, lam, mags[:, :3], mags[:, 3])
     L_rgb = l_rgb.sum() / R if R else 0.0
     L_D = l_d.sum() / R if R else 0.0
     gv = np.zeros(R) if g_var is None else np.asarray(g_var, np.float64) / s64[sel] ** 2
@@ -95,7 +96,7 @@ def train_step(spec, sampler, kf, table, ws, pixel_ids, occupancy=None, lam=1.0,
         a, b = offs[i], offs[i + 1]
         ds, dc, dsm, dcm = render.composite_ray_bwd(
             fws[i], colour[a:b], t_all[a:b], np.full(b - a, sampler.dt),
-            gC[i], gD[i], gv[i], gC_m[i], gD_m[i], abs(gv[i]))
+            gC[i], gD[i], gv[i], gC_m[i], gD_m[i], abs(gv[i]), mag=fms[i])
         dsig[a:b], dcol[a:b], dsig_m[a:b], dcol_m[a:b] = ds, dc, dsm, dcm
     dWs, dWm, de, de_m = field.mlp_bwd(spec, ws, cache, dsig, dsig_m, dcol, dcol_m, band)
     gtab, gtab_m = field.encode_bwd(spec, cache["corners"], de, de_m, len(table))
@@ -103,7 +104,8 @@ def train_step(spec, sampler, kf, table, ws, pixel_ids, occupancy=None, lam=1.0,
         sel=sel, counts=fs["counts"], kept=fs["kept"], ray_mask=fs["ray_mask"], R=R, S=S,
         t=t_all, ray_of=ray_of, offsets=offs, xn=xn, sigma=sigma, colour=colour,
         rgb=out_rgb, depth_z=out_d / s64[sel], var_z=out_v / s64[sel] ** 2, opacity=out_a,
-        var_z_mag=var_mag / s64[sel] ** 2,
+        rgb_mag=mags[:, :3], depth_z_mag=mags[:, 3] / s64[sel], var_z_mag=mags[:, 4] / s64[sel] ** 2,
+        opacity_mag=mags[:, 5],
         depth_ray=out_d, var_ray=out_v, scale=s64[sel],
         loss=L_rgb + lam * L_D, loss_rgb=L_rgb, loss_d=L_D,
         dsigma=dsig, dsigma_mag=dsig_m, dcolour=dcol, dcolour_mag=dcol_m,
@@ -143,15 +145,19 @@ def render_image(spec, table, ws, pose, intr, H, W, sampler, stop_T=0.0, pixel_i
     cache = field_forward(spec, table, ws, xn, d64[rr], band)
     sig = cache["sigma"].reshape(R, n)
     col = cache["colour"].reshape(R, n, 3)
-    out = dict(rgb=np.zeros((R, 3)), depth_z=np.zeros(R), var_z=np.zeros(R),
-               var_z_mag=np.zeros(R), opacity=np.zeros(R), n_used=np.zeros(R, np.int64),
-               alt=dict())
+    sig_m = cache["sigma_mag"].reshape(R, n)
+    col_m = cache["colour_mag"].reshape(R, n, 3)
+    out = dict(rgb=np.zeros((R, 3)), depth_z=np.zeros(R), var_z=np.zeros(R), opacity=np.zeros(R),
+               rgb_mag=np.zeros((R, 3)), depth_z_mag=np.zeros(R), var_z_mag=np.zeros(R),
+               opacity_mag=np.zeros(R), n_used=np.zeros(R, np.int64), alt=dict())
     dl = np.full(n, sampler.dt)
     for r in range(R):
         fw = render.composite_ray(sig[r], col[r], t, dl, stop_T)
+        fm = render.composite_magnitudes(fw, t, dl, sig_m[r], col[r], col_m[r], band)
         out["rgb"][r], out["depth_z"][r] = fw["C"], fw["D"] / s64[r]
         out["var_z"][r], out["opacity"][r], out["n_used"][r] = fw["V"] / s64[r] ** 2, fw["A"], fw["n_used"]
-        out["var_z_mag"][r] = float((fw["w"] * (np.abs(t) + abs(fw["D"])) ** 2).sum()) / s64[r] ** 2
+        out["rgb_mag"][r], out["depth_z_mag"][r] = fm["C"], fm["D"] / s64[r]
+        out["var_z_mag"][r], out["opacity_mag"][r] = fm["V"] / s64[r] ** 2, fm["A"]
         if stop_T > 0.0:
             k = fw["n_used"]
             near = [j for j in (k - 1, k) if 0 <= j < n and abs(fw["T"][j] / stop_T - 1.0) < 1e-5]

@@ -52,8 +52,8 @@ def test_autograd_matches_oracle_on_4096_rays(nsl, gpu):
     L.backward()
     assert float(L.detach()) == pytest.approx(o["loss"], rel=2e-5)
     outc = out.detach().cpu().numpy()
-    check_mag("rgb", outc[:, :3], o["rgb"], np.abs(o["rgb"]) + 1e-7, TOL)
-    check_mag("depth", outc[:, 3], o["depth_ray"], np.abs(o["depth_ray"]) + 1e-7, TOL)
+    check_mag("rgb", outc[:, :3], o["rgb"], o["rgb_mag"], TOL)
+    check_mag("depth", outc[:, 3], o["depth_ray"], o["depth_z_mag"] * o["scale"], TOL)
     g = P.grad.cpu().numpy()
     gtab, gws = split_grads(g, f.layout, spec)
     check_mag("grad table", gtab, o["grad_table"], o["grad_table_mag"], 2 * TOL)

@@ -86,8 +86,10 @@ def test_mixed_step_matches_oracle(nsl, gpu):
     assert g["state"].tolist() == [scale, 1.0, 0.0, 0.0]
     assert g["loss"][0] == pytest.approx(o["loss"], rel=TOL)
     sel = o["sel"]
-    check_mag("rgb", g["rays"][sel, :3], o["rgb"], np.abs(o["rgb"]) + 1e-7, TOL)
-    check_mag("depth", g["rays"][sel, 3], o["depth_z"], np.abs(o["depth_z"]) + 1e-7, TOL)
+    check_mag("rgb", g["rays"][sel, :3], o["rgb"], o["rgb_mag"], TOL)
+    check_mag("depth", g["rays"][sel, 3], o["depth_z"], o["depth_z_mag"], TOL)
+    check_mag("var", g["rays"][sel, 4], o["var_z"], o["var_z_mag"], TOL)
+    check_mag("opacity", g["rays"][sel, 5], o["opacity"], o["opacity_mag"], TOL)
     gtab, gws = split_grads(g["grads"] / scale, f.layout, spec)
     rels = [check_mag("grad table", gtab, o["grad_table"], o["grad_table_mag"], TOL)]
     for j in range(len(gws)):
@@ -187,10 +189,10 @@ def test_mixed_error_along_training(nsl, gpu, n_cams):
             ob = ostep.train_step(spec, sampler, kf, t64, w64, ids, band=TOL) if n_cams == 8 or step == 1 else None
             sel = o["sel"]
             def outs(o):
-                return [("rgb", o["rgb"], np.abs(o["rgb"]) + 1e-7, lambda r: r[sel, :3]),
-                        ("depth", o["depth_z"], np.abs(o["depth_z"]) + 1e-7, lambda r: r[sel, 3]),
+                return [("rgb", o["rgb"], o["rgb_mag"], lambda r: r[sel, :3]),
+                        ("depth", o["depth_z"], o["depth_z_mag"], lambda r: r[sel, 3]),
                         ("var", o["var_z"], o["var_z_mag"], lambda r: r[sel, 4]),
-                        ("opacity", o["opacity"], o["opacity"] + 1e-7, lambda r: r[sel, 5])]
+                        ("opacity", o["opacity"], o["opacity_mag"], lambda r: r[sel, 5])]
 
             def grads(o):
                 return [("table", o["grad_table"], o["grad_table_mag"])] + \

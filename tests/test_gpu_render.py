@@ -50,9 +50,9 @@ def test_render_matches_oracle(nsl, gpu, spec, stop_T):
         assert any(np.allclose(rgb[r], c["rgb"], rtol=1e-4, atol=1e-6) for c in cands)
     if stop_T > 0:
         assert (o["n_used"] < n).any()         # termination actually happened
-    check_mag("rgb", rgb[ok], o["rgb"][ok], np.abs(o["rgb"][ok]) + 1e-7, TOL)
-    check_mag("depth", depth[ok], o["depth_z"][ok], np.abs(o["depth_z"][ok]) + 1e-7, TOL)
-    check_mag("opacity", op[ok], o["opacity"][ok], o["opacity"][ok] + 1e-7, TOL)
+    check_mag("rgb", rgb[ok], o["rgb"][ok], o["rgb_mag"][ok], TOL)
+    check_mag("depth", depth[ok], o["depth_z"][ok], o["depth_z_mag"][ok], TOL)
+    check_mag("opacity", op[ok], o["opacity"][ok], o["opacity_mag"][ok], TOL)
     check_mag("var", var[ok], o["var_z"][ok], o["var_z_mag"][ok], TOL)
 
 

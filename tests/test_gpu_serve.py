@@ -76,4 +76,4 @@ def test_serving_mix_equals_alone_and_oracle(nsl, gpu):
                            stop_T=1e-4)
     ok = np.array([r not in o["alt"] for r in range(300)])
     got = small.out[0].cpu().numpy()
-    check_mag("served rgb", got[ok], o["rgb"][ok], np.abs(o["rgb"][ok]) + 1e-7, 1e-5)
+    check_mag("served rgb", got[ok], o["rgb"][ok], o["rgb_mag"][ok], 1e-5)
