@@ -215,6 +215,8 @@ def main(argv=None):
         nsl.train_step(mapper, field, P, G, M, V, c, id_sets[i % N_SETS], wsb, loss, stats[i % N_SETS])
 
     def timed(c, adam):
+        """Wall time of args.steps steps (synchronised on both sides) and the
+        per-step HIP-event durations on the step's stream."""
         P.copy_(t(flat))
         G.zero_()
         M.zero_()
@@ -222,22 +224,27 @@ def main(argv=None):
         for i in range(args.warmup):
             c.adam_step = i + 1
             step(i, c)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        ev[0].record()
         for i in range(args.steps):
             c.adam_step = args.warmup + i + 1
             step(i, c)
+            ev[i + 1].record()
         torch.cuda.synchronize()
-        return time.perf_counter() - t0
+        dt = time.perf_counter() - t0
+        per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+        return dt, per
 
     res = {}
     names = [v for v in args.only.split(",") if v] or list(variants)
     for name in names:
-        dt = timed(cfgs[name], False)
+        dt, per = timed(cfgs[name], False)
         st = stats.cpu().numpy()
         S_sets = st[:, 1].astype(np.int64)
         samples = sum(int(S_sets[i % N_SETS]) for i in range(args.steps))
-        dt_full = timed(full[name], True)
+        dt_full, per_full = timed(full[name], True)
         # per-phase HIP events on the step's stream
         P.copy_(t(flat))
         nsl.profile_enable(True)
@@ -249,7 +256,8 @@ def main(argv=None):
         nsl.profile_enable(False)
         res[name] = dict(value=samples / dt, ms=1e3 * dt / args.steps, full_value=samples / dt_full,
                          full_ms=1e3 * dt_full / args.steps, phases={k: v / n_done for k, v in ph.items()},
-                         S=float(np.mean([S_sets[i % N_SETS] for i in range(n_prof)])), R=st[:, 0].astype(np.int64))
+                         S=float(np.mean([S_sets[i % N_SETS] for i in range(n_prof)])), R=st[:, 0].astype(np.int64),
+                         step_ms=distribution(per), full_step_ms=distribution(per_full))
     if args.only:
         print(json.dumps({k: {"samples_per_s": v["value"], "phases_ms": v["phases"]} for k, v in res.items()}))
         return 0
@@ -261,6 +269,7 @@ def main(argv=None):
     roof, roofs = roofline(spec, mixed["phases"], mixed["S"], 2, PEAK_BF16)
     roof_fp32, roofs_fp32 = roofline(spec, fp32["phases"], fp32["S"], 4, PEAK_FP32)
 
+    bound = PEAK_HBM / GATHER_BYTES_MIXED
     out = {
         "metric": METRIC,
         "value": mixed["value"],
@@ -286,6 +295,13 @@ def main(argv=None):
             "phase": "fwd+bwd to parameter gradients (gradient clearing included)",
             "backward": "recompute adjoint of the MLP; the encoding kept from the forward (keep_encoding = 1)",
         },
+        "step_ms_hip_events": {"mixed": mixed["step_ms"], "fp32": fp32["step_ms"],
+                               "mixed_full": mixed["full_step_ms"], "fp32_full": fp32["full_step_ms"]},
+        "step_roofline": {
+            "note": "whole mixed fwd+bwd step against the gather-bound roofline: HBM peak / (512 B FP16 gather + "
+                    "1024 B FP32 scatter per sample); the gate is half of it",
+            "bound_samples_per_s": bound, "frac": mixed["value"] / bound, "gate_frac": 0.5,
+            "gate_samples_per_s": 0.5 * bound, "meets_gate": bool(mixed["value"] >= 0.5 * bound)},
         "fp32_samples_per_s": fp32["value"],
         "fp32_ms_per_step": fp32["ms"],
         "mixed_vs_fp32": mixed["value"] / fp32["value"],
@@ -303,12 +319,132 @@ def main(argv=None):
             "phases_ms": {"mixed": res["mixed"]["phases"], "fp32": res["fp32"]["phases"]},
         },
     }
+    out["peaks_measured"] = measure_peaks(nsl, torch, dev)
+    add_measured_fractions(out["rooflines"], out["peaks_measured"])
+    del mapper, wsb, P, G, M, V
+    torch.cuda.empty_cache()
+    out["tiny_field_batches"] = tiny_field_batches(nsl, torch, dev, W, args.warmup, max(10, args.steps // 2))
     if args.serve_requests > 0:
         out["serving"] = serving(nsl, torch, dev, W, args.serve_requests, args.serve_warmup)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, sampler, kf, occ, table, ws, args.cpu_candidates)
+        out["cpu_baseline_more"] = cpu_baseline_more(spec, sampler, kf, occ, table, ws)
     print(json.dumps(out), flush=True)
     return 0
+
+
+GATHER_BYTES_MIXED = 8 * 16 * 2 * 2 + 8 * 16 * 2 * 4    # FP16 gather + FP32 scatter per paper-scale sample
+
+
+def distribution(ms):
+    """median, p10, p90, min, max of per-step milliseconds"""
+    ms = np.asarray(ms, np.float64)
+    return {"median": float(np.median(ms)), "p10": float(np.percentile(ms, 10)),
+            "p90": float(np.percentile(ms, 90)), "min": float(ms.min()), "max": float(ms.max()), "n": int(ms.size)}
+
+
+def _event_ms(torch, fn, reps):
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def measure_peaks(nsl, torch, dev):
+    """Measured machine peaks (the library's probe kernels, HIP events):
+    HBM stream copy, random 4-byte gathers from a 2 MB table (one FP16 hash
+    level: L2-resident) and a 32 MB table (Infinity-Cache resident, about the
+    size of the paper-scale FP16 table), and FP32 / BF16 MFMA loops."""
+    out = {}
+    n = 1 << 28                                            # 1 GiB each way
+    src = torch.ones(n // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    ms = _event_ms(torch, lambda: nsl.peak_copy(src, dst), 10)
+    out["hbm_copy_GBps"] = 2 * n / (ms * 1e-3) / 1e9
+    del src, dst
+    threads, loads = 256 * 4096, 256
+    o = torch.empty(threads, dtype=torch.int32, device=dev)
+    for name, log2 in (("gather_l2_2MB", 19), ("gather_mall_32MB", 23)):
+        tab = torch.randint(0, 1 << 30, (1 << log2,), dtype=torch.int32, device=dev)
+        ms = _event_ms(torch, lambda: nsl.peak_gather(tab, log2, o, loads), 10)
+        out[name + "_Gloads_per_s"] = threads * loads / (ms * 1e-3) / 1e9
+        out[name + "_GBps_4B"] = 4 * threads * loads / (ms * 1e-3) / 1e9
+        del tab
+    wg, iters = 1024, 1000
+    f = torch.empty(wg * 256, dtype=torch.float32, device=dev)
+    for name, bf16, flop in (("mfma_fp32_TFLOPs", False, 2048), ("mfma_bf16_TFLOPs", True, 16384)):
+        ms = _event_ms(torch, lambda: nsl.peak_mfma(bf16, f, iters), 5)
+        out[name] = wg * 4 * 8 * iters * flop / (ms * 1e-3) / 1e12
+    return out
+
+
+def add_measured_fractions(rooflines, peaks):
+    """Each phase's achieved rate against the measured peak of its bound
+    (HBM copy for the byte-bound phases, the MFMA loop of its precision for
+    the MLP)."""
+    for prec, phases in rooflines.items():
+        for r in phases.values():
+            if r["bound"] == "hbm":
+                p = peaks["hbm_copy_GBps"]
+            else:
+                p = peaks["mfma_bf16_TFLOPs"] if prec == "mixed" else peaks["mfma_fp32_TFLOPs"]
+            r["measured_peak"] = p
+            r["frac_of_measured_peak"] = r["achieved"] / p
+
+
+def tiny_field_batches(nsl, torch, dev, W, warmup, steps):
+    """The tiny field (4 levels x 2^12) on batches of 2^18 and 2^20 samples
+    (8 and 32 cameras of 32x32 pixels, 32 samples per ray): fwd+bwd samples/s
+    in mixed precision and FP32, each with per-step HIP-event times."""
+    import dataclasses
+    spec = W.C1_FIELD
+    f = nsl.Field(spec)
+    lay = f.layout
+    table, wts = W.init_params(0, lay["table_floats"], spec.mlp_dims())
+    flat = np.zeros(lay["total"], np.float32)
+    flat[:len(table)] = table
+    for off, w in zip(lay["w_offsets"], wts):
+        flat[off:off + w.size] = w.ravel()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    out = {}
+    for n_cams in (8, 32):
+        kf = W.c4_keyframes(n_cams)
+        m = nsl.Mapper(n_cams, 32, 32, 1, device=dev)
+        m.upsert(list(range(n_cams)), t(kf.rgb), t(kf.pose.reshape(n_cams, 12)), t(kf.intr), t(kf.depth),
+                 t(kf.depth_var))
+        ids = t(W.c1_pixels(K=n_cams).view(np.int32))
+        sampler = dataclasses.replace(W.C1_SAMPLER, max_samples=n_cams * 1024 * 32)
+        S = n_cams * 1024 * 32
+        P = t(flat)
+        G = torch.zeros_like(P)
+        loss = torch.zeros(3, device=dev)
+        row = {"samples_per_step": S}
+        for prec_name, prec in (("mixed", nsl.PRECISION_MIXED), ("fp32", nsl.PRECISION_FP32)):
+            st = torch.tensor([2.0 ** 15, 0, 0, 0], dtype=torch.float32, device=dev)
+            cfg = nsl.step_config(sampler, zero_grads=True, keep_encoding=True, precision=prec,
+                                  scale_state=st if prec == nsl.PRECISION_MIXED else None)
+            ws = torch.empty(nsl.step_workspace_bytes(f, cfg, ids.numel()), dtype=torch.uint8, device=dev)
+            for _ in range(warmup):
+                nsl.train_step(m, f, P, G, None, None, cfg, ids, ws, loss)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+            torch.cuda.synchronize()
+            ev[0].record()
+            for i in range(steps):
+                nsl.train_step(m, f, P, G, None, None, cfg, ids, ws, loss)
+                ev[i + 1].record()
+            torch.cuda.synchronize()
+            per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+            row[prec_name] = {"samples_per_s": S * steps / (ev[0].elapsed_time(ev[-1]) * 1e-3),
+                              "step_ms": distribution(per)}
+            del ws
+        row["mixed_vs_fp32"] = row["mixed"]["samples_per_s"] / row["fp32"]["samples_per_s"]
+        out[f"2^{int(np.log2(S))}"] = row
+    return out
 
 
 def samples_per_ray(nsl, torch, mapper, field, cfg, id_sets, wsb, dev, max_samples):
@@ -398,6 +534,39 @@ def render_capacity(nsl, torch, dev, W, f, P, rcfg, reps=20):
     b.record()
     b.synchronize()
     return reps * H * Wd / (a.elapsed_time(b) * 1e-3)
+
+
+def cpu_baseline_more(spec, sampler, kf, occ, table, ws):
+    """The oracle with one BLAS thread on 1024 candidates of one paper-scale
+    set, and the tiny workload's full step (32 768 samples) with all threads."""
+    import workloads as W
+    from oracle import step as ostep
+    from threadpoolctl import threadpool_limits
+    t64 = np.asarray(table, np.float32).astype(np.float64)
+    w64 = [np.asarray(w, np.float32).astype(np.float64) for w in ws]
+    out = {}
+    ids = W.c2_candidates(N_CANDIDATES, seed=3)[:1024]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        r = ostep.train_step(spec, sampler, kf, t64, w64, ids, occupancy=occ)
+        dt = time.perf_counter() - t0
+    out["single_thread"] = dict(value=r["S"] / dt, unit="samples/s", cores=1, kind="oracle",
+                                sample=f"one fwd+bwd step of the FP64 oracle on the first 1024 candidates of one "
+                                       f"paper-scale set ({r['S']} samples), {dt:.1f} s wall")
+    spec1 = W.C1_FIELD
+    from oracle import field as ofield
+    lay = ofield.param_layout(spec1)
+    tab1, ws1 = W.init_params(0, lay["table_floats"], spec1.mlp_dims())
+    tab1 = np.asarray(tab1, np.float32).astype(np.float64)
+    ws1 = [np.asarray(w, np.float32).astype(np.float64) for w in ws1]
+    kf1 = W.c1_keyframes()
+    t0 = time.perf_counter()
+    r = ostep.train_step(spec1, W.C1_SAMPLER, kf1, tab1, ws1, W.c1_pixels())
+    dt = time.perf_counter() - t0
+    out["tiny_workload"] = dict(value=r["S"] / dt, unit="samples/s", kind="oracle",
+                                sample=f"one fwd+bwd step of the FP64 oracle on the tiny workload ({r['S']} samples), "
+                                       f"{dt:.2f} s wall")
+    return out
 
 
 def cpu_baseline(spec, sampler, kf, occ, table, ws, n_cand, n_sets=2):

@@ -222,6 +222,9 @@ int nsl_occupancy_set(nsl_mapper* m, const uint32_t* bits, int src_on_host,
  * written) sets scale_state[3] = 1, Adam skips the update (gradients are
  * cleared), the scale is halved and scale_state[2] counts the skip; otherwise
  * scale_state[1] counts clean steps and the scale doubles after 2000 of them.
+ * adam_step counts every step the caller runs, skipped ones included; the
+ * bias correction uses the number of updates made, adam_step - scale_state[2]
+ * (at least 1), read on the device.
  * Gradients carried over from earlier steps (zero_grads = 0 without Adam)
  * were checked by the step that wrote them.
  *
@@ -346,6 +349,63 @@ int nsl_composite_bwd(const float* sigma, const float* rgb, const float* t,
                       const uint32_t* ray_off, int R, float delta, const float* g_rgb,
                       const float* g_depth, const float* g_var, const float* g_opacity,
                       float* g_sigma, float* g_rgb_s, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * The mapping loss on its own (Sec. 3.2, Eq. 3, 4 and 7), for rays rendered
+ * by nsl_composite_fwd (the autograd path); the step computes the same
+ * per-ray terms inside its compositing kernel.
+ *
+ * out6 [R,6]: r, g, b, d*, V*, A in ray units, as nsl_composite_fwd writes
+ * them; rgb_target [R,3]; depth_z [R] (z-depth D); depth_var_z [R] (Sigma_D,
+ * a variance in m^2); ray_scale [R] = s = |d~| (ray length per unit of z).
+ * The depth target along the ray is D s with precision 1/(Sigma_D s^2); a
+ * non-finite D or Sigma_D, or Sigma_D <= 0, gives precision 0 (masked).
+ *   L_rgb = (1/R) sum_r |I*_r - I_r|^2,  L_D = (1/R) sum_r pi_r (d*_r - D_r s_r)^2,
+ *   L = L_rgb + lambda_d L_D.
+ * nsl_loss_fwd writes loss_out [3] = (L, L_rgb, L_D) (device), summed in a
+ * fixed order (deterministic), and the number of masked rays into n_masked
+ * (device uint32, may be NULL).  ws: nsl_loss_workspace_bytes(R) bytes.
+ * nsl_loss_bwd writes the seeds of the adjoint, g_out6 [R,6] = dJ/d out6,
+ * for upstream gradients g_loss (device [3]: dJ/dL, dJ/dL_rgb, dJ/dL_D;
+ * NULL means (1, 0, 0)); the V* and A columns get 0.  All pointers are
+ * device memory; R >= 1.  Both calls are asynchronous on the stream.
+ * ------------------------------------------------------------------------ */
+size_t nsl_loss_workspace_bytes(int R);
+int nsl_loss_fwd(const float* out6, int R, const float* rgb_target, const float* depth_z,
+                 const float* depth_var_z, const float* ray_scale, float lambda_d, float* loss_out,
+                 uint32_t* n_masked, void* workspace, size_t workspace_bytes, hipStream_t stream);
+int nsl_loss_bwd(const float* out6, int R, const float* rgb_target, const float* depth_z,
+                 const float* depth_var_z, const float* ray_scale, float lambda_d, const float* g_loss,
+                 float* g_out6, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * The hash-grid encoding and its adjoint on their own (Sec. 3.2 after Eq. 5:
+ * the map's inputs are the multiresolution hash-grid features of the prior
+ * work), with the kernels the step runs when it keeps the encoding.
+ *
+ * xn [S,3]: normalised positions (clamped to [0,1]).  e_out is level-major,
+ * [levels][S]: nsl_encode_fwd writes FP32 feature pairs (float2) from the
+ * FP32 table of params; nsl_encode_fwd_mixed writes each pair as two BF16
+ * values packed in 32 bits (first feature in the low half), from the FP16
+ * table copy of a shadow made by nsl_field_prepare_mixed, exactly as the
+ * mixed-precision MLP consumes them.
+ *
+ * nsl_encode_bwd scatters dL/de into the table part of grads: de is
+ * level-major [levels][S] float2 (FP32); each (sample, level, corner)
+ * contributes w_c * dL/de, formed in FP32 (precision NSL_PRECISION_FP32) or
+ * rounded to BF16 (NSL_PRECISION_MIXED, the mixed step's records), and every
+ * sum is FP32.  overwrite = 0 adds to grads; overwrite = 1 sets the table
+ * part to the gradient (untouched entries become 0).  The MLP part of grads
+ * is not touched.  grads and de must be 16-byte aligned; ws:
+ * nsl_encode_bwd_workspace_bytes(f, S) bytes.  S * 8 * levels < 2^32.
+ * ------------------------------------------------------------------------ */
+int nsl_encode_fwd(const nsl_field* f, const float* params, const float* xn, int S, float* e_out,
+                   hipStream_t stream);
+int nsl_encode_fwd_mixed(const nsl_field* f, const void* shadow, const float* xn, int S, uint32_t* e_out,
+                         hipStream_t stream);
+size_t nsl_encode_bwd_workspace_bytes(const nsl_field* f, int S);
+int nsl_encode_bwd(const nsl_field* f, const float* xn, int S, const float* de, int precision, int overwrite,
+                   float* grads, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* Bias-corrected Adam over n parameters, gradient = grads * grad_scale;
  * clears grads. */

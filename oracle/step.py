@@ -122,6 +122,24 @@ def adam(theta, m, v, g, t, lr, b1, b2, eps):
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
+def adam_magnitudes(theta, m, v, g, t, lr, b1, b2, eps, M_theta, M_m, M_v, M_g):
+    """First-order running-error magnitudes of one Adam step's results
+    (theta, m, v), given the magnitudes of its inputs: every factor replaced
+    by its magnitude, the square root halving a relative error, and the
+    sums m, v, theta - update counted term by term.  Returns (M_theta, M_m,
+    M_v) for the updated values."""
+    m1 = b1 * m + (1.0 - b1) * g
+    v1 = b2 * v + (1.0 - b2) * g * g
+    Mm = b1 * M_m + (1.0 - b1) * M_g
+    Mv = b2 * M_v + (1.0 - b2) * 2.0 * np.abs(g) * M_g
+    bc1, bc2 = 1.0 - b1 ** t, 1.0 - b2 ** t
+    den = np.sqrt(v1 / bc2) + eps
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rel_v = np.where(v1 > 0, Mv / np.where(v1 > 0, v1, 1.0), 0.0)
+    M_upd = lr / den * (Mm / bc1 + np.abs(m1) / bc1 * (1.0 + 0.5 * rel_v * np.sqrt(v1 / bc2) / den))
+    return M_theta + M_upd, Mm, Mv
+
+
 def render_image(spec, table, ws, pose, intr, H, W, sampler, stop_T=0.0, pixel_ids=None,
                  band=1e-5):
     """Forward-only render of an image (or of ``pixel_ids`` of it) with

@@ -3,9 +3,12 @@
 The adjoint of the field is the recompute kernel (nsl_field_bwd): it stores
 no activations, re-deriving each sample's encoding and network activations
 from its position.  The adjoint of compositing (nsl_composite_bwd) recomputes
-transmittance and the per-ray prefix sums from sigma, colour and t.  Loss
-functions written in torch on the rendered outputs therefore differentiate
-down to the field parameters through the same kernels as nsl_train_step.
+transmittance and the per-ray prefix sums from sigma, colour and t.  The
+mapping loss (nsl_loss_fwd / nsl_loss_bwd) forms the same per-ray terms and
+seeds as the step's compositing kernel, so the loss differentiates down to
+the field parameters through the step's own arithmetic; other losses
+written in torch on the rendered outputs differentiate through the same
+field and compositing kernels.
 
 Positions and directions are inputs (the poses are fixed at this boundary),
 so no gradient flows to them.
@@ -66,16 +69,32 @@ def render_samples(field, params, xn, dirs, t, ray_off, delta, workspace):
     return CompositeFunction.apply(sigma, rgb, t, ray_off, delta)
 
 
+class LossFunction(torch.autograd.Function):
+    """(out [R,6] ray units, targets) -> (L, L_rgb, L_D) (Eq. 3, 4, 7)."""
+
+    @staticmethod
+    def forward(ctx, out, scale, rgb_target, depth_target_z, depth_var_z, lambda_d):
+        args = (scale.contiguous(), rgb_target.contiguous(), depth_target_z.contiguous(), depth_var_z.contiguous())
+        loss = nsl.loss_fwd(out.detach().contiguous(), args[1], args[2], args[3], args[0], lambda_d)
+        ctx.save_for_backward(out, *args)
+        ctx.lambda_d = lambda_d
+        return loss
+
+    @staticmethod
+    def backward(ctx, g_loss):
+        out, scale, rgb_target, depth_z, depth_var = ctx.saved_tensors
+        g = nsl.loss_bwd(out.detach().contiguous(), rgb_target, depth_z, depth_var, scale, ctx.lambda_d,
+                         g_loss.contiguous())
+        return g, None, None, None, None, None
+
+
 def mapping_loss(out, scale, rgb_target, depth_target_z, depth_var_z, lambda_d=1.0):
-    """L_M = L_rgb + lambda_D L_D (Eq. 3, 4, 7) in torch, mean over rays.
+    """L_M = L_rgb + lambda_D L_D (Eq. 3, 4, 7), mean over rays, computed by
+    the library (nsl_loss_fwd; its adjoint nsl_loss_bwd).
 
     out: [R,6] ray units; scale: |d~| per ray; depth targets in z units.
     Unusable measurements (non-finite, non-positive variance) get weight 0.
+    Returns (L, L_rgb, L_D) as 0-d tensors.
     """
-    ok = torch.isfinite(depth_target_z) & torch.isfinite(depth_var_z) & (depth_var_z > 0)
-    prec = torch.where(ok, 1.0 / (torch.where(ok, depth_var_z, torch.ones_like(depth_var_z)) * scale * scale),
-                       torch.zeros_like(scale))
-    d_ray = torch.where(ok, depth_target_z * scale, torch.zeros_like(scale))
-    l_rgb = ((out[:, :3] - rgb_target) ** 2).sum(-1).mean()
-    l_d = (prec * (out[:, 3] - d_ray) ** 2).mean()
-    return l_rgb + lambda_d * l_d, l_rgb, l_d
+    loss = LossFunction.apply(out, scale, rgb_target, depth_target_z, depth_var_z, lambda_d)
+    return loss[0], loss[1], loss[2]

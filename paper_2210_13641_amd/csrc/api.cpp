@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/nsl.h"
+#include "../../include/nsl_peaks.h"
 #include "kernels.h"
 
 using namespace nsl;
@@ -696,6 +697,142 @@ int nsl_composite_bwd(const float* sigma, const float* rgb, const float* t, cons
   return NSL_OK;
 }
 
+size_t nsl_loss_workspace_bytes(int R) { return R < 0 ? 0 : align256(2 * sizeof(float) * (size_t)R); }
+
+static int check_loss_args(const float* out6, int R, const float* rgb_target, const float* depth_z,
+                           const float* depth_var_z, const float* ray_scale) {
+  if (!out6 || !rgb_target || !depth_z || !depth_var_z || !ray_scale) return fail(NSL_E_INVALID, "null argument");
+  if (R < 1) return fail(NSL_E_INVALID, "the loss needs at least one ray");
+  return NSL_OK;
+}
+
+int nsl_loss_fwd(const float* out6, int R, const float* rgb_target, const float* depth_z, const float* depth_var_z,
+                 const float* ray_scale, float lambda_d, float* loss_out, uint32_t* n_masked, void* ws,
+                 size_t ws_bytes, hipStream_t st) {
+  int rc = check_loss_args(out6, R, rgb_target, depth_z, depth_var_z, ray_scale);
+  if (rc) return rc;
+  if (!loss_out || !ws) return fail(NSL_E_INVALID, "null argument");
+  if (ws_bytes < nsl_loss_workspace_bytes(R)) return fail(NSL_E_WORKSPACE, "loss workspace too small");
+  float* parts = static_cast<float*>(ws);
+  if (n_masked) HIP_TRY(hipMemsetAsync(n_masked, 0, sizeof(uint32_t), st), "clear mask count");
+  HIP_TRY(loss_terms(out6, R, rgb_target, depth_z, depth_var_z, ray_scale, lambda_d, nullptr, parts, nullptr,
+                     n_masked, st),
+          "loss terms");
+  const LossSum ls{parts, R, lambda_d, loss_out};
+  HIP_TRY(loss_sum(ls, st), "loss sum");
+  return NSL_OK;
+}
+
+int nsl_loss_bwd(const float* out6, int R, const float* rgb_target, const float* depth_z, const float* depth_var_z,
+                 const float* ray_scale, float lambda_d, const float* g_loss, float* g_out6, hipStream_t st) {
+  int rc = check_loss_args(out6, R, rgb_target, depth_z, depth_var_z, ray_scale);
+  if (rc) return rc;
+  if (!g_out6) return fail(NSL_E_INVALID, "null argument");
+  HIP_TRY(loss_terms(out6, R, rgb_target, depth_z, depth_var_z, ray_scale, lambda_d, g_loss, nullptr, g_out6,
+                     nullptr, st),
+          "loss seeds");
+  return NSL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Encoding and its adjoint on their own
+// ---------------------------------------------------------------------------
+
+static int check_encode_args(const nsl_field* f, const float* xn, int S) {
+  if (!f || !xn) return fail(NSL_E_INVALID, "null argument");
+  if (S < 0) return fail(NSL_E_INVALID, "negative sample count");
+  if (!records_fit(f->cfg.levels, S)) return fail(NSL_E_INVALID, "S * 8 * levels must stay below 2^32");
+  return NSL_OK;
+}
+
+int nsl_encode_fwd(const nsl_field* f, const float* params, const float* xn, int S, float* e_out, hipStream_t st) {
+  int rc = check_encode_args(f, xn, S);
+  if (rc) return rc;
+  if (!params || !e_out) return fail(NSL_E_INVALID, "null argument");
+  SampleSrc src{};
+  src.xn = xn; src.box = f->box; src.n = S; src.ecache = e_out; src.ecache_stride = S;
+  FieldArgs fa{params, nullptr, f->lv};
+  HIP_TRY(field_encode(f->shape, fa, src, S, st), "encoding");
+  return NSL_OK;
+}
+
+int nsl_encode_fwd_mixed(const nsl_field* f, const void* shadow, const float* xn, int S, uint32_t* e_out,
+                         hipStream_t st) {
+  int rc = check_encode_args(f, xn, S);
+  if (rc) return rc;
+  if (!shadow || !e_out) return fail(NSL_E_INVALID, "null argument");
+  if (misaligned(shadow)) return fail(NSL_E_INVALID, "shadow must be 16-byte aligned");
+  SampleSrc src{};
+  src.xn = xn; src.box = f->box; src.n = S; src.ecache = e_out; src.ecache_stride = S;
+  HIP_TRY(mixed_encode(f->shape, f->lv, shadow, src, S, st), "encoding (mixed)");
+  return NSL_OK;
+}
+
+static size_t encode_bwd_carve(const nsl_field* f, int S, void* base, BinPlan* plan, RecordBuffers* rec) {
+  Carver cv(base);
+  const BinPlan p = plan_of(f, S);
+  RecordBuffers r = carve_records(cv, p);
+  if (plan) *plan = p;
+  if (rec) *rec = r;
+  return cv.used;
+}
+
+size_t nsl_encode_bwd_workspace_bytes(const nsl_field* f, int S) {
+  if (!f || S < 0 || !records_fit(f->cfg.levels, S)) return 0;
+  return encode_bwd_carve(f, S, nullptr, nullptr, nullptr);
+}
+
+int nsl_encode_bwd(const nsl_field* f, const float* xn, int S, const float* de, int precision, int overwrite,
+                   float* grads, void* ws, size_t ws_bytes, hipStream_t st) {
+  int rc = check_encode_args(f, xn, S);
+  if (rc) return rc;
+  if (!de || !grads || !ws) return fail(NSL_E_INVALID, "null argument");
+  if (precision != NSL_PRECISION_FP32 && precision != NSL_PRECISION_MIXED) return fail(NSL_E_INVALID, "bad precision");
+  if (misaligned(grads) || misaligned(de)) return fail(NSL_E_INVALID, "grads and de must be 16-byte aligned");
+  if (ws_bytes < nsl_encode_bwd_workspace_bytes(f, S)) return fail(NSL_E_WORKSPACE, "encode workspace too small");
+  BinPlan plan;
+  RecordBuffers rec;
+  encode_bwd_carve(f, S, ws, &plan, &rec);
+  rec.de = const_cast<float2*>(reinterpret_cast<const float2*>(de));  // read only
+  rec.stride = S;
+  SampleSrc src{};
+  src.xn = xn; src.box = f->box; src.n = S;
+  if (S == 0) {  // nothing to scatter; an overwrite still leaves the table gradient at zero
+    if (overwrite) HIP_TRY(fill_zero(grads, f->lay.table_floats, st), "clear table gradient");
+    return NSL_OK;
+  }
+  HIP_TRY(bin_scatter(plan, rec, src, f->lv, precision == NSL_PRECISION_MIXED, overwrite != 0, grads, nullptr, st),
+          "table gradient");
+  return NSL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Machine-peak probes
+// ---------------------------------------------------------------------------
+
+int nsl_peak_copy(const void* src, void* dst, size_t bytes, hipStream_t st) {
+  if (!src || !dst) return fail(NSL_E_INVALID, "null argument");
+  if (bytes % 16 || misaligned(src) || misaligned(dst)) return fail(NSL_E_INVALID, "16-byte aligned copies only");
+  HIP_TRY(peak_copy(src, dst, bytes, st), "peak copy");
+  return NSL_OK;
+}
+
+int nsl_peak_gather(const uint32_t* table, int log2_entries, uint32_t* out, int n_threads, int loads,
+                    hipStream_t st) {
+  if (!table || !out) return fail(NSL_E_INVALID, "null argument");
+  if (log2_entries < 4 || log2_entries > 30 || n_threads < 0 || n_threads % 256 || loads < 16 || loads % 16)
+    return fail(NSL_E_INVALID, "bad gather shape");
+  HIP_TRY(peak_gather(table, log2_entries, out, n_threads, loads, st), "peak gather");
+  return NSL_OK;
+}
+
+int nsl_peak_mfma(int bf16, float* out, int n_workgroups, int iters, hipStream_t st) {
+  if (!out) return fail(NSL_E_INVALID, "null argument");
+  if (n_workgroups < 0 || iters < 1) return fail(NSL_E_INVALID, "bad mfma loop shape");
+  HIP_TRY(peak_mfma(bf16 != 0, out, n_workgroups, iters, st), "peak mfma");
+  return NSL_OK;
+}
+
 int nsl_adam(float* p, float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps, int step,
              float grad_scale, hipStream_t st) {
   if (!p || !g || !m || !v) return fail(NSL_E_INVALID, "null argument");
@@ -752,18 +889,24 @@ size_t nsl_render_workspace_bytes(const nsl_field* f, int H, int W, const nsl_re
   return nsl_field_prepared_bytes(f) + align256(sizeof(nsl_render_request));
 }
 
-int nsl_render(const nsl_field* f, const float* params, const float* pose, const float* intr, int H, int W,
-               const nsl_render_config* c, float* rgb, float* depth, float* var, float* opacity, void* ws,
-               size_t ws_bytes, hipStream_t st) {
-  if (!f || !params || !pose || !intr || !c || !rgb || !depth || !var || !ws) return fail(NSL_E_INVALID, "null argument");
+static int check_render_args(const nsl_field* f, const float* params, const float* pose, const float* intr, int H,
+                             int W, const nsl_render_config* c, const float* rgb, const float* depth,
+                             const float* var) {
+  if (!f || !params || !pose || !intr || !c || !rgb || !depth || !var) return fail(NSL_E_INVALID, "null argument");
   if (H < 1 || W < 1 || (int64_t)H * W > (1 << 30)) return fail(NSL_E_INVALID, "bad image size");
-  int rc = check_render_cfg(c);
-  if (rc) return rc;
-  if (ws_bytes < nsl_render_workspace_bytes(f, H, W, c)) return fail(NSL_E_WORKSPACE, "render workspace too small");
+  return check_render_cfg(c);
+}
+
+// One image into rgb/depth/var/opacity: the parameters' MFMA operands and the
+// request record are written to ws (nsl_render_workspace_bytes).
+static int render_image(const nsl_field* f, const float* params, const float* pose, const float* intr, int H, int W,
+                        const nsl_render_config* c, float* rgb, float* depth, float* var, float* opacity, void* ws,
+                        hipStream_t st) {
   char* base = static_cast<char*>(ws);
   void* prepared = base;
   nsl_render_request* dev_req = reinterpret_cast<nsl_render_request*>(base + nsl_field_prepared_bytes(f));
-  if ((rc = nsl_field_prepare(f, params, prepared, st))) return rc;
+  int rc = nsl_field_prepare(f, params, prepared, st);
+  if (rc) return rc;
   nsl_render_request r;
   r.params = params;
   r.prepared = prepared;
@@ -779,6 +922,16 @@ int nsl_render(const nsl_field* f, const float* params, const float* pose, const
   const int n_tiles = (H * W + NSL_RENDER_TILE - 1) / NSL_RENDER_TILE;
   HIP_TRY(render_tiles(f->shape, f->lv, f->box, dev_req, 1, nullptr, n_tiles, render_params(c), st), "render");
   return NSL_OK;
+}
+
+int nsl_render(const nsl_field* f, const float* params, const float* pose, const float* intr, int H, int W,
+               const nsl_render_config* c, float* rgb, float* depth, float* var, float* opacity, void* ws,
+               size_t ws_bytes, hipStream_t st) {
+  int rc = check_render_args(f, params, pose, intr, H, W, c, rgb, depth, var);
+  if (rc) return rc;
+  if (!ws) return fail(NSL_E_INVALID, "null argument");
+  if (ws_bytes < nsl_render_workspace_bytes(f, H, W, c)) return fail(NSL_E_WORKSPACE, "render workspace too small");
+  return render_image(f, params, pose, intr, H, W, c, rgb, depth, var, opacity, ws, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -61,8 +61,11 @@ __device__ __forceinline__ float normalise_axis(float x, float lo, float inv) {
 }
 
 // floor(xn*N) taken on the exact product (TwoProduct: xn*N = ph + pl exactly),
-// clamped to N-1; f = xn*N - i0 rounded once.
-__device__ __forceinline__ int cell_floor(float xn, int n, float& f) {
+// clamped to N-1; f = xn*N - i0 and g = (i0 + 1) - xn*N, each rounded once
+// from the exact product (ph - i0 and (i0 + 1) - ph are exact), so both
+// trilinear factors keep full relative precision: 1 - f formed from a
+// rounded f loses it when f is near 1.
+__device__ __forceinline__ int cell_floor(float xn, int n, float& f, float& g) {
   // no contraction: fused, xn*N - i would be rounded once with the product's
   // error inside it, and adding pl would count that error twice
 #pragma clang fp contract(off)
@@ -74,6 +77,7 @@ __device__ __forceinline__ int cell_floor(float xn, int n, float& f) {
   int i = (int)fl;
   if (i > n - 1) i = n - 1;
   f = (ph - (float)i) + pl;
+  g = ((float)(i + 1) - ph) - pl;
   return i;
 }
 
@@ -87,6 +91,35 @@ __device__ __forceinline__ uint32_t grid_index(uint32_t x, uint32_t y, uint32_t 
 }
 
 __device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+// A pixel's depth target along its ray and the precision of its measurement
+// (Eq. 4 read with Sigma_D a variance): (D_z s, 1 / (Sigma_z s^2)) when D_z
+// and Sigma_z are finite and Sigma_z > 0, else (0, 0): an unusable
+// measurement carries no depth loss.
+__device__ __forceinline__ float2 depth_target(float Dz, float Vz, float s) {
+  const bool ok = isfinite(Dz) && isfinite(Vz) && Vz > 0.0f;
+  return ok ? make_float2(Dz * s, 1.0f / (Vz * s * s)) : make_float2(0.0f, 0.0f);
+}
+
+// One ray's terms of the mapping loss (Eq. 3, 4, 7) and the seeds of its
+// adjoint: l_rgb = |I* - I|^2, l_d = pi (d* - D)^2, dL/dI* = k_rgb (I* - I),
+// dL/dd* = k_d pi (d* - D), with the caller's factors k (2/R times the loss
+// scale, times lambda_D for the depth term, in the step).
+struct RayLoss {
+  float l_rgb, l_d, gC[3], gD;
+};
+__device__ __forceinline__ RayLoss ray_loss(const float C[3], float D, float4 target, float pi, float k_rgb,
+                                            float k_d) {
+  RayLoss o;
+  const float e0 = C[0] - target.x, e1 = C[1] - target.y, e2 = C[2] - target.z, ed = D - target.w;
+  o.l_rgb = e0 * e0 + e1 * e1 + e2 * e2;
+  o.l_d = pi * ed * ed;
+  o.gC[0] = k_rgb * e0;
+  o.gC[1] = k_rgb * e1;
+  o.gC[2] = k_rgb * e2;
+  o.gD = k_d * pi * ed;
+  return o;
+}
 
 // Wave-wide helpers (wave64).
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }

@@ -267,18 +267,14 @@ __global__ __launch_bounds__(256) void composite_loss_kernel(CompositeIO io, Los
   Chunk cc[kCacheChunks];
   const RaySums s = cached ? ray_forward_cached(io, b, n, cc) : ray_forward(io, b, n);
   const float Rf = (float)lo.stats[0];
-  const float4 tg = lo.target[r];
-  const float pi = lo.prec[r];
-  const float e0 = s.C[0] - tg.x, e1 = s.C[1] - tg.y, e2 = s.C[2] - tg.z, ed = s.D - tg.w;
-  const float l_rgb = e0 * e0 + e1 * e1 + e2 * e2;
-  const float l_d = pi * ed * ed;
   const float scale = lo.scale_dev ? lo.scale_dev[0] : lo.loss_scale;
   const float k = 2.0f * scale / Rf;
-  const float gC[3] = {k * e0, k * e1, k * e2};
-  const float gD = k * lo.lambda_d * pi * ed;
+  const RayLoss L = ray_loss(s.C, s.D, lo.target[r], lo.prec[r], k, k * lo.lambda_d);
+  const float gC[3] = {L.gC[0], L.gC[1], L.gC[2]};
+  const float gD = L.gD;
   if (lane_id() == 0) {
-    lo.parts[2 * r] = l_rgb / Rf;
-    lo.parts[2 * r + 1] = l_d / Rf;
+    lo.parts[2 * r] = L.l_rgb / Rf;
+    lo.parts[2 * r + 1] = L.l_d / Rf;
     if (lo.ray_out) {
       const float sc = lo.rays[2 * r].w;
       float* o = lo.ray_out + 6 * (size_t)r;
@@ -290,6 +286,44 @@ __global__ __launch_bounds__(256) void composite_loss_kernel(CompositeIO io, Los
     ray_backward_cached(b, n, s, cc, gC, gD, io.delta, g_sigma, g_rgb_s);
   else
     ray_backward(io, b, n, s, gC, gD, 0.0f, 0.0f, g_sigma, g_rgb_s);
+}
+
+// The loss of rays rendered outside the step (out6 from compositing, ray
+// units), one thread per ray: per-ray shares of L_rgb and L_D (divided by R)
+// into parts, and with g_out the seeds of the adjoint for the upstream
+// gradients g_loss of (L, L_rgb, L_D) (NULL: (1, 0, 0)); masked
+// measurements are counted into n_masked.
+__global__ __launch_bounds__(256) void loss_terms_kernel(const float* __restrict__ out6, int R,
+                                                         const float* __restrict__ rgb_target,
+                                                         const float* __restrict__ depth_z,
+                                                         const float* __restrict__ var_z,
+                                                         const float* __restrict__ ray_scale, float lambda_d,
+                                                         const float* __restrict__ g_loss, float* __restrict__ parts,
+                                                         float* __restrict__ g_out, uint32_t* __restrict__ n_masked) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool on = r < R;
+  float2 dp = make_float2(0.0f, 0.0f);
+  if (on) {
+    const float* o = out6 + 6 * (size_t)r;
+    const float C[3] = {o[0], o[1], o[2]};
+    dp = depth_target(depth_z[r], var_z[r], ray_scale[r]);
+    const float4 tg = make_float4(rgb_target[3 * r], rgb_target[3 * r + 1], rgb_target[3 * r + 2], dp.x);
+    const float gL = g_loss ? g_loss[0] : 1.0f, gLr = g_loss ? g_loss[1] : 0.0f, gLd = g_loss ? g_loss[2] : 0.0f;
+    const float Rf = (float)R;
+    const RayLoss L = ray_loss(C, o[3], tg, dp.y, 2.0f * (gL + gLr) / Rf, 2.0f * (gL * lambda_d + gLd) / Rf);
+    if (parts) {
+      parts[2 * r] = L.l_rgb / Rf;
+      parts[2 * r + 1] = L.l_d / Rf;
+    }
+    if (g_out) {
+      float* g = g_out + 6 * (size_t)r;
+      g[0] = L.gC[0]; g[1] = L.gC[1]; g[2] = L.gC[2]; g[3] = L.gD; g[4] = 0.0f; g[5] = 0.0f;
+    }
+  }
+  if (n_masked) {
+    const uint64_t bad = __ballot(on && dp.y == 0.0f);
+    if (lane_id() == 0 && bad) atomicAdd(n_masked, (uint32_t)__popcll(bad));
+  }
 }
 
 dim3 grid_for(int R) { return dim3((R + kWavesPerBlock - 1) / kWavesPerBlock); }
@@ -307,6 +341,15 @@ hipError_t composite_backward(const CompositeIO& io, const float* g_rgb, const f
   if (io.R > 0)
     hipLaunchKernelGGL(composite_bwd_kernel, grid_for(io.R), dim3(256), 0, st, io, g_rgb, g_depth,
                        g_var, g_opacity, g_sigma, g_rgb_s);
+  return hipGetLastError();
+}
+
+hipError_t loss_terms(const float* out6, int R, const float* rgb_target, const float* depth_z, const float* var_z,
+                      const float* ray_scale, float lambda_d, const float* g_loss, float* parts, float* g_out,
+                      uint32_t* n_masked, hipStream_t st) {
+  if (R > 0)
+    hipLaunchKernelGGL(loss_terms_kernel, dim3((R + 255) / 256), dim3(256), 0, st, out6, R, rgb_target, depth_z,
+                       var_z, ray_scale, lambda_d, g_loss, parts, g_out, n_masked);
   return hipGetLastError();
 }
 

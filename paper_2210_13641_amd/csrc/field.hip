@@ -593,6 +593,13 @@ hipError_t field_encode(int shape, const FieldArgs& a, const SampleSrc& src, int
                              : launch_encode<NetFull>(a, src, max_samples, st);
 }
 
+__global__ __launch_bounds__(256) void loss_sum_kernel(LossSum ls) { loss_sum_block(ls); }
+
+hipError_t loss_sum(const LossSum& ls, hipStream_t st) {
+  hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, st, ls);
+  return hipGetLastError();
+}
+
 hipError_t field_dw_reduce(int shape, const float* partial, int nblocks, const WOffsets& wo, float* grads,
                            float* overflow, const LossSum* ls, hipStream_t st) {
   return shape == kShapeTiny ? launch_dw_reduce<NetTiny>(partial, nblocks, wo, grads, overflow, ls, st)

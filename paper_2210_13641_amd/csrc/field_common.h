@@ -12,23 +12,31 @@ typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 // Per-sample inputs
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void load_sample(const SampleSrc& src, int s, float xn[3],
-                                            float d[3]) {
+// Normalised position of sample s (the direction is not read).
+__device__ __forceinline__ void load_position(const SampleSrc& src, int s, float xn[3]) {
   if (src.t) {
     const uint32_t r = src.ray[s];
     const float t = src.t[s];
     const float4 o = src.rays[2 * r];
     const float4 dd = src.rays[2 * r + 1];
-    d[0] = dd.x; d[1] = dd.y; d[2] = dd.z;
     xn[0] = normalise_axis(pos_axis(o.x, dd.x, t), src.box.lo[0], src.box.inv[0]);
     xn[1] = normalise_axis(pos_axis(o.y, dd.y, t), src.box.lo[1], src.box.inv[1]);
     xn[2] = normalise_axis(pos_axis(o.z, dd.z, t), src.box.lo[2], src.box.inv[2]);
   } else {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      xn[i] = fminf(fmaxf(src.xn[3 * s + i], 0.0f), 1.0f);
-      d[i] = src.dir[3 * s + i];
-    }
+    for (int i = 0; i < 3; ++i) xn[i] = fminf(fmaxf(src.xn[3 * s + i], 0.0f), 1.0f);
+  }
+}
+
+__device__ __forceinline__ void load_sample(const SampleSrc& src, int s, float xn[3],
+                                            float d[3]) {
+  load_position(src, s, xn);
+  if (src.t) {
+    const float4 dd = src.rays[2 * src.ray[s] + 1];
+    d[0] = dd.x; d[1] = dd.y; d[2] = dd.z;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) d[i] = src.dir[3 * s + i];
   }
 }
 
@@ -59,14 +67,14 @@ struct Corner8 {
 
 __device__ __forceinline__ void corners(float x, float y, float z, int n, bool dense,
                                         uint32_t mask, uint32_t off, Corner8& c) {
-  float fx, fy, fz;
-  const uint32_t ix = (uint32_t)cell_floor(x, n, fx);
-  const uint32_t iy = (uint32_t)cell_floor(y, n, fy);
-  const uint32_t iz = (uint32_t)cell_floor(z, n, fz);
+  float fx, fy, fz, ux, uy, uz;
+  const uint32_t ix = (uint32_t)cell_floor(x, n, fx, ux);
+  const uint32_t iy = (uint32_t)cell_floor(y, n, fy, uy);
+  const uint32_t iz = (uint32_t)cell_floor(z, n, fz, uz);
   c.cell[0] = ix;
   c.cell[1] = iy;
   c.cell[2] = iz;
-  const float gx[2] = {1.0f - fx, fx}, gy[2] = {1.0f - fy, fy}, gz[2] = {1.0f - fz, fz};
+  const float gx[2] = {ux, fx}, gy[2] = {uy, fy}, gz[2] = {uz, fz};
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const uint32_t cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
@@ -169,8 +177,8 @@ __global__ __launch_bounds__(256) void encode_levels_kernel(LevelInfo lv, const 
     s = gid / N::L;
   }
   if (s >= S) return;
-  float xn[3], d[3];
-  load_sample(src, s, xn, d);
+  float xn[3];
+  load_position(src, s, xn);
   const float2 v = encode_level(table, lv.table_mask, lv.res[l], (lv.dense_bits >> l) & 1u, lv.offset[l], xn);
   store_encoding(out + (size_t)l * stride + s, v);
 }

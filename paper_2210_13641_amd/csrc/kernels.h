@@ -102,6 +102,8 @@ struct LossSum {
   float lambda_d;
   float* loss;
 };
+// loss[0..2] from the per-ray shares alone (one workgroup, fixed order).
+hipError_t loss_sum(const LossSum& ls, hipStream_t st);
 // ls (may be null): the step's loss is summed by the same launch.
 hipError_t field_dw_reduce(int shape, const float* partial, int nblocks, const WOffsets& wo, float* grads,
                            float* overflow, const LossSum* ls, hipStream_t st);
@@ -210,6 +212,19 @@ hipError_t composite_backward(const CompositeIO& io, const float* g_rgb, const f
 // left to a LossSum (the step's last reduction launch).
 hipError_t composite_loss_backward(const CompositeIO& io, const LossIO& lo, float* g_sigma,
                                    float* g_rgb_s, hipStream_t st);
+
+// Per-ray loss shares (parts [R][2], nullable) and adjoint seeds (g_out
+// [R][6], nullable) of rays rendered outside the step; n_masked (nullable)
+// += rays whose depth measurement is unusable.
+hipError_t loss_terms(const float* out6, int R, const float* rgb_target, const float* depth_z, const float* var_z,
+                      const float* ray_scale, float lambda_d, const float* g_loss, float* parts, float* g_out,
+                      uint32_t* n_masked, hipStream_t st);
+
+// peaks.hip: machine-peak probes (not part of the step)
+hipError_t peak_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
+hipError_t peak_gather(const uint32_t* table, int log2_entries, uint32_t* out, int n_threads, int loads,
+                       hipStream_t st);
+hipError_t peak_mfma(int bf16, float* out, int n_workgroups, int iters, hipStream_t st);
 
 // cov.hip
 size_t cov_partial_blocks(int p);

@@ -93,10 +93,9 @@ __global__ __launch_bounds__(256) void rays_count_kernel(KeyframeStore kf, March
     rb.rays[2 * r] = make_float4(ray.o[0], ray.o[1], ray.o[2], ray.s);
     rb.rays[2 * r + 1] = make_float4(ray.d[0], ray.d[1], ray.d[2], 0.0f);
     const size_t p = (size_t)k * kf.H * kf.W + pix;
-    const float D = kf.depth[p], V = kf.var[p];
-    const bool ok = isfinite(D) && isfinite(V) && V > 0.0f;
-    rb.target[r] = make_float4(kf.rgb[3 * p], kf.rgb[3 * p + 1], kf.rgb[3 * p + 2], ok ? D * ray.s : 0.0f);
-    rb.prec[r] = ok ? 1.0f / (V * ray.s * ray.s) : 0.0f;
+    const float2 dp = depth_target(kf.depth[p], kf.var[p], ray.s);
+    rb.target[r] = make_float4(kf.rgb[3 * p], kf.rgb[3 * p + 1], kf.rgb[3 * p + 2], dp.x);
+    rb.prec[r] = dp.y;
   }
   uint32_t count = 0;
   if (mp.sampler == 0) {

@@ -7,11 +7,15 @@ namespace {
 
 // Bias-corrected Adam (dense), gradient = grads * gscale; clears grads.
 // Streams 4 floats per thread per array: params, grads, m, v.
+// With a loss-scale state, the step's gradient is unscaled by state[0], a
+// step whose gradient overflowed (state[3]) only clears the gradient, and
+// the bias correction counts the updates actually made: t = step - state[2]
+// (the steps skipped before this one), at least 1.
 __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, float* __restrict__ g,
                                                    float* __restrict__ m, float* __restrict__ v,
                                                    int64_t n, float lr, float b1, float b2,
                                                    float eps, float bc1, float bc2, float gscale,
-                                                   const float* __restrict__ state) {
+                                                   int step, const float* __restrict__ state) {
   const int64_t i4 = (int64_t)(blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * 4;
   if (state) {
     if (state[3] != 0.0f) {  // overflow: skip the update, clear the gradient
@@ -19,6 +23,9 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, float*
       return;
     }
     gscale = 1.0f / state[0];
+    const float t = fmaxf(1.0f, (float)step - state[2]);
+    bc1 = 1.0f - powf(b1, t);
+    bc2 = 1.0f - powf(b2, t);
   }
   if (i4 + 4 <= n) {
     float4 pp = *reinterpret_cast<float4*>(p + i4);
@@ -93,7 +100,7 @@ hipError_t adam_update(float* p, float* g, float* m, float* v, int64_t n, float 
   const float bc2 = 1.0f - powf(b2, (float)step);
   const int64_t threads = (n + 3) / 4;
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, p, g, m, v,
-                     n, lr, b1, b2, eps, bc1, bc2, grad_scale, scale_state);
+                     n, lr, b1, b2, eps, bc1, bc2, grad_scale, step, scale_state);
   return hipGetLastError();
 }
 

@@ -162,8 +162,8 @@ __global__ __launch_bounds__(kRecThreads) void bin_count_kernel(SampleSrc src, L
     if (tile * 16 >= S) break;
     const int s = tile * 16 + jc;
     const bool valid = s < S;
-    float xn[3] = {0.5f, 0.5f, 0.5f}, d[3];
-    if (valid) load_sample(src, s, xn, d);
+    float xn[3] = {0.5f, 0.5f, 0.5f};
+    if (valid) load_position(src, s, xn);
     float2 dl[kMaxLevels / 4];
     load_de(rb.de, rb.stride, lv.levels, g, s, valid, dl);
     for (int q = 0; q < lv.levels / 4; ++q) {
@@ -350,10 +350,7 @@ __global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, L
   const int s = (blk * kRecWaves + wave) * 16 + jc;
   const bool valid = s < S;
   float xn[3] = {0.5f, 0.5f, 0.5f};
-  {
-    float d[3];
-    if (valid) load_sample(src, s, xn, d);
-  }
+  if (valid) load_position(src, s, xn);
   float2 dl[kMaxLevels / 4];
   load_de(rb.de, rb.stride, lv.levels, g, s, valid, dl);
   __syncthreads();

@@ -110,6 +110,16 @@ _sig("nsl_mixed_shadow_bytes", _sz, [_vp])
 _sig("nsl_field_prepare_mixed", _i, [_vp, _vp, _vp, _vp])
 _sig("nsl_field_fwd_mixed", _i, [_vp, _vp, _vp, _vp, _i, _vp, _vp, _vp])
 _sig("nsl_field_bwd_mixed", _i, [_vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp])
+_sig("nsl_loss_workspace_bytes", _sz, [_i])
+_sig("nsl_loss_fwd", _i, [_vp, _i, _vp, _vp, _vp, _vp, _f, _vp, _vp, _vp, _sz, _vp])
+_sig("nsl_loss_bwd", _i, [_vp, _i, _vp, _vp, _vp, _vp, _f, _vp, _vp, _vp])
+_sig("nsl_encode_fwd", _i, [_vp, _vp, _vp, _i, _vp, _vp])
+_sig("nsl_encode_fwd_mixed", _i, [_vp, _vp, _vp, _i, _vp, _vp])
+_sig("nsl_encode_bwd_workspace_bytes", _sz, [_vp, _i])
+_sig("nsl_encode_bwd", _i, [_vp, _vp, _i, _vp, _i, _i, _vp, _vp, _sz, _vp])
+_sig("nsl_peak_copy", _i, [_vp, _vp, _sz, _vp])
+_sig("nsl_peak_gather", _i, [_vp, _i, _vp, _i, _i, _vp])
+_sig("nsl_peak_mfma", _i, [_i, _vp, _i, _i, _vp])
 _sig("nsl_covariance_workspace_bytes", _sz, [_i, _i])
 _sig("nsl_depth_covariance", _i, [_i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
 _sig("nsl_profile_enable", _i, [_i])
@@ -356,6 +366,68 @@ def adam(params, grads, m, v, lr, beta1, beta2, eps, step, grad_scale=1.0):
     _check(_lib.nsl_adam(_dev(params, torch.float32), _dev(grads, torch.float32), _dev(m, torch.float32),
                          _dev(v, torch.float32), params.numel(), lr, beta1, beta2, eps, step, grad_scale,
                          _stream()))
+
+
+def loss_fwd(out6, rgb_target, depth_z, depth_var_z, ray_scale, lambda_d=1.0, ws=None, n_masked=None):
+    """(L, L_rgb, L_D) as a device [3] tensor."""
+    R = out6.shape[0]
+    dev = out6.device
+    ws = torch.empty(_lib.nsl_loss_workspace_bytes(R), dtype=torch.uint8, device=dev) if ws is None else ws
+    loss = torch.empty(3, dtype=torch.float32, device=dev)
+    _check(_lib.nsl_loss_fwd(_dev(out6, torch.float32), R, _dev(rgb_target, torch.float32),
+                             _dev(depth_z, torch.float32), _dev(depth_var_z, torch.float32),
+                             _dev(ray_scale, torch.float32), lambda_d, _ptr(loss), _ptr(n_masked), _ptr(ws),
+                             ws.numel(), _stream()))
+    return loss
+
+
+def loss_bwd(out6, rgb_target, depth_z, depth_var_z, ray_scale, lambda_d=1.0, g_loss=None):
+    """dJ/d out6 [R,6] for upstream gradients g_loss [3] of (L, L_rgb, L_D)."""
+    g = torch.empty_like(out6)
+    _check(_lib.nsl_loss_bwd(_dev(out6, torch.float32), out6.shape[0], _dev(rgb_target, torch.float32),
+                             _dev(depth_z, torch.float32), _dev(depth_var_z, torch.float32),
+                             _dev(ray_scale, torch.float32), lambda_d,
+                             _dev(g_loss, torch.float32) if g_loss is not None else None, _ptr(g), _stream()))
+    return g
+
+
+def encode_fwd(field: "Field", params, xn):
+    """Level-major encoding [levels, S, 2] (FP32 table)."""
+    S = xn.shape[0]
+    e = torch.empty(field.spec.levels, S, 2, dtype=torch.float32, device=xn.device)
+    _check(_lib.nsl_encode_fwd(field.handle, _dev(params, torch.float32), _dev(xn, torch.float32), S, _ptr(e),
+                               _stream()))
+    return e
+
+
+def encode_fwd_mixed(field: "Field", shadow, xn):
+    """Level-major encoding [levels, S] of BF16 pairs packed in int32 (FP16 table copy)."""
+    S = xn.shape[0]
+    e = torch.empty(field.spec.levels, S, dtype=torch.int32, device=xn.device)
+    _check(_lib.nsl_encode_fwd_mixed(field.handle, _ptr(shadow), _dev(xn, torch.float32), S, _ptr(e), _stream()))
+    return e
+
+
+def encode_bwd(field: "Field", xn, de, grads, precision=PRECISION_FP32, overwrite=False, ws=None):
+    """Table part of grads += (or =) the scatter of dL/de [levels, S, 2]."""
+    S = xn.shape[0]
+    if ws is None:
+        ws = torch.empty(_lib.nsl_encode_bwd_workspace_bytes(field.handle, S), dtype=torch.uint8,
+                         device=xn.device)
+    _check(_lib.nsl_encode_bwd(field.handle, _dev(xn, torch.float32), S, _dev(de, torch.float32), precision,
+                               int(overwrite), _dev(grads, torch.float32), _ptr(ws), ws.numel(), _stream()))
+
+
+def peak_copy(src, dst):
+    _check(_lib.nsl_peak_copy(_ptr(src), _ptr(dst), src.numel() * src.element_size(), _stream()))
+
+
+def peak_gather(table, log2_entries, out, loads):
+    _check(_lib.nsl_peak_gather(_ptr(table), log2_entries, _ptr(out), out.numel(), loads, _stream()))
+
+
+def peak_mfma(bf16, out, iters):
+    _check(_lib.nsl_peak_mfma(int(bf16), _ptr(out), out.numel() // 256, iters, _stream()))
 
 
 def render_config(t_near, dt, n_samples, stop_T=0.0) -> RenderConfig:

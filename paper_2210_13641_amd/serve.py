@@ -2,8 +2,12 @@
 
 The mapping thread keeps training while it renders for visualisation
 (Sec. 3.3).  Requests (pose, intrinsics, image size) arrive at any time.
-Each is admitted when its output buffers fit the memory budget, bound to the
-parameter snapshot current at admission, and cut into 64-pixel tiles.  Every
+Each is admitted when its output buffers -- and, for the first request bound
+to a parameter snapshot, that snapshot -- fit the memory budget, bound to
+the parameter snapshot current at admission, and cut into 64-pixel tiles.
+The budget defaults to the device memory free when the server starts, less
+a reserve for the training step; a request that could never fit is
+rejected (NSL_E_BUDGET) and the loop goes on.  Every
 launch of nsl_render_batch packs tiles from all admitted requests, so a
 request that arrives while others are rendering joins the next launch
 instead of waiting for them to finish.  Because each tile reads its own
@@ -15,7 +19,9 @@ parameters plus their MFMA operands, taken on the training stream after a
 step and made visible to the render stream through an event.
 
 Latency is measured from the request's scheduled arrival to a timing event
-recorded on the render stream after the launch that holds its last tile.
+recorded on the render stream after the launch that holds its last tile;
+it splits into queueing (arrival to admission, host clock) and service
+(admission to completion).
 """
 from __future__ import annotations
 
@@ -68,6 +74,8 @@ class Request:
     next_pixel: int = 0
     done_event: torch.cuda.Event = None
     latency: float = None
+    admitted: float = None    # host seconds of admission
+    error: int = 0            # nsl status: E_BUDGET when the request can never fit
     slot: int = -1
 
     @property
@@ -75,14 +83,27 @@ class Request:
         return self.H * self.W
 
 
+def free_memory_budget(device, reserve_bytes):
+    """Device memory free now, less a reserve (the training step's
+    workspace and whatever else the caller will still allocate)."""
+    free, _ = torch.cuda.mem_get_info(device)
+    return max(0, int(free) - int(reserve_bytes))
+
+
 class RenderServer:
-    def __init__(self, field: nsl.Field, cfg: nsl.RenderConfig, device, budget_bytes=1 << 30,
+    def __init__(self, field: nsl.Field, cfg: nsl.RenderConfig, device, budget_bytes=None, reserve_bytes=0,
                  tiles_per_launch=2048, max_inflight=2, keep_snapshots=False):
+        """budget_bytes: memory the server may hold for outputs and request
+        snapshots (None: free device memory at start, less reserve_bytes)."""
         self.field, self.cfg, self.device = field, cfg, device
         self.keep_snapshots = keep_snapshots
         self.launch_sizes = []                    # (requests, tiles) per launch
-        self.budget = budget_bytes
+        self.budget = free_memory_budget(device, reserve_bytes) if budget_bytes is None else int(budget_bytes)
         self.used = 0
+        self.peak_used = 0
+        self.rejected = []
+        self.held = []                            # admitted requests whose memory is not yet released
+        self.admission_log = []                   # per admission: (requests held, snapshot versions held)
         self.tiles_per_launch = tiles_per_launch
         self.max_inflight = max_inflight
         self.stream = torch.cuda.Stream(device)
@@ -115,6 +136,8 @@ class RenderServer:
 
     def _release(self, snap):
         snap.refs -= 1
+        if snap.refs == 0:                        # its last request finished
+            self.used -= snap.nbytes
 
     # -- requests -----------------------------------------------------------
     def submit(self, rid, arrival, pose, intr, H, W):
@@ -123,13 +146,19 @@ class RenderServer:
     def _admit(self, now):
         while self.pending and self.pending[0].arrival <= now:
             r = self.pending[0]
-            need = r.n_pixels * OUT_BYTES_PER_PIXEL
-            if need > self.budget:
-                raise nsl.NslError(nsl.E_BUDGET, f"request {r.rid} needs {need} B, budget {self.budget} B")
-            if self.used + need > self.budget:
+            out_bytes = r.n_pixels * OUT_BYTES_PER_PIXEL
+            snap_bytes = self.snap.nbytes if self.snap.refs == 0 else 0   # charged to its first request
+            if out_bytes + self.snap.nbytes > self.budget:                # can never fit
+                self.pending.popleft()
+                r.error = nsl.E_BUDGET
+                self.rejected.append(r)
+                continue
+            if self.used + out_bytes + snap_bytes > self.budget:
                 break                              # wait for memory to free up
             self.pending.popleft()
-            self.used += need
+            self.used += out_bytes + snap_bytes
+            self.peak_used = max(self.peak_used, self.used)
+            r.admitted = now
             n = r.n_pixels
             dev = self.device
             with torch.cuda.stream(self.stream):
@@ -137,6 +166,8 @@ class RenderServer:
                          torch.empty(n, device=dev)]
             r.snap = self.snap
             r.snap.refs += 1
+            self.held.append(r)
+            self.admission_log.append((len(self.held), len({h.snap.version for h in self.held})))
             self.stream.wait_event(r.snap.ready)
             self.active.append(r)
 
@@ -198,6 +229,7 @@ class RenderServer:
                 done = self.origin_event.elapsed_time(r.done_event) / 1e3
                 r.latency = done - r.arrival
                 self.used -= r.n_pixels * OUT_BYTES_PER_PIXEL
+                self.held.remove(r)
                 self._release(r.snap)
                 if not self.keep_snapshots:
                     r.snap = None
@@ -226,15 +258,18 @@ class RenderServer:
             self._poll(block=not self.active and not self.pending)
 
 
-def serve(field, cfg, device, requests, params, train_fn=None, train_period=5e-3, budget_bytes=1 << 30,
-          tiles_per_launch=2048, warmup=0, keep_snapshots=False):
+def serve(field, cfg, device, requests, params, train_fn=None, train_period=5e-3, budget_bytes=None,
+          reserve_bytes=0, tiles_per_launch=2048, warmup=0, keep_snapshots=False):
     """Run the loop over `requests` (dicts with arrival, pose [12], intr [4],
     H, W).  train_fn() queues one training step on the current stream (the
     loop makes its training stream current); it is called every
-    train_period seconds of host time.  Returns the server, the finished
-    requests (with latency) and run statistics."""
+    train_period seconds of host time.  The memory budget is budget_bytes,
+    or the free device memory at start less reserve_bytes.  Returns the
+    server, the finished requests (with latency) and run statistics;
+    rejected requests are in srv.rejected."""
     train_stream = torch.cuda.Stream(device)
-    srv = RenderServer(field, cfg, device, budget_bytes, tiles_per_launch, keep_snapshots=keep_snapshots)
+    srv = RenderServer(field, cfg, device, budget_bytes, reserve_bytes, tiles_per_launch,
+                       keep_snapshots=keep_snapshots)
     srv.publish(params, train_stream)
     for i, q in enumerate(requests):
         srv.submit(i, q["arrival"], q["pose"], q["intr"], q["H"], q["W"])
@@ -265,8 +300,22 @@ def serve(field, cfg, device, requests, params, train_fn=None, train_period=5e-3
     def pct(p):
         return lat[min(len(lat) - 1, int(round(p / 100.0 * (len(lat) - 1))))] if lat else None
 
+    def pcts(xs):
+        xs = sorted(xs)
+        if not xs:
+            return None
+        at = lambda p: xs[min(len(xs) - 1, int(round(p / 100.0 * (len(xs) - 1))))]
+        return {"p50_ms": 1e3 * at(50), "p99_ms": 1e3 * at(99), "n": len(xs)}
+
+    by_size = {}
+    for r in measured:
+        by_size.setdefault(f"{r.W}x{r.H}", []).append(r.latency)
     stats = dict(requests=len(measured), p50_ms=1e3 * pct(50) if lat else None,
                  p99_ms=1e3 * pct(99) if lat else None, rays_per_s=pix / span if span > 0 else None,
                  train_steps=steps, wall_s=wall, launches=len(srv.launch_sizes),
-                 max_requests_per_launch=max((a for a, _ in srv.launch_sizes), default=0))
+                 max_requests_per_launch=max((a for a, _ in srv.launch_sizes), default=0),
+                 queueing=pcts([r.admitted - r.arrival for r in measured]),
+                 service=pcts([r.arrival + r.latency - r.admitted for r in measured]),
+                 latency_by_size={k: pcts(v) for k, v in sorted(by_size.items())},
+                 budget_bytes=srv.budget, peak_used_bytes=srv.peak_used, rejected=len(srv.rejected))
     return srv, done, stats

@@ -12,13 +12,17 @@ import pytest
 import workloads as W
 from oracle import field as ofield
 
-HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "nsl.h")
+INCLUDE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+HEADER = os.path.join(INCLUDE, "nsl.h")
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(nsl_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for h in sorted(os.listdir(INCLUDE)):
+        if h.endswith(".h"):
+            text = re.sub(r"/\*.*?\*/", "", open(os.path.join(INCLUDE, h)).read(), flags=re.S)
+            names |= set(re.findall(r"\b(nsl_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_every_declared_symbol_is_exported(nsl):
@@ -98,6 +102,25 @@ def test_host_side_errors(nsl):
     rc = lib.nsl_field_fwd(f.handle, odd, fake, fake, 16, fake, fake, fake, need, None)
     assert rc == nsl.E_INVALID and b"16-byte" in lib.nsl_last_error()
     assert lib.nsl_field_prepare_mixed(f.handle, fake, odd, None) == nsl.E_INVALID
+    # the loss and the encoding on their own
+    nl = lib.nsl_loss_workspace_bytes(5)
+    assert nl >= 40 and lib.nsl_loss_workspace_bytes(-1) == 0
+    rc = lib.nsl_loss_fwd(fake, 5, fake, fake, fake, fake, 1.0, fake, None, fake, nl - 1, None)
+    assert rc == nsl.E_WORKSPACE
+    assert lib.nsl_loss_fwd(fake, 0, fake, fake, fake, fake, 1.0, fake, None, fake, nl, None) == nsl.E_INVALID
+    assert lib.nsl_loss_bwd(fake, 5, fake, None, fake, fake, 1.0, None, fake, None) == nsl.E_INVALID
+    assert lib.nsl_encode_fwd(f.handle, fake, fake, -1, fake, None) == nsl.E_INVALID
+    assert lib.nsl_encode_fwd_mixed(f.handle, odd, fake, 4, fake, None) == nsl.E_INVALID
+    ne = lib.nsl_encode_bwd_workspace_bytes(f.handle, 64)
+    assert ne > lib.nsl_encode_bwd_workspace_bytes(f.handle, 16) > 0
+    assert lib.nsl_encode_bwd(f.handle, fake, 64, fake, 0, 0, fake, fake, ne - 1, None) == nsl.E_WORKSPACE
+    assert lib.nsl_encode_bwd(f.handle, fake, 64, fake, 7, 0, fake, fake, ne, None) == nsl.E_INVALID
+    assert lib.nsl_encode_bwd(f.handle, fake, 64, fake, 0, 0, odd, fake, ne, None) == nsl.E_INVALID
+    # machine-peak probes validate their shapes
+    assert lib.nsl_peak_copy(fake, fake, 24, None) == nsl.E_INVALID
+    assert lib.nsl_peak_gather(fake, 20, fake, 100, 16, None) == nsl.E_INVALID
+    assert lib.nsl_peak_gather(fake, 20, fake, 256, 15, None) == nsl.E_INVALID
+    assert lib.nsl_peak_mfma(1, None, 4, 10, None) == nsl.E_INVALID
 
 
 def test_workspace_queries_scale(nsl):

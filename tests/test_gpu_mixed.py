@@ -217,3 +217,49 @@ def test_mixed_error_along_training(nsl, gpu, n_cams):
     torch.cuda.synchronize()
     st = state.cpu().numpy()
     report(f"  final loss scale {st[0]:.0f}, skipped steps {st[2]:.0f}")
+
+
+def test_mixed_training_tracks_fp32(nsl, gpu):
+    """Mixed-precision and plain FP32 training of the tiny field from the
+    same start on the same 2^18-sample batches (8 cameras of 32x32, 32
+    samples per ray), 100 Adam steps each: the mixed loss stays within 5% of
+    the FP32 loss at every 10th step and within 2% at step 100, and both fall
+    by at least 10%.  Both curves are reported."""
+    import dataclasses
+    import torch
+    dev = gpu
+    spec = W.C1_FIELD
+    n_cams = 8
+    kf = W.c4_keyframes(n_cams)
+    ids = W.c1_pixels(K=n_cams)
+    sampler = dataclasses.replace(W.C1_SAMPLER, max_samples=n_cams * 1024 * 32)
+    f = nsl.Field(spec)
+    lay = f.layout
+    flat, _, _ = params_for(spec, lay, seed=0)
+    m = upload_keyframes(nsl, torch, kf, dev)
+    idt = _t(torch, dev, ids.view(np.int32))
+    curves = {}
+    for name, prec in (("mixed", nsl.PRECISION_MIXED), ("fp32", nsl.PRECISION_FP32)):
+        P = _t(torch, dev, flat)
+        G, M, V = torch.zeros_like(P), torch.zeros_like(P), torch.zeros_like(P)
+        st = torch.tensor([2.0 ** 15, 0.0, 0.0, 0.0], device=dev)
+        cfg = nsl.step_config(sampler, precision=prec, scale_state=st if prec == nsl.PRECISION_MIXED else None,
+                              zero_grads=False, do_adam=True, lr=W.ADAM_LR, betas=W.ADAM_BETAS, eps=W.ADAM_EPS,
+                              keep_encoding=True)
+        ws = torch.empty(nsl.step_workspace_bytes(f, cfg, len(ids)), dtype=torch.uint8, device=dev)
+        hist = torch.zeros(100, 3, device=dev)
+        for k in range(100):
+            cfg.adam_step = k + 1
+            nsl.train_step(m, f, P, G, M, V, cfg, idt, ws, hist[k])
+        torch.cuda.synchronize()
+        curves[name] = hist[:, 0].cpu().numpy().astype(np.float64)
+        if prec == nsl.PRECISION_MIXED:
+            report(f"  mixed: final loss scale {st[0].item():.0f}, skipped steps {st[2].item():.0f}")
+    lm, lf = curves["mixed"], curves["fp32"]
+    report("mixed vs FP32 training loss (tiny field, 2^18 samples): " +
+           " ".join(f"{k + 1}:{lm[k]:.5f}/{lf[k]:.5f}" for k in (0, 9, 19, 29, 39, 49, 59, 69, 79, 89, 99)))
+    rel = np.abs(lm - lf) / lf
+    assert rel[0] < 1e-2
+    assert np.all(rel[9::10] < 5e-2), rel[9::10]
+    assert rel[99] < 2e-2, rel[99]
+    assert lf[99] < 0.9 * lf[0] and lm[99] < 0.9 * lm[0]

@@ -279,7 +279,9 @@ def _step_gpu(nsl, torch, dev, spec, sampler, kf, ids, flat, occ=None, grid_res=
     return out
 
 
-def _compare_step(spec, g, o, lay, tol=TOL):
+def _compare_step(spec, g, o, lay, tol=TOL, grad_scale=1.0):
+    """Every output, loss term and gradient of a GPU step against the oracle
+    step; returns the relative L2 errors of the gradients."""
     R = o["R"]
     assert g["stats"][0] == R and g["stats"][1] == o["S"]
     sel = o["sel"]
@@ -294,15 +296,16 @@ def _compare_step(spec, g, o, lay, tol=TOL):
     assert g["loss"][0] == pytest.approx(o["loss"], rel=tol)
     assert g["loss"][1] == pytest.approx(o["loss_rgb"], rel=tol)
     assert g["loss"][2] == pytest.approx(o["loss_d"], rel=tol)
-    gtab, gws = split_grads(g["grads"], lay, spec)
+    gtab, gws = split_grads(g["grads"] / grad_scale, lay, spec)
     covered = np.zeros(len(g["grads"]), bool)
     covered[:lay["table_floats"]] = True
     for off, (a, b) in zip(lay["w_offsets"], spec.mlp_dims()):
         covered[off:off + a * b] = True
     assert np.all(g["grads"][~covered] == 0)        # the padding between blocks is cleared as well
-    check_mag("grad table", gtab, o["grad_table"], o["grad_table_mag"], tol)
+    rels = [check_mag("grad table", gtab, o["grad_table"], o["grad_table_mag"], tol)]
     for j in range(len(gws)):
-        check_mag(f"grad W{j}", gws[j], o["grad_w"][j], o["grad_w_mag"][j], tol)
+        rels.append(check_mag(f"grad W{j}", gws[j], o["grad_w"][j], o["grad_w_mag"][j], tol))
+    return rels
 
 
 def test_step_tiny_workload(nsl, torch_dev):
@@ -347,6 +350,32 @@ def test_step_paper_scale(nsl, torch_dev):
     o = ostep.train_step(spec, sampler, kf, t64, w64, ids, occupancy=occ)
     report(f"  R={o['R']} S={o['S']} ambiguous ReLU units={o['n_amb']}")
     _compare_step(spec, g, o, f.layout)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("table_range", [1e-4, 0.3], ids=["init", "trained-like"])
+def test_mixed_step_paper_scale(nsl, torch_dev, table_range):
+    """The headline configuration against the FP64 oracle: the paper-scale
+    step in mixed precision (FP16 table copy, BF16 MLP on MFMA, BF16
+    table-gradient records, FP32 sums) with the encoding kept from the
+    forward and the gradients overwritten, loss scale 2^15; every rendered
+    output, the loss terms and every table and weight gradient element at
+    2e-2 of the oracle's magnitudes, the oracle's ReLU units within 2e-2 of
+    their magnitude of zero taking either side."""
+    torch, dev = torch_dev
+    scene, occ, kf = c2_inputs()
+    report(f"mixed step: paper scale, keep_encoding, table range {table_range}")
+    spec, sampler = W.C2_FIELD, W.C2_SAMPLER
+    ids = W.c2_candidates(4096)
+    f = nsl.Field(spec)
+    flat, t64, w64 = params_for(spec, f.layout, seed=0, table_range=table_range)
+    g = _step_gpu(nsl, torch, dev, spec, sampler, kf, ids, flat, occ=occ, grid_res=128, keep_encoding=True,
+                  mixed=True, zero_grads=True)
+    o = ostep.train_step(spec, sampler, kf, t64, w64, ids, occupancy=occ, band=2e-2)
+    rels = _compare_step(spec, g, o, f.layout, tol=2e-2, grad_scale=2.0 ** 15)
+    units = o["S"] * (64 + 64 + 64)
+    report(f"  R={o['R']} S={o['S']} ambiguous ReLU units {o['n_amb']} of {units}; rel L2 error of gradients "
+           "(table, W0..W4): " + " ".join(f"{x:.2e}" for x in rels))
 
 
 @pytest.mark.parametrize("mixed", [False, True], ids=["fp32", "mixed"])

@@ -311,3 +311,39 @@ def test_composite_magnitudes_bound_field_errors(opaque):
             assert np.all(np.abs(got - base) <= tol * mag * (1 + 1e-6) + 1e-300), (k, (got - base) / (tol * mag))
         fm0 = render.composite_magnitudes(fw, t, dl, sigma, colour, colour, tol)
         assert fm["D"] >= fm0["D"] and fm["A"] >= fm0["A"] and np.all(fm["C"] >= fm0["C"])
+
+
+def test_adam_magnitudes_bound_input_errors():
+    """Adam's result magnitudes: moving g, m and v by up to tol times their
+    magnitudes moves theta, m and v by at most tol times the magnitudes of
+    the results, over five chained steps; for all-positive inputs the
+    coherent move of m and v uses their whole bound (the recursions have no
+    cancellation), so a magnitude too large fails."""
+    from oracle import step
+    rng = np.random.default_rng(4)
+    n, tol = 2000, 1e-7
+    lr, b1, b2, eps = 1e-2, 0.9, 0.99, 1e-15
+    for positive in (False, True):
+        th = rng.normal(size=n)
+        m = rng.normal(size=n) * 0.1
+        v = rng.uniform(0.01, 1.0, n)
+        if positive:
+            m = np.abs(m)
+        Mt, Mm, Mv = np.abs(th), np.abs(m), v.copy()
+        for t in range(1, 6):
+            g = rng.normal(size=n)
+            if positive:
+                g = np.abs(g)
+            Mg = np.abs(g)
+            th1, m1, v1 = step.adam(th, m, v, g, t, lr, b1, b2, eps)
+            Mt1, Mm1, Mv1 = step.adam_magnitudes(th, m, v, g, t, lr, b1, b2, eps, Mt, Mm, Mv, Mg)
+            for k in range(4):
+                mv = (lambda: np.ones(n)) if k == 0 else (lambda: rng.uniform(-1, 1, n))
+                th2, m2, v2 = step.adam(th + mv() * tol * Mt, m + mv() * tol * Mm, v + mv() * tol * Mv,
+                                        g + mv() * tol * Mg, t, lr, b1, b2, eps)
+                for nm, a, b, M in (("theta", th2, th1, Mt1), ("m", m2, m1, Mm1), ("v", v2, v1, Mv1)):
+                    r = np.abs(a - b) / (tol * M)
+                    assert r.max() <= 1.0 + 1e-5, (positive, t, k, nm, r.max())
+                    if positive and k == 0 and nm in ("m", "v"):
+                        assert r.min() >= 0.99, (t, nm, r.min())
+            th, m, v, Mt, Mm, Mv = th1, m1, v1, Mt1, Mm1, Mv1
