@@ -19,7 +19,8 @@
  *  - All device memory is owned by the caller and passed as plain device
  *    pointers; the library never allocates device memory.  Calls that need
  *    scratch space take a caller workspace whose size a *_workspace_bytes
- *    query returns (NSL_E_WORKSPACE if too small).  Host-side handles
+ *    query returns (NSL_E_WORKSPACE if too small); nsl_render_noalloc uses
+ *    a static device array of the library instead.  Host-side handles
  *    (nsl_field, nsl_mapper) are small host allocations.
  *  - Calls are asynchronous on the given stream; results are valid after the
  *    stream is synchronised.  Pointers must stay valid until then.
@@ -492,6 +493,21 @@ int nsl_render(const nsl_field* f, const float* params, const float* pose, const
                int H, int W, const nsl_render_config* cfg, float* rgb, float* depth_z,
                float* var_z, float* opacity, void* workspace, size_t workspace_bytes,
                hipStream_t stream);
+
+/* nsl_render without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The scratch it needs (the prepared
+ * MFMA operands and one request record: nsl_render_workspace_bytes, at most
+ * 77 056 bytes for the supported field shapes) lives in a static device
+ * array of the library, one per GPU, held until the process ends; a field
+ * whose scratch would exceed it is rejected with NSL_E_WORKSPACE.  The
+ * caller still passes the outputs.  No device memory is allocated, and
+ * nothing in the scratch needs to start at zero.  Calls that overlap on one
+ * GPU (on different streams, or from different threads) share that array
+ * and race: serialise them. */
+int nsl_render_noalloc(const nsl_field* f, const float* params, const float* pose, const float* intr,
+                       int H, int W, const nsl_render_config* cfg, float* rgb, float* depth_z,
+                       float* var_z, float* opacity, hipStream_t stream);
 
 #ifdef __cplusplus
 }

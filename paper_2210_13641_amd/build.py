@@ -17,7 +17,7 @@ OUT = os.path.join(HERE, "libnsl.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["api.cpp", "field.hip", "march.hip", "composite.hip", "misc.hip", "cov.hip", "field_mixed.hip",
-           "scatter.hip", "peaks.hip"]
+           "scatter.hip", "peaks.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = [

@@ -934,6 +934,20 @@ int nsl_render(const nsl_field* f, const float* params, const float* pose, const
   return render_image(f, params, pose, intr, H, W, c, rgb, depth, var, opacity, ws, st);
 }
 
+int nsl_render_noalloc(const nsl_field* f, const float* params, const float* pose, const float* intr, int H, int W,
+                       const nsl_render_config* c, float* rgb, float* depth, float* var, float* opacity,
+                       hipStream_t st) {
+  int rc = check_render_args(f, params, pose, intr, H, W, c, rgb, depth, var);
+  if (rc) return rc;
+  const size_t need = nsl_render_workspace_bytes(f, H, W, c);
+  if (need > noalloc_scratch_bytes())
+    return fail(NSL_E_WORKSPACE, "render needs %zu bytes of scratch, the static scratch holds %zu", need,
+                noalloc_scratch_bytes());
+  void* ws = nullptr;
+  HIP_TRY(noalloc_scratch(&ws), "static scratch address");
+  return render_image(f, params, pose, intr, H, W, c, rgb, depth, var, opacity, ws, st);
+}
+
 // ---------------------------------------------------------------------------
 // Covariances
 // ---------------------------------------------------------------------------

@@ -220,6 +220,11 @@ hipError_t loss_terms(const float* out6, int R, const float* rgb_target, const f
                       const float* ray_scale, float lambda_d, const float* g_loss, float* parts, float* g_out,
                       uint32_t* n_masked, hipStream_t st);
 
+// noalloc.hip: the static device scratch of nsl_render_noalloc (its size,
+// and its address on the current device, looked up once per device).
+size_t noalloc_scratch_bytes();
+hipError_t noalloc_scratch(void** out);
+
 // peaks.hip: machine-peak probes (not part of the step)
 hipError_t peak_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 hipError_t peak_gather(const uint32_t* table, int log2_entries, uint32_t* out, int n_threads, int loads,

@@ -105,6 +105,7 @@ _sig("nsl_field_prepared_bytes", _sz, [_vp])
 _sig("nsl_field_prepare", _i, [_vp, _vp, _vp, _vp])
 _sig("nsl_render_batch", _i, [_vp, _vp, _i, _vp, _i, C.POINTER(RenderConfig), _vp])
 _sig("nsl_render", _i, [_vp, _vp, _vp, _vp, _i, _i, C.POINTER(RenderConfig), _vp, _vp, _vp, _vp, _vp, _sz, _vp])
+_sig("nsl_render_noalloc", _i, [_vp, _vp, _vp, _vp, _i, _i, C.POINTER(RenderConfig), _vp, _vp, _vp, _vp, _vp])
 
 _sig("nsl_mixed_shadow_bytes", _sz, [_vp])
 _sig("nsl_field_prepare_mixed", _i, [_vp, _vp, _vp, _vp])
@@ -449,6 +450,15 @@ def render(field: Field, params, pose, intr, H, W, cfg: RenderConfig, ws, rgb=No
     _check(_lib.nsl_render(field.handle, _dev(params, torch.float32), _dev(pose, torch.float32),
                            _dev(intr, torch.float32), H, W, C.byref(cfg), _ptr(rgb), _ptr(depth), _ptr(var),
                            _ptr(opacity), _ptr(ws), ws.numel(), _stream()))
+    return rgb, depth, var, opacity
+
+
+def render_noalloc(field: Field, params, pose, intr, H, W, cfg: RenderConfig, rgb, depth, var, opacity=None):
+    """nsl_render_noalloc: the library's static scratch instead of a
+    workspace; every output is the caller's."""
+    _check(_lib.nsl_render_noalloc(field.handle, _dev(params, torch.float32), _dev(pose, torch.float32),
+                                   _dev(intr, torch.float32), H, W, C.byref(cfg), _ptr(rgb), _ptr(depth), _ptr(var),
+                                   _ptr(opacity), _stream()))
     return rgb, depth, var, opacity
 
 
