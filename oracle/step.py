@@ -10,7 +10,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import field, rays, render
+from . import field, mixed, rays, render
 
 
 def forward_samples(spec, sampler, kf, pixel_ids, occupancy=None):
@@ -46,17 +46,29 @@ def field_forward(spec, table, ws, xn, dirs, band=1e-5):
 
 
 def train_step(spec, sampler, kf, table, ws, pixel_ids, occupancy=None, lam=1.0,
-               band=1e-5, g_var=None):
+               band=1e-5, g_var=None, quantised=False, tol=None):
     """One forward+backward pass.  Returns a dict with per-ray outputs
     (rgb, depth_z, var_z, opacity), loss terms and gradients (with
     magnitudes).  ``g_var`` optionally seeds dL/dV*_z per selected ray (the
-    loss itself does not use V*)."""
+    loss itself does not use V*).
+
+    quantised: evaluate the field with the mixed-precision step's
+    quantisation points (``oracle/mixed.py``); band is then the ReLU
+    ambiguity band relative to each unit's own product sums, and tol
+    (default band) the tolerance the magnitudes serve."""
+    tol = band if tol is None else tol
     fs = forward_samples(spec, sampler, kf, pixel_ids, occupancy)
     sel = fs["sel"]
     R = len(sel)
     o64, d64, s64 = rays.rays_fp64(kf.pose, kf.intr, pixel_ids, fs["H"], fs["W"])
     t_all, ray_of, xn = sample_positions(spec, fs["o32"], fs["d32"], fs["ts"], sel)
-    cache = field_forward(spec, table, ws, xn, d64[sel][ray_of], band)
+    if quantised:
+        e, e_m, corners = mixed.encode_fwd(spec, table, xn)
+        sh = field.sh_basis(d64[sel][ray_of], spec.sh_bands)
+        cache = mixed.mlp_fwd(spec, ws, e, e_m, sh, band)
+        cache["corners"] = corners
+    else:
+        cache = field_forward(spec, table, ws, xn, d64[sel][ray_of], band)
     sigma, colour = cache["sigma"], cache["colour"]
     # targets
     k, v, u = rays.split_pixel_ids(pixel_ids, fs["H"], fs["W"])
@@ -77,7 +89,7 @@ def train_step(spec, sampler, kf, table, ws, pixel_ids, occupancy=None, lam=1.0,
         dl = np.full(b - a, sampler.dt)
         fw = render.composite_ray(sigma[a:b], colour[a:b], t_all[a:b], dl)
         fm = render.composite_magnitudes(fw, t_all[a:b], dl, cache["sigma_mag"][a:b], colour[a:b],
-                                         cache["colour_mag"][a:b], band)
+                                         cache["colour_mag"][a:b], tol)
         fws.append(fw)
         fms.append(fm)
         out_rgb[i], out_d[i], out_v[i], out_a[i] = fw["C"], fw["D"], fw["V"], fw["A"]
@@ -98,8 +110,12 @@ def train_step(spec, sampler, kf, table, ws, pixel_ids, occupancy=None, lam=1.0,
             fws[i], colour[a:b], t_all[a:b], np.full(b - a, sampler.dt),
             gC[i], gD[i], gv[i], gC_m[i], gD_m[i], abs(gv[i]), mag=fms[i])
         dsig[a:b], dcol[a:b], dsig_m[a:b], dcol_m[a:b] = ds, dc, dsm, dcm
-    dWs, dWm, de, de_m = field.mlp_bwd(spec, ws, cache, dsig, dsig_m, dcol, dcol_m, band)
-    gtab, gtab_m = field.encode_bwd(spec, cache["corners"], de, de_m, len(table))
+    if quantised:
+        dWs, dWm, de, de_m = mixed.mlp_bwd(spec, cache, dsig, dsig_m, dcol, dcol_m, tol)
+        gtab, gtab_m = mixed.encode_bwd(spec, cache["corners"], xn, de, de_m, len(table))
+    else:
+        dWs, dWm, de, de_m = field.mlp_bwd(spec, ws, cache, dsig, dsig_m, dcol, dcol_m, band)
+        gtab, gtab_m = field.encode_bwd(spec, cache["corners"], de, de_m, len(table))
     return dict(
         sel=sel, counts=fs["counts"], kept=fs["kept"], ray_mask=fs["ray_mask"], R=R, S=S,
         t=t_all, ray_of=ray_of, offsets=offs, xn=xn, sigma=sigma, colour=colour,

@@ -95,6 +95,16 @@ def test_mixed_step_matches_oracle(nsl, gpu):
     for j in range(len(gws)):
         rels.append(check_mag(f"grad W{j}", gws[j], o["grad_w"][j], o["grad_w_mag"][j], TOL))
     report("  rel L2 error of gradients: " + " ".join(f"{x:.2e}" for x in rels))
+    # against the oracle that quantises where the kernels do
+    q = ostep.train_step(spec, sampler, kf, t64, w64, ids, band=4e-3, quantised=True, tol=TOL)
+    assert g["loss"][0] == pytest.approx(q["loss"], rel=TOL)
+    for nm, k in (("rgb", slice(0, 3)), ("depth", 3), ("var", 4), ("opacity", 5)):
+        key = {"rgb": "rgb", "depth": "depth_z", "var": "var_z", "opacity": "opacity"}[nm]
+        check_mag(f"quantised {nm}", g["rays"][sel, k], q[key], q[key + "_mag"], TOL)
+    rq = [check_mag("quantised grad table", gtab, q["grad_table"], q["grad_table_mag"], TOL)]
+    for j in range(len(gws)):
+        rq.append(check_mag(f"quantised grad W{j}", gws[j], q["grad_w"][j], q["grad_w_mag"][j], TOL))
+    report("  against the quantised oracle, rel L2 error of gradients: " + " ".join(f"{x:.2e}" for x in rq))
 
 
 def test_dynamic_loss_scale_skips_overflow(nsl, gpu):

@@ -308,6 +308,22 @@ def _compare_step(spec, g, o, lay, tol=TOL, grad_scale=1.0):
     return rels
 
 
+def worst_ratio(g, o, lay, spec, tol, grad_scale=1.0):
+    """Largest |gpu - oracle| / (tol * max(magnitude, 1e-6 max magnitude)) of
+    the rendered outputs, the table gradient and each weight gradient."""
+    def r(a, b, m):
+        a, b, m = (np.asarray(x, np.float64).ravel() for x in (a, b, m))
+        m = np.abs(m)
+        return float(np.max(np.abs(a - b) / (tol * np.maximum(m, 1e-6 * m.max() + 1e-300)))) if m.size else 0.0
+    sel = o["sel"]
+    rays = g["rays"][sel]
+    gtab, gws = split_grads(g["grads"] / grad_scale, lay, spec)
+    out = [("rgb", r(rays[:, :3], o["rgb"], o["rgb_mag"])), ("depth", r(rays[:, 3], o["depth_z"], o["depth_z_mag"])),
+           ("var", r(rays[:, 4], o["var_z"], o["var_z_mag"])), ("table", r(gtab, o["grad_table"], o["grad_table_mag"]))]
+    out += [(f"W{j}", r(gws[j], o["grad_w"][j], o["grad_w_mag"][j])) for j in range(len(gws))]
+    return " ".join(f"{k} {v:.1e}" for k, v in out)
+
+
 def test_step_tiny_workload(nsl, torch_dev):
     torch, dev = torch_dev
     report("step: tiny workload, 1024 rays x 32 samples")
@@ -376,6 +392,21 @@ def test_mixed_step_paper_scale(nsl, torch_dev, table_range):
     units = o["S"] * (64 + 64 + 64)
     report(f"  R={o['R']} S={o['S']} ambiguous ReLU units {o['n_amb']} of {units}; rel L2 error of gradients "
            "(table, W0..W4): " + " ".join(f"{x:.2e}" for x in rels))
+    # the same step against the oracle that quantises where the kernels do
+    # (FP16 table, BF16 operands and records): only FP32 summation and rare
+    # BF16 ties remain between the two
+    q = ostep.train_step(spec, sampler, kf, t64, w64, ids, occupancy=occ, band=4e-3, quantised=True, tol=2e-2)
+    _compare_step(spec, g, q, f.layout, tol=2e-2, grad_scale=2.0 ** 15)
+    # relative errors against the quantised oracle whose ReLU decisions all
+    # follow the FP64 sign (no midpoints): what remains is FP32 summation and
+    # the decisions that FP32 took the other way
+    q0 = ostep.train_step(spec, sampler, kf, t64, w64, ids, occupancy=occ, band=0.0, quantised=True, tol=2e-2)
+    gtab, gws = split_grads(g["grads"] / 2.0 ** 15, f.layout, spec)
+    rel = lambda a, b: float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+    rq = [rel(gtab, q0["grad_table"])] + [rel(a, b) for a, b in zip(gws, q0["grad_w"])]
+    report(f"  against the quantised oracle: ambiguous ReLU units {q['n_amb']} of {units}; largest error / "
+           f"(tol * magnitude): {worst_ratio(g, q, f.layout, spec, 2e-2, 2.0 ** 15)}; rel L2 error of gradients "
+           "without midpoints: " + " ".join(f"{x:.2e}" for x in rq))
 
 
 @pytest.mark.parametrize("mixed", [False, True], ids=["fp32", "mixed"])

@@ -347,3 +347,107 @@ def test_adam_magnitudes_bound_input_errors():
                     if positive and k == 0 and nm in ("m", "v"):
                         assert r.min() >= 0.99, (t, nm, r.min())
             th, m, v, Mt, Mm, Mv = th1, m1, v1, Mt1, Mm1, Mv1
+
+
+# ----------------------------------------------------------------------------
+# The quantised (mixed-precision) oracle
+# ----------------------------------------------------------------------------
+
+def test_bf16_rounding_matches_the_library_conversion():
+    """round_bf16 equals torch's float32 -> bfloat16 conversion (round to
+    nearest, ties to even) on FP32 values, ties and neighbours of ties
+    included; FP16 rounding is numpy's."""
+    import torch
+    from oracle import mixed
+    rng = np.random.default_rng(0)
+    x = (rng.normal(size=20000) * np.exp(rng.uniform(-30, 30, 20000))).astype(np.float32)
+    bits = x.view(np.uint32)
+    ties = ((bits & ~np.uint32(0xFFFF)) | np.uint32(0x8000)).view(np.float32)      # exactly half-way
+    near = np.concatenate([ties, np.nextafter(ties, np.float32(np.inf)), np.nextafter(ties, np.float32(-np.inf))])
+    for v in (x, near, np.array([0.0, -0.0, 1.0, -1.0, 3.0], np.float32)):
+        want = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+        assert np.array_equal(mixed.round_bf16(v.astype(np.float64)), want)
+    assert np.array_equal(mixed.round_fp16(np.array([1.0 + 2 ** -11, 1.0 + 3 * 2 ** -11])),
+                          np.array([1.0, 1.0 + 2 ** -9]))                             # ties to even
+
+
+def test_quantised_oracle_without_quantisation_is_the_exact_oracle():
+    """With the identity as quantiser and no ambiguity band, the quantised
+    nets and scatter equal the exact ones."""
+    from oracle import mixed
+    ident = lambda a: np.asarray(a, np.float64)
+    for spec in (W.C1_FIELD, W.C2_FIELD):
+        ws, e, sh, dsig, dcol = _mlp_inputs(spec, 37, seed=4)
+        ce = field.mlp_fwd(spec, ws, e, np.abs(e), sh, 0.0)
+        dWe, dWme, dee, deme = field.mlp_bwd(spec, ws, ce, dsig, np.abs(dsig), dcol, np.abs(dcol), 0.0)
+        cq = mixed.mlp_fwd(spec, ws, e, np.abs(e), sh, 0.0, rnd=ident)
+        dWq, dWmq, deq, demq = mixed.mlp_bwd(spec, cq, dsig, np.abs(dsig), dcol, np.abs(dcol), 0.0)
+        for k in ("sigma", "colour", "sigma_mag", "colour_mag"):
+            assert np.array_equal(ce[k], cq[k]), k
+        for a, b in zip(dWe + dWme + [dee, deme], dWq + dWmq + [deq, demq]):
+            assert np.allclose(a, b, rtol=1e-13, atol=0)
+        if spec.levels > 4:
+            continue                                      # the scatter below on the tiny table only
+        rng = np.random.default_rng(1)
+        xn = rng.uniform(size=(37, 3))
+        xn[5:20] = xn[5]                                  # a run of samples in one cell
+        n = field.param_layout(spec)["table_floats"]
+        _, _, corners = field.encode_fwd(spec, np.zeros(n), xn)
+        ge, gme = field.encode_bwd(spec, corners, dee, deme, n)
+        gq, gmq = mixed.encode_bwd(spec, corners, xn, dee, deme, n, rnd=ident)
+        assert np.allclose(gq, ge, rtol=1e-12, atol=1e-15) and np.allclose(gmq, gme, rtol=1e-12, atol=1e-15)
+
+
+def test_quantised_records_against_a_sample_loop():
+    """The BF16 table-gradient records, formed sample by sample: a record per
+    run of consecutive samples of one aligned group of 16 that share a cell,
+    its value the BF16 rounding of the run's sum."""
+    from oracle import mixed
+    spec = W.C1_FIELD
+    rng = np.random.default_rng(6)
+    S = 53
+    xn = rng.uniform(size=(S, 3))
+    xn[10:24] = xn[10] + 1e-4 * rng.uniform(size=(14, 3))          # crosses a group boundary at 16
+    xn[40:44] = xn[40]
+    de = rng.normal(size=(S, 2 * spec.levels))
+    n = field.param_layout(spec)["table_floats"]
+    _, _, corners = field.encode_fwd(spec, np.zeros(n), xn)
+    got, _ = mixed.encode_bwd(spec, corners, xn, de, np.abs(de), n)
+    res, _, _, _ = field.level_layout(spec)
+    want = np.zeros(n)
+    for l, (idx, w) in enumerate(corners):
+        cell, _ = field.cell_coords(xn, res[l])
+        s = 0
+        while s < S:
+            e = s + 1
+            while e < S and e % 16 != 0 and np.array_equal(cell[e], cell[s]):
+                e += 1
+            for c in range(8):
+                for f in range(2):
+                    v = sum(w[c][k] * de[k, 2 * l + f] for k in range(s, e))
+                    want[2 * idx[c][s] + f] += mixed.round_bf16(v)
+            s = e
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-18)
+
+
+def test_quantised_step_within_the_mixed_tolerance_of_the_exact_step():
+    """Cross-check of the two oracles on the tiny workload: the quantised
+    step's outputs, loss and gradients lie within 2e-2 of the exact step's
+    magnitudes (whose ReLU band is 2e-2), and they differ from it (the
+    quantisation is there)."""
+    from oracle import step
+    spec, sampler = W.C1_FIELD, W.C1_SAMPLER
+    kf = W.c1_keyframes()
+    ids = W.random_rays_subset(200, 1024, seed=3)
+    lay = field.param_layout(spec)
+    table, ws = W.init_params(2, lay["table_floats"], spec.mlp_dims(), 0.3)
+    ex = step.train_step(spec, sampler, kf, table, ws, ids, band=2e-2)
+    q = step.train_step(spec, sampler, kf, table, ws, ids, band=4e-3, quantised=True, tol=2e-2)
+    tol = 2e-2
+    for k, m in (("rgb", "rgb_mag"), ("depth_z", "depth_z_mag"), ("var_z", "var_z_mag"), ("opacity", "opacity_mag")):
+        assert np.all(np.abs(q[k] - ex[k]) <= tol * ex[m] + 1e-300), k
+    assert abs(q["loss"] - ex["loss"]) <= tol * ex["loss"]
+    assert np.all(np.abs(q["grad_table"] - ex["grad_table"]) <= tol * ex["grad_table_mag"] + 1e-300)
+    for a, b, m in zip(q["grad_w"], ex["grad_w"], ex["grad_w_mag"]):
+        assert np.all(np.abs(a - b) <= tol * m + 1e-300)
+    assert not np.array_equal(q["grad_table"], ex["grad_table"])
