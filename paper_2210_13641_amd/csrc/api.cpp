@@ -444,17 +444,25 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   const bool prof = g_prof.on;
   auto mark = [&](int i) -> hipError_t { return prof ? hipEventRecord(g_prof.ev[i], st) : hipSuccess; };
   HIP_TRY(mark(0), "profile event");
+  // with the encoding kept (16 levels), the encoding kernel also counts the
+  // table-gradient records per block and bin, onto a cleared histogram
+  const bool counted = c->keep_encoding != 0 && f->cfg.levels == 16;
+  const int64_t hist_words = counted ? (int64_t)b.plan.nblk * b.plan.nbins : 0;
   if (mixed) {
-    // the gradient clearing and the overflow-flag reset ride along the FP16
-    // table copy
+    // the gradient clearing, the histogram clearing and the overflow-flag
+    // reset ride along the FP16 table copy
     HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, b.shadow, c->zero_grads ? grads : nullptr,
-                          total, c->scale_state ? c->scale_state + 3 : nullptr, st),
+                          total, c->scale_state ? c->scale_state + 3 : nullptr, counted ? b.rec.hist : nullptr,
+                          hist_words, st),
             "prep mixed");
   } else {
     if (c->scale_state) HIP_TRY(scale_begin(c->scale_state, st), "loss scale");
     // the table part is overwritten by the table-gradient reduction
     const int64_t z0 = f->lay.table_floats & ~(int64_t)3;
-    if (c->zero_grads) HIP_TRY(fill_zero(grads + z0, total - z0, st), "zero grads");
+    if (c->zero_grads || counted)
+      HIP_TRY(fill_zero(grads + z0, c->zero_grads ? total - z0 : 0, st, reinterpret_cast<float*>(b.rec.hist),
+                        hist_words),
+              "zero grads and histogram");
     HIP_TRY(field_prep(f->shape, params, f->wo, b.wprep, st), "prep weights");
   }
   HIP_TRY(mark(1), "profile event");
@@ -467,10 +475,11 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   src.ecache = b.ecache;
   src.ecache_stride = c->max_samples;
   if (src.ecache) {
+    uint32_t* hist = counted ? b.rec.hist : nullptr;
     if (mixed)
-      HIP_TRY(mixed_encode(f->shape, f->lv, b.shadow, src, c->max_samples, st), "encoding");
+      HIP_TRY(mixed_encode(f->shape, f->lv, b.shadow, src, c->max_samples, hist, b.plan.nbins, st), "encoding");
     else
-      HIP_TRY(field_encode(f->shape, fa, src, c->max_samples, st), "encoding");
+      HIP_TRY(field_encode(f->shape, fa, src, c->max_samples, hist, b.plan.nbins, st), "encoding");
   }
   HIP_TRY(mark(3), "profile event");
   if (mixed)
@@ -498,7 +507,8 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
             "field backward");
   HIP_TRY(mark(6), "profile event");
   float* overflow = c->scale_state ? c->scale_state + 3 : nullptr;  // set by the two gradient writers
-  HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, mixed, c->zero_grads != 0, grads, overflow, st), "table gradient");
+  HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, mixed, c->zero_grads != 0, grads, overflow, st, counted),
+          "table gradient");
   HIP_TRY(mark(7), "profile event");
   const LossSum ls{b.loss_parts, n, c->lambda_d, loss_out};
   HIP_TRY(field_dw_reduce(f->shape, b.partial, kBwdBlocks, f->wo, grads, overflow, &ls, st),
@@ -640,7 +650,7 @@ size_t nsl_mixed_shadow_bytes(const nsl_field* f) {
 int nsl_field_prepare_mixed(const nsl_field* f, const float* params, void* shadow, hipStream_t st) {
   if (!f || !params || !shadow) return fail(NSL_E_INVALID, "null argument");
   if (misaligned(params) || misaligned(shadow)) return fail(NSL_E_INVALID, "params and shadow must be 16-byte aligned");
-  HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, shadow, nullptr, 0, nullptr, st),
+  HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, shadow, nullptr, 0, nullptr, nullptr, 0, st),
           "prepare mixed");
   return NSL_OK;
 }
@@ -752,7 +762,7 @@ int nsl_encode_fwd(const nsl_field* f, const float* params, const float* xn, int
   SampleSrc src{};
   src.xn = xn; src.box = f->box; src.n = S; src.ecache = e_out; src.ecache_stride = S;
   FieldArgs fa{params, nullptr, f->lv};
-  HIP_TRY(field_encode(f->shape, fa, src, S, st), "encoding");
+  HIP_TRY(field_encode(f->shape, fa, src, S, nullptr, 0, st), "encoding");
   return NSL_OK;
 }
 
@@ -764,7 +774,7 @@ int nsl_encode_fwd_mixed(const nsl_field* f, const void* shadow, const float* xn
   if (misaligned(shadow)) return fail(NSL_E_INVALID, "shadow must be 16-byte aligned");
   SampleSrc src{};
   src.xn = xn; src.box = f->box; src.n = S; src.ecache = e_out; src.ecache_stride = S;
-  HIP_TRY(mixed_encode(f->shape, f->lv, shadow, src, S, st), "encoding (mixed)");
+  HIP_TRY(mixed_encode(f->shape, f->lv, shadow, src, S, nullptr, 0, st), "encoding (mixed)");
   return NSL_OK;
 }
 

@@ -167,6 +167,20 @@ __device__ __forceinline__ int row_from_below(int v) {
   return __builtin_amdgcn_update_dpp(0, v, 0x110 + N, 0xF, 0xF, true);
 }
 
+// Whether this lane starts a run of row_cell_runs below (a valid lane whose
+// lower row neighbour is invalid, outside the row or in another cell).
+__device__ __forceinline__ bool row_run_head(const uint32_t cell[3], bool valid) {
+  const int r = threadIdx.x & 15;
+  const int vb = row_from_below<1>((int)valid);  // every DPP read with all lanes active
+  uint32_t cb[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) cb[i] = (uint32_t)row_from_below<1>((int)cell[i]);
+  bool same_below = valid & (r != 0) & (vb != 0);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) same_below &= cb[i] == cell[i];
+  return valid & !same_below;
+}
+
 // Runs of consecutive valid lanes of each 16-lane row whose samples lie in
 // the same grid cell (equal cell coordinates).  Such lanes share all eight
 // corner entries, so one run structure serves every value: a segmented

@@ -92,12 +92,9 @@ __device__ __forceinline__ float2 load_entry(const _Float16* __restrict__ t, uin
   return make_float2((float)v[0], (float)v[1]);
 }
 
-// Trilinear blend of one level's two features at xn.
+// The trilinear blend of a cell's eight corners, in corner order.
 template <class T>
-__device__ __forceinline__ float2 encode_level(const T* __restrict__ table, uint32_t mask, int res, bool dense,
-                                               uint32_t off, const float xn[3]) {
-  Corner8 c;
-  corners(xn[0], xn[1], xn[2], res, dense, mask, off, c);
+__device__ __forceinline__ float2 blend_corners(const T* __restrict__ table, const Corner8& c) {
   float2 v[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) v[k] = load_entry(table, c.idx[k]);
@@ -108,6 +105,15 @@ __device__ __forceinline__ float2 encode_level(const T* __restrict__ table, uint
     a1 += c.w[k] * v[k].y;
   }
   return make_float2(a0, a1);
+}
+
+// Trilinear blend of one level's two features at xn.
+template <class T>
+__device__ __forceinline__ float2 encode_level(const T* __restrict__ table, uint32_t mask, int res, bool dense,
+                                               uint32_t off, const float xn[3]) {
+  Corner8 c;
+  corners(xn[0], xn[1], xn[2], res, dense, mask, off, c);
+  return blend_corners(table, c);
 }
 
 template <class N, class T>
@@ -161,26 +167,73 @@ __host__ __device__ constexpr int encode_grid(int max_samples) {
   return N::L >= 8 ? 16 * ((max_samples + 255) / 256) : (max_samples * N::L + 255) / 256;
 }
 
+// With hist set (16 levels only), the kernel also counts the table-gradient
+// records of its samples per bin of 2^kBinShift entries, exactly as the
+// scatter's counting pass would (a record per corner for the first sample of
+// each run of consecutive samples of an aligned group of 16 that share a
+// cell), and adds them to hist[block][bin] for its two 128-sample blocks;
+// hist must be zero beforehand.  The counting pass of the scatter is then
+// skipped.
+constexpr int kEncodeLevelBins = 72;   // bins a level's entries span (2^19 entries: at most 65)
+
 template <class N, class T, class E>
 __global__ __launch_bounds__(256) void encode_levels_kernel(LevelInfo lv, const T* __restrict__ table, SampleSrc src,
-                                                            E* __restrict__ out, int stride) {
+                                                            E* __restrict__ out, int stride,
+                                                            uint32_t* __restrict__ hist, int nbins) {
   const int S = src.n_dev ? (int)*src.n_dev : src.n;
-  int l, s;
+  int l, s, u = 0;
   if constexpr (N::L == 16) {
     const int per_level = (int)(gridDim.x / 16u);  // workgroups per XCD and level
     const int x = blockIdx.x % 8u, j = blockIdx.x / 8u;
     l = x + 8 * (j / per_level);
-    s = (j % per_level) * 256 + threadIdx.x;
+    u = j % per_level;
+    s = u * 256 + threadIdx.x;
   } else {
     const int gid = blockIdx.x * 256 + threadIdx.x;
     l = gid % N::L;
     s = gid / N::L;
   }
-  if (s >= S) return;
-  float xn[3];
-  load_position(src, s, xn);
-  const float2 v = encode_level(table, lv.table_mask, lv.res[l], (lv.dense_bits >> l) & 1u, lv.offset[l], xn);
-  store_encoding(out + (size_t)l * stride + s, v);
+  const bool valid = s < S;
+  if (N::L != 16 || !hist) {
+    if (!valid) return;
+    float xn[3];
+    load_position(src, s, xn);
+    const float2 v = encode_level(table, lv.table_mask, lv.res[l], (lv.dense_bits >> l) & 1u, lv.offset[l], xn);
+    store_encoding(out + (size_t)l * stride + s, v);
+    return;
+  }
+  __shared__ uint32_t cnt[2][kEncodeLevelBins];
+  for (int i = threadIdx.x; i < 2 * kEncodeLevelBins; i += 256) cnt[i / kEncodeLevelBins][i % kEncodeLevelBins] = 0u;
+  __syncthreads();
+  float xn[3] = {0.5f, 0.5f, 0.5f};
+  if (valid) load_position(src, s, xn);
+  Corner8 c;
+  corners(xn[0], xn[1], xn[2], lv.res[l], (lv.dense_bits >> l) & 1u, lv.table_mask, lv.offset[l], c);
+  if (valid) store_encoding(out + (size_t)l * stride + s, blend_corners(table, c));
+  const uint32_t b0 = lv.offset[l] >> kBinShift;
+  if (row_run_head(c.cell, valid)) {
+    uint32_t* h = cnt[threadIdx.x >> 7];
+    // the two x-neighbour corners (k, k + 1) nearly always share a bin
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+      const uint32_t ba = (c.idx[k] >> kBinShift) - b0, bb = (c.idx[k + 1] >> kBinShift) - b0;
+      if (ba == bb) {
+        atomicAdd(&h[ba], 2u);
+      } else {
+        atomicAdd(&h[ba], 1u);
+        atomicAdd(&h[bb], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  const uint32_t n1 = (uint32_t)lv.res[l] + 1u;
+  const uint32_t size = (lv.dense_bits >> l) & 1u ? n1 * n1 * n1 : lv.table_mask + 1u;
+  const int nb = (int)(((lv.offset[l] + size - 1u) >> kBinShift) - b0) + 1;
+  for (int i = threadIdx.x; i < 2 * nb; i += 256) {
+    const int half = i / nb, k = i % nb;
+    const uint32_t n = cnt[half][k];
+    if (n) atomicAdd(&hist[(size_t)(2 * u + half) * nbins + b0 + k], n);
+  }
 }
 
 // Real orthonormal SH coefficients 4g..4g+3 of direction d (0 beyond NSH).

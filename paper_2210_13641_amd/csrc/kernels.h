@@ -75,8 +75,10 @@ BinPlan bin_plan(uint32_t entries, int levels, int64_t max_samples);
 // gradient (every entry is written, so the caller need not clear it first).
 // overflow (may be null): set to 1.0f when a gradient value the call writes
 // is not finite (the loss-scale overflow flag).
+// counted: rb.hist already holds the record counts (from the encoding).
 hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
-                       bool bf16_values, bool overwrite, float* grad_table, float* overflow, hipStream_t st);
+                       bool bf16_values, bool overwrite, float* grad_table, float* overflow, hipStream_t st,
+                       bool counted = false);
 
 // field.hip
 size_t field_prep_floats(int shape);
@@ -107,8 +109,12 @@ hipError_t loss_sum(const LossSum& ls, hipStream_t st);
 // ls (may be null): the step's loss is summed by the same launch.
 hipError_t field_dw_reduce(int shape, const float* partial, int nblocks, const WOffsets& wo, float* grads,
                            float* overflow, const LossSum* ls, hipStream_t st);
-// The encoding of every sample of src into src.ecache (FP32 table).
-hipError_t field_encode(int shape, const FieldArgs& a, const SampleSrc& src, int max_samples, hipStream_t st);
+// The encoding of every sample of src into src.ecache (FP32 table).  With
+// hist (16 levels only; nullable), also the table-gradient record counts per
+// 128-sample block and bin, added to hist[nblk][nbins], which must be zero:
+// bin_scatter can then skip its counting pass.
+hipError_t field_encode(int shape, const FieldArgs& a, const SampleSrc& src, int max_samples, uint32_t* hist,
+                        int nbins, hipStream_t st);
 
 struct RenderParams {
   float t_near, dt, stop_T;
@@ -130,13 +136,17 @@ size_t mixed_shadow_bytes(int shape, int64_t table_floats);
 // part is left to bin_scatter's overwrite.  clear_flag (may be null) is set
 // to 0 by the same launch (the loss-scale overflow flag at the start of a
 // step).
+// zero_words (nullable): n_zero_words (a multiple of 4, 16-byte aligned)
+// words cleared by the same launch.
 hipError_t mixed_prepare(int shape, const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
-                         float* zero_grads, int64_t total, float* clear_flag, hipStream_t st);
+                         float* zero_grads, int64_t total, float* clear_flag, uint32_t* zero_words,
+                         int64_t n_zero_words, hipStream_t st);
 hipError_t mixed_forward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
                          float* sigma, float* rgb, hipStream_t st);
-// The encoding of every sample of src into src.ecache (FP16 table, BF16 out).
+// The encoding of every sample of src into src.ecache (FP16 table, BF16 out);
+// hist as for field_encode.
 hipError_t mixed_encode(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
-                        hipStream_t st);
+                        uint32_t* hist, int nbins, hipStream_t st);
 hipError_t mixed_backward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int nblocks,
                           const float* dsigma, const float* drgb, const RecordBuffers& rec, float* partial,
                           const WOffsets& wo, float* grads, hipStream_t st);
@@ -246,7 +256,9 @@ hipError_t adam_update(float* p, float* g, float* m, float* v, int64_t n, float 
 // then halve (overflow) or count clean steps and double after 2000.
 hipError_t scale_begin(float* state, hipStream_t st);
 hipError_t scale_end(float* state, hipStream_t st);
-hipError_t fill_zero(float* p, int64_t n, hipStream_t st);
+// p[0, n) = 0 and, in the same launch, q[0, m) = 0 (q nullable); both
+// 16-byte aligned.
+hipError_t fill_zero(float* p, int64_t n, hipStream_t st, float* q = nullptr, int64_t m = 0);
 // Writes one request record to device memory (taken by value at launch),
 // with its pose [12] and intrinsics [4] read from device memory.
 hipError_t store_request(const nsl_render_request* r, const float* pose, const float* intr,

@@ -533,11 +533,13 @@ BinPlan bin_plan(uint32_t entries, int levels, int64_t max_samples) {
 }
 
 hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
-                       bool bf16_values, bool overwrite, float* grad_table, float* overflow, hipStream_t st) {
+                       bool bf16_values, bool overwrite, float* grad_table, float* overflow, hipStream_t st,
+                       bool counted) {
   if (p.nbins == 0 || p.nblk == 0) return hipSuccess;
   float* zero_table = overwrite ? grad_table : nullptr;
   const size_t bins_lds = (size_t)p.nbins * sizeof(uint32_t);
-  hipLaunchKernelGGL(bin_count_kernel, dim3(p.nblk), dim3(kRecThreads), bins_lds, st, src, lv, rb, p.nbins);
+  if (!counted)
+    hipLaunchKernelGGL(bin_count_kernel, dim3(p.nblk), dim3(kRecThreads), bins_lds, st, src, lv, rb, p.nbins);
   hipLaunchKernelGGL(bin_colscan_kernel, dim3(colscan_grid(p.nbins)), dim3(kColBins * kColGroups), 0, st, rb,
                      p.nbins, p.nblk);
   hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins);
