@@ -55,9 +55,9 @@ def kernel_work(spec, table_bytes):
       field_fwd   the forward MLP;
       field_bwd   the MLP recomputed and its adjoint (input and weight
                   gradients);
-      table_grad  the table-gradient scatter, 8 x L x F FP32 values (five
-                  kernels: bin count, column scan, bin starts, placement,
-                  reduction)."""
+      table_grad  the table-gradient scatter, 8 x L x F FP32 values (four
+                  kernels: column scan, bin starts, placement, reduction; the
+                  encoding kernel counts the records per bin as it gathers)."""
     fwd_mac, dx_mac, dw_mac = mlp_macs(spec)
     n = 8 * spec.levels * spec.feat_per_level
     return {"encode": dict(flops=0, bytes=n * table_bytes),
@@ -80,13 +80,12 @@ def roofline_of(name, work, samples, ms, mlp_peak):
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_paper_scale.md")
 PMC_SOURCES = ("field.hip", "field_mixed.hip", "field_common.h", "net.h", "common.h", "scatter.hip", "kernels.h")
-BIN_KERNELS = ["nsl::bin_count_kernel", "nsl::bin_colscan_kernel", "nsl::bin_start_kernel",
-               "nsl::bin_place_kernel<nsl::RecBF16, 1, 2>", "nsl::bin_reduce_kernel<nsl::RecBF16>"]
+BIN_KERNELS = ["bin_colscan_kernel", "bin_start_kernel", "bin_place_kernel<RecBF16, 1, 2>",
+               "bin_reduce_kernel<RecBF16>"]
 PMC_ROWS = {("table_grad", 2): BIN_KERNELS,
-            ("field_bwd", 2): ["mixed_bwd_kernel<NetFull>"], ("field_bwd", 4): ["nsl::field_bwd_kernel<NetFull >"],
-            ("field_fwd", 2): ["mixed_fwd_kernel<NetFull>"], ("field_fwd", 4): ["nsl::field_fwd_kernel<NetFull >"],
-            ("encode", 2): ["encode_levels_kernel<NetFull, _Float16, unsigned int>"],
-            ("encode", 4): ["nsl::encode_levels_kernel<NetFull, float, HIP_vector_type<float, 2u> >"]}
+            ("field_bwd", 2): ["mixed_bwd_kernel<NetFull>"],
+            ("field_fwd", 2): ["mixed_fwd_kernel<NetFull>"],
+            ("encode", 2): ["encode_levels_kernel<NetFull, _Float16, unsigned int>"]}
 
 
 def measured_traffic(phase, table_bytes):
@@ -134,7 +133,8 @@ def roofline(spec, phase_ms, samples, table_bytes, mlp_peak):
                                  "profiles/pmc_traffic_paper_scale.md)")
             r["algorithmic_bytes"] = work[k]["bytes"] * samples
         if k == "table_grad":
-            r["kernels"] = "bin_count, bin_colscan, bin_start, bin_place, bin_reduce"
+            r["kernels"] = ("bin_colscan, bin_start, bin_place, bin_reduce (the records are counted by the encoding "
+                            "kernel)")
         all_r[k] = r
     dom = max(work, key=lambda k: phase_ms[k])
     return all_r[dom], all_r
