@@ -66,8 +66,8 @@ RecordBuffers carve_records(Carver& cv, const BinPlan& p) {
   RecordBuffers r{};
   r.de = cv.take<float2>((size_t)p.levels * p.stride);
   r.stride = p.stride;
-  r.hist = cv.take<uint32_t>((size_t)p.nblk * p.nbins);
-  r.off = cv.take<uint32_t>((size_t)p.nblk * p.nbins);
+  r.hist = cv.take<uint32_t>((size_t)p.nbins * p.nunits);
+  r.off = cv.take<uint32_t>((size_t)p.nbins * p.nunits);
   r.bin_total = cv.take<uint32_t>((size_t)p.nbins);
   r.bin_start = cv.take<uint32_t>((size_t)p.nbins + 1);
   r.chunk_start = cv.take<uint32_t>((size_t)p.nbins + 1);
@@ -168,7 +168,7 @@ int nsl_field_layout(const nsl_field_config* c, nsl_param_layout* out) {
     w = al(w + (int64_t)dims[j].first * dims[j].second);
   }
   out->total_floats = w;
-  if (off > (int64_t)kMaxBins * kBinEntries) return fail(NSL_E_INVALID, "table too large (more than 2^25 entries)");
+  if (off > kMaxTableEntries) return fail(NSL_E_INVALID, "table too large (more than 2^25 entries)");
   return NSL_OK;
 }
 
@@ -331,7 +331,7 @@ struct StepBuffers {
 };
 
 BinPlan plan_of(const nsl_field* f, int64_t max_samples) {
-  return bin_plan((uint32_t)(f->lay.table_floats / 2), f->cfg.levels, max_samples);
+  return bin_plan(f->lv, (uint32_t)(f->lay.table_floats / 2), max_samples);
 }
 
 size_t step_carve(const nsl_field* f, int n, int max_samples, bool mixed, bool keep_e, void* base, StepBuffers* b) {
@@ -445,24 +445,20 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   auto mark = [&](int i) -> hipError_t { return prof ? hipEventRecord(g_prof.ev[i], st) : hipSuccess; };
   HIP_TRY(mark(0), "profile event");
   // with the encoding kept (16 levels), the encoding kernel also counts the
-  // table-gradient records per block and bin, onto a cleared histogram
-  const bool counted = c->keep_encoding != 0 && f->cfg.levels == 16;
-  const int64_t hist_words = counted ? (int64_t)b.plan.nblk * b.plan.nbins : 0;
+  // table-gradient records per bin and unit
+  const bool counted =
+      c->keep_encoding != 0 && f->cfg.levels == 16 && b.plan.bl.max_level_bins <= kEncodeLevelBins;
   if (mixed) {
-    // the gradient clearing, the histogram clearing and the overflow-flag
-    // reset ride along the FP16 table copy
+    // the gradient clearing and the overflow-flag reset ride along the FP16
+    // table copy
     HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, b.shadow, c->zero_grads ? grads : nullptr,
-                          total, c->scale_state ? c->scale_state + 3 : nullptr, counted ? b.rec.hist : nullptr,
-                          hist_words, st),
+                          total, c->scale_state ? c->scale_state + 3 : nullptr, st),
             "prep mixed");
   } else {
     if (c->scale_state) HIP_TRY(scale_begin(c->scale_state, st), "loss scale");
     // the table part is overwritten by the table-gradient reduction
     const int64_t z0 = f->lay.table_floats & ~(int64_t)3;
-    if (c->zero_grads || counted)
-      HIP_TRY(fill_zero(grads + z0, c->zero_grads ? total - z0 : 0, st, reinterpret_cast<float*>(b.rec.hist),
-                        hist_words),
-              "zero grads and histogram");
+    if (c->zero_grads) HIP_TRY(fill_zero(grads + z0, total - z0, st), "zero grads");
     HIP_TRY(field_prep(f->shape, params, f->wo, b.wprep, st), "prep weights");
   }
   HIP_TRY(mark(1), "profile event");
@@ -477,9 +473,9 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   if (src.ecache) {
     uint32_t* hist = counted ? b.rec.hist : nullptr;
     if (mixed)
-      HIP_TRY(mixed_encode(f->shape, f->lv, b.shadow, src, c->max_samples, hist, b.plan.nbins, st), "encoding");
+      HIP_TRY(mixed_encode(f->shape, f->lv, b.shadow, src, c->max_samples, hist, b.plan.bl, st), "encoding");
     else
-      HIP_TRY(field_encode(f->shape, fa, src, c->max_samples, hist, b.plan.nbins, st), "encoding");
+      HIP_TRY(field_encode(f->shape, fa, src, c->max_samples, hist, b.plan.bl, st), "encoding");
   }
   HIP_TRY(mark(3), "profile event");
   if (mixed)
@@ -650,7 +646,7 @@ size_t nsl_mixed_shadow_bytes(const nsl_field* f) {
 int nsl_field_prepare_mixed(const nsl_field* f, const float* params, void* shadow, hipStream_t st) {
   if (!f || !params || !shadow) return fail(NSL_E_INVALID, "null argument");
   if (misaligned(params) || misaligned(shadow)) return fail(NSL_E_INVALID, "params and shadow must be 16-byte aligned");
-  HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, shadow, nullptr, 0, nullptr, nullptr, 0, st),
+  HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, shadow, nullptr, 0, nullptr, st),
           "prepare mixed");
   return NSL_OK;
 }
@@ -762,7 +758,7 @@ int nsl_encode_fwd(const nsl_field* f, const float* params, const float* xn, int
   SampleSrc src{};
   src.xn = xn; src.box = f->box; src.n = S; src.ecache = e_out; src.ecache_stride = S;
   FieldArgs fa{params, nullptr, f->lv};
-  HIP_TRY(field_encode(f->shape, fa, src, S, nullptr, 0, st), "encoding");
+  HIP_TRY(field_encode(f->shape, fa, src, S, nullptr, BinLevels{}, st), "encoding");
   return NSL_OK;
 }
 
@@ -774,7 +770,7 @@ int nsl_encode_fwd_mixed(const nsl_field* f, const void* shadow, const float* xn
   if (misaligned(shadow)) return fail(NSL_E_INVALID, "shadow must be 16-byte aligned");
   SampleSrc src{};
   src.xn = xn; src.box = f->box; src.n = S; src.ecache = e_out; src.ecache_stride = S;
-  HIP_TRY(mixed_encode(f->shape, f->lv, shadow, src, S, nullptr, 0, st), "encoding (mixed)");
+  HIP_TRY(mixed_encode(f->shape, f->lv, shadow, src, S, nullptr, BinLevels{}, st), "encoding (mixed)");
   return NSL_OK;
 }
 

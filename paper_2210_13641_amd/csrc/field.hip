@@ -580,19 +580,19 @@ hipError_t render_tiles(int shape, const LevelInfo& lv, const Aabb& box, const n
 }
 
 template <class N>
-static hipError_t launch_encode(const FieldArgs& a, const SampleSrc& src, int max_samples, uint32_t* hist, int nbins,
-                                hipStream_t st) {
+static hipError_t launch_encode(const FieldArgs& a, const SampleSrc& src, int max_samples, uint32_t* hist,
+                                const BinLevels& bl, hipStream_t st) {
   const int grid = encode_grid<N>(max_samples);
   if (grid > 0)
     hipLaunchKernelGGL((encode_levels_kernel<N, float, float2>), dim3(grid), dim3(256), 0, st, a.lv, a.table, src,
-                       static_cast<float2*>(src.ecache), src.ecache_stride, hist, nbins);
+                       static_cast<float2*>(src.ecache), src.ecache_stride, hist, bl);
   return hipGetLastError();
 }
 
 hipError_t field_encode(int shape, const FieldArgs& a, const SampleSrc& src, int max_samples, uint32_t* hist,
-                        int nbins, hipStream_t st) {
-  return shape == kShapeTiny ? launch_encode<NetTiny>(a, src, max_samples, hist, nbins, st)
-                             : launch_encode<NetFull>(a, src, max_samples, hist, nbins, st);
+                        const BinLevels& bl, hipStream_t st) {
+  return shape == kShapeTiny ? launch_encode<NetTiny>(a, src, max_samples, hist, bl, st)
+                             : launch_encode<NetFull>(a, src, max_samples, hist, bl, st);
 }
 
 __global__ __launch_bounds__(256) void loss_sum_kernel(LossSum ls) { loss_sum_block(ls); }

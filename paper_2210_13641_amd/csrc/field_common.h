@@ -167,26 +167,64 @@ __host__ __device__ constexpr int encode_grid(int max_samples) {
   return N::L >= 8 ? 16 * ((max_samples + 255) / 256) : (max_samples * N::L + 255) / 256;
 }
 
-// With hist set (16 levels only), the kernel also counts the table-gradient
-// records of its samples per bin of 2^kBinShift entries, exactly as the
-// scatter's counting pass would (a record per corner for the first sample of
-// each run of consecutive samples of an aligned group of 16 that share a
-// cell), and adds them to hist[block][bin] for its two 128-sample blocks;
-// hist must be zero beforehand.  The counting pass of the scatter is then
-// skipped.
-constexpr int kEncodeLevelBins = 72;   // bins a level's entries span (2^19 entries: at most 65)
+// Workgroup -> (level l, unit u) of the level-major kernels (the encoding
+// with 16 levels, the record counting and placement), unit u being samples
+// [u * kUnitSamples, (u + 1) * kUnitSamples) of level l.  Workgroups are
+// dispatched round-robin over the 8 XCDs, in order: with a multiple of 8
+// levels, XCD x takes level x for every unit, then level x + 8, and so on, so
+// that consecutive units of a level run on one XCD; with other level counts
+// consecutive workgroups take consecutive levels.
+__device__ __forceinline__ void level_unit(int levels, int nunits, int& l, int& u) {
+  if (levels % 8 == 0) {
+    const int x = (int)(blockIdx.x % 8u), j = (int)(blockIdx.x / 8u);
+    l = x + 8 * (j / nunits);
+    u = j % nunits;
+  } else {
+    l = (int)(blockIdx.x % (uint32_t)levels);
+    u = (int)(blockIdx.x / (uint32_t)levels);
+  }
+}
 
+// The table-gradient records of a lane that starts a run (see row_cell_runs:
+// one record per corner, for the first sample of each run of consecutive
+// samples of an aligned group of 16 that share a cell), counted per bin of
+// the level in cnt (LDS): the bin of entry idx is (idx - level_off) >>
+// kBinShift.  The two x-neighbour corners (k, k + 1) nearly always share a
+// bin, and then one atomic counts both.
+__device__ __forceinline__ void count_records(const Corner8& c, bool head, uint32_t level_off, uint32_t* cnt) {
+  if (!head) return;
+#pragma unroll
+  for (int k = 0; k < 8; k += 2) {
+    const uint32_t ba = (c.idx[k] - level_off) >> kBinShift, bb = (c.idx[k + 1] - level_off) >> kBinShift;
+    if (ba == bb) {
+      atomicAdd(&cnt[ba], 2u);
+    } else {
+      atomicAdd(&cnt[ba], 1u);
+      atomicAdd(&cnt[bb], 1u);
+    }
+  }
+}
+
+// The workgroup's counts of level l, unit u into hist[bin][unit].
+__device__ __forceinline__ void write_counts(const BinLevels& bl, int l, int u, const uint32_t* cnt,
+                                             uint32_t* __restrict__ hist) {
+  const int nb = (int)(bl.first[l + 1] - bl.first[l]);
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) hist[(size_t)(bl.first[l] + k) * bl.nunits + u] = cnt[k];
+}
+
+// With hist set (16 levels only), the kernel also counts the table-gradient
+// records of its unit per bin exactly as the scatter's counting pass would,
+// and writes them to hist[bin][unit] (every workgroup writes its row, so hist
+// needs no clearing).  The counting pass of the scatter is then skipped.
 template <class N, class T, class E>
 __global__ __launch_bounds__(256) void encode_levels_kernel(LevelInfo lv, const T* __restrict__ table, SampleSrc src,
                                                             E* __restrict__ out, int stride,
-                                                            uint32_t* __restrict__ hist, int nbins) {
+                                                            uint32_t* __restrict__ hist, BinLevels bl) {
+  static_assert(kUnitSamples == 256, "one sample per thread");
   const int S = src.n_dev ? (int)*src.n_dev : src.n;
   int l, s, u = 0;
   if constexpr (N::L == 16) {
-    const int per_level = (int)(gridDim.x / 16u);  // workgroups per XCD and level
-    const int x = blockIdx.x % 8u, j = blockIdx.x / 8u;
-    l = x + 8 * (j / per_level);
-    u = j % per_level;
+    level_unit(16, (int)(gridDim.x / 16u), l, u);
     s = u * 256 + threadIdx.x;
   } else {
     const int gid = blockIdx.x * 256 + threadIdx.x;
@@ -202,38 +240,17 @@ __global__ __launch_bounds__(256) void encode_levels_kernel(LevelInfo lv, const 
     store_encoding(out + (size_t)l * stride + s, v);
     return;
   }
-  __shared__ uint32_t cnt[2][kEncodeLevelBins];
-  for (int i = threadIdx.x; i < 2 * kEncodeLevelBins; i += 256) cnt[i / kEncodeLevelBins][i % kEncodeLevelBins] = 0u;
+  __shared__ uint32_t cnt[kEncodeLevelBins];
+  for (int i = threadIdx.x; i < kEncodeLevelBins; i += 256) cnt[i] = 0u;
   __syncthreads();
   float xn[3] = {0.5f, 0.5f, 0.5f};
   if (valid) load_position(src, s, xn);
   Corner8 c;
   corners(xn[0], xn[1], xn[2], lv.res[l], (lv.dense_bits >> l) & 1u, lv.table_mask, lv.offset[l], c);
   if (valid) store_encoding(out + (size_t)l * stride + s, blend_corners(table, c));
-  const uint32_t b0 = lv.offset[l] >> kBinShift;
-  if (row_run_head(c.cell, valid)) {
-    uint32_t* h = cnt[threadIdx.x >> 7];
-    // the two x-neighbour corners (k, k + 1) nearly always share a bin
-#pragma unroll
-    for (int k = 0; k < 8; k += 2) {
-      const uint32_t ba = (c.idx[k] >> kBinShift) - b0, bb = (c.idx[k + 1] >> kBinShift) - b0;
-      if (ba == bb) {
-        atomicAdd(&h[ba], 2u);
-      } else {
-        atomicAdd(&h[ba], 1u);
-        atomicAdd(&h[bb], 1u);
-      }
-    }
-  }
+  count_records(c, row_run_head(c.cell, valid), lv.offset[l], cnt);
   __syncthreads();
-  const uint32_t n1 = (uint32_t)lv.res[l] + 1u;
-  const uint32_t size = (lv.dense_bits >> l) & 1u ? n1 * n1 * n1 : lv.table_mask + 1u;
-  const int nb = (int)(((lv.offset[l] + size - 1u) >> kBinShift) - b0) + 1;
-  for (int i = threadIdx.x; i < 2 * nb; i += 256) {
-    const int half = i / nb, k = i % nb;
-    const uint32_t n = cnt[half][k];
-    if (n) atomicAdd(&hist[(size_t)(2 * u + half) * nbins + b0 + k], n);
-  }
+  write_counts(bl, l, u, cnt, hist);
 }
 
 // Real orthonormal SH coefficients 4g..4g+3 of direction d (0 beyond NSH).

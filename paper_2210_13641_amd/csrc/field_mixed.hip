@@ -146,17 +146,12 @@ template <class N>
 __global__ __launch_bounds__(256) void mixed_prepare_kernel(const float* __restrict__ params, WOffsets wo,
                                                             __bf16* __restrict__ ops, _Float16* __restrict__ t16,
                                                             int64_t tf, float* __restrict__ g, int64_t total,
-                                                            int tblocks, int oblocks, float* __restrict__ clear_flag,
-                                                            uint4* __restrict__ zero, int64_t zero_quads) {
+                                                            int tblocks, float* __restrict__ clear_flag) {
   if (clear_flag && blockIdx.x == 0 && threadIdx.x == 0) *clear_flag = 0.0f;
-  if ((int)blockIdx.x < tblocks) {
+  if ((int)blockIdx.x < tblocks)
     table_to_half(params, t16, tf, g, total, ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8);
-  } else if ((int)blockIdx.x < tblocks + oblocks) {
+  else
     prep_operand<N>(params, wo, ops, ((int)blockIdx.x - tblocks) * 256 + (int)threadIdx.x);
-  } else {
-    const int64_t q = ((int64_t)blockIdx.x - tblocks - oblocks) * 256 + threadIdx.x;
-    if (q < zero_quads) zero[q] = make_uint4(0u, 0u, 0u, 0u);
-  }
 }
 
 template <class N>
@@ -781,19 +776,15 @@ size_t mixed_shadow_bytes(int shape, int64_t table_floats) {
 
 template <class N>
 static hipError_t prep_impl(const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
-                            float* zero_grads, int64_t total, float* clear_flag, uint32_t* zero_words,
-                            int64_t n_zero_words, hipStream_t st) {
+                            float* zero_grads, int64_t total, float* clear_flag, hipStream_t st) {
   using M = Mixed<N>;
   const int n = M::FWD + M::BWD;
   _Float16* t16 = reinterpret_cast<_Float16*>(static_cast<char*>(shadow) + mixed_ops_bytes<N>());
   const int64_t span = zero_grads && total > table_floats ? total : table_floats;
   const int tblocks = (int)((span + 2047) / 2048);
   const int oblocks = (n + 255) / 256;
-  const int64_t quads = zero_words ? n_zero_words / 4 : 0;
-  const int zblocks = (int)((quads + 255) / 256);
-  hipLaunchKernelGGL(mixed_prepare_kernel<N>, dim3(tblocks + oblocks + zblocks), dim3(256), 0, st, params, wo,
-                     static_cast<__bf16*>(shadow), t16, table_floats, zero_grads, total, tblocks, oblocks, clear_flag,
-                     reinterpret_cast<uint4*>(zero_words), quads);
+  hipLaunchKernelGGL(mixed_prepare_kernel<N>, dim3(tblocks + oblocks), dim3(256), 0, st, params, wo,
+                     static_cast<__bf16*>(shadow), t16, table_floats, zero_grads, total, tblocks, clear_flag);
   return hipGetLastError();
 }
 
@@ -822,28 +813,25 @@ static hipError_t bwd_impl(const LevelInfo& lv, const void* shadow, const Sample
 
 template <class N>
 static hipError_t encode_impl(const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
-                              uint32_t* hist, int nbins, hipStream_t st) {
+                              uint32_t* hist, const BinLevels& bl, hipStream_t st) {
   const _Float16* t16 = reinterpret_cast<const _Float16*>(static_cast<const char*>(shadow) + mixed_ops_bytes<N>());
   const int grid = encode_grid<N>(max_samples);
   if (grid > 0)
     hipLaunchKernelGGL((encode_levels_kernel<N, _Float16, uint32_t>), dim3(grid), dim3(256), 0, st, lv, t16, src,
-                       static_cast<uint32_t*>(src.ecache), src.ecache_stride, hist, nbins);
+                       static_cast<uint32_t*>(src.ecache), src.ecache_stride, hist, bl);
   return hipGetLastError();
 }
 
 hipError_t mixed_encode(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
-                        uint32_t* hist, int nbins, hipStream_t st) {
-  return shape == kShapeTiny ? encode_impl<NetTiny>(lv, shadow, src, max_samples, hist, nbins, st)
-                             : encode_impl<NetFull>(lv, shadow, src, max_samples, hist, nbins, st);
+                        uint32_t* hist, const BinLevels& bl, hipStream_t st) {
+  return shape == kShapeTiny ? encode_impl<NetTiny>(lv, shadow, src, max_samples, hist, bl, st)
+                             : encode_impl<NetFull>(lv, shadow, src, max_samples, hist, bl, st);
 }
 
 hipError_t mixed_prepare(int shape, const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
-                         float* zero_grads, int64_t total, float* clear_flag, uint32_t* zero_words,
-                         int64_t n_zero_words, hipStream_t st) {
-  return shape == kShapeTiny ? prep_impl<NetTiny>(params, wo, table_floats, shadow, zero_grads, total, clear_flag,
-                                                  zero_words, n_zero_words, st)
-                             : prep_impl<NetFull>(params, wo, table_floats, shadow, zero_grads, total, clear_flag,
-                                                  zero_words, n_zero_words, st);
+                         float* zero_grads, int64_t total, float* clear_flag, hipStream_t st) {
+  return shape == kShapeTiny ? prep_impl<NetTiny>(params, wo, table_floats, shadow, zero_grads, total, clear_flag, st)
+                             : prep_impl<NetFull>(params, wo, table_floats, shadow, zero_grads, total, clear_flag, st);
 }
 
 hipError_t mixed_forward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,

@@ -44,14 +44,28 @@ struct SampleSrc {
 // scatter.hip: table-gradient records and their binned reduction.
 constexpr int kBinShift = 13;                 // 2^13 entries (64 KB of FP32 pairs) per bin
 constexpr int kBinEntries = 1 << kBinShift;
-constexpr int kMaxBins = 4096;                // bins of a table (LDS cursors of the placement)
 constexpr uint32_t kChunk = 65536;            // records per reduce workgroup
+constexpr int64_t kMaxTableEntries = (int64_t)1 << 25;  // all levels together
+constexpr int kUnitSamples = 256;             // samples of one level per counting / placement workgroup
+constexpr int kEncodeLevelBins = 128;         // bins of a level the counting encoding supports (2^20 entries)
+
+// The bins of the table: level l's entries [offset[l], offset[l] + size[l])
+// are cut into bins of kBinEntries entries from the level's first entry (the
+// last one shorter), numbered first[l] .. first[l + 1] - 1 over the table,
+// so no bin spans two levels.  Records are counted and placed per unit of
+// kUnitSamples consecutive samples of one level (nunits units per level).
+struct BinLevels {
+  int levels, nunits, max_level_bins;
+  uint32_t first[kMaxLevels + 1];
+  uint32_t offset[kMaxLevels];
+  uint32_t size[kMaxLevels];
+};
 
 struct RecordBuffers {
   float2* de;             // [levels][stride] dL/de of every sample (two features per level)
   int stride;             // samples per level row of de
-  uint32_t* hist;         // [nblk][nbins] records per block of samples and bin
-  uint32_t* off;          // [nblk][nbins]
+  uint32_t* hist;         // [nbins][nunits] records per bin and unit (unit u of the bin's level)
+  uint32_t* off;          // [nbins][nunits] exclusive prefix of hist over the units
   uint32_t* bin_total;    // [nbins]
   uint32_t* bin_start;    // [nbins + 1]
   uint32_t* chunk_start;  // [nbins + 1]
@@ -65,11 +79,12 @@ struct RecordBuffers {
 
 struct BinPlan {
   uint32_t entries;
-  int nbins, nblk, levels, stride, max_chunks;
+  int nbins, nunits, levels, stride, max_chunks;
   int64_t max_records;
+  BinLevels bl;
 };
 
-BinPlan bin_plan(uint32_t entries, int levels, int64_t max_samples);
+BinPlan bin_plan(const LevelInfo& lv, uint32_t entries, int64_t max_samples);
 // grad_table += the table gradient of the samples of src, from the dL/de
 // that the backward kernel left in rb.de; with overwrite, grad_table = that
 // gradient (every entry is written, so the caller need not clear it first).
@@ -110,11 +125,12 @@ hipError_t loss_sum(const LossSum& ls, hipStream_t st);
 hipError_t field_dw_reduce(int shape, const float* partial, int nblocks, const WOffsets& wo, float* grads,
                            float* overflow, const LossSum* ls, hipStream_t st);
 // The encoding of every sample of src into src.ecache (FP32 table).  With
-// hist (16 levels only; nullable), also the table-gradient record counts per
-// 128-sample block and bin, added to hist[nblk][nbins], which must be zero:
-// bin_scatter can then skip its counting pass.
+// hist (16 levels, at most kEncodeLevelBins bins a level; nullable), also the
+// table-gradient record counts per bin and unit, written to every
+// hist[bin][unit] of bl (no clearing needed): bin_scatter can then skip its
+// counting pass.  bl.nunits must be the units of max_samples.
 hipError_t field_encode(int shape, const FieldArgs& a, const SampleSrc& src, int max_samples, uint32_t* hist,
-                        int nbins, hipStream_t st);
+                        const BinLevels& bl, hipStream_t st);
 
 struct RenderParams {
   float t_near, dt, stop_T;
@@ -136,17 +152,14 @@ size_t mixed_shadow_bytes(int shape, int64_t table_floats);
 // part is left to bin_scatter's overwrite.  clear_flag (may be null) is set
 // to 0 by the same launch (the loss-scale overflow flag at the start of a
 // step).
-// zero_words (nullable): n_zero_words (a multiple of 4, 16-byte aligned)
-// words cleared by the same launch.
 hipError_t mixed_prepare(int shape, const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
-                         float* zero_grads, int64_t total, float* clear_flag, uint32_t* zero_words,
-                         int64_t n_zero_words, hipStream_t st);
+                         float* zero_grads, int64_t total, float* clear_flag, hipStream_t st);
 hipError_t mixed_forward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
                          float* sigma, float* rgb, hipStream_t st);
 // The encoding of every sample of src into src.ecache (FP16 table, BF16 out);
 // hist as for field_encode.
 hipError_t mixed_encode(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
-                        uint32_t* hist, int nbins, hipStream_t st);
+                        uint32_t* hist, const BinLevels& bl, hipStream_t st);
 hipError_t mixed_backward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int nblocks,
                           const float* dsigma, const float* drgb, const RecordBuffers& rec, float* partial,
                           const WOffsets& wo, float* grads, hipStream_t st);
@@ -258,7 +271,7 @@ hipError_t scale_begin(float* state, hipStream_t st);
 hipError_t scale_end(float* state, hipStream_t st);
 // p[0, n) = 0 and, in the same launch, q[0, m) = 0 (q nullable); both
 // 16-byte aligned.
-hipError_t fill_zero(float* p, int64_t n, hipStream_t st, float* q = nullptr, int64_t m = 0);
+hipError_t fill_zero(float* p, int64_t n, hipStream_t st);
 // Writes one request record to device memory (taken by value at launch),
 // with its pose [12] and intrinsics [4] read from device memory.
 hipError_t store_request(const nsl_render_request* r, const float* pose, const float* intr,

@@ -58,17 +58,13 @@ __global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, float*
   }
 }
 
-// Clears p[0, n) and, in the same launch, q[0, m) (blocks past those of p).
-__global__ __launch_bounds__(256) void fill_zero_kernel(float* p, int64_t n, int pblocks, float* q, int64_t m) {
-  const bool second = (int)blockIdx.x >= pblocks;
-  float* dst = second ? q : p;
-  const int64_t len = second ? m : n;
-  const int64_t b = second ? (int64_t)blockIdx.x - pblocks : (int64_t)blockIdx.x;
-  const int64_t i4 = (b * blockDim.x + threadIdx.x) * 4;
-  if (i4 + 4 <= len) {
-    *reinterpret_cast<float4*>(dst + i4) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+// Clears p[0, n).
+__global__ __launch_bounds__(256) void fill_zero_kernel(float* p, int64_t n) {
+  const int64_t i4 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i4 + 4 <= n) {
+    *reinterpret_cast<float4*>(p + i4) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   } else {
-    for (int64_t i = i4; i < len; ++i) dst[i] = 0.0f;
+    for (int64_t i = i4; i < n; ++i) p[i] = 0.0f;
   }
 }
 
@@ -109,12 +105,9 @@ hipError_t adam_update(float* p, float* g, float* m, float* v, int64_t n, float 
   return hipGetLastError();
 }
 
-hipError_t fill_zero(float* p, int64_t n, hipStream_t st, float* q, int64_t m) {
-  if (n < 0) n = 0;
-  if (!q || m < 0) m = 0;
-  const int pblocks = (int)(((n + 3) / 4 + 255) / 256), qblocks = (int)(((m + 3) / 4 + 255) / 256);
-  if (pblocks + qblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)(pblocks + qblocks)), dim3(256), 0, st, p, n, pblocks, q, m);
+hipError_t fill_zero(float* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)(((n + 3) / 4 + 255) / 256)), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 

@@ -6,14 +6,17 @@
 // Sec. 3.3).  Device-coherent atomics on gfx950 retire at roughly one lane
 // per clock per XCD whatever the address pattern, and LDS float atomics at a
 // third of a lane per clock per CU, so the sum is formed by a counting sort
-// into bins of 2^13 consecutive entries and an LDS reduction per bin:
+// into bins of 2^13 consecutive entries of a level and an LDS reduction per
+// bin:
 //
 //   (backward)  dL/de of every sample, level-major [level][sample]
-//   count       per block of samples: records per bin (LDS integer atomics)
-//   scan        per bin, exclusive prefix over blocks; bin totals
+//   count       per unit (256 consecutive samples of one level): records per
+//               bin of the level (LDS integer atomics); or done by the
+//               encoding kernel, which evaluates the same corners
+//   scan        per bin, exclusive prefix over the level's units; bin totals
 //   start       exclusive prefix over bins; chunks of kChunk records per bin
-//   place       the block's records again, ordered by bin in LDS, stored to
-//               their bins' slices
+//   place       per unit, the records again, ordered by bin in LDS and stored
+//               to their bins' slices
 //   reduce      one workgroup per chunk: LDS accumulation of the bin with
 //               64-bit compare-and-swap on (g0, g1) pairs, then grad += acc,
 //               or grad = acc when the step clears its gradients (a bin of
@@ -22,29 +25,30 @@
 //
 // A record is (entry, w * dL/de_l0, w * dL/de_l1), the values in FP32, or in
 // BF16 for the mixed-precision step (accumulated in FP32 all the same).
-// Count and place generate
-// the same records from the sample positions and dL/de: the 16 lanes of a
-// row hold 16 consecutive samples (mostly along one ray) at one level;
-// neighbouring lanes in the same cell form a run, and each run gives eight
-// records (one per corner) carrying the run's sums.
+// Count and place generate the same records from the sample positions and
+// dL/de: the 16 lanes of a row hold 16 consecutive samples (mostly along one
+// ray); neighbouring lanes in the same cell form a run, and each run gives
+// eight records (one per corner) carrying the run's sums.  Both run over the
+// units of a level on one XCD (see level_unit), so the slices that
+// consecutive units place into a bin are adjacent and merge in that XCD's L2.
+#include <algorithm>
+
 #include "field_common.h"
 
 namespace nsl {
 
 namespace {
 
-constexpr int kRecThreads = 512;                     // count and place
-constexpr int kRecWaves = kRecThreads / kWave;
-constexpr int kRecTilesPerWave = 1;
-constexpr int kRecSamples = kRecWaves * kRecTilesPerWave * 16;      // samples per block
-constexpr int kPlaceChunk = kRecWaves * kRecTilesPerWave * 64 * 8;  // records of one level group
-constexpr int kMaxPer = (kMaxBins + kRecThreads - 1) / kRecThreads;  // bins per thread in the placement scan
+constexpr int kUnitWaves = kUnitSamples / kWave;  // count and place: one sample per thread
+constexpr int kColThreads = 256;
 constexpr int kReduceThreads = 1024;
 
-// Record formats: FP32 values (entry, g0, g1), or, for mixed precision,
-// BF16 values (entry, g0 | g1 << 16).  In the sorted array a record keeps
-// only the entry's 16-bit offset in its bin (10 or 6 bytes a record).  Either
-// way the reduction accumulates in FP32.
+// Record formats: FP32 values (key, g0, g1), or, for mixed precision, BF16
+// values (key, g0 | g1 << 16), where key = the bin's index in its level << 16
+// | the entry's offset in the bin.  In the sorted array a record keeps only
+// the 16-bit offset (10 or 6 bytes a record).  Either way the reduction
+// accumulates in FP32.
+static_assert(kBinShift <= 16, "in-bin offsets are 16-bit");
 struct RecF32 {
   typedef uint3 T;
   static __device__ __forceinline__ T pack(uint32_t e, float a, float b) {
@@ -53,8 +57,7 @@ struct RecF32 {
   // In the sorted array a record takes 10 bytes: the entry's 16-bit offset
   // in its bin (the bin is implied by the slot) and the two FP32 values.
   static __device__ __forceinline__ void store(const RecordBuffers& rb, uint32_t pos, const T& r) {
-    static_assert(kBinShift <= 16, "in-bin offsets are 16-bit");
-    static_cast<uint16_t*>(rb.sorted)[pos] = (uint16_t)(r.x & (uint32_t)(kBinEntries - 1));
+    static_cast<uint16_t*>(rb.sorted)[pos] = (uint16_t)(r.x & 0xFFFFu);
     reinterpret_cast<uint2*>(rb.sorted_vals)[pos] = make_uint2(r.y, r.z);
   }
   // the values of the four slots 4 gi .. 4 gi + 3
@@ -81,8 +84,7 @@ struct RecBF16 {
   // In the sorted array a record takes 6 bytes: the entry's offset in its
   // bin (the bin is implied by the slot) and the two BF16 values.
   static __device__ __forceinline__ void store(const RecordBuffers& rb, uint32_t pos, const T& r) {
-    static_assert(kBinShift <= 16, "in-bin offsets are 16-bit");
-    static_cast<uint16_t*>(rb.sorted)[pos] = (uint16_t)(r.x & (uint32_t)(kBinEntries - 1));
+    static_cast<uint16_t*>(rb.sorted)[pos] = (uint16_t)(r.x & 0xFFFFu);
     rb.sorted_vals[pos] = r.y;
   }
   static __device__ __forceinline__ uint32_t key(const T& r) { return r.x; }
@@ -101,160 +103,78 @@ struct RecBF16 {
   }
 };
 
-// The records of one level (l = g + 4q for lane group g) of one tile: the
-// eight corners of this lane's cell with their run sums; on = this lane
-// starts a run of samples in one cell (and is valid).
-struct LevelRecords {
-  uint32_t idx[8];
-  float v0[8], v1[8];
-  bool on;
-};
-
-// dL/de of this lane's levels g + 4q (zero for samples beyond the batch).
-__device__ __forceinline__ void load_de(const float2* __restrict__ de, int stride, int levels, int g, int s,
-                                       bool valid, float2 d[kMaxLevels / 4]) {
-#pragma unroll
-  for (int q = 0; q < kMaxLevels / 4; ++q)
-    d[q] = valid && 4 * q < levels ? de[(size_t)(g + 4 * q) * stride + s] : make_float2(0.0f, 0.0f);
-}
-
-__device__ __forceinline__ void level_records(const LevelInfo& lv, float2 d, int l, bool valid, const float xn[3],
-                                              LevelRecords& r) {
-  Corner8 c;
-  corners(xn[0], xn[1], xn[2], lv.res[l], (lv.dense_bits >> l) & 1u, lv.table_mask, lv.offset[l], c);
-  float v[16];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    v[2 * k] = c.w[k] * d.x;
-    v[2 * k + 1] = c.w[k] * d.y;
-  }
-  r.on = row_cell_runs<16>(c.cell, valid, v) && valid;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    r.idx[k] = c.idx[k];
-    r.v0[k] = v[2 * k];
-    r.v1[k] = v[2 * k + 1];
-  }
-}
-
 __device__ __forceinline__ int sample_count(const SampleSrc& src) { return src.n_dev ? (int)*src.n_dev : src.n; }
 
-// Workgroups are dispatched round-robin over the 8 XCDs.  Block i runs the
-// sample range of logical block (i % 8) * (nblk / 8) + i / 8, so that each
-// XCD walks a contiguous stretch of logical blocks in order; the slices the
-// placement writes into a bin are ordered by logical block, hence the runs
-// that consecutive workgroups of one XCD store are adjacent in memory and
-// meet in that XCD's L2.  nblk is a multiple of 8.
-__device__ __forceinline__ int logical_block(int nblk) {
-  return (int)(blockIdx.x % 8u) * (nblk / 8) + (int)(blockIdx.x / 8u);
+// Entries [e0, e0 + ne) of bin b (b over the whole table).
+__device__ __forceinline__ void bin_entries(const BinLevels& bl, int b, uint32_t& e0, uint32_t& ne) {
+  int l = 0;
+  while (l + 1 < bl.levels && bl.first[l + 1] <= (uint32_t)b) ++l;
+  const uint32_t k = ((uint32_t)b - bl.first[l]) << kBinShift;
+  e0 = bl.offset[l] + k;
+  ne = min((uint32_t)kBinEntries, bl.size[l] - k);
 }
 
-__global__ __launch_bounds__(kRecThreads) void bin_count_kernel(SampleSrc src, LevelInfo lv, RecordBuffers rb,
-                                                               int nbins) {
-  extern __shared__ uint32_t h[];
-  for (int i = threadIdx.x; i < nbins; i += kRecThreads) h[i] = 0u;
+// This thread's sample of unit u of level l: its position (the cell centre of
+// the unit cube for samples beyond the batch) and whether it is one.
+__device__ __forceinline__ bool unit_sample(const SampleSrc& src, int u, int& s, float xn[3]) {
+  s = u * kUnitSamples + (int)threadIdx.x;
+  const bool valid = s < sample_count(src);
+  xn[0] = xn[1] = xn[2] = 0.5f;
+  if (valid) load_position(src, s, xn);
+  return valid;
+}
+
+__global__ __launch_bounds__(kUnitSamples) void bin_count_kernel(SampleSrc src, LevelInfo lv, BinLevels bl,
+                                                                uint32_t* __restrict__ hist) {
+  extern __shared__ uint32_t cnt[];
+  int l, u;
+  level_unit(bl.levels, bl.nunits, l, u);
+  for (int k = threadIdx.x; k < bl.max_level_bins; k += kUnitSamples) cnt[k] = 0u;
   __syncthreads();
-  const int S = sample_count(src);
-  const int blk = logical_block(gridDim.x);
-  const int wave = threadIdx.x / kWave, lane = lane_id(), g = lane >> 4, jc = lane & 15;
-  for (int j = 0; j < kRecTilesPerWave; ++j) {
-    const int tile = (blk * kRecWaves + wave) * kRecTilesPerWave + j;
-    if (tile * 16 >= S) break;
-    const int s = tile * 16 + jc;
-    const bool valid = s < S;
-    float xn[3] = {0.5f, 0.5f, 0.5f};
-    if (valid) load_position(src, s, xn);
-    float2 dl[kMaxLevels / 4];
-    load_de(rb.de, rb.stride, lv.levels, g, s, valid, dl);
-    for (int q = 0; q < lv.levels / 4; ++q) {
-      LevelRecords r;
-      level_records(lv, dl[q], g + 4 * q, valid, xn, r);
-      if (r.on) {
-        // the two x-neighbour corners (k, k + 1) nearly always share a bin:
-        // one atomic counts both
-#pragma unroll
-        for (int k = 0; k < 8; k += 2) {
-          const uint32_t ba = r.idx[k] >> kBinShift, bb = r.idx[k + 1] >> kBinShift;
-          if (ba == bb) {
-            atomicAdd(&h[ba], 2u);
-          } else {
-            atomicAdd(&h[ba], 1u);
-            atomicAdd(&h[bb], 1u);
-          }
-        }
-      }
-    }
-  }
+  int s;
+  float xn[3];
+  const bool valid = unit_sample(src, u, s, xn);
+  Corner8 c;
+  corners(xn[0], xn[1], xn[2], lv.res[l], (lv.dense_bits >> l) & 1u, lv.table_mask, lv.offset[l], c);
+  count_records(c, row_run_head(c.cell, valid), lv.offset[l], cnt);
   __syncthreads();
-  uint32_t* out = rb.hist + (size_t)blk * nbins;
-  for (int i = threadIdx.x; i < nbins; i += kRecThreads) out[i] = h[i];
+  write_counts(bl, l, u, cnt, hist);
 }
 
-// off[b'][b] = sum over blocks b'' < b' of hist[b''][b]; total[b] = sum over
-// all.  A workgroup takes 4 bins and splits the blocks into segments of
-// 256 x kColRows: thread group q (4 threads, one per bin) owns kColRows
-// consecutive blocks of a segment, loads their counts at once and keeps them
-// in registers; the 256 group sums of a bin are scanned by one wave (4 per
-// lane, then a DPP scan), and each thread writes the running prefix over its
-// blocks.  A 128-byte row segment holds 32 bins, read by 8 workgroups: those
-// are placed on one XCD (workgroups go round-robin over the 8 XCDs), so the
-// segment is fetched into one L2 only.
-constexpr int kColBins = 4;
-constexpr int kColGroups = 256;
-constexpr int kColRows = 8;
-__device__ __forceinline__ int colscan_first_bin() {
-  const int x = (int)(blockIdx.x % 8u), j = (int)(blockIdx.x / 8u);
-  return ((j / 8) * 8 + x) * 32 + (j % 8) * kColBins;
-}
-int colscan_grid(int nbins) { return 64 * ((nbins + 255) / 256); }
-
-__global__ __launch_bounds__(kColBins * kColGroups) void bin_colscan_kernel(RecordBuffers rb, int nbins, int nblk) {
-  __shared__ uint32_t part[kColGroups][kColBins];
-  __shared__ uint32_t tot[kColBins];
-  const int bl = threadIdx.x & (kColBins - 1), q = threadIdx.x / kColBins;
-  const int b = colscan_first_bin() + bl;
-  const bool on = b < nbins;
-  const int wave = threadIdx.x / kWave, lane = lane_id();
+// off[b][u] = sum over units u' < u of hist[b][u']; total[b] = sum over all
+// units.  One workgroup per bin; a thread takes four consecutive units.
+__global__ __launch_bounds__(kColThreads) void bin_colscan_kernel(RecordBuffers rb, int nunits) {
+  __shared__ uint32_t wsum[kColThreads / kWave];
+  const int b = (int)blockIdx.x, t = (int)threadIdx.x, wave = t / kWave, lane = lane_id();
+  const uint32_t* __restrict__ h = rb.hist + (size_t)b * nunits;
+  uint32_t* __restrict__ o = rb.off + (size_t)b * nunits;
   uint32_t carry = 0;
-  for (int seg = 0; seg < nblk; seg += kColGroups * kColRows) {
-    const int r0 = seg + q * kColRows;
-    uint32_t v[kColRows], sum = 0;
+  for (int seg = 0; seg < nunits; seg += 4 * kColThreads) {
+    const int i0 = seg + 4 * t;
+    uint32_t v[4], sum = 0;
 #pragma unroll
-    for (int k = 0; k < kColRows; ++k) v[k] = on && r0 + k < nblk ? rb.hist[(size_t)(r0 + k) * nbins + b] : 0u;
-#pragma unroll
-    for (int k = 0; k < kColRows; ++k) sum += v[k];
-    part[q][bl] = sum;
-    __syncthreads();
-    if (wave < kColBins) {
-      // wave w scans bin w: lane l holds groups 4l .. 4l + 3
-      uint32_t g[4], x = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        g[k] = part[4 * lane + k][wave];
-        x += g[k];
-      }
-      const uint32_t incl = wave_incl_scan_u32(x);
-      uint32_t run = incl - x;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        part[4 * lane + k][wave] = run;
-        run += g[k];
-      }
-      if (lane == kWave - 1) tot[wave] = incl;
+    for (int k = 0; k < 4; ++k) {
+      v[k] = i0 + k < nunits ? h[i0 + k] : 0u;
+      sum += v[k];
     }
+    const uint32_t incl = wave_incl_scan_u32(sum);
+    if (lane == kWave - 1) wsum[wave] = incl;
     __syncthreads();
-    uint32_t run = carry + part[q][bl];
-    if (on) {
+    uint32_t run = carry + incl - sum, all = 0;
 #pragma unroll
-      for (int k = 0; k < kColRows; ++k) {
-        if (r0 + k < nblk) rb.off[(size_t)(r0 + k) * nbins + b] = run;
-        run += v[k];
-      }
+    for (int w = 0; w < kColThreads / kWave; ++w) {
+      run += w < wave ? wsum[w] : 0u;
+      all += wsum[w];
     }
-    carry += tot[bl];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (i0 + k < nunits) o[i0 + k] = run;
+      run += v[k];
+    }
+    carry += all;
     __syncthreads();
   }
-  if (on && q == 0) rb.bin_total[b] = carry;
+  if (t == 0) rb.bin_total[b] = carry;
 }
 
 // bin_start = exclusive prefix of the totals, chunk_start = exclusive prefix
@@ -300,149 +220,124 @@ __global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int n
   }
 }
 
-// The block's records, one level group at a time: generated as in the
-// count, ordered by bin in LDS (counting sort with LDS integer atomics), and
-// stored so that the global stores of a wave cover runs of consecutive slots
-// of a few bins instead of one cache line per lane.
+// The unit's records (at most eight a sample), generated as in the count,
+// ordered by bin in LDS (counting sort with LDS integer atomics) and stored
+// so that the global stores of a wave cover runs of consecutive slots of a
+// few bins instead of one cache line per lane.
 //
 // zero_table (overwriting reductions only, else null): the gradient entries of
 // the bins that the reduction will not overwrite (bins with no records, or
 // with several chunks, which add with atomics) are cleared here first.
-template <class R, int G, int PER>
-__global__ __launch_bounds__(kRecThreads) void bin_place_kernel(SampleSrc src, LevelInfo lv, RecordBuffers rb,
-                                                               int nbins, float* __restrict__ zero_table,
-                                                               uint32_t entries) {
-  static_assert(kRecTilesPerWave == 1, "one tile per wave");
+template <class R>
+__global__ __launch_bounds__(kUnitSamples) void bin_place_kernel(SampleSrc src, LevelInfo lv, BinLevels bl,
+                                                                RecordBuffers rb, float* __restrict__ zero_table) {
   typedef typename R::T Rec;
-  // base: slot of the round's record i of bin b is base[b] + i; cnt: the
-  // round's count per bin; lst: its exclusive prefix.  Thread t owns bins
-  // [b0, b1) (at most PER) and keeps their global cursors in registers.
+  // cnt: the unit's records per bin of the level; lst: its exclusive prefix;
+  // base: the slot of the unit's record i of bin k is base[k] + i.
   extern __shared__ uint32_t bins_lds[];
-  uint32_t* base = bins_lds;
-  uint32_t* cnt = bins_lds + nbins;
-  uint32_t* lst = bins_lds + 2 * nbins;
-  __shared__ uint32_t wsum[kRecWaves];
-  __shared__ Rec stage[kPlaceChunk * G];
-  const int t = threadIdx.x;
-  const int blk = logical_block(gridDim.x);
-  const uint32_t* off = rb.off + (size_t)blk * nbins;
-  for (int b = t; b < nbins; b += kRecThreads) cnt[b] = 0u;
-  const int per = (nbins + kRecThreads - 1) / kRecThreads;  // at most PER
-  const int b0 = min(nbins, t * per), b1 = min(nbins, b0 + per);
-  uint32_t cur[PER];
-#pragma unroll
-  for (int k = 0; k < PER; ++k) cur[k] = b0 + k < b1 ? rb.bin_start[b0 + k] + off[b0 + k] : 0u;
+  uint32_t* cnt = bins_lds;
+  uint32_t* lst = bins_lds + bl.max_level_bins;
+  uint32_t* base = bins_lds + 2 * bl.max_level_bins;
+  __shared__ uint32_t wsum[kUnitWaves];
+  __shared__ Rec stage[kUnitSamples * 8];
+  const int t = (int)threadIdx.x, wave = t / kWave, lane = lane_id();
+  int l, u;
+  level_unit(bl.levels, bl.nunits, l, u);
+  const int nb = (int)(bl.first[l + 1] - bl.first[l]);
+  for (int k = t; k < nb; k += kUnitSamples) cnt[k] = 0u;
   if (zero_table) {
-    // two entries (one float4) per thread and step; the table is 16-byte
-    // aligned, an odd last entry is cleared on its own
-    const uint32_t units = (entries + 1) / 2;
-    for (uint32_t u = blockIdx.x * kRecThreads + t; u < units; u += gridDim.x * kRecThreads) {
-      const uint32_t e = 2 * u, bin = e >> kBinShift;
-      if (rb.chunk_start[bin + 1] - rb.chunk_start[bin] == 1u) continue;
-      if (e + 1 < entries)
-        reinterpret_cast<float4*>(zero_table)[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      else
-        reinterpret_cast<float2*>(zero_table)[e] = make_float2(0.0f, 0.0f);
+    const int nbins = (int)bl.first[bl.levels];
+    for (int b = (int)blockIdx.x; b < nbins; b += (int)gridDim.x) {
+      if (rb.chunk_start[b + 1] - rb.chunk_start[b] == 1u) continue;
+      uint32_t e0, ne;
+      bin_entries(bl, b, e0, ne);
+      float2* g = reinterpret_cast<float2*>(zero_table) + e0;
+      for (uint32_t e = t; e < ne; e += kUnitSamples) g[e] = make_float2(0.0f, 0.0f);
     }
   }
-  const int S = sample_count(src);
-  const int wave = t / kWave, lane = lane_id(), g = lane >> 4, jc = lane & 15;
-  const int s = (blk * kRecWaves + wave) * 16 + jc;
-  const bool valid = s < S;
-  float xn[3] = {0.5f, 0.5f, 0.5f};
-  if (valid) load_position(src, s, xn);
-  float2 dl[kMaxLevels / 4];
-  load_de(rb.de, rb.stride, lv.levels, g, s, valid, dl);
+  int s;
+  float xn[3];
+  const bool valid = unit_sample(src, u, s, xn);
+  const float2 d = valid ? rb.de[(size_t)l * rb.stride + s] : make_float2(0.0f, 0.0f);
+  Corner8 c;
+  const uint32_t loff = lv.offset[l];
+  corners(xn[0], xn[1], xn[2], lv.res[l], (lv.dense_bits >> l) & 1u, lv.table_mask, loff, c);
+  float v[16];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    v[2 * k] = c.w[k] * d.x;
+    v[2 * k + 1] = c.w[k] * d.y;
+  }
+  const bool on = row_cell_runs<16>(c.cell, valid, v) && valid;
+  Rec rec[8];
+  uint32_t rank[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t e = c.idx[k] - loff;
+    rec[k] = R::pack(((e >> kBinShift) << 16) | (e & (uint32_t)(kBinEntries - 1)), v[2 * k], v[2 * k + 1]);
+  }
   __syncthreads();
-  const int groups = lv.levels / 4;
-  for (int q0 = 0; q0 < groups; q0 += G) {
-    // G level groups per round: the records in their stored format, off
-    // lanes (and groups beyond the last) holding R::none()
-    Rec rec[G][8];
-    uint32_t rank[G][8];
+  // ranks in the bins; the two x-neighbour corners (k, k + 1) nearly always
+  // share a bin and then take two consecutive ranks from one atomic
+  if (on) {
 #pragma unroll
-    for (int h = 0; h < G; ++h) {
-      const int q = q0 + h;
-      if (q < groups) {
-        LevelRecords r;
-        level_records(lv, dl[q], g + 4 * q, valid, xn, r);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) rec[h][k] = r.on ? R::pack(r.idx[k], r.v0[k], r.v1[k]) : R::none();
+    for (int k = 0; k < 8; k += 2) {
+      const uint32_t ba = R::key(rec[k]) >> 16, bb = R::key(rec[k + 1]) >> 16;
+      if (ba == bb) {
+        rank[k] = atomicAdd(&cnt[ba], 2u);
+        rank[k + 1] = rank[k] + 1u;
       } else {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) rec[h][k] = R::none();
-      }
-      // ranks in the bins; the two x-neighbour corners (k, k + 1) nearly
-      // always share a bin and then take two consecutive ranks from one
-      // atomic (a lane's records are all present or all absent)
-#pragma unroll
-      for (int k = 0; k < 8; k += 2) {
-        if (R::key(rec[h][k]) != 0xFFFFFFFFu) {
-          const uint32_t ba = R::key(rec[h][k]) >> kBinShift, bb = R::key(rec[h][k + 1]) >> kBinShift;
-          if (ba == bb) {
-            rank[h][k] = atomicAdd(&cnt[ba], 2u);
-            rank[h][k + 1] = rank[h][k] + 1u;
-          } else {
-            rank[h][k] = atomicAdd(&cnt[ba], 1u);
-            rank[h][k + 1] = atomicAdd(&cnt[bb], 1u);
-          }
-        }
+        rank[k] = atomicAdd(&cnt[ba], 1u);
+        rank[k + 1] = atomicAdd(&cnt[bb], 1u);
       }
     }
-    __syncthreads();
-    // lst = exclusive prefix of cnt (per-thread runs of bins, a wave scan of
-    // the thread totals, then the totals of the waves before); the owners
-    // of the bins also set base, advance their cursors and clear the counts
-    // for the next round
-    uint32_t c[PER], mine = 0;
+  }
+  __syncthreads();
+  // lst = exclusive prefix of cnt (per-thread runs of bins, a wave scan of
+  // the thread totals, then the totals of the waves before); base from the
+  // bin's first slot and the unit's offset in it
+  const int per = (nb + kUnitSamples - 1) / kUnitSamples;
+  const int b0 = min(nb, t * per), b1 = min(nb, b0 + per);
+  uint32_t mine = 0;
+  for (int k = b0; k < b1; ++k) mine += cnt[k];
+  const uint32_t incl = wave_incl_scan_u32(mine);
+  if (lane == kWave - 1) wsum[wave] = incl;
+  __syncthreads();
+  uint32_t run = incl - mine, m = 0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      c[k] = b0 + k < b1 ? cnt[b0 + k] : 0u;
-      mine += c[k];
-    }
-    const uint32_t incl = wave_incl_scan_u32(mine);
-    if (lane == kWave - 1) wsum[wave] = incl;
-    __syncthreads();
-    uint32_t run = incl - mine, m = 0;
-    for (int w = 0; w < kRecWaves; ++w) {
-      run += w < wave ? wsum[w] : 0u;
-      m += wsum[w];
-    }
+  for (int w = 0; w < kUnitWaves; ++w) {
+    run += w < wave ? wsum[w] : 0u;
+    m += wsum[w];
+  }
+  for (int k = b0; k < b1; ++k) {
+    const uint32_t b = bl.first[l] + (uint32_t)k;
+    lst[k] = run;
+    base[k] = rb.bin_start[b] + rb.off[(size_t)b * bl.nunits + u] - run;
+    run += cnt[k];
+  }
+  __syncthreads();
+  if (on) {
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      if (b0 + k < b1) {
-        lst[b0 + k] = run;
-        base[b0 + k] = cur[k] - run;
-        cnt[b0 + k] = 0u;
-        cur[k] += c[k];
-      }
-      run += c[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int h = 0; h < G; ++h)
-#pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (R::key(rec[h][k]) != 0xFFFFFFFFu) stage[lst[R::key(rec[h][k]) >> kBinShift] + rank[h][k]] = rec[h][k];
-    __syncthreads();
-    for (uint32_t i = t; i < m; i += kRecThreads) {
-      const Rec r = stage[i];
-      R::store(rb, base[R::key(r) >> kBinShift] + i, r);
-    }
-    __syncthreads();
+    for (int k = 0; k < 8; ++k) stage[lst[R::key(rec[k]) >> 16] + rank[k]] = rec[k];
+  }
+  __syncthreads();
+  for (uint32_t i = t; i < m; i += kUnitSamples) {
+    const Rec r = stage[i];
+    R::store(rb, base[R::key(r) >> 16] + i, r);
   }
 }
 
 // overwrite: a bin of one chunk stores its sums over every entry (zeros
 // included) instead of adding them to the gradient.
 template <class R>
-__global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffers rb, int nbins, uint32_t entries,
+__global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffers rb, BinLevels bl,
                                                                     float* __restrict__ grad_table,
                                                                     float* __restrict__ overflow, bool overwrite) {
   // (g0, g1) of each entry as one 64-bit word: float pairs are added with
   // LDS 64-bit compare-and-swap, which retires far faster than LDS float
   // atomics on this architecture
   __shared__ unsigned long long acc[kBinEntries];
+  const int nbins = (int)bl.first[bl.levels];
   const uint32_t c = blockIdx.x;
   if (c >= rb.chunk_start[nbins]) return;
   const int b = (int)rb.chunk_bin[c];
@@ -451,7 +346,8 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
   const uint32_t last = min(rb.bin_start[b + 1], first + kChunk);
   for (int i = threadIdx.x; i < kBinEntries; i += kReduceThreads) acc[i] = 0ull;
   __syncthreads();
-  const uint32_t e0 = (uint32_t)b << kBinShift;
+  uint32_t e0, ne;
+  bin_entries(bl, b, e0, ne);
   // adds (a, cc) to entry e of the bin
   auto add = [&](uint32_t e, float a, float cc) {
     unsigned long long seen = acc[e];
@@ -491,7 +387,6 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
   __syncthreads();
   // every gradient value written is checked for the loss-scale overflow flag
   // (for the atomic adds, the value each add leaves)
-  const uint32_t ne = min((uint32_t)kBinEntries, entries - e0);
   float2* gt = reinterpret_cast<float2*>(grad_table) + e0;
   bool bad = false;
   for (uint32_t e = threadIdx.x; e < ne; e += kReduceThreads) {
@@ -520,14 +415,28 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
 
 }  // namespace
 
-BinPlan bin_plan(uint32_t entries, int levels, int64_t max_samples) {
-  BinPlan p;
+BinPlan bin_plan(const LevelInfo& lv, uint32_t entries, int64_t max_samples) {
+  BinPlan p{};
   p.entries = entries;
-  p.nbins = (int)((entries + kBinEntries - 1) / kBinEntries);
-  p.levels = levels;
+  p.levels = lv.levels;
   p.stride = (int)max_samples;
-  p.nblk = (int)((max_samples + kRecSamples - 1) / kRecSamples + 7) / 8 * 8;  // whole rounds over the XCDs
-  p.max_records = max_samples * 8 * levels;
+  p.nunits = (int)((max_samples + kUnitSamples - 1) / kUnitSamples);
+  BinLevels& bl = p.bl;
+  bl.levels = lv.levels;
+  bl.nunits = p.nunits;
+  uint32_t nb = 0;
+  for (int l = 0; l < lv.levels; ++l) {
+    const uint32_t end = l + 1 < lv.levels ? lv.offset[l + 1] : entries;
+    bl.offset[l] = lv.offset[l];
+    bl.size[l] = end - lv.offset[l];
+    bl.first[l] = nb;
+    const int k = (int)((bl.size[l] + kBinEntries - 1) >> kBinShift);
+    nb += (uint32_t)k;
+    bl.max_level_bins = std::max(bl.max_level_bins, k);
+  }
+  bl.first[lv.levels] = nb;
+  p.nbins = (int)nb;
+  p.max_records = max_samples * 8 * lv.levels;
   p.max_chunks = (int)(p.nbins + (p.max_records + kChunk - 1) / kChunk);
   return p;
 }
@@ -535,32 +444,24 @@ BinPlan bin_plan(uint32_t entries, int levels, int64_t max_samples) {
 hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
                        bool bf16_values, bool overwrite, float* grad_table, float* overflow, hipStream_t st,
                        bool counted) {
-  if (p.nbins == 0 || p.nblk == 0) return hipSuccess;
+  if (p.nbins == 0 || p.nunits == 0) return hipSuccess;
   float* zero_table = overwrite ? grad_table : nullptr;
-  const size_t bins_lds = (size_t)p.nbins * sizeof(uint32_t);
+  const dim3 grid(p.levels * p.nunits);
+  const size_t level_lds = (size_t)p.bl.max_level_bins * sizeof(uint32_t);
   if (!counted)
-    hipLaunchKernelGGL(bin_count_kernel, dim3(p.nblk), dim3(kRecThreads), bins_lds, st, src, lv, rb, p.nbins);
-  hipLaunchKernelGGL(bin_colscan_kernel, dim3(colscan_grid(p.nbins)), dim3(kColBins * kColGroups), 0, st, rb,
-                     p.nbins, p.nblk);
+    hipLaunchKernelGGL(bin_count_kernel, grid, dim3(kUnitSamples), level_lds, st, src, lv, p.bl, rb.hist);
+  hipLaunchKernelGGL(bin_colscan_kernel, dim3(p.nbins), dim3(kColThreads), 0, st, rb, p.nunits);
   hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins);
   if (bf16_values) {
-    if (p.nbins <= 2 * kRecThreads)
-      hipLaunchKernelGGL((bin_place_kernel<RecBF16, 1, 2>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv,
-                         rb, p.nbins, zero_table, p.entries);
-    else
-      hipLaunchKernelGGL((bin_place_kernel<RecBF16, 1, kMaxPer>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src,
-                         lv, rb, p.nbins, zero_table, p.entries);
-    hipLaunchKernelGGL(bin_reduce_kernel<RecBF16>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins,
-                       p.entries, grad_table, overflow, overwrite);
+    hipLaunchKernelGGL(bin_place_kernel<RecBF16>, grid, dim3(kUnitSamples), 3 * level_lds, st, src, lv, p.bl, rb,
+                       zero_table);
+    hipLaunchKernelGGL(bin_reduce_kernel<RecBF16>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.bl,
+                       grad_table, overflow, overwrite);
   } else {
-    if (p.nbins <= 2 * kRecThreads)
-      hipLaunchKernelGGL((bin_place_kernel<RecF32, 1, 2>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src, lv,
-                         rb, p.nbins, zero_table, p.entries);
-    else
-      hipLaunchKernelGGL((bin_place_kernel<RecF32, 1, kMaxPer>), dim3(p.nblk), dim3(kRecThreads), 3 * bins_lds, st, src,
-                         lv, rb, p.nbins, zero_table, p.entries);
-    hipLaunchKernelGGL(bin_reduce_kernel<RecF32>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.nbins,
-                       p.entries, grad_table, overflow, overwrite);
+    hipLaunchKernelGGL(bin_place_kernel<RecF32>, grid, dim3(kUnitSamples), 3 * level_lds, st, src, lv, p.bl, rb,
+                       zero_table);
+    hipLaunchKernelGGL(bin_reduce_kernel<RecF32>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.bl,
+                       grad_table, overflow, overwrite);
   }
   return hipGetLastError();
 }
