@@ -75,10 +75,26 @@ __device__ __forceinline__ void corners(float x, float y, float z, int n, bool d
   c.cell[1] = iy;
   c.cell[2] = iz;
   const float gx[2] = {ux, fx}, gy[2] = {uy, fy}, gz[2] = {uz, fz};
+  // grid_index per corner, with the per-axis terms formed once: a dense
+  // index is x + m y + m^2 z, a hashed one (x ^ P1 y ^ P2 z) & mask, and the
+  // upper corner's term is the lower one's plus m, m^2, P1 or P2 (all mod 2^32)
+  uint32_t ty[2], tz[2];
+  if (dense) {
+    const uint32_t m = (uint32_t)n + 1u, m2 = m * m;
+    ty[0] = iy * m;
+    tz[0] = iz * m2;
+    ty[1] = ty[0] + m;
+    tz[1] = tz[0] + m2;
+  } else {
+    ty[0] = iy * kPrime1;
+    tz[0] = iz * kPrime2;
+    ty[1] = ty[0] + kPrime1;
+    tz[1] = tz[0] + kPrime2;
+  }
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const uint32_t cx = k & 1, cy = (k >> 1) & 1, cz = (k >> 2) & 1;
-    c.idx[k] = off + grid_index(ix + cx, iy + cy, iz + cz, n, dense, mask);
+    c.idx[k] = off + (dense ? (ix + cx) + ty[cy] + tz[cz] : ((ix + cx) ^ ty[cy] ^ tz[cz]) & mask);
     c.w[k] = (gx[cx] * gy[cy]) * gz[cz];
   }
 }
