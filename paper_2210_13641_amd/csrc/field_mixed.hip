@@ -693,6 +693,324 @@ __global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(Le
   for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) out[i] = dW[i];
 }
 
+// ---------------------------------------------------------------------------
+// Backward, eight waves a workgroup (two per SIMD).  Each wave runs the
+// forward recompute and the input-gradient chain of one 16-sample tile; the
+// 128 samples of the workgroup's step are staged layer by layer into a
+// shared [feature][sample] buffer (two buffers, used alternately, so one
+// barrier a layer suffices), and each wave adds the products of its share of
+// the layer's weight-gradient tiles over the 128 samples.  A wave then holds
+// a few weight-gradient tiles instead of all of them, which leaves room for
+// two waves on a SIMD.
+// ---------------------------------------------------------------------------
+constexpr int kBwdWaves8 = 8;
+constexpr int kStepSamples = 16 * kBwdWaves8;  // samples of a workgroup step
+constexpr int kSRow = kStepSamples + 8;        // bf16 per staged row (the pad staggers rows over the banks)
+
+// The weight-gradient tiles of layer J (16x16, numbered m * NJ + n) go
+// round-robin over the waves, continuing from the tiles of the layers that
+// come before J in backward order, so that every wave owns about as many.
+template <class N, int J>
+struct OwnAcc {
+  static constexpr int MI = (N::kin(J) + 15) / 16, NJ = (N::kout(J) + 15) / 16, TILES = MI * NJ;
+  static constexpr int before() {
+    int o = 0;
+    for (int i = N::NW - 1; i > J; --i) o += ((N::kin(i) + 15) / 16) * ((N::kout(i) + 15) / 16);
+    return o;
+  }
+  static constexpr int SLOTS = (TILES + kBwdWaves8 - 1) / kBwdWaves8;
+  f4 v[SLOTS];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int k = 0; k < SLOTS; ++k) v[k] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  }
+  // tile of slot k of wave w, or -1
+  static __device__ __forceinline__ int tile(int w, int k) {
+    const int t = (w - before() % kBwdWaves8 + kBwdWaves8) % kBwdWaves8 + k * kBwdWaves8;
+    return t < TILES ? t : -1;
+  }
+  // v += X^T dY over the staged samples, for the tiles wave w owns
+  __device__ __forceinline__ void add(const __bf16* Xs, const __bf16* Ys, int w, int lane) {
+    const int gk = lane >> 4, i = lane & 15;
+#pragma unroll
+    for (int k = 0; k < SLOTS; ++k) {
+      const int t = tile(w, k);
+      if (t < 0) continue;
+      const int m = t / NJ, n = t % NJ;
+      const __bf16* xr = Xs + (16 * m + i) * kSRow + 8 * gk;
+      const __bf16* yr = Ys + (16 * n + i) * kSRow + 8 * gk;
+#pragma unroll
+      for (int c = 0; c < kStepSamples / 32; ++c)
+        v[k] = mfma32(*reinterpret_cast<const bf8*>(xr + 32 * c), *reinterpret_cast<const bf8*>(yr + 32 * c), v[k]);
+    }
+  }
+  // dW (LDS, row-major kin x kout, zeroed) += the owned tiles (disjoint over
+  // the waves, so all waves may write at once)
+  __device__ __forceinline__ void flush(float* dW, int w, int lane) const {
+    const int gk = lane >> 4, i = lane & 15;
+#pragma unroll
+    for (int k = 0; k < SLOTS; ++k) {
+      const int t = tile(w, k);
+      if (t < 0) continue;
+      const int m = t / NJ, n = t % NJ, col = 16 * n + i;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * m + 4 * gk + r;
+        if (row < N::kin(J) && col < N::kout(J)) dW[row * N::kout(J) + col] += v[k][r];
+      }
+    }
+  }
+};
+
+template <class N>
+struct OwnAll {
+  OwnAcc<N, 0> w0;
+  OwnAcc<N, 1> w1;
+  OwnAcc<N, 2> w2;
+  OwnAcc<N, N::NCH == 2 ? 3 : 2> w3;  // second colour hidden layer (unused with one)
+  OwnAcc<N, N::NW - 1> wl;
+};
+
+// One tile's staged values: rows 16m + 4g + r of column c (lane group g).
+template <int MB>
+__device__ __forceinline__ void stage1_packed(uint16_t* S, const bf8* a, int g, int c) {
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) S[(16 * m + 4 * g + r) * kSRow + c] = (uint16_t)bf_bits(a[m >> 1], 4 * (m & 1) + r);
+}
+template <int MB>
+__device__ __forceinline__ void stage1_f32(uint16_t* S, const f4* v, int g, int c) {
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; r += 2) {
+      const uint32_t w = bf16_pair(v[m][r], v[m][r + 1]);
+      S[(16 * m + 4 * g + r) * kSRow + c] = (uint16_t)(w & 0xFFFFu);
+      S[(16 * m + 4 * g + r + 1) * kSRow + c] = (uint16_t)(w >> 16);
+    }
+}
+
+// dL/de of one tile held back one step (as PendingDe).
+template <class N>
+struct PendingDe1 {
+  f4 de[N::bmt(0)];
+  int s;
+  bool valid;
+  __device__ __forceinline__ void store(const RecordBuffers& rec, int g) const {
+    if (!valid) return;
+#pragma unroll
+    for (int q = 0; q < N::LPL; ++q) {
+      const int k0 = 2 * q, k1 = 2 * q + 1;
+      rec.de[(size_t)(g + 4 * q) * rec.stride + s] = make_float2(de[k0 >> 2][k0 & 3], de[k1 >> 2][k1 & 3]);
+    }
+  }
+};
+
+// Staging buffer b of the two: X rows, then Y rows.
+template <class N>
+__device__ __forceinline__ __bf16* stage_x(__bf16* stage, int b) {
+  return stage + b * (N::XROWS + N::YROWS) * kSRow;
+}
+template <class N>
+__device__ __forceinline__ __bf16* stage_y(__bf16* stage, int b) {
+  return stage_x<N>(stage, b) + N::XROWS * kSRow;
+}
+
+// Forward recompute, backward chain and dL/de of this wave's tile (samples
+// s = 128 p + 16 w + jc), with the workgroup's weight-gradient products of
+// each layer in between; the previous tile's dL/de (pend) is stored after the
+// forward and replaced by this tile's.
+template <class N>
+__device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const __bf16* __restrict__ Ab,
+                                          __bf16* stage, int& buf, const TileIn<N>& in, int s, bool valid,
+                                          const RecordBuffers& rec, OwnAll<N>& dw, PendingDe1<N>& pend, int w,
+                                          int lane) {
+  using M = Mixed<N>;
+  constexpr f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  const int g = lane >> 4, jc = lane & 15, c = 16 * w + jc;
+  PActs<N> a[1];
+  f4 sh[1];
+  tile_operands<N>(in, g, a[0], sh[0]);
+  fwd_tiles<N, 1>(Af, lane, sh, a);
+  pend.store(rec, g);
+
+  f4 dz = zero;
+  if (g == 0) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const float cc = sigmoidf(a[0].z[r]);
+      dz[r] = in.dr[r] * cc * (1.0f - cc);
+    }
+  }
+  constexpr int K3 = N::NCH == 2 ? (N::HC / 16) * (N::HC / 32) : 1;
+  constexpr int MT0 = N::bmt(0);
+  bf8 w4[N::HC / 16], w3[K3], w2[N::HC / 32], w1[N::HD / 16], w0[MT0 * (N::HD / 32)];
+  load_ops<N>(Ab + M::boff(N::NW - 1), lane, w4);
+  const bf8* hl = N::NCH == 2 ? a[0].h4 : a[0].h3;
+  // last colour layer
+  f4 dhl[N::HC / 16];
+  {
+    const bf8 b = pack8(dz, zero);
+#pragma unroll
+    for (int m = 0; m < N::HC / 16; ++m) dhl[m] = relu_grad(mfma32(w4[m], b, zero), hl[m >> 1], m & 1);
+  }
+  if constexpr (N::NCH == 2) load_ops<N>(Ab + M::boff(3), lane, w3);
+  else load_ops<N>(Ab + M::boff(2), lane, w2);
+  stage1_packed<N::HC / 16>(reinterpret_cast<uint16_t*>(stage_x<N>(stage, buf)), hl, g, c);
+  stage1_f32<1>(reinterpret_cast<uint16_t*>(stage_y<N>(stage, buf)), &dz, g, c);
+  __syncthreads();
+  dw.wl.add(stage_x<N>(stage, buf), stage_y<N>(stage, buf), w, lane);
+  buf ^= 1;
+  f4 dh3[N::HC / 16];
+  if constexpr (N::NCH == 2) {
+    f4 acc[N::HC / 16];
+#pragma unroll
+    for (int m = 0; m < N::HC / 16; ++m) acc[m] = zero;
+#pragma unroll
+    for (int k = 0; k < N::HC / 32; ++k) {
+      const bf8 b = pack8(dhl[2 * k], dhl[2 * k + 1]);
+#pragma unroll
+      for (int m = 0; m < N::HC / 16; ++m) acc[m] = mfma32(w3[m * (N::HC / 32) + k], b, acc[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < N::HC / 16; ++m) dh3[m] = relu_grad(acc[m], a[0].h3[m >> 1], m & 1);
+    load_ops<N>(Ab + M::boff(2), lane, w2);
+    stage1_packed<N::HC / 16>(reinterpret_cast<uint16_t*>(stage_x<N>(stage, buf)), a[0].h3, g, c);
+    stage1_f32<N::HC / 16>(reinterpret_cast<uint16_t*>(stage_y<N>(stage, buf)), dhl, g, c);
+    __syncthreads();
+    dw.w3.add(stage_x<N>(stage, buf), stage_y<N>(stage, buf), w, lane);
+    buf ^= 1;
+  } else {
+#pragma unroll
+    for (int m = 0; m < N::HC / 16; ++m) dh3[m] = dhl[m];
+  }
+  // first colour layer: gradient of the geometry features
+  f4 dgeo = zero;
+#pragma unroll
+  for (int k = 0; k < N::HC / 32; ++k) dgeo = mfma32(w2[k], pack8(dh3[2 * k], dh3[2 * k + 1]), dgeo);
+  load_ops<N>(Ab + M::boff(1), lane, w1);
+  stage1_packed<2>(reinterpret_cast<uint16_t*>(stage_x<N>(stage, buf)), &a[0].osh, g, c);
+  stage1_f32<N::HC / 16>(reinterpret_cast<uint16_t*>(stage_y<N>(stage, buf)), dh3, g, c);
+  __syncthreads();
+  dw.w2.add(stage_x<N>(stage, buf), stage_y<N>(stage, buf), w, lane);
+  buf ^= 1;
+  if (g == 0) dgeo[0] += expf(a[0].o[0]) * in.ds;
+  // second density layer
+  f4 dh1[N::HD / 16];
+  {
+    const bf8 b = pack8(dgeo, zero);
+#pragma unroll
+    for (int m = 0; m < N::HD / 16; ++m) dh1[m] = relu_grad(mfma32(w1[m], b, zero), a[0].h1[m >> 1], m & 1);
+  }
+  load_ops<N>(Ab + M::boff(0), lane, w0);
+  stage1_packed<N::HD / 16>(reinterpret_cast<uint16_t*>(stage_x<N>(stage, buf)), a[0].h1, g, c);
+  stage1_f32<1>(reinterpret_cast<uint16_t*>(stage_y<N>(stage, buf)), &dgeo, g, c);
+  __syncthreads();
+  dw.w1.add(stage_x<N>(stage, buf), stage_y<N>(stage, buf), w, lane);
+  buf ^= 1;
+  // first density layer: dL/de
+  f4 de[MT0];
+#pragma unroll
+  for (int m = 0; m < MT0; ++m) de[m] = zero;
+#pragma unroll
+  for (int k = 0; k < N::HD / 32; ++k) {
+    const bf8 b = pack8(dh1[2 * k], dh1[2 * k + 1]);
+#pragma unroll
+    for (int m = 0; m < MT0; ++m) de[m] = mfma32(w0[m * (N::HD / 32) + k], b, de[m]);
+  }
+  {
+    uint16_t* X = reinterpret_cast<uint16_t*>(stage_x<N>(stage, buf));
+#pragma unroll
+    for (int k = 0; k < N::NSLOT; ++k) X[fwd_in_feature<N>(0, k, g) * kSRow + c] = (uint16_t)bf_bits(a[0].e, k);
+    if constexpr (N::ENC < 16) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) X[(N::ENC + 2 * g + k) * kSRow + c] = 0;
+    }
+  }
+  stage1_f32<N::HD / 16>(reinterpret_cast<uint16_t*>(stage_y<N>(stage, buf)), dh1, g, c);
+  __syncthreads();
+  dw.w0.add(stage_x<N>(stage, buf), stage_y<N>(stage, buf), w, lane);
+  buf ^= 1;
+  pend.s = s;
+  pend.valid = valid;
+#pragma unroll
+  for (int m = 0; m < MT0; ++m) pend.de[m] = de[m];
+}
+
+// kBwdWaves8 waves per workgroup, two per SIMD; the workgroup takes steps
+// (128 samples) blockIdx.x, blockIdx.x + gridDim.x, ...  With the kept
+// encoding, a wave fetches its next tile's inputs while it computes the
+// current one (ray indices two steps ahead).
+template <class N>
+__global__ __launch_bounds__(kBwdWaves8 * kWave, 1) void mixed_bwd8_kernel(
+    LevelInfo lv, const _Float16* __restrict__ table, const __bf16* __restrict__ prep, SampleSrc src,
+    const float* __restrict__ dsigma, const float* __restrict__ drgb, RecordBuffers rec,
+    float* __restrict__ dw_partial) {
+  using M = Mixed<N>;
+  constexpr int SBUF = (N::XROWS + N::YROWS) * kSRow;
+  static_assert(2 * SBUF * (int)sizeof(__bf16) >= N::NWEIGHTS * (int)sizeof(float),
+                "the weight-gradient sums reuse the staging buffers");
+  __shared__ __attribute__((aligned(16))) __bf16 Af[M::FWD];
+  __shared__ __attribute__((aligned(16))) __bf16 Ab[M::BWD];
+  __shared__ __attribute__((aligned(16))) __bf16 stage[2 * SBUF];
+  load_bf16<N>(Af, prep, M::FWD);
+  load_bf16<N>(Ab, prep + M::FWD, M::BWD);
+  __syncthreads();
+
+  const int S = src.n_dev ? (int)*src.n_dev : src.n;
+  const int w = threadIdx.x / kWave, lane = lane_id(), g = lane >> 4, jc = lane & 15;
+  OwnAll<N> dw;
+  dw.w0.zero(); dw.w1.zero(); dw.w2.zero(); dw.wl.zero();
+  if constexpr (N::NCH == 2) dw.w3.zero();
+  LaneLevels<N> ll;
+  lane_levels<N>(lv, g, ll);
+  PendingDe1<N> pend;
+  pend.valid = false;
+  pend.s = 0;
+  int buf = 0;
+  const int nsteps = (S + kStepSamples - 1) / kStepSamples, step = gridDim.x;
+  const int off = 16 * w + jc;
+  if (src.ecache) {
+    const int p0 = blockIdx.x;
+    TileIn<N> cur;
+    const int s0 = kStepSamples * p0 + off;
+    fetch_tile<N, true>(src, table, lv, ll, dsigma, drgb, s0, s0 < S, g, ray_of<N>(src, s0, S), cur);
+    uint32_t rid1 = ray_of<N>(src, kStepSamples * (p0 + step) + off, S);
+    for (int p = p0; p < nsteps; p += step) {
+      const int s = kStepSamples * p + off;
+      TileIn<N> nxt;
+      const int s1 = s + kStepSamples * step;
+      fetch_tile<N, true>(src, table, lv, ll, dsigma, drgb, s1, s1 < S, g, rid1, nxt);
+      const uint32_t rid2 = ray_of<N>(src, s1 + kStepSamples * step, S);
+      bwd_tile8<N>(Af, Ab, stage, buf, cur, s, s < S, rec, dw, pend, w, lane);
+      cur = nxt;
+      rid1 = rid2;
+    }
+  } else {
+    for (int p = blockIdx.x; p < nsteps; p += step) {
+      const int s = kStepSamples * p + off;
+      TileIn<N> cur;
+      fetch_tile<N, false>(src, table, lv, ll, dsigma, drgb, s, s < S, g, 0u, cur);
+      bwd_tile8<N>(Af, Ab, stage, buf, cur, s, s < S, rec, dw, pend, w, lane);
+    }
+  }
+  pend.store(rec, g);
+  // the workgroup's weight-gradient sums, in the staging space
+  __syncthreads();
+  float* dW = reinterpret_cast<float*>(stage);
+  for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) dW[i] = 0.0f;
+  __syncthreads();
+  dw.w0.flush(dW + N::woff(0), w, lane);
+  dw.w1.flush(dW + N::woff(1), w, lane);
+  dw.w2.flush(dW + N::woff(2), w, lane);
+  if constexpr (N::NCH == 2) dw.w3.flush(dW + N::woff(3), w, lane);
+  dw.wl.flush(dW + N::woff(N::NW - 1), w, lane);
+  __syncthreads();
+  float* out = dw_partial + (size_t)blockIdx.x * N::NWEIGHTS;
+  for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) out[i] = dW[i];
+}
+
 // Forward: density and colour of 16-sample tiles, one tile per wave at a
 // time (four waves per SIMD stay resident, which hides latency better than
 // pairing tiles here).  The grid is a fixed number of workgroups, so the
@@ -806,7 +1124,7 @@ static hipError_t bwd_impl(const LevelInfo& lv, const void* shadow, const Sample
                            const WOffsets& wo, float* grads, hipStream_t st) {
   const __bf16* ops = static_cast<const __bf16*>(shadow);
   const _Float16* t16 = reinterpret_cast<const _Float16*>(static_cast<const char*>(shadow) + mixed_ops_bytes<N>());
-  hipLaunchKernelGGL(mixed_bwd_kernel<N>, dim3(nblocks), dim3(kMixedBwdWaves * kWave), 0, st, lv, t16, ops, src,
+  hipLaunchKernelGGL(mixed_bwd8_kernel<N>, dim3(nblocks), dim3(kBwdWaves8 * kWave), 0, st, lv, t16, ops, src,
                      dsigma, drgb, rec, partial);
   return hipGetLastError();
 }
