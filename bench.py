@@ -80,10 +80,10 @@ def roofline_of(name, work, samples, ms, mlp_peak):
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_paper_scale.md")
 PMC_SOURCES = ("field.hip", "field_mixed.hip", "field_common.h", "net.h", "common.h", "scatter.hip", "kernels.h")
-BIN_KERNELS = ["bin_colscan_kernel", "bin_start_kernel", "bin_place_kernel<RecBF16, 1, 2>",
+BIN_KERNELS = ["bin_colscan_kernel", "bin_start_kernel", "bin_place_kernel<RecBF16>",
                "bin_reduce_kernel<RecBF16>"]
 PMC_ROWS = {("table_grad", 2): BIN_KERNELS,
-            ("field_bwd", 2): ["mixed_bwd_kernel<NetFull>"],
+            ("field_bwd", 2): ["mixed_bwd8_kernel<NetFull>"],
             ("field_fwd", 2): ["mixed_fwd_kernel<NetFull>"],
             ("encode", 2): ["encode_levels_kernel<NetFull, _Float16, unsigned int>"]}
 

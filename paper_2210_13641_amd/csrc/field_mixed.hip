@@ -166,17 +166,10 @@ __device__ __forceinline__ void load_bf16(__bf16* dst, const __bf16* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Backward: two 16-sample tiles per wave step.  Each weight operand read from
-// LDS feeds both tiles' MFMAs, so the two dependency chains overlap on the
-// one wave a SIMD holds.  Activations the backward needs are kept as the BF16
-// operands the next layer consumed; the weight-gradient products contract
-// over the 32 samples of the pair on v_mfma_f32_16x16x32_bf16, staged
-// [feature][sample] with the two tiles interleaved (column 2j + t), so every
-// staging store writes both tiles' values as one 32-bit word.
+// Pieces shared by the forward and backward kernels: the activations of a
+// tile (kept by the backward as the BF16 operands the next layer consumed),
+// its inputs, and the forward of T tiles interleaved layer by layer.
 // ---------------------------------------------------------------------------
-
-constexpr int kPairRow = 40;        // bf16 per staged row: 32 samples + pad
-constexpr int kPairRowW = kPairRow / 2;
 
 template <class N>
 struct PActs {
@@ -346,351 +339,6 @@ __device__ __forceinline__ void tile_operands(const TileIn<N>& in, int g, PActs<
   float shv[4];
   sh_lane<N>(in.d, g, shv);
   sh = f4{shv[0], shv[1], shv[2], shv[3]};
-}
-
-// Staging rows (u32 words: column pair j of row f at f * kPairRowW + j).
-// MB 16-row blocks of a packed activation of the two tiles.
-template <int MB>
-__device__ __forceinline__ void stage_packed(uint32_t* S, const bf8* a0, const bf8* a1, int g, int jc) {
-#pragma unroll
-  for (int m = 0; m < MB; ++m)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int u = 4 * (m & 1) + r;
-      S[(16 * m + 4 * g + r) * kPairRowW + jc] = bf_bits(a0[m >> 1], u) | (bf_bits(a1[m >> 1], u) << 16);
-    }
-}
-template <int MB>
-__device__ __forceinline__ void stage_f32(uint32_t* S, const f4* v0, const f4* v1, int g, int jc) {
-#pragma unroll
-  for (int m = 0; m < MB; ++m)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) S[(16 * m + 4 * g + r) * kPairRowW + jc] = bf16_pair(v0[m][r], v1[m][r]);
-}
-
-// acc += X^T dY over the 32 staged samples.
-template <int KIN, int KOUT>
-__device__ __forceinline__ void dw_pair(const __bf16* Xs, const __bf16* Ys, DWAcc<KIN, KOUT>& acc, int lane) {
-  constexpr int MI = DWAcc<KIN, KOUT>::MI, NJ = DWAcc<KIN, KOUT>::NJ;
-  const int gk = lane >> 4, i = lane & 15;
-  bf8 xa[MI], yb[NJ];
-#pragma unroll
-  for (int m = 0; m < MI; ++m) xa[m] = *reinterpret_cast<const bf8*>(Xs + (16 * m + i) * kPairRow + 8 * gk);
-#pragma unroll
-  for (int n = 0; n < NJ; ++n) yb[n] = *reinterpret_cast<const bf8*>(Ys + (16 * n + i) * kPairRow + 8 * gk);
-#pragma unroll
-  for (int m = 0; m < MI; ++m)
-#pragma unroll
-    for (int n = 0; n < NJ; ++n) acc.v[m * NJ + n] = mfma32(xa[m], yb[n], acc.v[m * NJ + n]);
-}
-
-template <class N>
-struct PairAcc {
-  DWAcc<N::ENC, N::HD> w0;
-  DWAcc<N::HD, 16> w1;
-  DWAcc<N::CIN, N::HC> w2;
-  DWAcc<N::HC, N::HC> w3;  // second colour hidden layer (unused with one)
-  DWAcc<N::HC, 3> wl;
-};
-
-// dL/de of a tile pair held back one pair: stored after the next pair's
-// forward, so the stores are in flight while that pair computes instead of
-// being waited for with the next pair's prefetched inputs.
-template <class N>
-struct PendingDe {
-  f4 de[2][N::bmt(0)];
-  int s[2];
-  bool valid[2];
-  // this lane's levels g + 4q, level-major: the 16 lanes of a row store 16
-  // consecutive samples of one level
-  __device__ __forceinline__ void store(const RecordBuffers& rec, int g) const {
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      if (valid[t]) {
-#pragma unroll
-        for (int q = 0; q < N::LPL; ++q) {
-          const int k0 = 2 * q, k1 = 2 * q + 1;
-          rec.de[(size_t)(g + 4 * q) * rec.stride + s[t]] =
-              make_float2(de[t][k0 >> 2][k0 & 3], de[t][k1 >> 2][k1 & 3]);
-        }
-      }
-    }
-  }
-};
-
-// Forward recompute, backward chain, weight-gradient products and dL/de of
-// one tile pair (tiles t: samples 32p + 16t + jc); the previous pair's
-// dL/de (pend) is stored after the forward and replaced by this pair's.
-template <class N>
-__device__ __forceinline__ void bwd_pair(const __bf16* __restrict__ Af, const __bf16* __restrict__ Ab,
-                                         __bf16* Xs, __bf16* Ys, const TileIn<N> (&in)[2], const int (&s)[2],
-                                         const bool (&valid)[2], const RecordBuffers& rec, PairAcc<N>& dw,
-                                         PendingDe<N>& pend, int lane) {
-  using M = Mixed<N>;
-  constexpr int T = 2;
-  constexpr f4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-  const int g = lane >> 4, jc = lane & 15;
-  uint32_t* Xw = reinterpret_cast<uint32_t*>(Xs);
-  uint32_t* Yw = reinterpret_cast<uint32_t*>(Ys);
-  PActs<N> a[T];
-  f4 sh[T];
-#pragma unroll
-  for (int t = 0; t < T; ++t) tile_operands<N>(in[t], g, a[t], sh[t]);
-  fwd_tiles<N, T>(Af, lane, sh, a);
-  pend.store(rec, g);
-
-  f4 dz[T];
-#pragma unroll
-  for (int t = 0; t < T; ++t) {
-    dz[t] = zero;
-    if (g == 0) {
-#pragma unroll
-      for (int r = 0; r < 3; ++r) {
-        const float c = sigmoidf(a[t].z[r]);
-        dz[t][r] = in[t].dr[r] * c * (1.0f - c);
-      }
-    }
-  }
-  // Each layer's transposed weight operands are read from LDS before the
-  // previous layer's weight-gradient product, whose LDS fences would
-  // otherwise keep the reads waiting in front of the layer's MFMAs.
-  constexpr int K3 = N::NCH == 2 ? (N::HC / 16) * (N::HC / 32) : 1;
-  constexpr int MT0 = N::bmt(0);
-  bf8 w4[N::HC / 16], w3[K3], w2[N::HC / 32], w1[N::HD / 16], w0[MT0 * (N::HD / 32)];
-  load_ops<N>(Ab + M::boff(N::NW - 1), lane, w4);
-  // last colour layer
-  f4 dhl[T][N::HC / 16];
-  {
-    bf8 b[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) b[t] = pack8(dz[t], zero);
-#pragma unroll
-    for (int m = 0; m < N::HC / 16; ++m)
-#pragma unroll
-      for (int t = 0; t < T; ++t)
-        dhl[t][m] = relu_grad(mfma32(w4[m], b[t], zero), N::NCH == 2 ? a[t].h4[m >> 1] : a[t].h3[m >> 1], m & 1);
-  }
-  if constexpr (N::NCH == 2) load_ops<N>(Ab + M::boff(3), lane, w3);
-  else load_ops<N>(Ab + M::boff(2), lane, w2);
-  stage_packed<N::HC / 16>(Xw, N::NCH == 2 ? a[0].h4 : a[0].h3, N::NCH == 2 ? a[1].h4 : a[1].h3, g, jc);
-  stage_f32<1>(Yw, &dz[0], &dz[1], g, jc);
-  wave_lds_fence();
-  dw_pair(Xs, Ys, dw.wl, lane);
-  wave_lds_fence();
-
-  f4 dh3[T][N::HC / 16];
-  if constexpr (N::NCH == 2) {
-    f4 acc[T][N::HC / 16];
-#pragma unroll
-    for (int t = 0; t < T; ++t)
-#pragma unroll
-      for (int m = 0; m < N::HC / 16; ++m) acc[t][m] = zero;
-#pragma unroll
-    for (int k = 0; k < N::HC / 32; ++k) {
-      bf8 b[T];
-#pragma unroll
-      for (int t = 0; t < T; ++t) b[t] = pack8(dhl[t][2 * k], dhl[t][2 * k + 1]);
-#pragma unroll
-      for (int m = 0; m < N::HC / 16; ++m)
-#pragma unroll
-        for (int t = 0; t < T; ++t) acc[t][m] = mfma32(w3[m * (N::HC / 32) + k], b[t], acc[t][m]);
-    }
-#pragma unroll
-    for (int t = 0; t < T; ++t)
-#pragma unroll
-      for (int m = 0; m < N::HC / 16; ++m) dh3[t][m] = relu_grad(acc[t][m], a[t].h3[m >> 1], m & 1);
-    load_ops<N>(Ab + M::boff(2), lane, w2);
-    stage_packed<N::HC / 16>(Xw, a[0].h3, a[1].h3, g, jc);
-    stage_f32<N::HC / 16>(Yw, dhl[0], dhl[1], g, jc);
-    wave_lds_fence();
-    dw_pair(Xs, Ys, dw.w3, lane);
-    wave_lds_fence();
-  } else {
-#pragma unroll
-    for (int t = 0; t < T; ++t)
-#pragma unroll
-      for (int m = 0; m < N::HC / 16; ++m) dh3[t][m] = dhl[t][m];
-  }
-  // first colour layer: gradient of the geometry features
-  f4 dgeo[T];
-  {
-#pragma unroll
-    for (int t = 0; t < T; ++t) dgeo[t] = zero;
-#pragma unroll
-    for (int k = 0; k < N::HC / 32; ++k)
-#pragma unroll
-      for (int t = 0; t < T; ++t) dgeo[t] = mfma32(w2[k], pack8(dh3[t][2 * k], dh3[t][2 * k + 1]), dgeo[t]);
-  }
-  load_ops<N>(Ab + M::boff(1), lane, w1);
-  stage_packed<2>(Xw, &a[0].osh, &a[1].osh, g, jc);
-  stage_f32<N::HC / 16>(Yw, dh3[0], dh3[1], g, jc);
-  wave_lds_fence();
-  dw_pair(Xs, Ys, dw.w2, lane);
-  wave_lds_fence();
-  if (g == 0) {
-#pragma unroll
-    for (int t = 0; t < T; ++t) dgeo[t][0] += expf(a[t].o[0]) * in[t].ds;
-  }
-  // second density layer
-  f4 dh1[T][N::HD / 16];
-  {
-    bf8 b[T];
-#pragma unroll
-    for (int t = 0; t < T; ++t) b[t] = pack8(dgeo[t], zero);
-#pragma unroll
-    for (int m = 0; m < N::HD / 16; ++m)
-#pragma unroll
-      for (int t = 0; t < T; ++t) dh1[t][m] = relu_grad(mfma32(w1[m], b[t], zero), a[t].h1[m >> 1], m & 1);
-  }
-  load_ops<N>(Ab + M::boff(0), lane, w0);
-  stage_packed<N::HD / 16>(Xw, a[0].h1, a[1].h1, g, jc);
-  stage_f32<1>(Yw, &dgeo[0], &dgeo[1], g, jc);
-  wave_lds_fence();
-  dw_pair(Xs, Ys, dw.w1, lane);
-  wave_lds_fence();
-  // first density layer: dL/de
-  f4 de[T][MT0];
-  {
-#pragma unroll
-    for (int t = 0; t < T; ++t)
-#pragma unroll
-      for (int m = 0; m < MT0; ++m) de[t][m] = zero;
-#pragma unroll
-    for (int k = 0; k < N::HD / 32; ++k) {
-      bf8 b[T];
-#pragma unroll
-      for (int t = 0; t < T; ++t) b[t] = pack8(dh1[t][2 * k], dh1[t][2 * k + 1]);
-#pragma unroll
-      for (int m = 0; m < MT0; ++m)
-#pragma unroll
-        for (int t = 0; t < T; ++t) de[t][m] = mfma32(w0[m * (N::HD / 32) + k], b[t], de[t][m]);
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < N::NSLOT; ++k)
-    Xw[fwd_in_feature<N>(0, k, g) * kPairRowW + jc] = bf_bits(a[0].e, k) | (bf_bits(a[1].e, k) << 16);
-  if constexpr (N::ENC < 16) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k) Xw[(N::ENC + 2 * g + k) * kPairRowW + jc] = 0u;
-  }
-  stage_f32<N::HD / 16>(Yw, dh1[0], dh1[1], g, jc);
-  wave_lds_fence();
-  dw_pair(Xs, Ys, dw.w0, lane);
-  wave_lds_fence();
-#pragma unroll
-  for (int t = 0; t < T; ++t) {
-    pend.s[t] = s[t];
-    pend.valid[t] = valid[t];
-#pragma unroll
-    for (int m = 0; m < MT0; ++m) pend.de[t][m] = de[t][m];
-  }
-}
-
-// Tile pairs of a wave: pair p, p + step, ...  With the kept encoding, the
-// next pair's inputs are fetched while this pair computes (ray indices two
-// pairs ahead, so the dependent direction load has its index in hand).
-template <class N, bool KEEP>
-__device__ __forceinline__ void bwd_pairs(const __bf16* __restrict__ Af, const __bf16* __restrict__ Ab,
-                                          const _Float16* __restrict__ table, const LevelInfo& lv,
-                                          const SampleSrc& src, const float* __restrict__ dsigma,
-                                          const float* __restrict__ drgb, const RecordBuffers& rec, __bf16* Xs,
-                                          __bf16* Ys, PairAcc<N>& dw, int first, int step, int S, int lane) {
-  const int g = lane >> 4, jc = lane & 15;
-  const int npairs = (S + 31) / 32;
-  LaneLevels<N> ll;
-  lane_levels<N>(lv, g, ll);
-  TileIn<N> cur[2];
-  uint32_t rid1[2] = {0u, 0u};
-  PendingDe<N> pend;
-  pend.valid[0] = pend.valid[1] = false;
-  pend.s[0] = pend.s[1] = 0;
-  if constexpr (KEEP) {
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      const int s0 = 32 * first + 16 * t + jc;
-      fetch_tile<N, true>(src, table, lv, ll, dsigma, drgb, s0, s0 < S, g, ray_of<N>(src, s0, S), cur[t]);
-      rid1[t] = ray_of<N>(src, 32 * (first + step) + 16 * t + jc, S);
-    }
-  }
-  for (int p = first; p < npairs; p += step) {
-    int s[2];
-    bool valid[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      s[t] = 32 * p + 16 * t + jc;
-      valid[t] = s[t] < S;
-    }
-    TileIn<N> nxt[2];
-    uint32_t rid2[2];
-    if constexpr (KEEP) {
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int s1 = 32 * (p + step) + 16 * t + jc;
-        fetch_tile<N, true>(src, table, lv, ll, dsigma, drgb, s1, s1 < S, g, rid1[t], nxt[t]);
-        rid2[t] = ray_of<N>(src, 32 * (p + 2 * step) + 16 * t + jc, S);
-      }
-    } else {
-#pragma unroll
-      for (int t = 0; t < 2; ++t)
-        fetch_tile<N, false>(src, table, lv, ll, dsigma, drgb, s[t], valid[t], g, 0u, cur[t]);
-    }
-    bwd_pair<N>(Af, Ab, Xs, Ys, cur, s, valid, rec, dw, pend, lane);
-    if constexpr (KEEP) {
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        cur[t] = nxt[t];
-        rid1[t] = rid2[t];
-      }
-    }
-  }
-  pend.store(rec, g);
-}
-
-// kMixedBwdWaves waves per workgroup, one per SIMD: the weight-gradient
-// accumulators of a wave live in registers for the whole kernel.
-template <class N>
-__global__ __launch_bounds__(kMixedBwdWaves * kWave, 1) void mixed_bwd_kernel(LevelInfo lv, const _Float16* __restrict__ table,
-                                                           const __bf16* __restrict__ prep, SampleSrc src,
-                                                           const float* __restrict__ dsigma,
-                                                           const float* __restrict__ drgb, RecordBuffers rec,
-                                                           float* __restrict__ dw_partial) {
-  using M = Mixed<N>;
-  constexpr int STAGE = (N::XROWS + N::YROWS) * kPairRow;
-  __shared__ __attribute__((aligned(16))) __bf16 Af[M::FWD];
-  __shared__ __attribute__((aligned(16))) __bf16 Ab[M::BWD];
-  __shared__ __attribute__((aligned(16))) float dW[N::NWEIGHTS];
-  __shared__ __attribute__((aligned(16))) __bf16 stage_all[kMixedBwdWaves * STAGE];
-  load_bf16<N>(Af, prep, M::FWD);
-  load_bf16<N>(Ab, prep + M::FWD, M::BWD);
-  for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) dW[i] = 0.0f;
-  __syncthreads();
-
-  const int S = src.n_dev ? (int)*src.n_dev : src.n;
-  const int wave = threadIdx.x / kWave;
-  const int lane = lane_id();
-  __bf16* Xs = stage_all + wave * STAGE;
-  __bf16* Ys = Xs + N::XROWS * kPairRow;
-  PairAcc<N> dw;
-  dw.w0.zero(); dw.w1.zero(); dw.w2.zero(); dw.wl.zero();
-  if constexpr (N::NCH == 2) dw.w3.zero();
-  const int first = blockIdx.x * kMixedBwdWaves + wave, step = gridDim.x * kMixedBwdWaves;
-  if (src.ecache)
-    bwd_pairs<N, true>(Af, Ab, table, lv, src, dsigma, drgb, rec, Xs, Ys, dw, first, step, S, lane);
-  else
-    bwd_pairs<N, false>(Af, Ab, table, lv, src, dsigma, drgb, rec, Xs, Ys, dw, first, step, S, lane);
-  for (int w = 0; w < kMixedBwdWaves; ++w) {
-    __syncthreads();
-    if (wave == w) {
-      dw.w0.flush(dW + N::woff(0), lane);
-      dw.w1.flush(dW + N::woff(1), lane);
-      dw.w2.flush(dW + N::woff(2), lane);
-      if constexpr (N::NCH == 2) dw.w3.flush(dW + N::woff(3), lane);
-      dw.wl.flush(dW + N::woff(N::NW - 1), lane);
-    }
-  }
-  __syncthreads();
-  float* out = dw_partial + (size_t)blockIdx.x * N::NWEIGHTS;
-  for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) out[i] = dW[i];
 }
 
 // ---------------------------------------------------------------------------

@@ -102,7 +102,6 @@ hipError_t field_prep(int shape, const float* params, const WOffsets& wo, float*
 hipError_t field_forward(int shape, const FieldArgs& a, const SampleSrc& src, int max_samples,
                          float* sigma, float* rgb, hipStream_t st);
 constexpr int kFieldBwdWaves = 4;             // waves per workgroup of the FP32 backward
-constexpr int kMixedBwdWaves = 4;             // waves per workgroup of the mixed backward
 // Writes dL/de of every sample to rec.de and the weight gradients of each
 // workgroup to partial[nblocks][weights]; field_dw_reduce then adds them
 // into grads and bin_scatter the table gradient.
