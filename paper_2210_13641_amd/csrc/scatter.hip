@@ -317,8 +317,17 @@ __global__ __launch_bounds__(kUnitSamples) void bin_place_kernel(SampleSrc src, 
   }
   __syncthreads();
   if (on) {
+    // a pair that took consecutive ranks in one bin takes consecutive slots
 #pragma unroll
-    for (int k = 0; k < 8; ++k) stage[lst[R::key(rec[k]) >> 16] + rank[k]] = rec[k];
+    for (int k = 0; k < 8; k += 2) {
+      const uint32_t ba = R::key(rec[k]) >> 16, bb = R::key(rec[k + 1]) >> 16;
+      const uint32_t sa = lst[ba] + rank[k];
+      stage[sa] = rec[k];
+      if (ba == bb)
+        stage[sa + 1] = rec[k + 1];
+      else
+        stage[lst[bb] + rank[k + 1]] = rec[k + 1];
+    }
   }
   __syncthreads();
   for (uint32_t i = t; i < m; i += kUnitSamples) {

@@ -2,6 +2,8 @@
 FP64 oracle: the mapping loss and its seeds (nsl_loss_fwd / nsl_loss_bwd),
 the hash-grid encoding in both precisions (nsl_encode_fwd[_mixed]) and the
 table-gradient scatter from a given dL/de (nsl_encode_bwd)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -98,8 +100,15 @@ def test_encode_entry_points_match_oracle(nsl, gpu, spec, S):
     check_mag("encoding mixed", gotm, want, mag, 2e-2)
 
 
-@pytest.mark.parametrize("spec,S", [(W.C1_FIELD, 2049), (W.C2_FIELD, 4099), (W.C2_FIELD, 65537)],
-                         ids=["tiny", "full", "full-64k"])
+# The tiny network over 2^22-entry levels: a dense level of 129^3 entries
+# (263 bins) and three hashed levels of 512 bins, so that a level has more
+# bins than the placement has threads and each thread owns several.
+LARGE_TABLE = dataclasses.replace(W.C1_FIELD, log2_table=22, base_res=128)
+
+
+@pytest.mark.parametrize("spec,S", [(W.C1_FIELD, 2049), (W.C2_FIELD, 4099), (W.C2_FIELD, 65537),
+                                    (LARGE_TABLE, 65537)],
+                         ids=["tiny", "full", "full-64k", "large-table"])
 def test_encode_bwd_entry_point_matches_oracle(nsl, gpu, spec, S):
     """nsl_encode_bwd scatters a random dL/de into the table gradient: every
     table entry against the oracle's scatter at 1e-5 (FP32 records) and 2e-2
