@@ -278,9 +278,10 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
  *   3 field forward (MLP; with keep_encoding = 0 also the table gather),
  *   4 compositing + loss + its adjoint, 5 field backward kernel (MLP
  *   recompute and adjoint, weight gradients per workgroup, dL/de),
- *   6 table gradient (bin count, scans, placement, reduction), 7 weight-
- *   gradient reduction and the sum of the loss, 8 Adam (and the loss-scale
- *   update).
+ *   6 table gradient (bin count, scans, placement, reduction), with the
+ *   weight-gradient reduction and the sum of the loss done by the same
+ *   launches, 7 (empty: kept so that the phase numbers stay), 8 Adam (and
+ *   the loss-scale update).
  * nsl_profile_read copies the sums (ms[NSL_PHASES]) and the number of
  * profiled steps; enabling again resets them. */
 #define NSL_PHASES 9

@@ -503,12 +503,12 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
             "field backward");
   HIP_TRY(mark(6), "profile event");
   float* overflow = c->scale_state ? c->scale_state + 3 : nullptr;  // set by the two gradient writers
-  HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, mixed, c->zero_grads != 0, grads, overflow, st, counted),
-          "table gradient");
+  // the weight-gradient and loss sums ride along the scatter's column scan
+  const WeightSum wsum{f->shape, b.partial, kBwdBlocks, f->wo, grads, overflow,
+                     LossSum{b.loss_parts, n, c->lambda_d, loss_out}};
+  HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, mixed, c->zero_grads != 0, grads, overflow, st, counted, &wsum),
+          "table, weight and loss gradients");
   HIP_TRY(mark(7), "profile event");
-  const LossSum ls{b.loss_parts, n, c->lambda_d, loss_out};
-  HIP_TRY(field_dw_reduce(f->shape, b.partial, kBwdBlocks, f->wo, grads, overflow, &ls, st),
-          "weight gradient and loss");
   HIP_TRY(mark(8), "profile event");
   if (c->do_adam)
     HIP_TRY(adam_update(params, grads, adam_m, adam_v, total, c->lr, c->beta1, c->beta2, c->eps, c->adam_step,

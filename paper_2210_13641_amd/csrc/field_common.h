@@ -396,26 +396,31 @@ __device__ __forceinline__ void loss_sum_block(const LossSum& ls) {
 // fixed order: a workgroup takes 16 weights, each of its 16 thread groups
 // sums every 16th partial (all loads of a thread in flight at once), and the
 // 16 sums are added in LDS.  With ls.loss set, one more workgroup sums the
-// loss of the step.
+// loss of the step.  Workgroup b of nb (256 threads) of such a launch.
 template <class N>
-__global__ __launch_bounds__(256) void dw_reduce_kernel(const float* __restrict__ partial, int nblocks, WOffsets wo,
-                                                        float* __restrict__ grads, float* __restrict__ overflow,
-                                                        LossSum ls) {
-  if (ls.loss && blockIdx.x == gridDim.x - 1) {
+constexpr int dw_reduce_blocks(bool with_loss) {
+  return (N::NWEIGHTS + 15) / 16 + (with_loss ? 1 : 0);
+}
+
+template <class N>
+__device__ __forceinline__ void dw_reduce_block(const float* __restrict__ partial, int nblocks, const WOffsets& wo,
+                                                float* __restrict__ grads, float* __restrict__ overflow,
+                                                const LossSum& ls, int b, int nb) {
+  if (ls.loss && b == nb - 1) {
     loss_sum_block(ls);
     return;
   }
   __shared__ float red[16][16];
   const int wl = threadIdx.x & 15, pg = threadIdx.x >> 4;
-  const int i = blockIdx.x * 16 + wl;
+  const int i = b * 16 + wl;
   float acc = 0.0f;
   if (i < N::NWEIGHTS) {
     for (int b0 = pg; b0 < nblocks; b0 += 256) {
       float v[16];  // sixteen loads in flight, added in block order
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
-        const int b = b0 + 16 * k;
-        v[k] = b < nblocks ? partial[(size_t)b * N::NWEIGHTS + i] : 0.0f;
+        const int bb = b0 + 16 * k;
+        v[k] = bb < nblocks ? partial[(size_t)bb * N::NWEIGHTS + i] : 0.0f;
       }
 #pragma unroll
       for (int k = 0; k < 16; ++k) acc += v[k];
@@ -436,10 +441,17 @@ __global__ __launch_bounds__(256) void dw_reduce_kernel(const float* __restrict_
 }
 
 template <class N>
+__global__ __launch_bounds__(256) void dw_reduce_kernel(const float* __restrict__ partial, int nblocks, WOffsets wo,
+                                                        float* __restrict__ grads, float* __restrict__ overflow,
+                                                        LossSum ls) {
+  dw_reduce_block<N>(partial, nblocks, wo, grads, overflow, ls, (int)blockIdx.x, (int)gridDim.x);
+}
+
+template <class N>
 __host__ inline hipError_t launch_dw_reduce(const float* partial, int nblocks, const WOffsets& wo, float* grads,
                                            float* overflow, const LossSum* ls, hipStream_t st) {
   const LossSum none{};
-  hipLaunchKernelGGL(dw_reduce_kernel<N>, dim3((N::NWEIGHTS + 15) / 16 + (ls ? 1 : 0)), dim3(256), 0, st, partial,
+  hipLaunchKernelGGL(dw_reduce_kernel<N>, dim3(dw_reduce_blocks<N>(ls != nullptr)), dim3(256), 0, st, partial,
                      nblocks, wo, grads, overflow, ls ? *ls : none);
   return hipGetLastError();
 }

@@ -41,6 +41,16 @@ struct SampleSrc {
   int ecache_stride;
 };
 
+// The loss of a step from the per-ray shares parts[R][2] (L_rgb, L_D) that
+// composite_loss_backward leaves: loss[0..2] = (L_rgb + lambda_d L_D, L_rgb,
+// L_D), summed in a fixed order (loss_sum_block).
+struct LossSum {
+  const float* parts;
+  int R;
+  float lambda_d;
+  float* loss;
+};
+
 // scatter.hip: table-gradient records and their binned reduction.
 constexpr int kBinShift = 13;                 // 2^13 entries (64 KB of FP32 pairs) per bin
 constexpr int kBinEntries = 1 << kBinShift;
@@ -91,9 +101,21 @@ BinPlan bin_plan(const LevelInfo& lv, uint32_t entries, int64_t max_samples);
 // overflow (may be null): set to 1.0f when a gradient value the call writes
 // is not finite (the loss-scale overflow flag).
 // counted: rb.hist already holds the record counts (from the encoding).
+// ws (may be null): the weight-gradient sum (and the loss sum) of the same
+// step, done by extra workgroups of the column-scan launch (it depends only
+// on the backward's partials, and the launch is short of work).
+struct WeightSum {
+  int shape;
+  const float* partial;
+  int nblocks;
+  WOffsets wo;
+  float* grads;
+  float* overflow;
+  LossSum ls;  // ls.loss null: no loss sum
+};
 hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
                        bool bf16_values, bool overwrite, float* grad_table, float* overflow, hipStream_t st,
-                       bool counted = false);
+                       bool counted = false, const WeightSum* ws = nullptr);
 
 // field.hip
 size_t field_prep_floats(int shape);
@@ -109,15 +131,6 @@ hipError_t field_backward(int shape, const FieldArgs& a, const SampleSrc& src, i
                           const float* dsigma, const float* drgb, const RecordBuffers& rec,
                           float* partial, const WOffsets& wo, float* grads, hipStream_t st);
 
-// The loss of a step from the per-ray shares parts[R][2] (L_rgb, L_D) that
-// composite_loss_backward leaves: loss[0..2] = (L_rgb + lambda_d L_D, L_rgb,
-// L_D), summed in a fixed order.
-struct LossSum {
-  const float* parts;
-  int R;
-  float lambda_d;
-  float* loss;
-};
 // loss[0..2] from the per-ray shares alone (one workgroup, fixed order).
 hipError_t loss_sum(const LossSum& ls, hipStream_t st);
 // ls (may be null): the step's loss is summed by the same launch.

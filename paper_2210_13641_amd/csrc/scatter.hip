@@ -143,9 +143,9 @@ __global__ __launch_bounds__(kUnitSamples) void bin_count_kernel(SampleSrc src, 
 
 // off[b][u] = sum over units u' < u of hist[b][u']; total[b] = sum over all
 // units.  One workgroup per bin; a thread takes four consecutive units.
-__global__ __launch_bounds__(kColThreads) void bin_colscan_kernel(RecordBuffers rb, int nunits) {
+__device__ __forceinline__ void colscan_bin(const RecordBuffers& rb, int nunits, int b) {
   __shared__ uint32_t wsum[kColThreads / kWave];
-  const int b = (int)blockIdx.x, t = (int)threadIdx.x, wave = t / kWave, lane = lane_id();
+  const int t = (int)threadIdx.x, wave = t / kWave, lane = lane_id();
   const uint32_t* __restrict__ h = rb.hist + (size_t)b * nunits;
   uint32_t* __restrict__ o = rb.off + (size_t)b * nunits;
   uint32_t carry = 0;
@@ -175,6 +175,24 @@ __global__ __launch_bounds__(kColThreads) void bin_colscan_kernel(RecordBuffers 
     __syncthreads();
   }
   if (t == 0) rb.bin_total[b] = carry;
+}
+
+__global__ __launch_bounds__(kColThreads) void bin_colscan_kernel(RecordBuffers rb, int nunits) {
+  colscan_bin(rb, nunits, (int)blockIdx.x);
+}
+
+// The column scan of nbins bins, then (workgroups nbins onwards) the
+// weight-gradient and loss sums of the step.
+template <class N>
+__global__ __launch_bounds__(kColThreads) void bin_colscan_dw_kernel(RecordBuffers rb, int nunits, int nbins,
+                                                                    WeightSum ws) {
+  static_assert(kColThreads == 256, "the weight-gradient sum takes 256-thread workgroups");
+  if ((int)blockIdx.x < nbins) {
+    colscan_bin(rb, nunits, (int)blockIdx.x);
+    return;
+  }
+  dw_reduce_block<N>(ws.partial, ws.nblocks, ws.wo, ws.grads, ws.overflow, ws.ls, (int)blockIdx.x - nbins,
+                     (int)gridDim.x - nbins);
 }
 
 // bin_start = exclusive prefix of the totals, chunk_start = exclusive prefix
@@ -452,14 +470,28 @@ BinPlan bin_plan(const LevelInfo& lv, uint32_t entries, int64_t max_samples) {
 
 hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
                        bool bf16_values, bool overwrite, float* grad_table, float* overflow, hipStream_t st,
-                       bool counted) {
-  if (p.nbins == 0 || p.nunits == 0) return hipSuccess;
+                       bool counted, const WeightSum* ws) {
+  if (p.nbins == 0 || p.nunits == 0) {
+    return ws ? field_dw_reduce(ws->shape, ws->partial, ws->nblocks, ws->wo, ws->grads, ws->overflow,
+                                ws->ls.loss ? &ws->ls : nullptr, st)
+              : hipSuccess;
+  }
   float* zero_table = overwrite ? grad_table : nullptr;
   const dim3 grid(p.levels * p.nunits);
   const size_t level_lds = (size_t)p.bl.max_level_bins * sizeof(uint32_t);
   if (!counted)
     hipLaunchKernelGGL(bin_count_kernel, grid, dim3(kUnitSamples), level_lds, st, src, lv, p.bl, rb.hist);
-  hipLaunchKernelGGL(bin_colscan_kernel, dim3(p.nbins), dim3(kColThreads), 0, st, rb, p.nunits);
+  if (ws) {
+    const bool loss = ws->ls.loss != nullptr;
+    if (ws->shape == kShapeTiny)
+      hipLaunchKernelGGL(bin_colscan_dw_kernel<NetTiny>, dim3(p.nbins + dw_reduce_blocks<NetTiny>(loss)),
+                         dim3(kColThreads), 0, st, rb, p.nunits, p.nbins, *ws);
+    else
+      hipLaunchKernelGGL(bin_colscan_dw_kernel<NetFull>, dim3(p.nbins + dw_reduce_blocks<NetFull>(loss)),
+                         dim3(kColThreads), 0, st, rb, p.nunits, p.nbins, *ws);
+  } else {
+    hipLaunchKernelGGL(bin_colscan_kernel, dim3(p.nbins), dim3(kColThreads), 0, st, rb, p.nunits);
+  }
   hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins);
   if (bf16_values) {
     hipLaunchKernelGGL(bin_place_kernel<RecBF16>, grid, dim3(kUnitSamples), 3 * level_lds, st, src, lv, p.bl, rb,
