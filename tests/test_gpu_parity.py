@@ -2,6 +2,7 @@
 the FP64 oracle on the same seeded inputs.  FP32 tolerance 1e-5 relative to
 the oracle's magnitude of each element (value for rendered sums, abs-sum of
 contributions for gradients); integer and sample-set outputs bit-exact."""
+import dataclasses
 import json
 import math
 import os
@@ -434,16 +435,21 @@ def test_step_overwrite_matches_accumulate(nsl, torch_dev, mixed):
     assert np.allclose(ga, gb, rtol=1e-5, atol=1e-6 * np.abs(ga).max())
 
 
+@pytest.mark.parametrize("log2_table", [19, 20, 21], ids=["2^19", "2^20", "2^21"])
 @pytest.mark.parametrize("mixed", [False, True], ids=["fp32", "mixed"])
-def test_step_keep_encoding_matches_recompute(nsl, torch_dev, mixed):
+def test_step_keep_encoding_matches_recompute(nsl, torch_dev, mixed, log2_table):
     """With the encoding kept from the forward instead of gathered again, the
     paper-scale step gives the same forward results, loss and weight
     gradients bit for bit, and the same table gradient up to the summation
-    order of its reduction."""
+    order of its reduction.  The kept-encoding kernel counts the
+    table-gradient records itself while a level spans at most 128 bins (2^20
+    entries); with larger levels the scatter counts them, as it always does
+    when the encoding is gathered again."""
     torch, dev = torch_dev
     scene, occ, kf = c2_inputs()
-    report(f"step: keep_encoding vs recompute, paper scale, {'mixed' if mixed else 'fp32'}")
-    spec, sampler = W.C2_FIELD, W.C2_SAMPLER
+    report(f"step: keep_encoding vs recompute, paper scale, 2^{log2_table} entries a level, "
+           f"{'mixed' if mixed else 'fp32'}")
+    spec, sampler = dataclasses.replace(W.C2_FIELD, log2_table=log2_table), W.C2_SAMPLER
     ids = W.c2_candidates(4096)
     f = nsl.Field(spec)
     flat, _, _ = params_for(spec, f.layout, seed=0, table_range=0.3)
