@@ -444,10 +444,9 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   const bool prof = g_prof.on;
   auto mark = [&](int i) -> hipError_t { return prof ? hipEventRecord(g_prof.ev[i], st) : hipSuccess; };
   HIP_TRY(mark(0), "profile event");
-  // with the encoding kept (16 levels), the encoding kernel also counts the
+  // with the encoding kept, the encoding kernel also counts the
   // table-gradient records per bin and unit
-  const bool counted =
-      c->keep_encoding != 0 && f->cfg.levels == 16 && b.plan.bl.max_level_bins <= kEncodeLevelBins;
+  const bool counted = c->keep_encoding != 0 && b.plan.bl.max_level_bins <= kEncodeLevelBins;
   if (mixed) {
     // the gradient clearing and the overflow-flag reset ride along the FP16
     // table copy

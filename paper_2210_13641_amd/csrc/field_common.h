@@ -172,15 +172,15 @@ __device__ __forceinline__ void read_encoding(const E* __restrict__ ec, int stri
 }
 
 // The encoding of every sample, written level-major for the MLP kernels.
-// Workgroups are dispatched round-robin over the 8 XCDs, in order; with 16
-// levels, the workgroups of XCD x evaluate level x for every sample and then
-// level x + 8, so at any time each XCD's L2 holds the table slice of one
-// level (2 MB in FP16) instead of seeing the whole table, and the random
-// corner reads hit in L2.  One thread per (sample, level); with fewer
-// levels, threads take (sample, level) pairs in order.
+// One thread per (sample, level), one workgroup per unit (256 samples of one
+// level, see level_unit).  Workgroups are dispatched round-robin over the 8
+// XCDs, in order; with 16 levels, the workgroups of XCD x evaluate level x
+// for every sample and then level x + 8, so at any time each XCD's L2 holds
+// the table slice of one level (2 MB in FP16) instead of seeing the whole
+// table, and the random corner reads hit in L2.
 template <class N>
 __host__ __device__ constexpr int encode_grid(int max_samples) {
-  return N::L >= 8 ? 16 * ((max_samples + 255) / 256) : (max_samples * N::L + 255) / 256;
+  return N::L * ((max_samples + 255) / 256);
 }
 
 // Workgroup -> (level l, unit u) of the level-major kernels (the encoding
@@ -228,27 +228,21 @@ __device__ __forceinline__ void write_counts(const BinLevels& bl, int l, int u, 
   for (int k = threadIdx.x; k < nb; k += blockDim.x) hist[(size_t)(bl.first[l] + k) * bl.nunits + u] = cnt[k];
 }
 
-// With hist set (16 levels only), the kernel also counts the table-gradient
-// records of its unit per bin exactly as the scatter's counting pass would,
-// and writes them to hist[bin][unit] (every workgroup writes its row, so hist
-// needs no clearing).  The counting pass of the scatter is then skipped.
+// With hist set, the kernel also counts the table-gradient records of its
+// unit per bin exactly as the scatter's counting pass would, and writes them
+// to hist[bin][unit] (every workgroup writes its row, so hist needs no
+// clearing).  The counting pass of the scatter is then skipped.
 template <class N, class T, class E>
 __global__ __launch_bounds__(256) void encode_levels_kernel(LevelInfo lv, const T* __restrict__ table, SampleSrc src,
                                                             E* __restrict__ out, int stride,
                                                             uint32_t* __restrict__ hist, BinLevels bl) {
   static_assert(kUnitSamples == 256, "one sample per thread");
   const int S = src.n_dev ? (int)*src.n_dev : src.n;
-  int l, s, u = 0;
-  if constexpr (N::L == 16) {
-    level_unit(16, (int)(gridDim.x / 16u), l, u);
-    s = u * 256 + threadIdx.x;
-  } else {
-    const int gid = blockIdx.x * 256 + threadIdx.x;
-    l = gid % N::L;
-    s = gid / N::L;
-  }
+  int l, u;
+  level_unit(N::L, (int)(gridDim.x / (uint32_t)N::L), l, u);
+  const int s = u * 256 + (int)threadIdx.x;
   const bool valid = s < S;
-  if (N::L != 16 || !hist) {
+  if (!hist) {
     if (!valid) return;
     float xn[3];
     load_position(src, s, xn);

@@ -54,7 +54,7 @@ struct LossSum {
 // scatter.hip: table-gradient records and their binned reduction.
 constexpr int kBinShift = 13;                 // 2^13 entries (64 KB of FP32 pairs) per bin
 constexpr int kBinEntries = 1 << kBinShift;
-constexpr uint32_t kChunk = 65536;            // records per reduce workgroup
+constexpr uint32_t kChunk = 65536;            // records per reduce workgroup (at most)
 constexpr int64_t kMaxTableEntries = (int64_t)1 << 25;  // all levels together
 constexpr int kUnitSamples = 256;             // samples of one level per counting / placement workgroup
 constexpr int kEncodeLevelBins = 128;         // bins of a level the counting encoding supports (2^20 entries)
@@ -90,6 +90,7 @@ struct RecordBuffers {
 struct BinPlan {
   uint32_t entries;
   int nbins, nunits, levels, stride, max_chunks;
+  uint32_t chunk;  // records per reduce workgroup: kChunk, or fewer for tables of few bins
   int64_t max_records;
   BinLevels bl;
 };
@@ -137,7 +138,7 @@ hipError_t loss_sum(const LossSum& ls, hipStream_t st);
 hipError_t field_dw_reduce(int shape, const float* partial, int nblocks, const WOffsets& wo, float* grads,
                            float* overflow, const LossSum* ls, hipStream_t st);
 // The encoding of every sample of src into src.ecache (FP32 table).  With
-// hist (16 levels, at most kEncodeLevelBins bins a level; nullable), also the
+// hist (at most kEncodeLevelBins bins a level; nullable), also the
 // table-gradient record counts per bin and unit, written to every
 // hist[bin][unit] of bl (no clearing needed): bin_scatter can then skip its
 // counting pass.  bl.nunits must be the units of max_samples.

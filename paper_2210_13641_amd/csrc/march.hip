@@ -117,56 +117,61 @@ __global__ __launch_bounds__(256) void rays_count_kernel(KeyframeStore kf, March
 
 constexpr int kScanThreads = 1024;
 
-// Single-block exclusive scan of the counts, batch cut and statistics: each
-// thread sums a run of consecutive rays, a wave scan (DPP) and the totals of
-// the waves before give its exclusive offset.
+// Single-block exclusive scan of the counts, batch cut and statistics, over
+// segments of 4 * kScanThreads rays: each thread loads four consecutive rays
+// (counts and precisions, one 16-byte load each), a wave scan (DPP) and the
+// totals of the waves before give its exclusive offset, and the segment's
+// total carries over to the next.
 __global__ __launch_bounds__(kScanThreads) void scan_cut_kernel(RayBuffers rb, int n, int max_samples) {
   __shared__ uint32_t wtot[kScanThreads / kWave];
   __shared__ uint32_t red[3][kScanThreads / kWave];
   const int tid = threadIdx.x, wave = tid / kWave;
-  const int per = (n + kScanThreads - 1) / kScanThreads;
-  const int b = tid * per, e = min(n, b + per);
-  // up to kCutRegs rays per thread (n <= 4096) are loaded once, counts and
-  // precisions together, and kept in registers for the second pass
-  constexpr int kCutRegs = 4;
-  uint32_t cr[kCutRegs];
-  bool pz[kCutRegs];
-  uint32_t sum = 0;
-  if (per <= kCutRegs) {
+  uint32_t carry = 0, nr = 0, nk = 0, nm = 0;
+  for (int seg = 0; seg < n; seg += 4 * kScanThreads) {
+    const int i0 = seg + 4 * tid;
+    uint32_t cr[4] = {0u, 0u, 0u, 0u};
+    bool pz[4] = {false, false, false, false};
+    if (i0 + 4 <= n) {
+      const uint4 c4 = *reinterpret_cast<const uint4*>(rb.counts + i0);
+      const float4 p4 = *reinterpret_cast<const float4*>(rb.prec + i0);
+      cr[0] = c4.x; cr[1] = c4.y; cr[2] = c4.z; cr[3] = c4.w;
+      pz[0] = p4.x == 0.0f; pz[1] = p4.y == 0.0f; pz[2] = p4.z == 0.0f; pz[3] = p4.w == 0.0f;
+    } else {
 #pragma unroll
-    for (int k = 0; k < kCutRegs; ++k) {
-      cr[k] = b + k < e ? rb.counts[b + k] : 0u;
-      pz[k] = b + k < e && rb.prec[b + k] == 0.0f;
-      sum += cr[k];
-    }
-  } else {
-    for (int i = b; i < e; ++i) sum += rb.counts[i];
-  }
-  const uint32_t incl = wave_incl_scan_u32(sum);
-  if (lane_id() == kWave - 1) wtot[wave] = incl;
-  __syncthreads();
-  uint32_t run = incl - sum;  // exclusive
-  for (int w = 0; w < wave; ++w) run += wtot[w];
-  uint32_t nr = 0, nk = 0, nm = 0;
-  auto cut = [&](int i, uint32_t c, bool masked) {
-    rb.offsets[i] = run;
-    run += c;
-    if (run <= (uint32_t)max_samples) {
-      ++nk;
-      if (c > 0) {
-        ++nr;
-        if (masked) ++nm;
+      for (int k = 0; k < 4; ++k) {
+        if (i0 + k < n) {
+          cr[k] = rb.counts[i0 + k];
+          pz[k] = rb.prec[i0 + k] == 0.0f;
+        }
       }
     }
-  };
-  if (per <= kCutRegs) {
+    const uint32_t sum = cr[0] + cr[1] + cr[2] + cr[3];
+    const uint32_t incl = wave_incl_scan_u32(sum);
+    if (lane_id() == kWave - 1) wtot[wave] = incl;
+    __syncthreads();
+    uint32_t run = carry + incl - sum, total = 0;  // exclusive
+    for (int w = 0; w < kScanThreads / kWave; ++w) {
+      run += w < wave ? wtot[w] : 0u;
+      total += wtot[w];
+    }
 #pragma unroll
-    for (int k = 0; k < kCutRegs; ++k)
-      if (b + k < e) cut(b + k, cr[k], pz[k]);
-  } else {
-    for (int i = b; i < e; ++i) cut(i, rb.counts[i], rb.prec[i] == 0.0f);
+    for (int k = 0; k < 4; ++k) {
+      if (i0 + k < n) {
+        rb.offsets[i0 + k] = run;
+        run += cr[k];
+        if (run <= (uint32_t)max_samples) {
+          ++nk;
+          if (cr[k] > 0) {
+            ++nr;
+            if (pz[k]) ++nm;
+          }
+        }
+      }
+    }
+    carry += total;
+    __syncthreads();
   }
-  if (tid == kScanThreads - 1) rb.offsets[n] = run;
+  if (tid == 0) rb.offsets[n] = carry;
   // reductions
   for (int o = 32; o > 0; o >>= 1) {
     nr += __shfl_xor(nr, o, kWave);

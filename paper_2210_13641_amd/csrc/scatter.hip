@@ -14,7 +14,9 @@
 //               bin of the level (LDS integer atomics); or done by the
 //               encoding kernel, which evaluates the same corners
 //   scan        per bin, exclusive prefix over the level's units; bin totals
-//   start       exclusive prefix over bins; chunks of kChunk records per bin
+//   start       exclusive prefix over bins; chunks of at most kChunk records
+//               per bin (fewer when the table has few bins, so that the
+//               records still spread over many workgroups)
 //   place       per unit, the records again, ordered by bin in LDS and stored
 //               to their bins' slices
 //   reduce      one workgroup per chunk: LDS accumulation of the bin with
@@ -49,6 +51,7 @@ constexpr int kReduceThreads = 1024;
 // the 16-bit offset (10 or 6 bytes a record).  Either way the reduction
 // accumulates in FP32.
 static_assert(kBinShift <= 16, "in-bin offsets are 16-bit");
+static_assert((kReduceThreads & (kReduceThreads - 1)) == 0, "the scattered group order needs a power of two");
 struct RecF32 {
   typedef uint3 T;
   static __device__ __forceinline__ T pack(uint32_t e, float a, float b) {
@@ -196,8 +199,9 @@ __global__ __launch_bounds__(kColThreads) void bin_colscan_dw_kernel(RecordBuffe
 }
 
 // bin_start = exclusive prefix of the totals, chunk_start = exclusive prefix
-// of ceil(total / kChunk); both with the grand total at [nbins].
-__global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int nbins) {
+// of ceil(total / chunk); both with the grand total at [nbins].
+constexpr int kMaxStartBins = (int)(kMaxTableEntries / kBinEntries) + kMaxLevels;  // bins of any table
+__global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int nbins, uint32_t chunk) {
   __shared__ uint32_t w_rec[1024 / kWave], w_chk[1024 / kWave];
   const int t = threadIdx.x;
   const int per = (nbins + 1023) / 1024;
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int n
   for (int b = b0; b < b1; ++b) {
     const uint32_t n = rb.bin_total[b];
     rec += n;
-    chk += (n + kChunk - 1) / kChunk;
+    chk += (n + chunk - 1) / chunk;
   }
   // wave scans, then the totals of the waves before
   const int wave = t / kWave;
@@ -223,18 +227,32 @@ __global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int n
     all_r += w_rec[w];
     all_c += w_chk[w];
   }
+  // the chunk starts also go to LDS, where every thread then finds the bin of
+  // chunks t, t + 1024, ... by binary search (a bin of many chunks would
+  // otherwise leave one thread writing all of its entries)
+  __shared__ uint32_t cs[kMaxStartBins + 1];
   for (int b = b0; b < b1; ++b) {
     const uint32_t n = rb.bin_total[b];
     rb.bin_start[b] = run_r;
     rb.chunk_start[b] = run_c;
-    const uint32_t nc = (n + kChunk - 1) / kChunk;
-    for (uint32_t k = 0; k < nc; ++k) rb.chunk_bin[run_c + k] = (uint32_t)b;
+    cs[b] = run_c;
     run_r += n;
-    run_c += nc;
+    run_c += (n + chunk - 1) / chunk;
   }
   if (t == 1023) {
     rb.bin_start[nbins] = all_r;
     rb.chunk_start[nbins] = all_c;
+    cs[nbins] = all_c;
+  }
+  __syncthreads();
+  for (uint32_t c = t; c < all_c; c += 1024) {
+    int lo = 0, hi = nbins;  // the last bin b with cs[b] <= c (bins of no chunks are skipped)
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) / 2;
+      if (cs[mid] <= c) lo = mid;
+      else hi = mid;
+    }
+    rb.chunk_bin[c] = (uint32_t)lo;
   }
 }
 
@@ -357,7 +375,7 @@ __global__ __launch_bounds__(kUnitSamples) void bin_place_kernel(SampleSrc src, 
 // overwrite: a bin of one chunk stores its sums over every entry (zeros
 // included) instead of adding them to the gradient.
 template <class R>
-__global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffers rb, BinLevels bl,
+__global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffers rb, BinLevels bl, uint32_t chunk,
                                                                     float* __restrict__ grad_table,
                                                                     float* __restrict__ overflow, bool overwrite) {
   // (g0, g1) of each entry as one 64-bit word: float pairs are added with
@@ -369,8 +387,8 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
   if (c >= rb.chunk_start[nbins]) return;
   const int b = (int)rb.chunk_bin[c];
   const uint32_t nch = rb.chunk_start[b + 1] - rb.chunk_start[b];
-  const uint32_t first = rb.bin_start[b] + (c - rb.chunk_start[b]) * kChunk;
-  const uint32_t last = min(rb.bin_start[b + 1], first + kChunk);
+  const uint32_t first = rb.bin_start[b] + (c - rb.chunk_start[b]) * chunk;
+  const uint32_t last = min(rb.bin_start[b + 1], first + chunk);
   for (int i = threadIdx.x; i < kBinEntries; i += kReduceThreads) acc[i] = 0ull;
   __syncthreads();
   uint32_t e0, ne;
@@ -390,19 +408,25 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
   // [first, last) are skipped.
   const uint32_t g0 = first / 4, g1 = (last + 3) / 4;
   const uint2* __restrict__ keys = static_cast<const uint2*>(rb.sorted);
+  // With small chunks (tables of few bins, whose coarse levels put runs of
+  // records of one entry next to each other), the threads take the groups
+  // in a scattered order (t -> 29 t mod 1024), so that the lanes of a wave
+  // meet different entries in their compare-and-swap instead of queueing on
+  // one; with full chunks they read consecutive groups, coalesced.
+  const uint32_t tp = chunk < kChunk ? (threadIdx.x * 29u) & (kReduceThreads - 1) : threadIdx.x;
   for (uint32_t gb = g0; gb < g1; gb += kReduceThreads * 2) {
     uint2 kk[2];
     float2 vv[2][4];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const uint32_t gi = gb + j * kReduceThreads + threadIdx.x;
+      const uint32_t gi = gb + j * kReduceThreads + tp;
       const uint32_t gc = gi < g1 ? gi : g0;  // a group of this chunk either way
       kk[j] = keys[gc];
       R::vals4(rb, gc, vv[j]);
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const uint32_t p0 = 4 * (gb + j * kReduceThreads + threadIdx.x);
+      const uint32_t p0 = 4 * (gb + j * kReduceThreads + tp);
       const uint32_t k4[4] = {kk[j].x & 0xFFFFu, kk[j].x >> 16, kk[j].y & 0xFFFFu, kk[j].y >> 16};
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -464,7 +488,17 @@ BinPlan bin_plan(const LevelInfo& lv, uint32_t entries, int64_t max_samples) {
   bl.first[lv.levels] = nb;
   p.nbins = (int)nb;
   p.max_records = max_samples * 8 * lv.levels;
-  p.max_chunks = (int)(p.nbins + (p.max_records + kChunk - 1) / kChunk);
+  // a table of few bins (the tiny field has four) would leave a few huge
+  // chunks: there the chunk shrinks (to a power of two of at least 4096) so
+  // that a full batch of records makes up to about 8192 chunks; their sums
+  // then meet in the gradient through atomics, one per touched entry and chunk
+  p.chunk = kChunk;
+  if (p.nbins < 256) {
+    uint32_t c = 4096;
+    while (c < kChunk && (int64_t)c * 2 * 8192 <= p.max_records) c *= 2;
+    p.chunk = c;
+  }
+  p.max_chunks = (int)(p.nbins + (p.max_records + p.chunk - 1) / p.chunk);
   return p;
 }
 
@@ -492,17 +526,17 @@ hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSr
   } else {
     hipLaunchKernelGGL(bin_colscan_kernel, dim3(p.nbins), dim3(kColThreads), 0, st, rb, p.nunits);
   }
-  hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins);
+  hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins, p.chunk);
   if (bf16_values) {
     hipLaunchKernelGGL(bin_place_kernel<RecBF16>, grid, dim3(kUnitSamples), 3 * level_lds, st, src, lv, p.bl, rb,
                        zero_table);
     hipLaunchKernelGGL(bin_reduce_kernel<RecBF16>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.bl,
-                       grad_table, overflow, overwrite);
+                       p.chunk, grad_table, overflow, overwrite);
   } else {
     hipLaunchKernelGGL(bin_place_kernel<RecF32>, grid, dim3(kUnitSamples), 3 * level_lds, st, src, lv, p.bl, rb,
                        zero_table);
     hipLaunchKernelGGL(bin_reduce_kernel<RecF32>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.bl,
-                       grad_table, overflow, overwrite);
+                       p.chunk, grad_table, overflow, overwrite);
   }
   return hipGetLastError();
 }
