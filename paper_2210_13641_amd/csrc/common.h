@@ -220,9 +220,15 @@ __device__ __forceinline__ bool row_cell_runs(const uint32_t cell[3], bool valid
       tail = nt;                                                      \
     }                                                                 \
   }
+  // once every lane's sum reaches the end of its run (no lane still has a
+  // continuation), the remaining steps would add nothing: runs of one or two
+  // samples, the usual case at the middle levels, stop after the first step
   NSL_RUN_STEP(1)
+  if (__ballot(!tail) == 0ull) return !same_below;
   NSL_RUN_STEP(2)
+  if (__ballot(!tail) == 0ull) return !same_below;
   NSL_RUN_STEP(4)
+  if (__ballot(!tail) == 0ull) return !same_below;
   NSL_RUN_STEP(8)
 #undef NSL_RUN_STEP
   return !same_below;
