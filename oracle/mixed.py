@@ -10,9 +10,10 @@ these points, and nowhere else:
   each hidden activation (after its ReLU), the density outputs and SH
   coefficients fed to the colour net, and every upstream gradient of the
   backward chain (after its ReLU mask) -- is rounded to BF16;
-* each table-gradient record, the sum of w_c * dL/de over a run of
-  consecutive samples that share a grid cell (runs taken within aligned
-  groups of 16 samples of the batch order), is rounded to BF16.
+* dL/de leaves the backward rounded to BF16, and each table-gradient
+  record, the sum of w_c * dL/de over a run of consecutive samples that
+  share a grid cell (runs taken within aligned groups of 16 samples of the
+  batch order), is rounded to BF16.
 
 Products and sums are exact here (FP64); density, colour, compositing and
 the loss are unquantised.  A quantisation point decides a discrete value,
@@ -100,8 +101,9 @@ def mlp_bwd(spec, cache, dsigma, dsigma_mag, dcol, dcol_mag, band_tol=2e-2):
     """Reverse mode with every product operand quantised as the kernels do:
     the upstream gradient of each layer is rounded once, after its ReLU
     mask, and that value feeds both the weight gradient and the next input
-    gradient.  Returns (dW, dW magnitudes, dL/de (unquantised), its
-    magnitude)."""
+    gradient.  Returns (dW, dW magnitudes, dL/de rounded by the quantiser
+    (the backward stores it as BF16 pairs for the table-gradient records),
+    its magnitude)."""
     W, rnd = cache["W"], cache["rnd"]
     aW = [np.abs(w) for w in W]
     c = cache["colour"]
@@ -139,7 +141,7 @@ def mlp_bwd(spec, cache, dsigma, dsigma_mag, dcol, dcol_mag, band_tol=2e-2):
     e = cache["e"]
     dWs[0] = e.T @ g
     dWm[0] = np.abs(e).T @ g_m + cache["e_mag"].T @ np.abs(g)
-    return dWs, dWm, g @ W[0].T, g_m @ aW[0].T
+    return dWs, dWm, rnd(g @ W[0].T), g_m @ aW[0].T
 
 
 def encode_bwd(spec, corners, xn, de, de_mag, n_table_floats, rnd=round_bf16, group=16):

@@ -438,6 +438,7 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   StepBuffers b;
   const bool mixed = c->precision == NSL_PRECISION_MIXED;
   step_carve(f, n, c->max_samples, mixed, c->keep_encoding != 0, ws, &b);
+  b.rec.de_bf16 = mixed;  // the mixed backward stores dL/de as BF16 pairs
   if (stats_out) b.rb.stats = reinterpret_cast<uint32_t*>(stats_out);
   b.rb.loss = loss_out;
   const int64_t total = f->lay.total_floats;
@@ -670,6 +671,7 @@ int nsl_field_bwd_mixed(const nsl_field* f, const void* shadow, const float* xn,
   SampleSrc src;
   int rc = field_common(f, nullptr, xn, dirs, S, ws, ws_bytes, true, w, src);
   if (rc) return rc;
+  w.rec.de_bf16 = true;  // the mixed backward stores dL/de as BF16 pairs
   HIP_TRY(mixed_backward(f->shape, f->lv, shadow, src, kBwdBlocks, dsigma, drgb, w.rec, w.partial, f->wo, grads, st),
           "field backward (mixed)");
   HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, nullptr, nullptr, st), "weight gradient");

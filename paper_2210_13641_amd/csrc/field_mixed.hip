@@ -439,7 +439,8 @@ __device__ __forceinline__ void stage1_f32(uint16_t* S, const f4* v, int g, int 
     }
 }
 
-// dL/de of one tile held back one step (as PendingDe).
+// dL/de of one tile held back one step, stored after the next tile's
+// forward; as BF16 pairs (the table-gradient records it feeds are BF16 too).
 template <class N>
 struct PendingDe1 {
   f4 de[N::bmt(0)];
@@ -450,7 +451,8 @@ struct PendingDe1 {
 #pragma unroll
     for (int q = 0; q < N::LPL; ++q) {
       const int k0 = 2 * q, k1 = 2 * q + 1;
-      rec.de[(size_t)(g + 4 * q) * rec.stride + s] = make_float2(de[k0 >> 2][k0 & 3], de[k1 >> 2][k1 & 3]);
+      reinterpret_cast<uint32_t*>(rec.de)[(size_t)(g + 4 * q) * rec.stride + s] =
+          bf16_pair(de[k0 >> 2][k0 & 3], de[k1 >> 2][k1 & 3]);
     }
   }
 };

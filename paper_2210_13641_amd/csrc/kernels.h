@@ -72,8 +72,11 @@ struct BinLevels {
 };
 
 struct RecordBuffers {
-  float2* de;             // [levels][stride] dL/de of every sample (two features per level)
+  float2* de;             // [levels][stride] dL/de of every sample (two features per level): FP32
+                          // pairs, or with de_bf16 the BF16 pairs (g0 | g1 << 16, 32 bits) the
+                          // mixed-precision backward stores
   int stride;             // samples per level row of de
+  bool de_bf16;
   uint32_t* hist;         // [nbins][nunits] records per bin and unit (unit u of the bin's level)
   uint32_t* off;          // [nbins][nunits] exclusive prefix of hist over the units
   uint32_t* bin_total;    // [nbins]

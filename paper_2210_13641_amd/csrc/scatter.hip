@@ -294,7 +294,16 @@ __global__ __launch_bounds__(kUnitSamples) void bin_place_kernel(SampleSrc src, 
   int s;
   float xn[3];
   const bool valid = unit_sample(src, u, s, xn);
-  const float2 d = valid ? rb.de[(size_t)l * rb.stride + s] : make_float2(0.0f, 0.0f);
+  float2 d = make_float2(0.0f, 0.0f);
+  if (valid) {
+    const size_t i = (size_t)l * rb.stride + s;
+    if (rb.de_bf16) {
+      const uint32_t w = reinterpret_cast<const uint32_t*>(rb.de)[i];
+      d = make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xFFFF0000u));
+    } else {
+      d = rb.de[i];
+    }
+  }
   Corner8 c;
   const uint32_t loff = lv.offset[l];
   corners(xn[0], xn[1], xn[2], lv.res[l], (lv.dense_bits >> l) & 1u, lv.table_mask, loff, c);
