@@ -201,6 +201,22 @@ __device__ __forceinline__ void level_unit(int levels, int nunits, int& l, int& 
   }
 }
 
+// As level_unit, but with a multiple of 8 levels the workgroups of XCD x
+// alternate between its levels x, x + 8, ... unit by unit, so that the
+// samples' inputs that every level reads are fetched into that XCD's L2
+// once for all of its levels (for kernels that gather no table, whose L2
+// need not hold one level's slice at a time).
+__device__ __forceinline__ void level_unit_interleaved(int levels, int nunits, int& l, int& u) {
+  if (levels % 8 == 0) {
+    const int m = levels / 8;
+    const int x = (int)(blockIdx.x % 8u), j = (int)(blockIdx.x / 8u);
+    l = x + 8 * (j % m);
+    u = j / m;
+  } else {
+    level_unit(levels, nunits, l, u);
+  }
+}
+
 // The table-gradient records of a lane that starts a run (see row_cell_runs:
 // one record per corner, for the first sample of each run of consecutive
 // samples of an aligned group of 16 that share a cell), counted per bin of
