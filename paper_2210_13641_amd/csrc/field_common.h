@@ -217,18 +217,34 @@ __device__ __forceinline__ void level_unit_interleaved(int levels, int nunits, i
   }
 }
 
+// The x-neighbour corners k, k + 1 (k even) of a cell lie at in-level
+// offsets e0 and e1 that nearly always differ in low bits only: a hashed
+// level multiplies x by 1, and a dense one stores x + 1 next to x, so that
+// e1 = e0 ^ (2^p - 1) with p the carry length of the increment.  When
+// 1 <= p <= 7 (the bin is the same, since bins are 2^13 entries) the two
+// corners can travel as one paired record; returns p, else 0.
+__device__ __forceinline__ uint32_t pair_code(uint32_t e0, uint32_t e1) {
+  const uint32_t d = e0 ^ e1;
+  return (d != 0u && d < 128u && (d & (d + 1u)) == 0u) ? 32u - (uint32_t)__clz((int)d) : 0u;
+}
+
 // The table-gradient records of a lane that starts a run (see row_cell_runs:
 // one record per corner, for the first sample of each run of consecutive
 // samples of an aligned group of 16 that share a cell), counted per bin of
 // the level in cnt (LDS): the bin of entry idx is (idx - level_off) >>
 // kBinShift.  The two x-neighbour corners (k, k + 1) nearly always share a
-// bin, and then one atomic counts both.
+// bin, and then one atomic counts both; with kPaired, two corners that
+// pair_code joins take one slot.
+template <bool kPaired>
 __device__ __forceinline__ void count_records(const Corner8& c, bool head, uint32_t level_off, uint32_t* cnt) {
   if (!head) return;
 #pragma unroll
   for (int k = 0; k < 8; k += 2) {
-    const uint32_t ba = (c.idx[k] - level_off) >> kBinShift, bb = (c.idx[k + 1] - level_off) >> kBinShift;
-    if (ba == bb) {
+    const uint32_t e0 = c.idx[k] - level_off, e1 = c.idx[k + 1] - level_off;
+    const uint32_t ba = e0 >> kBinShift, bb = e1 >> kBinShift;
+    if (kPaired && pair_code(e0, e1) != 0u) {
+      atomicAdd(&cnt[ba], 1u);
+    } else if (ba == bb) {
       atomicAdd(&cnt[ba], 2u);
     } else {
       atomicAdd(&cnt[ba], 1u);
@@ -247,7 +263,9 @@ __device__ __forceinline__ void write_counts(const BinLevels& bl, int l, int u, 
 // With hist set, the kernel also counts the table-gradient records of its
 // unit per bin exactly as the scatter's counting pass would, and writes them
 // to hist[bin][unit] (every workgroup writes its row, so hist needs no
-// clearing).  The counting pass of the scatter is then skipped.
+// clearing).  The counting pass of the scatter is then skipped.  The
+// mixed-precision step (FP16 table) places its records in x-neighbour pairs,
+// the FP32 step one corner a record.
 template <class N, class T, class E>
 __global__ __launch_bounds__(256) void encode_levels_kernel(LevelInfo lv, const T* __restrict__ table, SampleSrc src,
                                                             E* __restrict__ out, int stride,
@@ -274,7 +292,7 @@ __global__ __launch_bounds__(256) void encode_levels_kernel(LevelInfo lv, const 
   Corner8 c;
   corners(xn[0], xn[1], xn[2], lv.res[l], (lv.dense_bits >> l) & 1u, lv.table_mask, lv.offset[l], c);
   if (valid) store_encoding(out + (size_t)l * stride + s, blend_corners(table, c));
-  count_records(c, row_run_head(c.cell, valid), lv.offset[l], cnt);
+  count_records<sizeof(T) == 2>(c, row_run_head(c.cell, valid), lv.offset[l], cnt);
   __syncthreads();
   write_counts(bl, l, u, cnt, hist);
 }

@@ -54,7 +54,7 @@ struct LossSum {
 // scatter.hip: table-gradient records and their binned reduction.
 constexpr int kBinShift = 13;                 // 2^13 entries (64 KB of FP32 pairs) per bin
 constexpr int kBinEntries = 1 << kBinShift;
-constexpr uint32_t kChunk = 65536;            // records per reduce workgroup (at most)
+constexpr uint32_t kChunk = 65536;            // corner additions per reduce workgroup (at most)
 constexpr int64_t kMaxTableEntries = (int64_t)1 << 25;  // all levels together
 constexpr int kUnitSamples = 256;             // samples of one level per counting / placement workgroup
 constexpr int kEncodeLevelBins = 128;         // bins of a level the counting encoding supports (2^20 entries)
@@ -93,7 +93,7 @@ struct RecordBuffers {
 struct BinPlan {
   uint32_t entries;
   int nbins, nunits, levels, stride, max_chunks;
-  uint32_t chunk;  // records per reduce workgroup: kChunk, or fewer for tables of few bins
+  uint32_t chunk;  // corner additions per reduce workgroup: kChunk, or fewer for tables of few bins
   int64_t max_records;
   BinLevels bl;
 };

@@ -45,71 +45,78 @@ constexpr int kUnitWaves = kUnitSamples / kWave;  // count and place: one sample
 constexpr int kColThreads = 256;
 constexpr int kReduceThreads = 1024;
 
-// Record formats: FP32 values (key, g0, g1), or, for mixed precision, BF16
-// values (key, g0 | g1 << 16), where key = the bin's index in its level << 16
-// | the entry's offset in the bin.  In the sorted array a record keeps only
-// the 16-bit offset (10 or 6 bytes a record).  Either way the reduction
-// accumulates in FP32.
-static_assert(kBinShift <= 16, "in-bin offsets are 16-bit");
+// Record formats: FP32 values (key, g0, g1), one corner a record; or, for
+// mixed precision, BF16 values (key, g0 | g1 << 16, g0' | g1' << 16) of a
+// corner and, when pair_code joins them, of its x-neighbour too.  key = the
+// bin's index in its level << 16 | p << 13 | the entry's offset in the bin,
+// p being the pair code (0: one corner; else the partner's offset is the
+// offset ^ (2^p - 1)).  In the sorted array a record keeps only the low 16
+// bits of the key and its values (10 bytes a record either way: FP32
+// (g0, g1), or the two BF16 pairs).  Either way the reduction accumulates in FP32.
+static_assert(kBinShift <= 13, "in-bin offsets take 13 bits, the pair code 3");
 static_assert((kReduceThreads & (kReduceThreads - 1)) == 0, "the scattered group order needs a power of two");
 struct RecF32 {
   typedef uint3 T;
+  static constexpr bool kPaired = false;
   // the placement takes a level's units one after another on an XCD (its
   // 10-byte records fill more partly written lines when two levels' bins
   // are written at once: 88 against 84 us interleaved)
   static constexpr bool kInterleaveLevels = false;
-  static __device__ __forceinline__ T pack(uint32_t e, float a, float b) {
-    return make_uint3(e, __float_as_uint(a), __float_as_uint(b));
+  static __device__ __forceinline__ T pack(uint32_t key, float a, float b) {
+    return make_uint3(key, __float_as_uint(a), __float_as_uint(b));
   }
+  static __device__ __forceinline__ T pack_pair(uint32_t key, float a, float b, float, float) { return pack(key, a, b); }
   // In the sorted array a record takes 10 bytes: the entry's 16-bit offset
   // in its bin (the bin is implied by the slot) and the two FP32 values.
   static __device__ __forceinline__ void store(const RecordBuffers& rb, uint32_t pos, const T& r) {
     static_cast<uint16_t*>(rb.sorted)[pos] = (uint16_t)(r.x & 0xFFFFu);
     reinterpret_cast<uint2*>(rb.sorted_vals)[pos] = make_uint2(r.y, r.z);
   }
-  // the values of the four slots 4 gi .. 4 gi + 3
-  static __device__ __forceinline__ void vals4(const RecordBuffers& rb, uint32_t gi, float2 (&v)[4]) {
+  // the values of the four slots 4 gi .. 4 gi + 3 (x, y: the record's entry)
+  static __device__ __forceinline__ void vals4(const RecordBuffers& rb, uint32_t gi, float4 (&v)[4]) {
     const uint4* p = reinterpret_cast<const uint4*>(rb.sorted_vals) + 2 * (size_t)gi;
     const uint4 a = p[0], b = p[1];
-    v[0] = make_float2(__uint_as_float(a.x), __uint_as_float(a.y));
-    v[1] = make_float2(__uint_as_float(a.z), __uint_as_float(a.w));
-    v[2] = make_float2(__uint_as_float(b.x), __uint_as_float(b.y));
-    v[3] = make_float2(__uint_as_float(b.z), __uint_as_float(b.w));
+    v[0] = make_float4(__uint_as_float(a.x), __uint_as_float(a.y), 0.0f, 0.0f);
+    v[1] = make_float4(__uint_as_float(a.z), __uint_as_float(a.w), 0.0f, 0.0f);
+    v[2] = make_float4(__uint_as_float(b.x), __uint_as_float(b.y), 0.0f, 0.0f);
+    v[3] = make_float4(__uint_as_float(b.z), __uint_as_float(b.w), 0.0f, 0.0f);
   }
   static __device__ __forceinline__ uint32_t key(const T& r) { return r.x; }
-  static __device__ __forceinline__ float2 val(const T& r) {
-    return make_float2(__uint_as_float(r.y), __uint_as_float(r.z));
-  }
-  static __device__ __forceinline__ T none() { return make_uint3(0xFFFFFFFFu, 0u, 0u); }
 };
 struct RecBF16 {
-  typedef uint2 T;
+  typedef uint3 T;
+  // x-neighbour corners share a record: the records of a step are about
+  // half as many, at 10 bytes instead of twice 6
+  static constexpr bool kPaired = true;
   // the placement alternates an XCD's levels unit by unit, so each sample's
   // t and ray index are fetched once for both of its levels
   static constexpr bool kInterleaveLevels = true;
-  static __device__ __forceinline__ T pack(uint32_t e, float a, float b) {
+  static __device__ __forceinline__ uint32_t bf2(float a, float b) {
     const __bf16 x = (__bf16)a, y = (__bf16)b;
-    return make_uint2(e, (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16));
+    return (uint32_t)__builtin_bit_cast(uint16_t, x) | ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16);
   }
-  // In the sorted array a record takes 6 bytes: the entry's offset in its
-  // bin (the bin is implied by the slot) and the two BF16 values.
+  static __device__ __forceinline__ float lo(uint32_t w) { return __uint_as_float(w << 16); }
+  static __device__ __forceinline__ float hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+  static __device__ __forceinline__ T pack(uint32_t key, float a, float b) { return make_uint3(key, bf2(a, b), 0u); }
+  static __device__ __forceinline__ T pack_pair(uint32_t key, float a, float b, float c, float d) {
+    return make_uint3(key, bf2(a, b), bf2(c, d));
+  }
+  // In the sorted array a record takes 10 bytes: the low 16 bits of its key
+  // (the bin is implied by the slot) and the two BF16 pairs.
   static __device__ __forceinline__ void store(const RecordBuffers& rb, uint32_t pos, const T& r) {
     static_cast<uint16_t*>(rb.sorted)[pos] = (uint16_t)(r.x & 0xFFFFu);
-    rb.sorted_vals[pos] = r.y;
+    reinterpret_cast<uint2*>(rb.sorted_vals)[pos] = make_uint2(r.y, r.z);
   }
   static __device__ __forceinline__ uint32_t key(const T& r) { return r.x; }
-  static __device__ __forceinline__ float2 val(const T& r) {
-    return make_float2((float)__builtin_bit_cast(__bf16, (uint16_t)(r.y & 0xFFFFu)),
-                       (float)__builtin_bit_cast(__bf16, (uint16_t)(r.y >> 16)));
-  }
-  static __device__ __forceinline__ T none() { return make_uint2(0xFFFFFFFFu, 0u); }
-  // the values of the four slots 4 gi .. 4 gi + 3
-  static __device__ __forceinline__ void vals4(const RecordBuffers& rb, uint32_t gi, float2 (&v)[4]) {
-    const uint4 w = reinterpret_cast<const uint4*>(rb.sorted_vals)[gi];
-    v[0] = val(make_uint2(0u, w.x));
-    v[1] = val(make_uint2(0u, w.y));
-    v[2] = val(make_uint2(0u, w.z));
-    v[3] = val(make_uint2(0u, w.w));
+  // the values of the four slots 4 gi .. 4 gi + 3 (x, y: the record's entry;
+  // z, w: its partner's)
+  static __device__ __forceinline__ void vals4(const RecordBuffers& rb, uint32_t gi, float4 (&v)[4]) {
+    const uint4* p = reinterpret_cast<const uint4*>(rb.sorted_vals) + 2 * (size_t)gi;
+    const uint4 a = p[0], b = p[1];
+    v[0] = make_float4(lo(a.x), hi(a.x), lo(a.y), hi(a.y));
+    v[1] = make_float4(lo(a.z), hi(a.z), lo(a.w), hi(a.w));
+    v[2] = make_float4(lo(b.x), hi(b.x), lo(b.y), hi(b.y));
+    v[3] = make_float4(lo(b.z), hi(b.z), lo(b.w), hi(b.w));
   }
 };
 
@@ -134,6 +141,7 @@ __device__ __forceinline__ bool unit_sample(const SampleSrc& src, int u, int& s,
   return valid;
 }
 
+template <bool kPaired>
 __global__ __launch_bounds__(kUnitSamples) void bin_count_kernel(SampleSrc src, LevelInfo lv, BinLevels bl,
                                                                 uint32_t* __restrict__ hist) {
   extern __shared__ uint32_t cnt[];
@@ -146,7 +154,7 @@ __global__ __launch_bounds__(kUnitSamples) void bin_count_kernel(SampleSrc src, 
   const bool valid = unit_sample(src, u, s, xn);
   Corner8 c;
   corners(xn[0], xn[1], xn[2], lv.res[l], (lv.dense_bits >> l) & 1u, lv.table_mask, lv.offset[l], c);
-  count_records(c, row_run_head(c.cell, valid), lv.offset[l], cnt);
+  count_records<kPaired>(c, row_run_head(c.cell, valid), lv.offset[l], cnt);
   __syncthreads();
   write_counts(bl, l, u, cnt, hist);
 }
@@ -282,7 +290,11 @@ __global__ __launch_bounds__(kUnitSamples) void bin_place_kernel(SampleSrc src, 
   uint32_t* lst = bins_lds + bl.max_level_bins;
   uint32_t* base = bins_lds + 2 * bl.max_level_bins;
   __shared__ uint32_t wsum[kUnitWaves];
-  __shared__ Rec stage[kUnitSamples * 8];
+  // paired records are about four a sample: a stage of six a sample keeps
+  // the workgroup's LDS under 20 KB (eight workgroups a CU); a unit with more
+  // records stores them unstaged
+  constexpr int kStage = kUnitSamples * (R::kPaired ? 6 : 8);
+  __shared__ Rec stage[kStage];
   const int t = (int)threadIdx.x, wave = t / kWave, lane = lane_id();
   int l, u;
   if (R::kInterleaveLevels)
@@ -324,21 +336,36 @@ __global__ __launch_bounds__(kUnitSamples) void bin_place_kernel(SampleSrc src, 
     v[2 * k + 1] = c.w[k] * d.y;
   }
   const bool on = row_cell_runs<16>(c.cell, valid, v) && valid;
+  // records k (and k + 1 unless the pair shares record k): the key is
+  // the bin << 16 | pair code << 13 | in-bin offset
   Rec rec[8];
-  uint32_t rank[8];
+  uint32_t rank[8], pc[4];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const uint32_t e = c.idx[k] - loff;
-    rec[k] = R::pack(((e >> kBinShift) << 16) | (e & (uint32_t)(kBinEntries - 1)), v[2 * k], v[2 * k + 1]);
+  for (int k = 0; k < 8; k += 2) {
+    const uint32_t e0 = c.idx[k] - loff, e1 = c.idx[k + 1] - loff;
+    const uint32_t p = R::kPaired ? pair_code(e0, e1) : 0u;
+    pc[k / 2] = p;
+    const uint32_t k0 = ((e0 >> kBinShift) << 16) | (p << 13) | (e0 & (uint32_t)(kBinEntries - 1));
+    const uint32_t k1 = ((e1 >> kBinShift) << 16) | (e1 & (uint32_t)(kBinEntries - 1));
+    if (p != 0u) {
+      rec[k] = R::pack_pair(k0, v[2 * k], v[2 * k + 1], v[2 * k + 2], v[2 * k + 3]);
+      rec[k + 1] = rec[k];
+    } else {
+      rec[k] = R::pack(k0, v[2 * k], v[2 * k + 1]);
+      rec[k + 1] = R::pack(k1, v[2 * k + 2], v[2 * k + 3]);
+    }
   }
   __syncthreads();
-  // ranks in the bins; the two x-neighbour corners (k, k + 1) nearly always
-  // share a bin and then take two consecutive ranks from one atomic
+  // ranks in the bins: a paired record takes one; two records of the
+  // x-neighbour corners (k, k + 1) nearly always share a bin and then take
+  // two consecutive ranks from one atomic
   if (on) {
 #pragma unroll
     for (int k = 0; k < 8; k += 2) {
       const uint32_t ba = R::key(rec[k]) >> 16, bb = R::key(rec[k + 1]) >> 16;
-      if (ba == bb) {
+      if (pc[k / 2] != 0u) {
+        rank[k] = atomicAdd(&cnt[ba], 1u);
+      } else if (ba == bb) {
         rank[k] = atomicAdd(&cnt[ba], 2u);
         rank[k + 1] = rank[k] + 1u;
       } else {
@@ -371,13 +398,26 @@ __global__ __launch_bounds__(kUnitSamples) void bin_place_kernel(SampleSrc src, 
     run += cnt[k];
   }
   __syncthreads();
+  if (m > (uint32_t)kStage) {  // (uniform) each record straight to its slot
+    if (on) {
+#pragma unroll
+      for (int k = 0; k < 8; k += 2) {
+        const uint32_t ba = R::key(rec[k]) >> 16, bb = R::key(rec[k + 1]) >> 16;
+        R::store(rb, base[ba] + lst[ba] + rank[k], rec[k]);
+        if (pc[k / 2] == 0u) R::store(rb, base[bb] + lst[bb] + rank[k + 1], rec[k + 1]);
+      }
+    }
+    return;
+  }
   if (on) {
-    // a pair that took consecutive ranks in one bin takes consecutive slots
+    // two records that took consecutive ranks in one bin take consecutive
+    // slots
 #pragma unroll
     for (int k = 0; k < 8; k += 2) {
       const uint32_t ba = R::key(rec[k]) >> 16, bb = R::key(rec[k + 1]) >> 16;
       const uint32_t sa = lst[ba] + rank[k];
       stage[sa] = rec[k];
+      if (pc[k / 2] != 0u) continue;
       if (ba == bb)
         stage[sa + 1] = rec[k + 1];
       else
@@ -395,7 +435,7 @@ __global__ __launch_bounds__(kUnitSamples) void bin_place_kernel(SampleSrc src, 
 // included) instead of adding them to the gradient.
 template <class R>
 __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffers rb, BinLevels bl, uint32_t chunk,
-                                                                    float* __restrict__ grad_table,
+                                                                    bool scattered, float* __restrict__ grad_table,
                                                                     float* __restrict__ overflow, bool overwrite) {
   // (g0, g1) of each entry as one 64-bit word: float pairs are added with
   // LDS 64-bit compare-and-swap, which retires far faster than LDS float
@@ -432,10 +472,10 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
   // in a scattered order (t -> 29 t mod 1024), so that the lanes of a wave
   // meet different entries in their compare-and-swap instead of queueing on
   // one; with full chunks they read consecutive groups, coalesced.
-  const uint32_t tp = chunk < kChunk ? (threadIdx.x * 29u) & (kReduceThreads - 1) : threadIdx.x;
+  const uint32_t tp = scattered ? (threadIdx.x * 29u) & (kReduceThreads - 1) : threadIdx.x;
   for (uint32_t gb = g0; gb < g1; gb += kReduceThreads * 2) {
     uint2 kk[2];
-    float2 vv[2][4];
+    float4 vv[2][4];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const uint32_t gi = gb + j * kReduceThreads + tp;
@@ -450,7 +490,12 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         if (p0 + u < first || p0 + u >= last) continue;
-        add(k4[u], vv[j][u].x, vv[j][u].y);
+        const uint32_t o = k4[u] & (uint32_t)(kBinEntries - 1);
+        add(o, vv[j][u].x, vv[j][u].y);
+        if (R::kPaired) {
+          const uint32_t pc = k4[u] >> 13;
+          if (pc != 0u) add(o ^ ((1u << pc) - 1u), vv[j][u].z, vv[j][u].w);
+        }
       }
     }
   }
@@ -517,7 +562,9 @@ BinPlan bin_plan(const LevelInfo& lv, uint32_t entries, int64_t max_samples) {
     while (c < kChunk && (int64_t)c * 2 * 8192 <= p.max_records) c *= 2;
     p.chunk = c;
   }
-  p.max_chunks = (int)(p.nbins + (p.max_records + p.chunk - 1) / p.chunk);
+  // paired records (two corner additions each) are cut into chunks of half
+  // as many
+  p.max_chunks = (int)(p.nbins + (p.max_records + p.chunk / 2 - 1) / (p.chunk / 2));
   return p;
 }
 
@@ -533,7 +580,12 @@ hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSr
   const dim3 grid(p.levels * p.nunits);
   const size_t level_lds = (size_t)p.bl.max_level_bins * sizeof(uint32_t);
   if (!counted)
-    hipLaunchKernelGGL(bin_count_kernel, grid, dim3(kUnitSamples), level_lds, st, src, lv, p.bl, rb.hist);
+    if (bf16_values)
+      hipLaunchKernelGGL(bin_count_kernel<RecBF16::kPaired>, grid, dim3(kUnitSamples), level_lds, st, src, lv, p.bl,
+                         rb.hist);
+    else
+      hipLaunchKernelGGL(bin_count_kernel<RecF32::kPaired>, grid, dim3(kUnitSamples), level_lds, st, src, lv, p.bl,
+                         rb.hist);
   if (ws) {
     const bool loss = ws->ls.loss != nullptr;
     if (ws->shape == kShapeTiny)
@@ -545,17 +597,22 @@ hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSr
   } else {
     hipLaunchKernelGGL(bin_colscan_kernel, dim3(p.nbins), dim3(kColThreads), 0, st, rb, p.nunits);
   }
-  hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins, p.chunk);
+  // a chunk holds at most p.chunk corner additions: as many records, or half
+  // as many paired ones; the small chunks of tables of few bins read their
+  // record groups in a scattered order
+  const uint32_t chunk = bf16_values && RecBF16::kPaired ? p.chunk / 2 : p.chunk;
+  const bool scattered = p.chunk < kChunk;
+  hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins, chunk);
   if (bf16_values) {
     hipLaunchKernelGGL(bin_place_kernel<RecBF16>, grid, dim3(kUnitSamples), 3 * level_lds, st, src, lv, p.bl, rb,
                        zero_table);
     hipLaunchKernelGGL(bin_reduce_kernel<RecBF16>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.bl,
-                       p.chunk, grad_table, overflow, overwrite);
+                       chunk, scattered, grad_table, overflow, overwrite);
   } else {
     hipLaunchKernelGGL(bin_place_kernel<RecF32>, grid, dim3(kUnitSamples), 3 * level_lds, st, src, lv, p.bl, rb,
                        zero_table);
     hipLaunchKernelGGL(bin_reduce_kernel<RecF32>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.bl,
-                       p.chunk, grad_table, overflow, overwrite);
+                       chunk, scattered, grad_table, overflow, overwrite);
   }
   return hipGetLastError();
 }

@@ -106,22 +106,30 @@ def test_encode_entry_points_match_oracle(nsl, gpu, spec, S):
 LARGE_TABLE = dataclasses.replace(W.C1_FIELD, log2_table=22, base_res=128)
 
 
-@pytest.mark.parametrize("spec,S", [(W.C1_FIELD, 2049), (W.C2_FIELD, 4099), (W.C2_FIELD, 65537),
-                                    (LARGE_TABLE, 65537)],
-                         ids=["tiny", "full", "full-64k", "large-table"])
-def test_encode_bwd_entry_point_matches_oracle(nsl, gpu, spec, S):
+@pytest.mark.parametrize("spec,S,unpaired", [(W.C1_FIELD, 2049, False), (W.C2_FIELD, 4099, False),
+                                             (W.C2_FIELD, 65537, False), (LARGE_TABLE, 65537, False),
+                                             (W.C2_FIELD, 4099, True)],
+                         ids=["tiny", "full", "full-64k", "large-table", "full-unpaired"])
+def test_encode_bwd_entry_point_matches_oracle(nsl, gpu, spec, S, unpaired):
     """nsl_encode_bwd scatters a random dL/de into the table gradient: every
     table entry against the oracle's scatter at 1e-5 (FP32 records) and 2e-2
     (BF16 records), overwriting (untouched entries become 0) and
     accumulating onto a prior value; the weights' part of grads is left
-    alone."""
+    alone.  unpaired: the first 1024 samples lie in x-cell 127 of the finest
+    level (2048 cells a side), whose x-neighbour corners differ in eight low
+    bits of the hashed index and so travel as two records, not one paired
+    record: those units hold more records than the placement stages."""
     import torch
     dev = gpu
     f = nsl.Field(spec)
     lay = f.layout
     rng = np.random.default_rng(S + 1)
     xn = rng.uniform(size=(S, 3)).astype(np.float32)
-    xn[: S // 4] = np.clip(0.5 * xn[0] + 1e-3 * rng.uniform(size=(S // 4, 3)), 0, 1)   # shared cells
+    if unpaired:
+        assert spec.levels == 16 and spec.max_res == 2048
+        xn[:1024, 0] = ((127.0 + rng.uniform(0.05, 0.95, 1024)) / 2048.0).astype(np.float32)
+    else:
+        xn[: S // 4] = np.clip(0.5 * xn[0] + 1e-3 * rng.uniform(size=(S // 4, 3)), 0, 1)   # shared cells
     de = rng.normal(size=(spec.levels, S, 2)).astype(np.float32)
     _, _, corners = ofield.encode_fwd(spec, np.zeros(lay["table_floats"]), xn)
     de_sf = de.transpose(1, 0, 2).reshape(S, 2 * spec.levels).astype(np.float64)
