@@ -439,7 +439,7 @@ int nsl_depth_covariance(int c, int p, const double* C, const double* Et, const 
 /* ------------------------------------------------------------------------
  * Rendering (Sec. 3.3: the mapping thread also renders for interactive
  * visualisation).  Uniform samples t_i = t_near + (i+1/2)*dt,
- * i < n_samples <= 64; a ray stops before its first sample with
+ * i < n_samples <= NSL_RENDER_MAX_SAMPLES; a ray stops before its first sample with
  * T_i < stop_T (0 disables), which also ends its work.  One wave renders
  * one ray; per pixel: rgb, depth_z, var_z (z units) and opacity.
  * ------------------------------------------------------------------------ */
@@ -450,6 +450,7 @@ typedef struct nsl_render_config {
 } nsl_render_config;
 
 #define NSL_RENDER_TILE 64  /* pixels per render tile (one workgroup) */
+#define NSL_RENDER_MAX_SAMPLES 1024  /* samples per ray at most */
 
 /* Parameter snapshot operands: the weights of `params` laid out for the
  * MFMA kernels.  A snapshot (params copy + prepared operands) stays valid

@@ -856,7 +856,8 @@ int nsl_adam(float* p, float* g, float* m, float* v, int64_t n, float lr, float 
 
 static int check_render_cfg(const nsl_render_config* c) {
   if (!c) return fail(NSL_E_INVALID, "null render config");
-  if (c->n_samples < 1 || c->n_samples > 64) return fail(NSL_E_INVALID, "n_samples must be in [1, 64]");
+  if (c->n_samples < 1 || c->n_samples > kRenderMaxSamples)
+    return fail(NSL_E_INVALID, "n_samples must be in [1, %d]", kRenderMaxSamples);
   if (!(c->dt > 0.0f) || !(c->stop_T >= 0.0f) || !(c->t_near >= 0.0f)) return fail(NSL_E_INVALID, "bad render config");
   return NSL_OK;
 }

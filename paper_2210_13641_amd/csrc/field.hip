@@ -446,13 +446,15 @@ __global__ __launch_bounds__(kFieldBwdWaves * kWave, 1) void field_bwd_kernel(Fi
 // exit once the transmittance left for the ray is below stop_T.
 // ---------------------------------------------------------------------------
 
-constexpr int kRenderMaxTiles = 4;  // n_samples <= 64
-
+// The weight and t of every composited sample wait in LDS (per wave, the
+// samples of its current ray) for the second pass of V*, so a ray may take up
+// to kRenderMaxSamples samples.
 template <class N>
 __global__ __launch_bounds__(256) void render_kernel(LevelInfo lv, Aabb box, const nsl_render_request* __restrict__ reqs,
                                                      int n_req, const nsl_render_tile* __restrict__ tiles,
                                                      RenderParams rp) {
   __shared__ __attribute__((aligned(16))) float Af[N::FWD_FLOATS];
+  extern __shared__ float2 wt_lds[];  // [4 waves][16 * ntiles] (w, t), written by the lanes of row 0
   nsl_render_tile tile;
   if (tiles) {
     tile = tiles[blockIdx.x];
@@ -473,6 +475,7 @@ __global__ __launch_bounds__(256) void render_kernel(LevelInfo lv, Aabb box, con
   LaneLevels<N> ll;
   lane_levels<N>(lv, g, ll);
   const int ntiles = (rp.n_samples + 15) / 16;
+  float2* wt = wt_lds + (size_t)wave * 16 * ntiles;
   for (int px = first + wave; px < last; px += 4) {
     const int v = px / rq.W, u = px - v * rq.W;
     float o[3], d[3], s;
@@ -480,12 +483,9 @@ __global__ __launch_bounds__(256) void render_kernel(LevelInfo lv, Aabb box, con
     Acts<N> act;
     sh_lane<N>(d, g, act.sh);
     float carry = 0.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, D = 0.0f, A = 0.0f;
-    float wt[kRenderMaxTiles], tt[kRenderMaxTiles];
-#pragma unroll
-    for (int ti = 0; ti < kRenderMaxTiles; ++ti) wt[ti] = tt[ti] = 0.0f;  // tiles after an early exit stay 0
-#pragma unroll
-    for (int ti = 0; ti < kRenderMaxTiles; ++ti) {
-      if (ti >= ntiles) continue;
+    int used = 0;  // tiles composited (the rest of the ray is not)
+    wave_lds_fence();  // the previous ray's V* reads are done before this ray's writes
+    for (int ti = 0; ti < ntiles; ++ti) {
       const int j = ti * 16 + jc;
       const bool valid = j < rp.n_samples;
       float t;
@@ -504,8 +504,8 @@ __global__ __launch_bounds__(256) void render_kernel(LevelInfo lv, Aabb box, con
       const float T = expf(-(carry + (incl - tau)));
       const bool on = valid && !(rp.stop_T > 0.0f && T < rp.stop_T);
       const float w = on ? T * -expm1f(-tau) : 0.0f;
-      wt[ti] = w;
-      tt[ti] = t;
+      if (g == 0) wt[j] = make_float2(w, t);
+      used = ti + 1;
       C0 += w * sigmoidf(act.z[0]);
       C1 += w * sigmoidf(act.z[1]);
       C2 += w * sigmoidf(act.z[2]);
@@ -519,10 +519,16 @@ __global__ __launch_bounds__(256) void render_kernel(LevelInfo lv, Aabb box, con
     C2 = row_sum(C2);
     D = row_sum(D);
     A = row_sum(A);
+    // V* = sum w (t - d*)^2, d* of row 0, over the composited samples
+    const float Dr = __shfl(D, 0, kWave);
+    wave_lds_fence();
     float V = 0.0f;
+    for (int i = lane; i < 16 * used; i += kWave) {
+      const float2 p = wt[i];
+      V += p.x * (p.y - Dr) * (p.y - Dr);
+    }
 #pragma unroll
-    for (int ti = 0; ti < kRenderMaxTiles; ++ti) V += wt[ti] * (tt[ti] - D) * (tt[ti] - D);
-    V = row_sum(V);
+    for (int o2 = 1; o2 < kWave; o2 <<= 1) V += __shfl_xor(V, o2, kWave);
     if (lane == 0) {
       rq.rgb[3 * (size_t)px] = C0;
       rq.rgb[3 * (size_t)px + 1] = C1;
@@ -568,7 +574,8 @@ template <class N>
 static hipError_t launch_render(const LevelInfo& lv, const Aabb& box, const nsl_render_request* reqs, int n_req,
                                 const nsl_render_tile* tiles, int n_tiles, const RenderParams& rp, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(render_kernel<N>, dim3(n_tiles), dim3(256), 0, st, lv, box, reqs, n_req, tiles, rp);
+  const size_t lds = (size_t)4 * 16 * ((rp.n_samples + 15) / 16) * sizeof(float2);
+  hipLaunchKernelGGL(render_kernel<N>, dim3(n_tiles), dim3(256), lds, st, lv, box, reqs, n_req, tiles, rp);
   return hipGetLastError();
 }
 

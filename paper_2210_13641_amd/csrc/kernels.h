@@ -150,8 +150,9 @@ hipError_t field_encode(int shape, const FieldArgs& a, const SampleSrc& src, int
 
 struct RenderParams {
   float t_near, dt, stop_T;
-  int n_samples;
+  int n_samples;  // at most kRenderMaxSamples
 };
+constexpr int kRenderMaxSamples = NSL_RENDER_MAX_SAMPLES;
 // Fused ray-major rendering of tiles (tiles == nullptr: tile t covers pixels
 // [64t, 64t+64) of request 0).
 hipError_t render_tiles(int shape, const LevelInfo& lv, const Aabb& box, const nsl_render_request* reqs,

@@ -28,13 +28,19 @@ def _render(nsl, torch, dev, f, P, pose, intr, H, Wd, cfg):
     return rgb.cpu().numpy(), depth.cpu().numpy(), var.cpu().numpy(), op.cpu().numpy()
 
 
-@pytest.mark.parametrize("spec,stop_T", [(W.C1_FIELD, 0.0), (W.C1_FIELD, 0.3), (W.C2_FIELD, 0.0),
-                                         (W.C2_FIELD, 0.3)], ids=["tiny", "tiny-stop", "full", "full-stop"])
-def test_render_matches_oracle(nsl, gpu, spec, stop_T):
+@pytest.mark.parametrize("spec,stop_T,n,H,Wd", [(W.C1_FIELD, 0.0, 32, 18, 27), (W.C1_FIELD, 0.3, 32, 18, 27),
+                                                (W.C2_FIELD, 0.0, 32, 18, 27), (W.C2_FIELD, 0.3, 32, 18, 27),
+                                                (W.C1_FIELD, 0.0, 200, 18, 27), (W.C2_FIELD, 0.3, 200, 9, 11),
+                                                (W.C2_FIELD, 0.0, 1024, 5, 13)],
+                         ids=["tiny", "tiny-stop", "full", "full-stop", "tiny-200", "full-stop-200", "full-1024"])
+def test_render_matches_oracle(nsl, gpu, spec, stop_T, n, H, Wd):
+    """Rendered colour, depth, opacity and V* against the oracle's render at
+    1e-5 of their magnitudes; images are not a multiple of the 64-pixel tile,
+    and the sample counts include a ragged last tile (200) and the largest
+    count a ray may take (1024)."""
     import torch
     dev = gpu
-    H, Wd, n = 18, 27, 32                  # not a multiple of the 64-pixel tile
-    report(f"render: levels={spec.levels} {Wd}x{H} stop_T={stop_T}")
+    report(f"render: levels={spec.levels} {Wd}x{H} n={n} stop_T={stop_T}")
     f = nsl.Field(spec)
     flat, t64, w64 = params_for(spec, f.layout, seed=8, table_range=2.0)
     pose = W.look_at_pose((1.5 * np.cos(0.4), 1.5 * np.sin(0.4), 0.2)).astype(np.float32)
