@@ -448,9 +448,16 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   // with the encoding kept, the encoding kernel also counts the
   // table-gradient records per bin and unit
   const bool counted = c->keep_encoding != 0 && b.plan.bl.max_level_bins <= kEncodeLevelBins;
-  if (mixed) {
-    // the gradient clearing and the overflow-flag reset ride along the FP16
-    // table copy
+  // the mixed step prepares (FP16 table copy, gradient clearing,
+  // overflow-flag reset, BF16 operands) and counts the candidates' samples in
+  // one launch; profiled steps keep them apart to time the two phases
+  const bool fused_count = mixed && !prof;
+  if (fused_count) {
+    HIP_TRY(mixed_prepare_count(f->shape, params, f->wo, f->lay.table_floats, b.shadow,
+                                c->zero_grads ? grads : nullptr, total, c->scale_state ? c->scale_state + 3 : nullptr,
+                                store_of(m), march_of(f, c), ids, n, b.rb, st),
+            "prep mixed and ray setup");
+  } else if (mixed) {
     HIP_TRY(mixed_prepare(f->shape, params, f->wo, f->lay.table_floats, b.shadow, c->zero_grads ? grads : nullptr,
                           total, c->scale_state ? c->scale_state + 3 : nullptr, st),
             "prep mixed");
@@ -462,7 +469,13 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
     HIP_TRY(field_prep(f->shape, params, f->wo, b.wprep, st), "prep weights");
   }
   HIP_TRY(mark(1), "profile event");
-  if ((rc = run_march(m, f, c, ids, n, b, st))) return rc;
+  if (fused_count) {
+    const MarchParams mp = march_of(f, c);
+    HIP_TRY(march_scan(mp, n, b.rb, st), "march scan");
+    HIP_TRY(march_emit(store_of(m), mp, ids, n, b.rb, b.t, b.ray, st), "march emit");
+  } else if ((rc = run_march(m, f, c, ids, n, b, st))) {
+    return rc;
+  }
   HIP_TRY(mark(2), "profile event");
 
   FieldArgs fa{params, b.wprep, f->lv};

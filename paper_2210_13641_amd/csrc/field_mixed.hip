@@ -8,6 +8,7 @@
 // filled from two 16-row output tiles of the previous layer (rows 4g..4g+3
 // of each), and the weights are laid out for that permutation.
 #include "field_common.h"
+#include "march_common.h"
 
 namespace nsl {
 
@@ -141,17 +142,41 @@ __device__ __forceinline__ void table_to_half(const float* __restrict__ t, _Floa
 // One launch prepares a mixed-precision step: workgroups [0, tblocks) copy
 // the table to FP16 (and clear the gradient tail), the rest lay out the BF16
 // weight operands; clear_flag (may be null), the loss-scale overflow flag, is
-// reset by the first thread.
+// reset by the first thread.  Workgroup b of the preparation.
+template <class N>
+__device__ __forceinline__ void prepare_block(const float* __restrict__ params, const WOffsets& wo,
+                                              __bf16* __restrict__ ops, _Float16* __restrict__ t16, int64_t tf,
+                                              float* __restrict__ g, int64_t total, int tblocks,
+                                              float* __restrict__ clear_flag, int b) {
+  if (clear_flag && b == 0 && threadIdx.x == 0) *clear_flag = 0.0f;
+  if (b < tblocks)
+    table_to_half(params, t16, tf, g, total, ((int64_t)b * 256 + threadIdx.x) * 8);
+  else
+    prep_operand<N>(params, wo, ops, (b - tblocks) * 256 + (int)threadIdx.x);
+}
+
 template <class N>
 __global__ __launch_bounds__(256) void mixed_prepare_kernel(const float* __restrict__ params, WOffsets wo,
                                                             __bf16* __restrict__ ops, _Float16* __restrict__ t16,
                                                             int64_t tf, float* __restrict__ g, int64_t total,
                                                             int tblocks, float* __restrict__ clear_flag) {
-  if (clear_flag && blockIdx.x == 0 && threadIdx.x == 0) *clear_flag = 0.0f;
-  if ((int)blockIdx.x < tblocks)
-    table_to_half(params, t16, tf, g, total, ((int64_t)blockIdx.x * 256 + threadIdx.x) * 8);
-  else
-    prep_operand<N>(params, wo, ops, ((int)blockIdx.x - tblocks) * 256 + (int)threadIdx.x);
+  prepare_block<N>(params, wo, ops, t16, tf, g, total, tblocks, clear_flag, (int)blockIdx.x);
+}
+
+// The step's first launch: workgroups [0, ncount) set up the candidate rays
+// and count their samples, the rest prepare the step as above.  The two are
+// independent, so the latency-bound marching overlaps the streaming table
+// copy instead of following it.
+template <class N>
+__global__ __launch_bounds__(256) void mixed_prepare_count_kernel(
+    const float* __restrict__ params, WOffsets wo, __bf16* __restrict__ ops, _Float16* __restrict__ t16, int64_t tf,
+    float* __restrict__ g, int64_t total, int tblocks, float* __restrict__ clear_flag, KeyframeStore kf,
+    MarchParams mp, const uint32_t* __restrict__ ids, int n, RayBuffers rb, int ncount) {
+  if ((int)blockIdx.x < ncount) {
+    march_detail::rays_count_block(kf, mp, ids, n, rb, (int)blockIdx.x);
+    return;
+  }
+  prepare_block<N>(params, wo, ops, t16, tf, g, total, tblocks, clear_flag, (int)blockIdx.x - ncount);
 }
 
 template <class N>
@@ -742,17 +767,28 @@ size_t mixed_shadow_bytes(int shape, int64_t table_floats) {
   return ops + ((size_t)table_floats * 2 + 255) / 256 * 256;
 }
 
+// With kf set, the same launch also sets up the n candidate rays and counts
+// their samples.
 template <class N>
 static hipError_t prep_impl(const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
-                            float* zero_grads, int64_t total, float* clear_flag, hipStream_t st) {
+                            float* zero_grads, int64_t total, float* clear_flag, const KeyframeStore* kf,
+                            const MarchParams* mp, const uint32_t* ids, int n, const RayBuffers* rb,
+                            hipStream_t st) {
   using M = Mixed<N>;
-  const int n = M::FWD + M::BWD;
+  const int nops = M::FWD + M::BWD;
   _Float16* t16 = reinterpret_cast<_Float16*>(static_cast<char*>(shadow) + mixed_ops_bytes<N>());
   const int64_t span = zero_grads && total > table_floats ? total : table_floats;
   const int tblocks = (int)((span + 2047) / 2048);
-  const int oblocks = (n + 255) / 256;
-  hipLaunchKernelGGL(mixed_prepare_kernel<N>, dim3(tblocks + oblocks), dim3(256), 0, st, params, wo,
-                     static_cast<__bf16*>(shadow), t16, table_floats, zero_grads, total, tblocks, clear_flag);
+  const int oblocks = (nops + 255) / 256;
+  if (kf) {
+    const int ncount = (int)march_block_count(n);
+    hipLaunchKernelGGL(mixed_prepare_count_kernel<N>, dim3(ncount + tblocks + oblocks), dim3(256), 0, st, params,
+                       wo, static_cast<__bf16*>(shadow), t16, table_floats, zero_grads, total, tblocks, clear_flag,
+                       *kf, *mp, ids, n, *rb, ncount);
+  } else {
+    hipLaunchKernelGGL(mixed_prepare_kernel<N>, dim3(tblocks + oblocks), dim3(256), 0, st, params, wo,
+                       static_cast<__bf16*>(shadow), t16, table_floats, zero_grads, total, tblocks, clear_flag);
+  }
   return hipGetLastError();
 }
 
@@ -798,8 +834,20 @@ hipError_t mixed_encode(int shape, const LevelInfo& lv, const void* shadow, cons
 
 hipError_t mixed_prepare(int shape, const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
                          float* zero_grads, int64_t total, float* clear_flag, hipStream_t st) {
-  return shape == kShapeTiny ? prep_impl<NetTiny>(params, wo, table_floats, shadow, zero_grads, total, clear_flag, st)
-                             : prep_impl<NetFull>(params, wo, table_floats, shadow, zero_grads, total, clear_flag, st);
+  return shape == kShapeTiny ? prep_impl<NetTiny>(params, wo, table_floats, shadow, zero_grads, total, clear_flag,
+                                                   nullptr, nullptr, nullptr, 0, nullptr, st)
+                             : prep_impl<NetFull>(params, wo, table_floats, shadow, zero_grads, total, clear_flag,
+                                                   nullptr, nullptr, nullptr, 0, nullptr, st);
+}
+
+hipError_t mixed_prepare_count(int shape, const float* params, const WOffsets& wo, int64_t table_floats,
+                               void* shadow, float* zero_grads, int64_t total, float* clear_flag,
+                               const KeyframeStore& kf, const MarchParams& mp, const uint32_t* ids, int n,
+                               const RayBuffers& rb, hipStream_t st) {
+  return shape == kShapeTiny ? prep_impl<NetTiny>(params, wo, table_floats, shadow, zero_grads, total, clear_flag,
+                                                   &kf, &mp, ids, n, &rb, st)
+                             : prep_impl<NetFull>(params, wo, table_floats, shadow, zero_grads, total, clear_flag,
+                                                   &kf, &mp, ids, n, &rb, st);
 }
 
 hipError_t mixed_forward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,

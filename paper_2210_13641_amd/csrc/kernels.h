@@ -215,7 +215,15 @@ hipError_t march_rays(const KeyframeStore& kf, const MarchParams& mp, const uint
                       const RayBuffers& rb, hipStream_t st);
 hipError_t march_emit(const KeyframeStore& kf, const MarchParams& mp, const uint32_t* ids, int n,
                       const RayBuffers& rb, float* t_out, uint32_t* ray_out, hipStream_t st);
+// The offsets and batch cut of counts the ray setup has written.
+hipError_t march_scan(const MarchParams& mp, int n, const RayBuffers& rb, hipStream_t st);
 size_t march_block_count(int n);
+// mixed_prepare and the ray setup and sample counts of march_rays in one
+// launch (field_mixed.hip); march_scan then completes march_rays.
+hipError_t mixed_prepare_count(int shape, const float* params, const WOffsets& wo, int64_t table_floats,
+                               void* shadow, float* zero_grads, int64_t total, float* clear_flag,
+                               const KeyframeStore& kf, const MarchParams& mp, const uint32_t* ids, int n,
+                               const RayBuffers& rb, hipStream_t st);
 
 // composite.hip
 struct CompositeIO {
