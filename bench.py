@@ -55,11 +55,12 @@ def kernel_work(spec, table_bytes):
       field_fwd   the forward MLP;
       field_bwd   the MLP recomputed and its adjoint (input and weight
                   gradients);
-      table_grad  the table-gradient scatter, 8 x L x F FP32 values (four
-                  kernels: column scan, bin starts, placement, reduction; the
-                  encoding kernel counts the records per bin as it gathers,
-                  and the column-scan launch also sums the weight gradients
-                  and the loss)."""
+      table_grad  the table-gradient scatter, 8 x L x F FP32 values (two
+                  kernels: placement and reduction; the encoding kernel
+                  counts the records per bin as it gathers, the forward and
+                  compositing launches run the column scan and the bin
+                  starts, and the placement launch also sums the weight
+                  gradients and the loss)."""
     fwd_mac, dx_mac, dw_mac = mlp_macs(spec)
     n = 8 * spec.levels * spec.feat_per_level
     return {"encode": dict(flops=0, bytes=n * table_bytes),
@@ -81,9 +82,9 @@ def roofline_of(name, work, samples, ms, mlp_peak):
 
 
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_paper_scale.md")
-PMC_SOURCES = ("field.hip", "field_mixed.hip", "field_common.h", "net.h", "common.h", "scatter.hip", "kernels.h")
-BIN_KERNELS = ["bin_colscan_dw_kernel<NetFull >", "bin_start_kernel", "bin_place_kernel<RecBF16>",
-               "bin_reduce_kernel<RecBF16>"]
+PMC_SOURCES = ("field.hip", "field_mixed.hip", "field_common.h", "net.h", "common.h", "scatter.hip", "kernels.h",
+               "bins.h")
+BIN_KERNELS = ["bin_place_kernel<RecBF16, NetFull>", "bin_reduce_kernel<RecBF16>"]
 PMC_ROWS = {("table_grad", 2): BIN_KERNELS,
             ("field_bwd", 2): ["mixed_bwd8_kernel<NetFull>"],
             ("field_fwd", 2): ["mixed_fwd_kernel<NetFull>"],
@@ -135,9 +136,9 @@ def roofline(spec, phase_ms, samples, table_bytes, mlp_peak):
                                  "profiles/pmc_traffic_paper_scale.md)")
             r["algorithmic_bytes"] = work[k]["bytes"] * samples
         if k == "table_grad":
-            r["kernels"] = ("bin_colscan_dw, bin_start, bin_place, bin_reduce (the records are counted by the "
-                            "encoding kernel; the column-scan launch also sums the weight gradients and the loss, "
-                            "about 19 MB of its traffic)")
+            r["kernels"] = ("bin_place, bin_reduce (the records are counted by the encoding kernel, the column "
+                            "scan and bin starts run beside the forward MLP and the compositing; the placement "
+                            "launch also sums the weight gradients and the loss, about 19 MB of its traffic)")
         all_r[k] = r
     dom = max(work, key=lambda k: phase_ms[k])
     return all_r[dom], all_r

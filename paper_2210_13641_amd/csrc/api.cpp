@@ -491,10 +491,21 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
       HIP_TRY(field_encode(f->shape, fa, src, c->max_samples, hist, b.plan.bl, st), "encoding");
   }
   HIP_TRY(mark(3), "profile event");
+  // with the records counted, the table-gradient column scan and bin starts
+  // ride along the forward and the compositing launches
+  BinPrep bp{};
+  if (counted) {
+    bp.rb = b.rec;
+    bp.nunits = b.plan.nunits;
+    bp.nbins = b.plan.nbins;
+    bp.chunk = bin_chunk(b.plan, mixed);
+  }
+  const BinPrep* prescan = counted && b.plan.nbins > 0 && b.plan.nunits > 0 ? &bp : nullptr;
   if (mixed)
-    HIP_TRY(mixed_forward(f->shape, f->lv, b.shadow, src, c->max_samples, b.sigma, b.rgb, st), "field forward");
+    HIP_TRY(mixed_forward(f->shape, f->lv, b.shadow, src, c->max_samples, b.sigma, b.rgb, st, prescan),
+            "field forward");
   else
-    HIP_TRY(field_forward(f->shape, fa, src, c->max_samples, b.sigma, b.rgb, st), "field forward");
+    HIP_TRY(field_forward(f->shape, fa, src, c->max_samples, b.sigma, b.rgb, st, prescan), "field forward");
   HIP_TRY(mark(4), "profile event");
 
   CompositeIO io{};
@@ -504,7 +515,7 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
   lo.target = b.rb.target; lo.prec = b.rb.prec; lo.rays = b.rb.rays; lo.stats = b.rb.stats;
   lo.lambda_d = c->lambda_d; lo.loss_scale = c->loss_scale; lo.scale_dev = c->scale_state;
   lo.loss = loss_out; lo.parts = b.loss_parts; lo.ray_out = ray_out;
-  HIP_TRY(composite_loss_backward(io, lo, b.dsigma, b.drgb, st), "composite");
+  HIP_TRY(composite_loss_backward(io, lo, b.dsigma, b.drgb, st, prescan), "composite");
   HIP_TRY(mark(5), "profile event");
 
   if (mixed)
@@ -516,10 +527,12 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
             "field backward");
   HIP_TRY(mark(6), "profile event");
   float* overflow = c->scale_state ? c->scale_state + 3 : nullptr;  // set by the two gradient writers
-  // the weight-gradient and loss sums ride along the scatter's column scan
+  // the weight-gradient and loss sums ride along the scatter's placement (or,
+  // when it scans the counts itself, its column scan)
   const WeightSum wsum{f->shape, b.partial, kBwdBlocks, f->wo, grads, overflow,
                      LossSum{b.loss_parts, n, c->lambda_d, loss_out}};
-  HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, mixed, c->zero_grads != 0, grads, overflow, st, counted, &wsum),
+  HIP_TRY(bin_scatter(b.plan, b.rec, src, f->lv, mixed, c->zero_grads != 0, grads, overflow, st, counted, &wsum,
+                      prescan != nullptr),
           "table, weight and loss gradients");
   HIP_TRY(mark(7), "profile event");
   HIP_TRY(mark(8), "profile event");

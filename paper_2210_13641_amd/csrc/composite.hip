@@ -8,7 +8,7 @@
 // (q = c for colour, t for d*, 1 for the opacity A),
 // dV*/dtau_k = [T_{k+1} u_k - (V* - V_{<=k})] - 2 d* (1 - A) dd*/dtau_k with
 // u_i = (t_i - d*)^2; dL/dsigma_k = delta dL/dtau_k and dL/dc_k = g_C w_k.
-#include "kernels.h"
+#include "bins.h"
 
 namespace nsl {
 
@@ -247,7 +247,13 @@ __device__ __forceinline__ void ray_backward_cached(uint32_t b, uint32_t n, cons
 // Train step: forward sums, loss terms and seeds, adjoint.
 __global__ __launch_bounds__(256) void composite_loss_kernel(CompositeIO io, LossIO lo,
                                                              float* __restrict__ g_sigma,
-                                                             float* __restrict__ g_rgb_s) {
+                                                             float* __restrict__ g_rgb_s, BinPrep bp) {
+  // with bp.nbins, the last workgroup sets the table-gradient bin starts
+  // (bins.h): they need only the column scan of the forward launch
+  if (bp.nbins > 0 && blockIdx.x == gridDim.x - 1) {
+    bin_start_block<256>(bp.rb, bp.nbins, bp.chunk);
+    return;
+  }
   const int r = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
   if (r >= io.R) return;
   uint32_t b, n;
@@ -354,10 +360,12 @@ hipError_t loss_terms(const float* out6, int R, const float* rgb_target, const f
 }
 
 hipError_t composite_loss_backward(const CompositeIO& io, const LossIO& lo, float* g_sigma,
-                                   float* g_rgb_s, hipStream_t st) {
-  if (io.R > 0) {
-    hipLaunchKernelGGL(composite_loss_kernel, grid_for(io.R), dim3(256), 0, st, io, lo, g_sigma, g_rgb_s);
-  }
+                                   float* g_rgb_s, hipStream_t st, const BinPrep* bp) {
+  const BinPrep none{};
+  const BinPrep& b = bp ? *bp : none;
+  const int grid = (int)grid_for(io.R).x + (b.nbins > 0 ? 1 : 0);
+  if (grid > 0)
+    hipLaunchKernelGGL(composite_loss_kernel, dim3(grid), dim3(256), 0, st, io, lo, g_sigma, g_rgb_s, b);
   return hipGetLastError();
 }
 

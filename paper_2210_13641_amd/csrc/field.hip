@@ -7,6 +7,7 @@
 // the first MFMA layer (net.h).  Nothing but sigma and colour leaves the
 // forward kernel; the backward kernel re-derives every activation from the
 // sample position instead of reading stored activations.
+#include "bins.h"
 #include "field_common.h"
 
 namespace nsl {
@@ -166,10 +167,17 @@ __device__ __forceinline__ void fwd_tile_out(const float* Af, int lane, int g, i
 constexpr int kFieldFwdGrid = 768;
 constexpr bool kFieldFwdPrefetch = true;
 
+// Workgroups past the MLP's (bp.nbins of them) run the table-gradient column
+// scan (bins.h), which needs only the record counts of the encoding.
 template <class N>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void field_fwd_kernel(FieldArgs a, SampleSrc src,
                                                         float* __restrict__ sigma_out,
-                                                        float* __restrict__ rgb_out) {
+                                                        float* __restrict__ rgb_out, BinPrep bp) {
+  const int G = (int)gridDim.x - bp.nbins;  // the MLP's workgroups
+  if ((int)blockIdx.x >= G) {
+    colscan_bin(bp.rb, bp.nunits, (int)blockIdx.x - G);
+    return;
+  }
   __shared__ __attribute__((aligned(16))) float Af[N::FWD_FLOATS];
   load_operands<N>(Af, a.wprep, N::FWD_FLOATS);
   __syncthreads();
@@ -177,7 +185,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void f
   const int ntiles = (S + 15) / 16;
   const int lane = lane_id(), g = lane >> 4, jc = lane & 15;
   const int first = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-  const int step = gridDim.x * (blockDim.x / kWave);
+  const int step = G * (blockDim.x / kWave);
   if (first >= ntiles) return;
   if (kFieldFwdPrefetch && src.ecache) {
     auto rid = [&](int s) -> uint32_t { return src.t && s < S ? src.ray[s] : 0u; };
@@ -553,11 +561,13 @@ static hipError_t launch_prep(const float* params, const WOffsets& wo, float* ou
 
 template <class N>
 static hipError_t launch_fwd(const FieldArgs& a, const SampleSrc& src, int max_samples,
-                             float* sigma, float* rgb, hipStream_t st) {
+                             float* sigma, float* rgb, hipStream_t st, const BinPrep* bp) {
   const int tiles = (max_samples + 15) / 16;
-  if (tiles == 0) return hipSuccess;
   const int grid = (tiles + 3) / 4 < kFieldFwdGrid ? (tiles + 3) / 4 : kFieldFwdGrid;
-  hipLaunchKernelGGL(field_fwd_kernel<N>, dim3(grid), dim3(256), 0, st, a, src, sigma, rgb);
+  const BinPrep none{};
+  const BinPrep& b = bp ? *bp : none;
+  if (grid + b.nbins > 0)
+    hipLaunchKernelGGL(field_fwd_kernel<N>, dim3(grid + b.nbins), dim3(256), 0, st, a, src, sigma, rgb, b);
   return hipGetLastError();
 }
 
@@ -602,7 +612,10 @@ hipError_t field_encode(int shape, const FieldArgs& a, const SampleSrc& src, int
                              : launch_encode<NetFull>(a, src, max_samples, hist, bl, st);
 }
 
-__global__ __launch_bounds__(256) void loss_sum_kernel(LossSum ls) { loss_sum_block(ls); }
+__global__ __launch_bounds__(256) void loss_sum_kernel(LossSum ls) {
+  __shared__ float lds[kSumScratchFloats];
+  loss_sum_block(ls, lds);
+}
 
 hipError_t loss_sum(const LossSum& ls, hipStream_t st) {
   hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(256), 0, st, ls);
@@ -631,9 +644,9 @@ hipError_t field_prep(int shape, const float* params, const WOffsets& wo, float*
 }
 
 hipError_t field_forward(int shape, const FieldArgs& a, const SampleSrc& src, int max_samples,
-                         float* sigma, float* rgb, hipStream_t st) {
-  return shape == kShapeTiny ? launch_fwd<NetTiny>(a, src, max_samples, sigma, rgb, st)
-                             : launch_fwd<NetFull>(a, src, max_samples, sigma, rgb, st);
+                         float* sigma, float* rgb, hipStream_t st, const BinPrep* bp) {
+  return shape == kShapeTiny ? launch_fwd<NetTiny>(a, src, max_samples, sigma, rgb, st, bp)
+                             : launch_fwd<NetFull>(a, src, max_samples, sigma, rgb, st, bp);
 }
 
 hipError_t field_backward(int shape, const FieldArgs& a, const SampleSrc& src, int nblocks,

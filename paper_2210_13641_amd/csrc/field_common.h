@@ -190,15 +190,20 @@ __host__ __device__ constexpr int encode_grid(int max_samples) {
 // levels, XCD x takes level x for every unit, then level x + 8, and so on, so
 // that consecutive units of a level run on one XCD; with other level counts
 // consecutive workgroups take consecutive levels.
-__device__ __forceinline__ void level_unit(int levels, int nunits, int& l, int& u) {
+// wg: the workgroup's index among those of the kernel (a launch that puts
+// other work in its first workgroups passes blockIdx.x less a multiple of 8).
+__device__ __forceinline__ void level_unit(int levels, int nunits, int& l, int& u, uint32_t wg) {
   if (levels % 8 == 0) {
-    const int x = (int)(blockIdx.x % 8u), j = (int)(blockIdx.x / 8u);
+    const int x = (int)(wg % 8u), j = (int)(wg / 8u);
     l = x + 8 * (j / nunits);
     u = j % nunits;
   } else {
-    l = (int)(blockIdx.x % (uint32_t)levels);
-    u = (int)(blockIdx.x / (uint32_t)levels);
+    l = (int)(wg % (uint32_t)levels);
+    u = (int)(wg / (uint32_t)levels);
   }
+}
+__device__ __forceinline__ void level_unit(int levels, int nunits, int& l, int& u) {
+  level_unit(levels, nunits, l, u, blockIdx.x);
 }
 
 // As level_unit, but with a multiple of 8 levels the workgroups of XCD x
@@ -206,14 +211,14 @@ __device__ __forceinline__ void level_unit(int levels, int nunits, int& l, int& 
 // samples' inputs that every level reads are fetched into that XCD's L2
 // once for all of its levels (for kernels that gather no table, whose L2
 // need not hold one level's slice at a time).
-__device__ __forceinline__ void level_unit_interleaved(int levels, int nunits, int& l, int& u) {
+__device__ __forceinline__ void level_unit_interleaved(int levels, int nunits, int& l, int& u, uint32_t wg) {
   if (levels % 8 == 0) {
     const int m = levels / 8;
-    const int x = (int)(blockIdx.x % 8u), j = (int)(blockIdx.x / 8u);
+    const int x = (int)(wg % 8u), j = (int)(wg / 8u);
     l = x + 8 * (j % m);
     u = j / m;
   } else {
-    level_unit(levels, nunits, l, u);
+    level_unit(levels, nunits, l, u, wg);
   }
 }
 
@@ -383,10 +388,15 @@ struct DWAcc {
   }
 };
 
+// LDS scratch of the sums below (floats), passed in by the kernel, which may
+// lend memory it uses otherwise.
+constexpr int kSumScratchFloats = 512;
+
 // The loss of a step from its per-ray shares, summed in a fixed order by one
 // 256-thread workgroup: loss = (L_rgb + lambda_d L_D, L_rgb, L_D).
-__device__ __forceinline__ void loss_sum_block(const LossSum& ls) {
-  __shared__ float s0[256], s1[256];
+__device__ __forceinline__ void loss_sum_block(const LossSum& ls, float* lds) {
+  float* s0 = lds;
+  float* s1 = lds + 256;
   const int t = threadIdx.x;
   const float2* __restrict__ p2 = reinterpret_cast<const float2*>(ls.parts);
   float a = 0.0f, b = 0.0f;
@@ -433,12 +443,12 @@ constexpr int dw_reduce_blocks(bool with_loss) {
 template <class N>
 __device__ __forceinline__ void dw_reduce_block(const float* __restrict__ partial, int nblocks, const WOffsets& wo,
                                                 float* __restrict__ grads, float* __restrict__ overflow,
-                                                const LossSum& ls, int b, int nb) {
+                                                const LossSum& ls, int b, int nb, float* lds) {
   if (ls.loss && b == nb - 1) {
-    loss_sum_block(ls);
+    loss_sum_block(ls, lds);
     return;
   }
-  __shared__ float red[16][16];
+  float(*red)[16] = reinterpret_cast<float(*)[16]>(lds);
   const int wl = threadIdx.x & 15, pg = threadIdx.x >> 4;
   const int i = b * 16 + wl;
   float acc = 0.0f;
@@ -472,7 +482,8 @@ template <class N>
 __global__ __launch_bounds__(256) void dw_reduce_kernel(const float* __restrict__ partial, int nblocks, WOffsets wo,
                                                         float* __restrict__ grads, float* __restrict__ overflow,
                                                         LossSum ls) {
-  dw_reduce_block<N>(partial, nblocks, wo, grads, overflow, ls, (int)blockIdx.x, (int)gridDim.x);
+  __shared__ float lds[kSumScratchFloats];
+  dw_reduce_block<N>(partial, nblocks, wo, grads, overflow, ls, (int)blockIdx.x, (int)gridDim.x, lds);
 }
 
 template <class N>

@@ -7,6 +7,7 @@
 // columns): a 16x16x32 k-step takes 8 consecutive k-slots per lane group,
 // filled from two 16-row output tiles of the previous layer (rows 4g..4g+3
 // of each), and the weights are laid out for that permutation.
+#include "bins.h"
 #include "field_common.h"
 #include "march_common.h"
 
@@ -705,11 +706,20 @@ __device__ __forceinline__ void fwd_store(const PActs<N>& a, int g, int s, bool 
   }
 }
 
+//
+// Workgroups past the MLP's (bp.nbins of them) run the table-gradient column
+// scan (bins.h), which needs only the record counts of the encoding.
 template <class N>
 __global__ __launch_bounds__(256) void mixed_fwd_kernel(LevelInfo lv, const _Float16* __restrict__ table,
                                                         const __bf16* __restrict__ prep, SampleSrc src,
-                                                        float* __restrict__ sigma_out, float* __restrict__ rgb_out) {
+                                                        float* __restrict__ sigma_out, float* __restrict__ rgb_out,
+                                                        BinPrep bp) {
   using M = Mixed<N>;
+  const int G = (int)gridDim.x - bp.nbins;  // the MLP's workgroups
+  if ((int)blockIdx.x >= G) {
+    colscan_bin(bp.rb, bp.nunits, (int)blockIdx.x - G);
+    return;
+  }
   __shared__ __attribute__((aligned(16))) __bf16 Af[M::FWD];
   load_bf16<N>(Af, prep, M::FWD);
   __syncthreads();
@@ -717,7 +727,7 @@ __global__ __launch_bounds__(256) void mixed_fwd_kernel(LevelInfo lv, const _Flo
   const int ntiles = (S + 15) / 16;
   const int lane = lane_id(), g = lane >> 4, jc = lane & 15;
   const int first = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x / kWave);
-  const int step = gridDim.x * (blockDim.x / kWave);
+  const int step = G * (blockDim.x / kWave);
   if (first >= ntiles) return;
   LaneLevels<N> ll;
   lane_levels<N>(lv, g, ll);
@@ -794,13 +804,16 @@ static hipError_t prep_impl(const float* params, const WOffsets& wo, int64_t tab
 
 template <class N>
 static hipError_t fwd_impl(const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
-                           float* sigma, float* rgb, hipStream_t st) {
+                           float* sigma, float* rgb, hipStream_t st, const BinPrep* bp) {
   const int tiles = (max_samples + 15) / 16;
-  if (tiles == 0) return hipSuccess;
   const __bf16* ops = static_cast<const __bf16*>(shadow);
   const _Float16* t16 = reinterpret_cast<const _Float16*>(static_cast<const char*>(shadow) + mixed_ops_bytes<N>());
   const int grid = (tiles + 3) / 4 < kMixedFwdGrid ? (tiles + 3) / 4 : kMixedFwdGrid;
-  hipLaunchKernelGGL(mixed_fwd_kernel<N>, dim3(grid), dim3(256), 0, st, lv, t16, ops, src, sigma, rgb);
+  const BinPrep none{};
+  const BinPrep& b = bp ? *bp : none;
+  if (grid + b.nbins > 0)
+    hipLaunchKernelGGL(mixed_fwd_kernel<N>, dim3(grid + b.nbins), dim3(256), 0, st, lv, t16, ops, src, sigma, rgb,
+                       b);
   return hipGetLastError();
 }
 
@@ -851,9 +864,9 @@ hipError_t mixed_prepare_count(int shape, const float* params, const WOffsets& w
 }
 
 hipError_t mixed_forward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
-                         float* sigma, float* rgb, hipStream_t st) {
-  return shape == kShapeTiny ? fwd_impl<NetTiny>(lv, shadow, src, max_samples, sigma, rgb, st)
-                             : fwd_impl<NetFull>(lv, shadow, src, max_samples, sigma, rgb, st);
+                         float* sigma, float* rgb, hipStream_t st, const BinPrep* bp) {
+  return shape == kShapeTiny ? fwd_impl<NetTiny>(lv, shadow, src, max_samples, sigma, rgb, st, bp)
+                             : fwd_impl<NetFull>(lv, shadow, src, max_samples, sigma, rgb, st, bp);
 }
 
 hipError_t mixed_backward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int nblocks,

@@ -97,6 +97,19 @@ struct BinPlan {
   int64_t max_records;
   BinLevels bl;
 };
+// Records per reduce workgroup for FP32 or BF16 (paired) records.
+uint32_t bin_chunk(const BinPlan& p, bool bf16_values);
+
+// The column scan (one workgroup of 256 threads per bin) and the bin starts
+// (one workgroup) of a table-gradient sort whose records the encoding kernel
+// has counted, run as extra workgroups of launches that do not depend on
+// them: the forward MLP takes the column scan, the compositing the bin
+// starts.  nbins = 0: none.
+struct BinPrep {
+  RecordBuffers rb;
+  int nunits, nbins;
+  uint32_t chunk;
+};
 
 BinPlan bin_plan(const LevelInfo& lv, uint32_t entries, int64_t max_samples);
 // grad_table += the table gradient of the samples of src, from the dL/de
@@ -117,16 +130,20 @@ struct WeightSum {
   float* overflow;
   LossSum ls;  // ls.loss null: no loss sum
 };
+// prescanned: the column scan and the bin starts have run already (as the
+// extra workgroups of the forward and compositing launches that BinPrep
+// describes), so the scatter is the placement, with the weight and loss sums
+// of ws as extra workgroups, and the reduction.
 hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
                        bool bf16_values, bool overwrite, float* grad_table, float* overflow, hipStream_t st,
-                       bool counted = false, const WeightSum* ws = nullptr);
+                       bool counted = false, const WeightSum* ws = nullptr, bool prescanned = false);
 
 // field.hip
 size_t field_prep_floats(int shape);
 size_t field_nweights(int shape);
 hipError_t field_prep(int shape, const float* params, const WOffsets& wo, float* out, hipStream_t st);
 hipError_t field_forward(int shape, const FieldArgs& a, const SampleSrc& src, int max_samples,
-                         float* sigma, float* rgb, hipStream_t st);
+                         float* sigma, float* rgb, hipStream_t st, const BinPrep* bp = nullptr);
 constexpr int kFieldBwdWaves = 4;             // waves per workgroup of the FP32 backward
 // Writes dL/de of every sample to rec.de and the weight gradients of each
 // workgroup to partial[nblocks][weights]; field_dw_reduce then adds them
@@ -172,7 +189,7 @@ size_t mixed_shadow_bytes(int shape, int64_t table_floats);
 hipError_t mixed_prepare(int shape, const float* params, const WOffsets& wo, int64_t table_floats, void* shadow,
                          float* zero_grads, int64_t total, float* clear_flag, hipStream_t st);
 hipError_t mixed_forward(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
-                         float* sigma, float* rgb, hipStream_t st);
+                         float* sigma, float* rgb, hipStream_t st, const BinPrep* bp = nullptr);
 // The encoding of every sample of src into src.ecache (FP16 table, BF16 out);
 // hist as for field_encode.
 hipError_t mixed_encode(int shape, const LevelInfo& lv, const void* shadow, const SampleSrc& src, int max_samples,
@@ -259,7 +276,7 @@ hipError_t composite_backward(const CompositeIO& io, const float* g_rgb, const f
 // Writes the per-ray loss shares to lo.parts; their sum into lo.loss is
 // left to a LossSum (the step's last reduction launch).
 hipError_t composite_loss_backward(const CompositeIO& io, const LossIO& lo, float* g_sigma,
-                                   float* g_rgb_s, hipStream_t st);
+                                   float* g_rgb_s, hipStream_t st, const BinPrep* bp = nullptr);
 
 // Per-ray loss shares (parts [R][2], nullable) and adjoint seeds (g_out
 // [R][6], nullable) of rays rendered outside the step; n_masked (nullable)

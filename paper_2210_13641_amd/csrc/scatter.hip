@@ -35,6 +35,7 @@
 // consecutive units place into a bin are adjacent and merge in that XCD's L2.
 #include <algorithm>
 
+#include "bins.h"
 #include "field_common.h"
 
 namespace nsl {
@@ -42,7 +43,6 @@ namespace nsl {
 namespace {
 
 constexpr int kUnitWaves = kUnitSamples / kWave;  // count and place: one sample per thread
-constexpr int kColThreads = 256;
 constexpr int kReduceThreads = 1024;
 
 // Record formats: FP32 values (key, g0, g1), one corner a record; or, for
@@ -159,42 +159,6 @@ __global__ __launch_bounds__(kUnitSamples) void bin_count_kernel(SampleSrc src, 
   write_counts(bl, l, u, cnt, hist);
 }
 
-// off[b][u] = sum over units u' < u of hist[b][u']; total[b] = sum over all
-// units.  One workgroup per bin; a thread takes four consecutive units.
-__device__ __forceinline__ void colscan_bin(const RecordBuffers& rb, int nunits, int b) {
-  __shared__ uint32_t wsum[kColThreads / kWave];
-  const int t = (int)threadIdx.x, wave = t / kWave, lane = lane_id();
-  const uint32_t* __restrict__ h = rb.hist + (size_t)b * nunits;
-  uint32_t* __restrict__ o = rb.off + (size_t)b * nunits;
-  uint32_t carry = 0;
-  for (int seg = 0; seg < nunits; seg += 4 * kColThreads) {
-    const int i0 = seg + 4 * t;
-    uint32_t v[4], sum = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      v[k] = i0 + k < nunits ? h[i0 + k] : 0u;
-      sum += v[k];
-    }
-    const uint32_t incl = wave_incl_scan_u32(sum);
-    if (lane == kWave - 1) wsum[wave] = incl;
-    __syncthreads();
-    uint32_t run = carry + incl - sum, all = 0;
-#pragma unroll
-    for (int w = 0; w < kColThreads / kWave; ++w) {
-      run += w < wave ? wsum[w] : 0u;
-      all += wsum[w];
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (i0 + k < nunits) o[i0 + k] = run;
-      run += v[k];
-    }
-    carry += all;
-    __syncthreads();
-  }
-  if (t == 0) rb.bin_total[b] = carry;
-}
-
 __global__ __launch_bounds__(kColThreads) void bin_colscan_kernel(RecordBuffers rb, int nunits) {
   colscan_bin(rb, nunits, (int)blockIdx.x);
 }
@@ -209,66 +173,13 @@ __global__ __launch_bounds__(kColThreads) void bin_colscan_dw_kernel(RecordBuffe
     colscan_bin(rb, nunits, (int)blockIdx.x);
     return;
   }
+  __shared__ float lds[kSumScratchFloats];
   dw_reduce_block<N>(ws.partial, ws.nblocks, ws.wo, ws.grads, ws.overflow, ws.ls, (int)blockIdx.x - nbins,
-                     (int)gridDim.x - nbins);
+                     (int)gridDim.x - nbins, lds);
 }
 
-// bin_start = exclusive prefix of the totals, chunk_start = exclusive prefix
-// of ceil(total / chunk); both with the grand total at [nbins].
-constexpr int kMaxStartBins = (int)(kMaxTableEntries / kBinEntries) + kMaxLevels;  // bins of any table
 __global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int nbins, uint32_t chunk) {
-  __shared__ uint32_t w_rec[1024 / kWave], w_chk[1024 / kWave];
-  const int t = threadIdx.x;
-  const int per = (nbins + 1023) / 1024;
-  const int b0 = min(nbins, t * per), b1 = min(nbins, b0 + per);
-  uint32_t rec = 0, chk = 0;
-  for (int b = b0; b < b1; ++b) {
-    const uint32_t n = rb.bin_total[b];
-    rec += n;
-    chk += (n + chunk - 1) / chunk;
-  }
-  // wave scans, then the totals of the waves before
-  const int wave = t / kWave;
-  const uint32_t ir = wave_incl_scan_u32(rec), ic = wave_incl_scan_u32(chk);
-  if (lane_id() == kWave - 1) {
-    w_rec[wave] = ir;
-    w_chk[wave] = ic;
-  }
-  __syncthreads();
-  uint32_t run_r = ir - rec, run_c = ic - chk, all_r = 0, all_c = 0;
-  for (int w = 0; w < 1024 / kWave; ++w) {
-    run_r += w < wave ? w_rec[w] : 0u;
-    run_c += w < wave ? w_chk[w] : 0u;
-    all_r += w_rec[w];
-    all_c += w_chk[w];
-  }
-  // the chunk starts also go to LDS, where every thread then finds the bin of
-  // chunks t, t + 1024, ... by binary search (a bin of many chunks would
-  // otherwise leave one thread writing all of its entries)
-  __shared__ uint32_t cs[kMaxStartBins + 1];
-  for (int b = b0; b < b1; ++b) {
-    const uint32_t n = rb.bin_total[b];
-    rb.bin_start[b] = run_r;
-    rb.chunk_start[b] = run_c;
-    cs[b] = run_c;
-    run_r += n;
-    run_c += (n + chunk - 1) / chunk;
-  }
-  if (t == 1023) {
-    rb.bin_start[nbins] = all_r;
-    rb.chunk_start[nbins] = all_c;
-    cs[nbins] = all_c;
-  }
-  __syncthreads();
-  for (uint32_t c = t; c < all_c; c += 1024) {
-    int lo = 0, hi = nbins;  // the last bin b with cs[b] <= c (bins of no chunks are skipped)
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) / 2;
-      if (cs[mid] <= c) lo = mid;
-      else hi = mid;
-    }
-    rb.chunk_bin[c] = (uint32_t)lo;
-  }
+  bin_start_block<1024>(rb, nbins, chunk);
 }
 
 // The unit's records (at most eight a sample), generated as in the count,
@@ -279,9 +190,15 @@ __global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int n
 // zero_table (overwriting reductions only, else null): the gradient entries of
 // the bins that the reduction will not overwrite (bins with no records, or
 // with several chunks, which add with atomics) are cleared here first.
-template <class R>
+//
+// The first nsum workgroups (a prescanned step's) sum the weight gradients
+// and the loss of ws instead (dw_reduce_block, in the stage's memory), beside
+// the placement; the placement starts at workgroup nskip, a multiple of 8 not
+// below nsum, so that its units keep their XCDs.
+template <class R, class N>
 __global__ __launch_bounds__(kUnitSamples) void bin_place_kernel(SampleSrc src, LevelInfo lv, BinLevels bl,
-                                                                RecordBuffers rb, float* __restrict__ zero_table) {
+                                                                RecordBuffers rb, float* __restrict__ zero_table,
+                                                                WeightSum ws, int nsum, int nskip) {
   typedef typename R::T Rec;
   // cnt: the unit's records per bin of the level; lst: its exclusive prefix;
   // base: the slot of the unit's record i of bin k is base[k] + i.
@@ -295,17 +212,26 @@ __global__ __launch_bounds__(kUnitSamples) void bin_place_kernel(SampleSrc src, 
   // records stores them unstaged
   constexpr int kStage = kUnitSamples * (R::kPaired ? 6 : 8);
   __shared__ Rec stage[kStage];
+  static_assert(sizeof(stage) >= kSumScratchFloats * sizeof(float), "the sums borrow the stage");
+  if ((int)blockIdx.x < nskip) {
+    if ((int)blockIdx.x < nsum)
+      dw_reduce_block<N>(ws.partial, ws.nblocks, ws.wo, ws.grads, ws.overflow, ws.ls, (int)blockIdx.x, nsum,
+                         reinterpret_cast<float*>(stage));
+    return;
+  }
+  const uint32_t wg = blockIdx.x - (uint32_t)nskip;
+  const int nplace = (int)gridDim.x - nskip;
   const int t = (int)threadIdx.x, wave = t / kWave, lane = lane_id();
   int l, u;
   if (R::kInterleaveLevels)
-    level_unit_interleaved(bl.levels, bl.nunits, l, u);
+    level_unit_interleaved(bl.levels, bl.nunits, l, u, wg);
   else
-    level_unit(bl.levels, bl.nunits, l, u);
+    level_unit(bl.levels, bl.nunits, l, u, wg);
   const int nb = (int)(bl.first[l + 1] - bl.first[l]);
   for (int k = t; k < nb; k += kUnitSamples) cnt[k] = 0u;
   if (zero_table) {
     const int nbins = (int)bl.first[bl.levels];
-    for (int b = (int)blockIdx.x; b < nbins; b += (int)gridDim.x) {
+    for (int b = (int)wg; b < nbins; b += nplace) {
       if (rb.chunk_start[b + 1] - rb.chunk_start[b] == 1u) continue;
       uint32_t e0, ne;
       bin_entries(bl, b, e0, ne);
@@ -568,52 +494,81 @@ BinPlan bin_plan(const LevelInfo& lv, uint32_t entries, int64_t max_samples) {
   return p;
 }
 
+uint32_t bin_chunk(const BinPlan& p, bool bf16_values) {
+  // a chunk holds at most p.chunk corner additions: as many records, or half
+  // as many paired ones
+  return bf16_values && RecBF16::kPaired ? p.chunk / 2 : p.chunk;
+}
+
+namespace {
+
+template <class R, class N>
+void launch_place(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
+                  float* zero_table, const WeightSum* sums, hipStream_t st) {
+  const int nplace = p.levels * p.nunits;
+  const int nsum = sums ? dw_reduce_blocks<N>(sums->ls.loss != nullptr) : 0;
+  const int nskip = (nsum + 7) / 8 * 8;
+  const size_t level_lds = (size_t)p.bl.max_level_bins * sizeof(uint32_t);
+  hipLaunchKernelGGL((bin_place_kernel<R, N>), dim3(nskip + nplace), dim3(kUnitSamples), 3 * level_lds, st, src, lv,
+                     p.bl, rb, zero_table, sums ? *sums : WeightSum{}, nsum, nskip);
+}
+
+template <class R>
+void place_and_reduce(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
+                      bool overwrite, float* grad_table, float* overflow, const WeightSum* sums, hipStream_t st) {
+  float* zero_table = overwrite ? grad_table : nullptr;
+  if (sums && sums->shape == kShapeTiny)
+    launch_place<R, NetTiny>(p, rb, src, lv, zero_table, sums, st);
+  else
+    launch_place<R, NetFull>(p, rb, src, lv, zero_table, sums, st);
+  // the small chunks of tables of few bins read their record groups in a
+  // scattered order
+  const bool scattered = p.chunk < kChunk;
+  hipLaunchKernelGGL(bin_reduce_kernel<R>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.bl,
+                     bin_chunk(p, R::kPaired), scattered, grad_table, overflow, overwrite);
+}
+
+}  // namespace
+
 hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSrc& src, const LevelInfo& lv,
                        bool bf16_values, bool overwrite, float* grad_table, float* overflow, hipStream_t st,
-                       bool counted, const WeightSum* ws) {
+                       bool counted, const WeightSum* ws, bool prescanned) {
   if (p.nbins == 0 || p.nunits == 0) {
     return ws ? field_dw_reduce(ws->shape, ws->partial, ws->nblocks, ws->wo, ws->grads, ws->overflow,
                                 ws->ls.loss ? &ws->ls : nullptr, st)
               : hipSuccess;
   }
-  float* zero_table = overwrite ? grad_table : nullptr;
-  const dim3 grid(p.levels * p.nunits);
-  const size_t level_lds = (size_t)p.bl.max_level_bins * sizeof(uint32_t);
-  if (!counted)
-    if (bf16_values)
-      hipLaunchKernelGGL(bin_count_kernel<RecBF16::kPaired>, grid, dim3(kUnitSamples), level_lds, st, src, lv, p.bl,
-                         rb.hist);
-    else
-      hipLaunchKernelGGL(bin_count_kernel<RecF32::kPaired>, grid, dim3(kUnitSamples), level_lds, st, src, lv, p.bl,
-                         rb.hist);
-  if (ws) {
-    const bool loss = ws->ls.loss != nullptr;
-    if (ws->shape == kShapeTiny)
-      hipLaunchKernelGGL(bin_colscan_dw_kernel<NetTiny>, dim3(p.nbins + dw_reduce_blocks<NetTiny>(loss)),
-                         dim3(kColThreads), 0, st, rb, p.nunits, p.nbins, *ws);
-    else
-      hipLaunchKernelGGL(bin_colscan_dw_kernel<NetFull>, dim3(p.nbins + dw_reduce_blocks<NetFull>(loss)),
-                         dim3(kColThreads), 0, st, rb, p.nunits, p.nbins, *ws);
-  } else {
-    hipLaunchKernelGGL(bin_colscan_kernel, dim3(p.nbins), dim3(kColThreads), 0, st, rb, p.nunits);
+  if (!prescanned) {
+    const dim3 grid(p.levels * p.nunits);
+    const size_t level_lds = (size_t)p.bl.max_level_bins * sizeof(uint32_t);
+    if (!counted) {
+      if (bf16_values)
+        hipLaunchKernelGGL(bin_count_kernel<RecBF16::kPaired>, grid, dim3(kUnitSamples), level_lds, st, src, lv,
+                           p.bl, rb.hist);
+      else
+        hipLaunchKernelGGL(bin_count_kernel<RecF32::kPaired>, grid, dim3(kUnitSamples), level_lds, st, src, lv,
+                           p.bl, rb.hist);
+    }
+    if (ws) {
+      const bool loss = ws->ls.loss != nullptr;
+      if (ws->shape == kShapeTiny)
+        hipLaunchKernelGGL(bin_colscan_dw_kernel<NetTiny>, dim3(p.nbins + dw_reduce_blocks<NetTiny>(loss)),
+                           dim3(kColThreads), 0, st, rb, p.nunits, p.nbins, *ws);
+      else
+        hipLaunchKernelGGL(bin_colscan_dw_kernel<NetFull>, dim3(p.nbins + dw_reduce_blocks<NetFull>(loss)),
+                           dim3(kColThreads), 0, st, rb, p.nunits, p.nbins, *ws);
+    } else {
+      hipLaunchKernelGGL(bin_colscan_kernel, dim3(p.nbins), dim3(kColThreads), 0, st, rb, p.nunits);
+    }
+    hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins, bin_chunk(p, bf16_values));
   }
-  // a chunk holds at most p.chunk corner additions: as many records, or half
-  // as many paired ones; the small chunks of tables of few bins read their
-  // record groups in a scattered order
-  const uint32_t chunk = bf16_values && RecBF16::kPaired ? p.chunk / 2 : p.chunk;
-  const bool scattered = p.chunk < kChunk;
-  hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins, chunk);
-  if (bf16_values) {
-    hipLaunchKernelGGL(bin_place_kernel<RecBF16>, grid, dim3(kUnitSamples), 3 * level_lds, st, src, lv, p.bl, rb,
-                       zero_table);
-    hipLaunchKernelGGL(bin_reduce_kernel<RecBF16>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.bl,
-                       chunk, scattered, grad_table, overflow, overwrite);
-  } else {
-    hipLaunchKernelGGL(bin_place_kernel<RecF32>, grid, dim3(kUnitSamples), 3 * level_lds, st, src, lv, p.bl, rb,
-                       zero_table);
-    hipLaunchKernelGGL(bin_reduce_kernel<RecF32>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.bl,
-                       chunk, scattered, grad_table, overflow, overwrite);
-  }
+  // with the scans done earlier, the weight and loss sums ride along the
+  // placement
+  const WeightSum* sums = prescanned ? ws : nullptr;
+  if (bf16_values)
+    place_and_reduce<RecBF16>(p, rb, src, lv, overwrite, grad_table, overflow, sums, st);
+  else
+    place_and_reduce<RecF32>(p, rb, src, lv, overwrite, grad_table, overflow, sums, st);
   return hipGetLastError();
 }
 
