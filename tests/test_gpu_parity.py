@@ -233,18 +233,35 @@ def test_march_occupancy_bit_exact(nsl, torch_dev):
     assert oc.max() == 256 and (oc == 0).any()
 
 
-def test_march_uniform_and_bad_ids(nsl, torch_dev):
+@pytest.mark.parametrize("reps", [1, 40], ids=["1026", "40962"])
+def test_march_uniform_and_bad_ids(nsl, torch_dev, reps):
+    """Uniform samples of the tiny camera's pixels plus two ids past the
+    keyframe store (empty rays); 40962 candidates (more samples than the
+    batch takes) use the separate single-block scan, 1026 the scan inside
+    the sample emission.  Counts, every offset, the statistics (rays,
+    samples, kept candidates, rays with unusable depth) and the kept samples
+    against the oracle's batch cut."""
     torch, dev = torch_dev
     kf = W.c1_keyframes()
     f = nsl.Field(W.C1_FIELD)
     m = upload_keyframes(nsl, torch, kf, dev)
-    ids = np.concatenate([W.c1_pixels(), np.array([1024, 5000], np.uint32)])   # two ids past the store
+    ids = np.concatenate([np.tile(W.c1_pixels(), reps), np.array([1024, 5000], np.uint32)])
+    n = len(ids)
     cfg = nsl.step_config(W.C1_SAMPLER)
     counts, offs, t, ray, stats = _march_gpu(nsl, torch, dev, m, f, cfg, ids)
-    assert counts[:1024].tolist() == [32] * 1024 and counts[1024:].tolist() == [0, 0]
-    assert stats.tolist()[:3] == [1024, 32768, 1026]
-    assert np.array_equal(t[:32768], np.tile(orays.uniform_t(W.C1_SAMPLER), 1024))
-    assert np.array_equal(ray[:32768], np.repeat(np.arange(1024), 32))
+    want = np.where(ids < 1024, 32, 0)
+    assert np.array_equal(counts, want)
+    assert np.array_equal(offs, np.concatenate([[0], np.cumsum(want)]))
+    kept, rmask = orays.batch_cut(want, W.C1_SAMPLER.max_samples)
+    S = int(np.cumsum(want)[kept].max())
+    pix = np.minimum(ids, 1023)
+    usable = np.isfinite(kf.depth.reshape(-1)[pix]) & np.isfinite(kf.depth_var.reshape(-1)[pix]) & \
+        (kf.depth_var.reshape(-1)[pix] > 0)
+    assert stats.tolist() == [int(rmask.sum()), S, int(kept.sum()), int((rmask & ~usable).sum())]
+    assert (reps == 1) == bool(kept.all())           # the cut applies to the larger batch
+    sel = np.nonzero(rmask)[0]
+    assert np.array_equal(t[:S], np.tile(orays.uniform_t(W.C1_SAMPLER), len(sel)))
+    assert np.array_equal(ray[:S], np.repeat(sel, 32))
 
 
 # ----------------------------------------------------------------------------
