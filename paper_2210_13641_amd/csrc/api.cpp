@@ -499,6 +499,7 @@ int nsl_train_step(nsl_mapper* m, const nsl_field* f, float* params, float* grad
     bp.nunits = b.plan.nunits;
     bp.nbins = b.plan.nbins;
     bp.chunk = bin_chunk(b.plan, mixed);
+    bp.split = bin_split(b.plan);
   }
   const BinPrep* prescan = counted && b.plan.nbins > 0 && b.plan.nunits > 0 ? &bp : nullptr;
   if (mixed)

@@ -47,12 +47,25 @@ __device__ __forceinline__ void colscan_bin(const RecordBuffers& rb, int nunits,
   if (t == 0) rb.bin_total[b] = carry;
 }
 
+// The records of each chunk of a bin of n records, and its chunks: one chunk
+// when the bin fits; with split, a bin that does not fit takes chunks of half
+// the size.  Such bins are the heavy bins of the coarse dense levels, whose
+// chunks also meet the most compare-and-swap retries in the reduction, so
+// they are spread over more workgroups.
+__host__ __device__ __forceinline__ uint32_t chunk_size_of(uint32_t n, uint32_t chunk, bool split) {
+  return split && n > chunk ? chunk / 2 : chunk;
+}
+__host__ __device__ __forceinline__ uint32_t chunks_of(uint32_t n, uint32_t chunk, bool split) {
+  const uint32_t c = chunk_size_of(n, chunk, split);
+  return (n + c - 1) / c;
+}
+
 // bin_start = exclusive prefix of the totals, chunk_start = exclusive prefix
-// of ceil(total / chunk); both with the grand total at [nbins].
+// of the chunks per bin; both with the grand total at [nbins].
 // One workgroup of THREADS threads.
 constexpr int kMaxStartBins = (int)(kMaxTableEntries / kBinEntries) + kMaxLevels;  // bins of any table
 template <int THREADS>
-__device__ __forceinline__ void bin_start_block(const RecordBuffers& rb, int nbins, uint32_t chunk) {
+__device__ __forceinline__ void bin_start_block(const RecordBuffers& rb, int nbins, uint32_t chunk, bool split) {
   __shared__ uint32_t w_rec[THREADS / kWave], w_chk[THREADS / kWave];
   const int t = threadIdx.x;
   const int per = (nbins + THREADS - 1) / THREADS;
@@ -61,7 +74,7 @@ __device__ __forceinline__ void bin_start_block(const RecordBuffers& rb, int nbi
   for (int b = b0; b < b1; ++b) {
     const uint32_t n = rb.bin_total[b];
     rec += n;
-    chk += (n + chunk - 1) / chunk;
+    chk += chunks_of(n, chunk, split);
   }
   // wave scans, then the totals of the waves before
   const int wave = t / kWave;
@@ -88,7 +101,7 @@ __device__ __forceinline__ void bin_start_block(const RecordBuffers& rb, int nbi
     rb.chunk_start[b] = run_c;
     cs[b] = run_c;
     run_r += n;
-    run_c += (n + chunk - 1) / chunk;
+    run_c += chunks_of(n, chunk, split);
   }
   if (t == THREADS - 1) {
     rb.bin_start[nbins] = all_r;

@@ -251,7 +251,7 @@ __global__ __launch_bounds__(256) void composite_loss_kernel(CompositeIO io, Los
   // with bp.nbins, the last workgroup sets the table-gradient bin starts
   // (bins.h): they need only the column scan of the forward launch
   if (bp.nbins > 0 && blockIdx.x == gridDim.x - 1) {
-    bin_start_block<256>(bp.rb, bp.nbins, bp.chunk);
+    bin_start_block<256>(bp.rb, bp.nbins, bp.chunk, bp.split);
     return;
   }
   const int r = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;

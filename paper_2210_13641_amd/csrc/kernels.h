@@ -97,8 +97,10 @@ struct BinPlan {
   int64_t max_records;
   BinLevels bl;
 };
-// Records per reduce workgroup for FP32 or BF16 (paired) records.
+// Records per reduce workgroup for FP32 or BF16 (paired) records, and whether
+// bins of more records than that take chunks of half the size (bins.h).
 uint32_t bin_chunk(const BinPlan& p, bool bf16_values);
+bool bin_split(const BinPlan& p);
 
 // The column scan (one workgroup of 256 threads per bin) and the bin starts
 // (one workgroup) of a table-gradient sort whose records the encoding kernel
@@ -109,6 +111,7 @@ struct BinPrep {
   RecordBuffers rb;
   int nunits, nbins;
   uint32_t chunk;
+  bool split;
 };
 
 BinPlan bin_plan(const LevelInfo& lv, uint32_t entries, int64_t max_samples);

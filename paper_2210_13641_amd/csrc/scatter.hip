@@ -178,8 +178,8 @@ __global__ __launch_bounds__(kColThreads) void bin_colscan_dw_kernel(RecordBuffe
                      (int)gridDim.x - nbins, lds);
 }
 
-__global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int nbins, uint32_t chunk) {
-  bin_start_block<1024>(rb, nbins, chunk);
+__global__ __launch_bounds__(1024) void bin_start_kernel(RecordBuffers rb, int nbins, uint32_t chunk, bool split) {
+  bin_start_block<1024>(rb, nbins, chunk, split);
 }
 
 // The unit's records (at most eight a sample), generated as in the count,
@@ -361,7 +361,8 @@ __global__ __launch_bounds__(kUnitSamples) void bin_place_kernel(SampleSrc src, 
 // included) instead of adding them to the gradient.
 template <class R>
 __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffers rb, BinLevels bl, uint32_t chunk,
-                                                                    bool scattered, float* __restrict__ grad_table,
+                                                                    bool scattered, bool split,
+                                                                    float* __restrict__ grad_table,
                                                                     float* __restrict__ overflow, bool overwrite) {
   // (g0, g1) of each entry as one 64-bit word: float pairs are added with
   // LDS 64-bit compare-and-swap, which retires far faster than LDS float
@@ -372,8 +373,9 @@ __global__ __launch_bounds__(kReduceThreads) void bin_reduce_kernel(RecordBuffer
   if (c >= rb.chunk_start[nbins]) return;
   const int b = (int)rb.chunk_bin[c];
   const uint32_t nch = rb.chunk_start[b + 1] - rb.chunk_start[b];
-  const uint32_t first = rb.bin_start[b] + (c - rb.chunk_start[b]) * chunk;
-  const uint32_t last = min(rb.bin_start[b + 1], first + chunk);
+  const uint32_t csz = chunk_size_of(rb.bin_start[b + 1] - rb.bin_start[b], chunk, split);
+  const uint32_t first = rb.bin_start[b] + (c - rb.chunk_start[b]) * csz;
+  const uint32_t last = min(rb.bin_start[b + 1], first + csz);
   for (int i = threadIdx.x; i < kBinEntries; i += kReduceThreads) acc[i] = 0ull;
   __syncthreads();
   uint32_t e0, ne;
@@ -489,10 +491,13 @@ BinPlan bin_plan(const LevelInfo& lv, uint32_t entries, int64_t max_samples) {
     p.chunk = c;
   }
   // paired records (two corner additions each) are cut into chunks of half
-  // as many
-  p.max_chunks = (int)(p.nbins + (p.max_records + p.chunk / 2 - 1) / (p.chunk / 2));
+  // as many, and bins that take several chunks into chunks of half the size
+  p.max_chunks = (int)(p.nbins + (p.max_records + p.chunk / 4 - 1) / (p.chunk / 4));
   return p;
 }
+
+// Tables of few bins already cut small chunks.
+bool bin_split(const BinPlan& p) { return p.chunk >= kChunk; }
 
 uint32_t bin_chunk(const BinPlan& p, bool bf16_values) {
   // a chunk holds at most p.chunk corner additions: as many records, or half
@@ -525,7 +530,7 @@ void place_and_reduce(const BinPlan& p, const RecordBuffers& rb, const SampleSrc
   // scattered order
   const bool scattered = p.chunk < kChunk;
   hipLaunchKernelGGL(bin_reduce_kernel<R>, dim3(p.max_chunks), dim3(kReduceThreads), 0, st, rb, p.bl,
-                     bin_chunk(p, R::kPaired), scattered, grad_table, overflow, overwrite);
+                     bin_chunk(p, R::kPaired), scattered, bin_split(p), grad_table, overflow, overwrite);
 }
 
 }  // namespace
@@ -560,7 +565,8 @@ hipError_t bin_scatter(const BinPlan& p, const RecordBuffers& rb, const SampleSr
     } else {
       hipLaunchKernelGGL(bin_colscan_kernel, dim3(p.nbins), dim3(kColThreads), 0, st, rb, p.nunits);
     }
-    hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins, bin_chunk(p, bf16_values));
+    hipLaunchKernelGGL(bin_start_kernel, dim3(1), dim3(1024), 0, st, rb, p.nbins, bin_chunk(p, bf16_values),
+                       bin_split(p));
   }
   // with the scans done earlier, the weight and loss sums ride along the
   // placement
