@@ -201,7 +201,9 @@ def main(argv=None):
     for name, (mx, keep) in variants.items():
         prec = dict(precision=nsl.PRECISION_MIXED, scale_state=scale) if mx else {}
         cfgs[name] = nsl.step_config(sampler, zero_grads=True, keep_encoding=keep, **prec)
-        full[name] = nsl.step_config(sampler, zero_grads=False, do_adam=True, lr=W.ADAM_LR, betas=W.ADAM_BETAS,
+        # a training loop's step: this step's gradients replace the last (the
+        # table-gradient reduction overwrites them), then Adam
+        full[name] = nsl.step_config(sampler, zero_grads=True, do_adam=True, lr=W.ADAM_LR, betas=W.ADAM_BETAS,
                                      eps=W.ADAM_EPS, keep_encoding=keep, **prec)
     wsb = torch.empty(max(nsl.step_workspace_bytes(field, c, N_CANDIDATES) for c in cfgs.values()),
                       dtype=torch.uint8, device=dev)

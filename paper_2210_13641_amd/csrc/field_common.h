@@ -172,15 +172,18 @@ __device__ __forceinline__ void read_encoding(const E* __restrict__ ec, int stri
 }
 
 // The encoding of every sample, written level-major for the MLP kernels.
-// One thread per (sample, level), one workgroup per unit (256 samples of one
-// level, see level_unit).  Workgroups are dispatched round-robin over the 8
+// One workgroup per kEncodeUnits consecutive units of one level (units of
+// 256 samples, see level_unit), a thread taking one sample of each, so that
+// the dependent loads of its samples (ray index and t, the ray, the corners)
+// are in flight together.  Workgroups are dispatched round-robin over the 8
 // XCDs, in order; with 16 levels, the workgroups of XCD x evaluate level x
 // for every sample and then level x + 8, so at any time each XCD's L2 holds
 // the table slice of one level (2 MB in FP16) instead of seeing the whole
 // table, and the random corner reads hit in L2.
+constexpr int kEncodeUnits = 2;
 template <class N>
 __host__ __device__ constexpr int encode_grid(int max_samples) {
-  return N::L * ((max_samples + 255) / 256);
+  return N::L * ((max_samples + 256 * kEncodeUnits - 1) / (256 * kEncodeUnits));
 }
 
 // Workgroup -> (level l, unit u) of the level-major kernels (the encoding
@@ -275,31 +278,39 @@ template <class N, class T, class E>
 __global__ __launch_bounds__(256) void encode_levels_kernel(LevelInfo lv, const T* __restrict__ table, SampleSrc src,
                                                             E* __restrict__ out, int stride,
                                                             uint32_t* __restrict__ hist, BinLevels bl) {
-  static_assert(kUnitSamples == 256, "one sample per thread");
+  static_assert(kUnitSamples == 256, "one sample of each unit per thread");
+  constexpr int U = kEncodeUnits;
   const int S = src.n_dev ? (int)*src.n_dev : src.n;
-  int l, u;
-  level_unit(N::L, (int)(gridDim.x / (uint32_t)N::L), l, u);
-  const int s = u * 256 + (int)threadIdx.x;
-  const bool valid = s < S;
-  if (!hist) {
-    if (!valid) return;
-    float xn[3];
-    load_position(src, s, xn);
-    const float2 v = encode_level(table, lv.table_mask, lv.res[l], (lv.dense_bits >> l) & 1u, lv.offset[l], xn);
-    store_encoding(out + (size_t)l * stride + s, v);
-    return;
+  int l, ug;
+  level_unit(N::L, (int)(gridDim.x / (uint32_t)N::L), l, ug);
+  const bool dense = (lv.dense_bits >> l) & 1u;
+  int s[U];
+  bool valid[U];
+  float xn[U][3];
+#pragma unroll
+  for (int k = 0; k < U; ++k) {
+    s[k] = (ug * U + k) * 256 + (int)threadIdx.x;
+    valid[k] = s[k] < S;
+    xn[k][0] = xn[k][1] = xn[k][2] = 0.5f;
+    if (valid[k]) load_position(src, s[k], xn[k]);
   }
-  __shared__ uint32_t cnt[kEncodeLevelBins];
-  for (int i = threadIdx.x; i < kEncodeLevelBins; i += 256) cnt[i] = 0u;
+  Corner8 c[U];
+#pragma unroll
+  for (int k = 0; k < U; ++k) corners(xn[k][0], xn[k][1], xn[k][2], lv.res[l], dense, lv.table_mask, lv.offset[l], c[k]);
+#pragma unroll
+  for (int k = 0; k < U; ++k)
+    if (valid[k]) store_encoding(out + (size_t)l * stride + s[k], blend_corners(table, c[k]));
+  if (!hist) return;
+  __shared__ uint32_t cnt[U][kEncodeLevelBins];
+  for (int i = threadIdx.x; i < U * kEncodeLevelBins; i += 256) (&cnt[0][0])[i] = 0u;
   __syncthreads();
-  float xn[3] = {0.5f, 0.5f, 0.5f};
-  if (valid) load_position(src, s, xn);
-  Corner8 c;
-  corners(xn[0], xn[1], xn[2], lv.res[l], (lv.dense_bits >> l) & 1u, lv.table_mask, lv.offset[l], c);
-  if (valid) store_encoding(out + (size_t)l * stride + s, blend_corners(table, c));
-  count_records<sizeof(T) == 2>(c, row_run_head(c.cell, valid), lv.offset[l], cnt);
+#pragma unroll
+  for (int k = 0; k < U; ++k)
+    count_records<sizeof(T) == 2>(c[k], row_run_head(c[k].cell, valid[k]), lv.offset[l], cnt[k]);
   __syncthreads();
-  write_counts(bl, l, u, cnt, hist);
+#pragma unroll
+  for (int k = 0; k < U; ++k)
+    if (ug * U + k < bl.nunits) write_counts(bl, l, ug * U + k, cnt[k], hist);
 }
 
 // Real orthonormal SH coefficients 4g..4g+3 of direction d (0 beyond NSH).
