@@ -689,7 +689,9 @@ __global__ __launch_bounds__(kBwdWaves8 * kWave, 1) void mixed_bwd8_kernel(
 
 // Forward: density and colour of 16-sample tiles, one tile per wave at a
 // time (four waves per SIMD stay resident, which hides latency better than
-// pairing tiles here).  The grid is a fixed number of workgroups, so the
+// pairing tiles here; the register budget is held to four waves, without
+// which the compiler takes 136 registers, three waves, and the fixed grid
+// needs a second round).  The grid is a fixed number of workgroups, so the
 // weight operands are staged into LDS once per workgroup rather than once per
 // four tiles; with the kept encoding, a wave fetches its next tile's inputs
 // while it computes the current one (ray indices two tiles ahead).
@@ -710,10 +712,9 @@ __device__ __forceinline__ void fwd_store(const PActs<N>& a, int g, int s, bool 
 // Workgroups past the MLP's (bp.nbins of them) run the table-gradient column
 // scan (bins.h), which needs only the record counts of the encoding.
 template <class N>
-__global__ __launch_bounds__(256) void mixed_fwd_kernel(LevelInfo lv, const _Float16* __restrict__ table,
-                                                        const __bf16* __restrict__ prep, SampleSrc src,
-                                                        float* __restrict__ sigma_out, float* __restrict__ rgb_out,
-                                                        BinPrep bp) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void mixed_fwd_kernel(
+    LevelInfo lv, const _Float16* __restrict__ table, const __bf16* __restrict__ prep, SampleSrc src,
+    float* __restrict__ sigma_out, float* __restrict__ rgb_out, BinPrep bp) {
   using M = Mixed<N>;
   const int G = (int)gridDim.x - bp.nbins;  // the MLP's workgroups
   if ((int)blockIdx.x >= G) {
