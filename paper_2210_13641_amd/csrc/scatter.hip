@@ -14,9 +14,12 @@
 //               bin of the level (LDS integer atomics); or done by the
 //               encoding kernel, which evaluates the same corners
 //   scan        per bin, exclusive prefix over the level's units; bin totals
-//   start       exclusive prefix over bins; chunks of at most kChunk records
-//               per bin (fewer when the table has few bins, so that the
-//               records still spread over many workgroups)
+//               (bins.h; in the training step, beside the forward MLP)
+//   start       exclusive prefix over bins; chunks of at most a chunk of
+//               corner additions per bin (fewer when the table has few bins,
+//               so that the records still spread over many workgroups; half
+//               as many for bins that need several) (bins.h; in the step,
+//               beside the compositing)
 //   place       per unit, the records again, ordered by bin in LDS and stored
 //               to their bins' slices
 //   reduce      one workgroup per chunk: LDS accumulation of the bin with
@@ -26,13 +29,15 @@
 //               with atomics, one per touched entry)
 //
 // A record is (entry, w * dL/de_l0, w * dL/de_l1), the values in FP32, or in
-// BF16 for the mixed-precision step (accumulated in FP32 all the same).
-// Count and place generate the same records from the sample positions and
-// dL/de: the 16 lanes of a row hold 16 consecutive samples (mostly along one
-// ray); neighbouring lanes in the same cell form a run, and each run gives
-// eight records (one per corner) carrying the run's sums.  Both run over the
-// units of a level on one XCD (see level_unit), so the slices that
-// consecutive units place into a bin are adjacent and merge in that XCD's L2.
+// BF16 for the mixed-precision step (accumulated in FP32 all the same), whose
+// records also carry the x-neighbour corner when its entry differs from the
+// first in a run of low bits (pair_code).  Count and place generate the same
+// records from the sample positions and dL/de: the 16 lanes of a row hold 16
+// consecutive samples (mostly along one ray); neighbouring lanes in the same
+// cell form a run, and each run gives eight corner values carrying the run's
+// sums.  Both run over the units of a level on one XCD (see level_unit), so
+// the slices that consecutive units place into a bin are adjacent and merge
+// in that XCD's L2.
 #include <algorithm>
 
 #include "bins.h"
