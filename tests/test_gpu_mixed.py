@@ -170,17 +170,22 @@ def test_mixed_error_along_training(nsl, gpu, n_cams):
     state = torch.tensor([2.0 ** 15, 0.0, 0.0, 0.0], device=dev)
     train = nsl.step_config(sampler, precision=nsl.PRECISION_MIXED, scale_state=state, zero_grads=False,
                             do_adam=True, lr=W.ADAM_LR, betas=W.ADAM_BETAS, eps=W.ADAM_EPS)
-    ws = torch.empty(nsl.step_workspace_bytes(f, train, len(ids)), dtype=torch.uint8, device=dev)
+    kept = nsl.step_config(sampler, precision=nsl.PRECISION_MIXED, scale_state=state, keep_encoding=True)
+    ws = torch.empty(max(nsl.step_workspace_bytes(f, c, len(ids)) for c in (train, kept)), dtype=torch.uint8,
+                     device=dev)
     loss = torch.zeros(3, device=dev)
     n = len(ids)
     report(f"mixed training: {n_cams} cameras, {n * 32} samples per step, 100 Adam steps, scale 2^15; "
            "errors against the exact FP64 oracle as relative L2 / max |error| per running-error magnitude")
 
     def probe(precision):
+        # the mixed probe keeps the encoding from the forward (the records
+        # counted by the encoding, the small-table chunks, the scans beside
+        # the forward and the compositing); the FP32 probe gathers it again
         st = state.clone()
         scale = float(st[0].item()) if precision == nsl.PRECISION_MIXED else 1.0
         cfg = nsl.step_config(sampler, precision=precision, scale_state=st if precision == nsl.PRECISION_MIXED
-                              else None, zero_grads=True)
+                              else None, zero_grads=True, keep_encoding=precision == nsl.PRECISION_MIXED)
         g = torch.zeros_like(P)
         lo = torch.zeros(3, device=dev)
         rays = torch.zeros(n, 6, device=dev)

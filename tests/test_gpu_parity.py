@@ -372,7 +372,10 @@ def test_step_tiny_trained_like_field(nsl, torch_dev):
 
 @pytest.mark.slow
 def test_step_paper_scale(nsl, torch_dev):
-    """The full paper-scale step: 4096 candidates -> 2^18-sample cut."""
+    """The full paper-scale step in FP32: 4096 candidates -> 2^18-sample cut,
+    with the encoding gathered again by the backward and with it kept from
+    the forward (records counted by the encoding, the scans beside the
+    forward and the compositing), both against the oracle at 1e-5."""
     torch, dev = torch_dev
     scene, occ, kf = c2_inputs()
     report("step: paper scale, 16 levels x 2^19, 2^18 samples")
@@ -380,10 +383,11 @@ def test_step_paper_scale(nsl, torch_dev):
     ids = W.c2_candidates(4096)
     f = nsl.Field(spec)
     flat, t64, w64 = params_for(spec, f.layout, seed=0)
-    g = _step_gpu(nsl, torch, dev, spec, sampler, kf, ids, flat, occ=occ, grid_res=128)
     o = ostep.train_step(spec, sampler, kf, t64, w64, ids, occupancy=occ)
     report(f"  R={o['R']} S={o['S']} ambiguous ReLU units={o['n_amb']}")
-    _compare_step(spec, g, o, f.layout)
+    for keep in (False, True):
+        g = _step_gpu(nsl, torch, dev, spec, sampler, kf, ids, flat, occ=occ, grid_res=128, keep_encoding=keep)
+        _compare_step(spec, g, o, f.layout)
 
 
 @pytest.mark.slow
