@@ -496,8 +496,10 @@ BinPlan bin_plan(const LevelInfo& lv, uint32_t entries, int64_t max_samples) {
     p.chunk = c;
   }
   // paired records (two corner additions each) are cut into chunks of half
-  // as many, and bins that take several chunks into chunks of half the size
-  p.max_chunks = (int)(p.nbins + (p.max_records + p.chunk / 4 - 1) / (p.chunk / 4));
+  // as many, and, unless the table has few bins, bins that take several
+  // chunks into chunks of half the size (bin_split)
+  const uint32_t smallest = bin_split(p) ? p.chunk / 4 : p.chunk / 2;
+  p.max_chunks = (int)(p.nbins + (p.max_records + smallest - 1) / smallest);
   return p;
 }
 
