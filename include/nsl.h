@@ -409,6 +409,27 @@ size_t nsl_encode_bwd_workspace_bytes(const nsl_field* f, int S);
 int nsl_encode_bwd(const nsl_field* f, const float* xn, int S, const float* de, int precision, int overwrite,
                    float* grads, void* workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * The field's MLP on its own (Sec. 3.2 after Eq. 7: the density sigma and
+ * colour c of a sample come from one evaluation of the density and colour
+ * networks), on a given encoding, with the kernels the step runs when it
+ * keeps the encoding (FP32).
+ *
+ * enc: level-major [levels][S] FP32 feature pairs (float2), as
+ * nsl_encode_fwd writes them; dirs [S,3]: unit view directions.
+ * nsl_mlp_fwd writes sigma [S] and rgb [S,3].  nsl_mlp_bwd, given dsigma [S]
+ * and drgb [S,3], accumulates (+=) the weight gradients into the MLP part of
+ * grads (the table part is not touched) and writes dL/de to d_enc, laid out
+ * like enc (the input of nsl_encode_bwd).  Workspace:
+ * nsl_field_workspace_bytes(f, S).  params, grads, enc and d_enc must be
+ * 16-byte aligned.
+ * ------------------------------------------------------------------------ */
+int nsl_mlp_fwd(const nsl_field* f, const float* params, const float* enc, const float* dirs, int S,
+                float* sigma, float* rgb, void* workspace, size_t workspace_bytes, hipStream_t stream);
+int nsl_mlp_bwd(const nsl_field* f, const float* params, const float* enc, const float* dirs, int S,
+                const float* dsigma, const float* drgb, float* grads, float* d_enc, void* workspace,
+                size_t workspace_bytes, hipStream_t stream);
+
 /* Bias-corrected Adam over n parameters, gradient = grads * grad_scale;
  * clears grads. */
 int nsl_adam(float* params, float* grads, float* m, float* v, int64_t n, float lr, float beta1,

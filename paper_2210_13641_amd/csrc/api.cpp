@@ -840,6 +840,57 @@ int nsl_encode_bwd(const nsl_field* f, const float* xn, int S, const float* de, 
   return NSL_OK;
 }
 
+// The MLP alone on a given level-major FP32 encoding (the kept-encoding path
+// of the field kernels).
+static int mlp_common(const nsl_field* f, const float* params, const float* enc, const float* dirs, int S, void* ws,
+                      size_t ws_bytes, FieldWs& w, SampleSrc& src) {
+  if (!f || !params || !enc || !dirs || !ws) return fail(NSL_E_INVALID, "null argument");
+  if (S < 0) return fail(NSL_E_INVALID, "negative sample count");
+  if (!records_fit(f->cfg.levels, S)) return fail(NSL_E_INVALID, "S * 8 * levels must stay below 2^32");
+  if (misaligned(params) || misaligned(enc)) return fail(NSL_E_INVALID, "params and enc must be 16-byte aligned");
+  if (ws_bytes < nsl_field_workspace_bytes(f, S)) return fail(NSL_E_WORKSPACE, "field workspace too small");
+  field_carve(f, S, ws, &w);
+  src = SampleSrc{};
+  src.dir = dirs; src.box = f->box; src.n = S; src.n_dev = nullptr;
+  src.ecache = const_cast<float*>(enc);  // read only
+  src.ecache_stride = S;
+  return NSL_OK;
+}
+
+int nsl_mlp_fwd(const nsl_field* f, const float* params, const float* enc, const float* dirs, int S, float* sigma,
+                float* rgb, void* ws, size_t ws_bytes, hipStream_t st) {
+  if (!sigma || !rgb) return fail(NSL_E_INVALID, "null output");
+  FieldWs w;
+  SampleSrc src;
+  int rc = mlp_common(f, params, enc, dirs, S, ws, ws_bytes, w, src);
+  if (rc) return rc;
+  HIP_TRY(field_prep(f->shape, params, f->wo, w.wprep, st), "prep weights");
+  FieldArgs fa{params, w.wprep, f->lv};
+  HIP_TRY(field_forward(f->shape, fa, src, S, sigma, rgb, st), "mlp forward");
+  return NSL_OK;
+}
+
+int nsl_mlp_bwd(const nsl_field* f, const float* params, const float* enc, const float* dirs, int S,
+                const float* dsigma, const float* drgb, float* grads, float* d_enc, void* ws, size_t ws_bytes,
+                hipStream_t st) {
+  if (!dsigma || !drgb || !grads || !d_enc) return fail(NSL_E_INVALID, "null argument");
+  if (misaligned(grads) || misaligned(d_enc)) return fail(NSL_E_INVALID, "grads and d_enc must be 16-byte aligned");
+  FieldWs w;
+  SampleSrc src;
+  int rc = mlp_common(f, params, enc, dirs, S, ws, ws_bytes, w, src);
+  if (rc) return rc;
+  HIP_TRY(field_prep(f->shape, params, f->wo, w.wprep, st), "prep weights");
+  FieldArgs fa{params, w.wprep, f->lv};
+  RecordBuffers rec = w.rec;
+  rec.de = reinterpret_cast<float2*>(d_enc);
+  rec.stride = S;
+  rec.de_bf16 = false;
+  HIP_TRY(field_backward(f->shape, fa, src, kBwdBlocks, dsigma, drgb, rec, w.partial, f->wo, grads, st),
+          "mlp backward");
+  HIP_TRY(field_dw_reduce(f->shape, w.partial, kBwdBlocks, f->wo, grads, nullptr, nullptr, st), "weight gradient");
+  return NSL_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Machine-peak probes
 // ---------------------------------------------------------------------------

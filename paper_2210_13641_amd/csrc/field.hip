@@ -294,7 +294,12 @@ __global__ __launch_bounds__(kFieldBwdWaves * kWave, 1) void field_bwd_kernel(Fi
     const int s = tile * 16 + jc;
     const bool valid = s < S;
     float xn[3] = {0.5f, 0.5f, 0.5f}, d[3] = {0.0f, 0.0f, 1.0f};
-    if (valid) load_sample(src, s, xn, d);
+    if (valid) {
+      if (src.ecache)
+        load_direction(src, s, d);  // the position is not needed with the encoding given
+      else
+        load_sample(src, s, xn, d);
+    }
     Acts<N> act;
     if (src.ecache) {
       read_encoding<N>(static_cast<const float2*>(src.ecache), src.ecache_stride, g, s, valid, act.e);

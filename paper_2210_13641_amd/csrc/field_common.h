@@ -28,9 +28,8 @@ __device__ __forceinline__ void load_position(const SampleSrc& src, int s, float
   }
 }
 
-__device__ __forceinline__ void load_sample(const SampleSrc& src, int s, float xn[3],
-                                            float d[3]) {
-  load_position(src, s, xn);
+// View direction of sample s.
+__device__ __forceinline__ void load_direction(const SampleSrc& src, int s, float d[3]) {
   if (src.t) {
     const float4 dd = src.rays[2 * src.ray[s] + 1];
     d[0] = dd.x; d[1] = dd.y; d[2] = dd.z;
@@ -38,6 +37,12 @@ __device__ __forceinline__ void load_sample(const SampleSrc& src, int s, float x
 #pragma unroll
     for (int i = 0; i < 3; ++i) d[i] = src.dir[3 * s + i];
   }
+}
+
+__device__ __forceinline__ void load_sample(const SampleSrc& src, int s, float xn[3],
+                                            float d[3]) {
+  load_position(src, s, xn);
+  load_direction(src, s, d);
 }
 
 // Per-lane level constants (levels g, g+4, ... of this lane group).

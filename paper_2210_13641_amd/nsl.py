@@ -97,6 +97,8 @@ _sig("nsl_march", _i, [_vp, _vp, C.POINTER(StepConfig), _vp, _i, _vp, _sz, _vp, 
 _sig("nsl_field_workspace_bytes", _sz, [_vp, _i])
 _sig("nsl_field_fwd", _i, [_vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _sz, _vp])
 _sig("nsl_field_bwd", _i, [_vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp, _sz, _vp])
+_sig("nsl_mlp_fwd", _i, [_vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _sz, _vp])
+_sig("nsl_mlp_bwd", _i, [_vp, _vp, _vp, _vp, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp])
 _sig("nsl_composite_fwd", _i, [_vp, _vp, _vp, _vp, _i, _f, _f, _vp, _vp])
 _sig("nsl_composite_bwd", _i, [_vp, _vp, _vp, _vp, _i, _f, _vp, _vp, _vp, _vp, _vp, _vp, _vp])
 _sig("nsl_adam", _i, [_vp, _vp, _vp, _vp, C.c_int64, _f, _f, _f, _f, _i, _f, _vp])
@@ -399,6 +401,26 @@ def encode_fwd(field: "Field", params, xn):
     _check(_lib.nsl_encode_fwd(field.handle, _dev(params, torch.float32), _dev(xn, torch.float32), S, _ptr(e),
                                _stream()))
     return e
+
+
+def mlp_fwd(field: "Field", params, enc, dirs, ws):
+    """sigma [S] and rgb [S,3] of the MLP on a level-major encoding [levels, S, 2]."""
+    S = dirs.shape[0]
+    sigma = torch.empty(S, device=dirs.device, dtype=torch.float32)
+    rgb = torch.empty(S, 3, device=dirs.device, dtype=torch.float32)
+    _check(_lib.nsl_mlp_fwd(field.handle, _dev(params, torch.float32), _dev(enc, torch.float32),
+                            _dev(dirs, torch.float32), S, _ptr(sigma), _ptr(rgb), _ptr(ws), ws.numel(), _stream()))
+    return sigma, rgb
+
+
+def mlp_bwd(field: "Field", params, enc, dirs, dsigma, drgb, grads, ws):
+    """Weight part of grads += the MLP's adjoint; returns dL/de [levels, S, 2]."""
+    S = dirs.shape[0]
+    d_enc = torch.empty(field.spec.levels, S, 2, dtype=torch.float32, device=dirs.device)
+    _check(_lib.nsl_mlp_bwd(field.handle, _dev(params, torch.float32), _dev(enc, torch.float32),
+                            _dev(dirs, torch.float32), S, _dev(dsigma, torch.float32), _dev(drgb, torch.float32),
+                            _dev(grads, torch.float32), _ptr(d_enc), _ptr(ws), ws.numel(), _stream()))
+    return d_enc
 
 
 def encode_fwd_mixed(field: "Field", shadow, xn):

@@ -149,3 +149,44 @@ def test_encode_bwd_entry_point_matches_oracle(nsl, gpu, spec, S, unpaired):
         check_mag(f"encode bwd accumulate p{prec}", g[:nt], gt + 0.5, gtm + 0.5, tol)
         assert np.all(g[nt:] == 0.5)
     report(f"encode bwd: {spec.levels} levels, S={S}, {int(np.count_nonzero(gtm))} entries touched")
+
+
+@pytest.mark.parametrize("spec,S", [(W.C1_FIELD, 1037), (W.C2_FIELD, 1037), (W.C2_FIELD, 65537)],
+                         ids=["tiny", "full", "full-64k"])
+def test_mlp_entry_points_match_oracle(nsl, gpu, spec, S):
+    """nsl_mlp_fwd and nsl_mlp_bwd on a given level-major encoding: sigma and
+    colour, dL/de and every weight gradient against the oracle's networks at
+    1e-5 of their magnitudes; the weight gradients accumulate onto what
+    grads held, and the table part of grads is left alone."""
+    import torch
+    dev = gpu
+    f = nsl.Field(spec)
+    lay = f.layout
+    flat, _, w64 = params_for(spec, lay, seed=5, table_range=0.5)
+    rng = np.random.default_rng(S + 7)
+    L = spec.levels
+    e = rng.normal(scale=0.3, size=(S, 2 * L)).astype(np.float32)
+    e[:3] = 0.0                                     # samples whose encoding is zero
+    d = rng.normal(size=(S, 3))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    enc = np.ascontiguousarray(e.reshape(S, L, 2).transpose(1, 0, 2))
+    P, E, D = _t(torch, dev, flat), _t(torch, dev, enc), _t(torch, dev, d)
+    ws = torch.empty(f.workspace_bytes(S), dtype=torch.uint8, device=dev)
+    sig, rgb = nsl.mlp_fwd(f, P, E, D, ws)
+    e64 = e.astype(np.float64)
+    cache = ofield.mlp_fwd(spec, w64, e64, np.abs(e64), ofield.sh_basis(d.astype(np.float64), spec.sh_bands))
+    check_mag("mlp sigma", sig.cpu().numpy(), cache["sigma"], cache["sigma_mag"], 1e-5)
+    check_mag("mlp colour", rgb.cpu().numpy(), cache["colour"], cache["colour_mag"], 1e-5)
+    dsig = rng.normal(size=S).astype(np.float32)
+    drgb = rng.normal(size=(S, 3)).astype(np.float32)
+    G = torch.full((lay["total"],), 0.5, device=dev)
+    de = nsl.mlp_bwd(f, P, E, D, _t(torch, dev, dsig), _t(torch, dev, drgb), G, ws).cpu().numpy()
+    dWs, dWm, de_o, dem = ofield.mlp_bwd(spec, w64, cache, dsig.astype(np.float64), np.abs(dsig).astype(np.float64),
+                                         drgb.astype(np.float64), np.abs(drgb).astype(np.float64))
+    check_mag("mlp dL/de", de.transpose(1, 0, 2).reshape(S, 2 * L), de_o, dem, 1e-5)
+    g = G.cpu().numpy().astype(np.float64)
+    gtab, gws = split_grads(g, lay, spec)
+    assert np.all(gtab == 0.5)
+    for j, (a, b, m) in enumerate(zip(gws, dWs, dWm)):
+        check_mag(f"mlp grad W{j}", a, b + 0.5, m + 0.5, 1e-5)
+    report(f"mlp entry points: {L} levels, S={S}")
