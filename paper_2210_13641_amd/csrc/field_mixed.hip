@@ -370,10 +370,11 @@ __device__ __forceinline__ void tile_operands(const TileIn<N>& in, int g, PActs<
 // ---------------------------------------------------------------------------
 // Backward, eight waves a workgroup (two per SIMD).  Each wave runs the
 // forward recompute and the input-gradient chain of one 16-sample tile; the
-// 128 samples of the workgroup's step are staged layer by layer into a
-// shared [feature][sample] buffer (two buffers, used alternately, so one
-// barrier a layer suffices), and each wave adds the products of its share of
-// the layer's weight-gradient tiles over the 128 samples.  A wave then holds
+// 128 samples of the workgroup's step are staged into a shared
+// [feature][sample] buffer, two or one layers at a time (three groups a tile;
+// two buffers, used alternately, so one barrier a group suffices), and each
+// wave adds the products of its share of the group's weight-gradient tiles
+// over the 128 samples.  A wave then holds
 // a few weight-gradient tiles instead of all of them, which leaves room for
 // two waves on a SIMD.
 // ---------------------------------------------------------------------------
@@ -483,19 +484,45 @@ struct PendingDe1 {
   }
 };
 
-// Staging buffer b of the two: X rows, then Y rows.
+// Staging groups: the layers whose weight-gradient products follow one
+// barrier together (the colour layers; the geometry-feature layer and the
+// second density layer; the first density layer).  Within a group each layer
+// has its X rows (16 per input tile) and then its dY rows (16 per output
+// tile), layers in backward order; a buffer holds the largest group.
 template <class N>
-__device__ __forceinline__ __bf16* stage_x(__bf16* stage, int b) {
-  return stage + b * (N::XROWS + N::YROWS) * kSRow;
+struct StageRows {
+  static constexpr int xr(int j) { return (N::kin(j) + 15) / 16 * 16; }
+  static constexpr int yr(int j) { return (N::kout(j) + 15) / 16 * 16; }
+  static constexpr int group(int j) { return j >= 3 || j == N::NW - 1 ? 0 : j >= 1 ? 1 : 2; }
+  static constexpr int x(int j) {
+    int o = 0;
+    for (int i = N::NW - 1; i > j; --i)
+      if (group(i) == group(j)) o += xr(i) + yr(i);
+    return o;
+  }
+  static constexpr int y(int j) { return x(j) + xr(j); }
+  static constexpr int rows(int gr) {
+    int o = 0;
+    for (int i = 0; i < N::NW; ++i)
+      if (group(i) == gr) o += xr(i) + yr(i);
+    return o;
+  }
+  static constexpr int ROWS = N::cmax(rows(0), N::cmax(rows(1), rows(2)));
+};
+
+// Row r of staging buffer b.
+template <class N>
+__device__ __forceinline__ __bf16* srow(__bf16* stage, int b, int r) {
+  return stage + (b * StageRows<N>::ROWS + r) * kSRow;
 }
 template <class N>
-__device__ __forceinline__ __bf16* stage_y(__bf16* stage, int b) {
-  return stage_x<N>(stage, b) + N::XROWS * kSRow;
+__device__ __forceinline__ uint16_t* srow16(__bf16* stage, int b, int r) {
+  return reinterpret_cast<uint16_t*>(srow<N>(stage, b, r));
 }
 
 // Forward recompute, backward chain and dL/de of this wave's tile (samples
 // s = 128 p + 16 w + jc), with the workgroup's weight-gradient products of
-// each layer in between; the previous tile's dL/de (pend) is stored after the
+// each staging group in between; the previous tile's dL/de (pend) is stored after the
 // forward and replaced by this tile's.
 template <class N>
 __device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const __bf16* __restrict__ Ab,
@@ -522,9 +549,10 @@ __device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const _
   constexpr int K3 = N::NCH == 2 ? (N::HC / 16) * (N::HC / 32) : 1;
   constexpr int MT0 = N::bmt(0);
   bf8 w4[N::HC / 16], w3[K3], w2[N::HC / 32], w1[N::HD / 16], w0[MT0 * (N::HD / 32)];
+  using SR = StageRows<N>;
   load_ops<N>(Ab + M::boff(N::NW - 1), lane, w4);
   const bf8* hl = N::NCH == 2 ? a[0].h4 : a[0].h3;
-  // last colour layer
+  // colour layers: the last one, then (with two) the second hidden one
   f4 dhl[N::HC / 16];
   {
     const bf8 b = pack8(dz, zero);
@@ -533,11 +561,8 @@ __device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const _
   }
   if constexpr (N::NCH == 2) load_ops<N>(Ab + M::boff(3), lane, w3);
   else load_ops<N>(Ab + M::boff(2), lane, w2);
-  stage1_packed<N::HC / 16>(reinterpret_cast<uint16_t*>(stage_x<N>(stage, buf)), hl, g, c);
-  stage1_f32<1>(reinterpret_cast<uint16_t*>(stage_y<N>(stage, buf)), &dz, g, c);
-  __syncthreads();
-  dw.wl.add(stage_x<N>(stage, buf), stage_y<N>(stage, buf), w, lane);
-  buf ^= 1;
+  stage1_packed<N::HC / 16>(srow16<N>(stage, buf, SR::x(N::NW - 1)), hl, g, c);
+  stage1_f32<1>(srow16<N>(stage, buf, SR::y(N::NW - 1)), &dz, g, c);
   f4 dh3[N::HC / 16];
   if constexpr (N::NCH == 2) {
     f4 acc[N::HC / 16];
@@ -552,27 +577,24 @@ __device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const _
 #pragma unroll
     for (int m = 0; m < N::HC / 16; ++m) dh3[m] = relu_grad(acc[m], a[0].h3[m >> 1], m & 1);
     load_ops<N>(Ab + M::boff(2), lane, w2);
-    stage1_packed<N::HC / 16>(reinterpret_cast<uint16_t*>(stage_x<N>(stage, buf)), a[0].h3, g, c);
-    stage1_f32<N::HC / 16>(reinterpret_cast<uint16_t*>(stage_y<N>(stage, buf)), dhl, g, c);
-    __syncthreads();
-    dw.w3.add(stage_x<N>(stage, buf), stage_y<N>(stage, buf), w, lane);
-    buf ^= 1;
+    stage1_packed<N::HC / 16>(srow16<N>(stage, buf, SR::x(3)), a[0].h3, g, c);
+    stage1_f32<N::HC / 16>(srow16<N>(stage, buf, SR::y(3)), dhl, g, c);
   } else {
 #pragma unroll
     for (int m = 0; m < N::HC / 16; ++m) dh3[m] = dhl[m];
   }
-  // first colour layer: gradient of the geometry features
+  __syncthreads();
+  dw.wl.add(srow<N>(stage, buf, SR::x(N::NW - 1)), srow<N>(stage, buf, SR::y(N::NW - 1)), w, lane);
+  if constexpr (N::NCH == 2) dw.w3.add(srow<N>(stage, buf, SR::x(3)), srow<N>(stage, buf, SR::y(3)), w, lane);
+  buf ^= 1;
+  // first colour layer (gradient of the geometry features), second density layer
   f4 dgeo = zero;
 #pragma unroll
   for (int k = 0; k < N::HC / 32; ++k) dgeo = mfma32(w2[k], pack8(dh3[2 * k], dh3[2 * k + 1]), dgeo);
   load_ops<N>(Ab + M::boff(1), lane, w1);
-  stage1_packed<2>(reinterpret_cast<uint16_t*>(stage_x<N>(stage, buf)), &a[0].osh, g, c);
-  stage1_f32<N::HC / 16>(reinterpret_cast<uint16_t*>(stage_y<N>(stage, buf)), dh3, g, c);
-  __syncthreads();
-  dw.w2.add(stage_x<N>(stage, buf), stage_y<N>(stage, buf), w, lane);
-  buf ^= 1;
+  stage1_packed<2>(srow16<N>(stage, buf, SR::x(2)), &a[0].osh, g, c);
+  stage1_f32<N::HC / 16>(srow16<N>(stage, buf, SR::y(2)), dh3, g, c);
   if (g == 0) dgeo[0] += expf(a[0].o[0]) * in.ds;
-  // second density layer
   f4 dh1[N::HD / 16];
   {
     const bf8 b = pack8(dgeo, zero);
@@ -580,10 +602,11 @@ __device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const _
     for (int m = 0; m < N::HD / 16; ++m) dh1[m] = relu_grad(mfma32(w1[m], b, zero), a[0].h1[m >> 1], m & 1);
   }
   load_ops<N>(Ab + M::boff(0), lane, w0);
-  stage1_packed<N::HD / 16>(reinterpret_cast<uint16_t*>(stage_x<N>(stage, buf)), a[0].h1, g, c);
-  stage1_f32<1>(reinterpret_cast<uint16_t*>(stage_y<N>(stage, buf)), &dgeo, g, c);
+  stage1_packed<N::HD / 16>(srow16<N>(stage, buf, SR::x(1)), a[0].h1, g, c);
+  stage1_f32<1>(srow16<N>(stage, buf, SR::y(1)), &dgeo, g, c);
   __syncthreads();
-  dw.w1.add(stage_x<N>(stage, buf), stage_y<N>(stage, buf), w, lane);
+  dw.w2.add(srow<N>(stage, buf, SR::x(2)), srow<N>(stage, buf, SR::y(2)), w, lane);
+  dw.w1.add(srow<N>(stage, buf, SR::x(1)), srow<N>(stage, buf, SR::y(1)), w, lane);
   buf ^= 1;
   // first density layer: dL/de
   f4 de[MT0];
@@ -596,7 +619,7 @@ __device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const _
     for (int m = 0; m < MT0; ++m) de[m] = mfma32(w0[m * (N::HD / 32) + k], b, de[m]);
   }
   {
-    uint16_t* X = reinterpret_cast<uint16_t*>(stage_x<N>(stage, buf));
+    uint16_t* X = srow16<N>(stage, buf, SR::x(0));
 #pragma unroll
     for (int k = 0; k < N::NSLOT; ++k) X[fwd_in_feature<N>(0, k, g) * kSRow + c] = (uint16_t)bf_bits(a[0].e, k);
     if constexpr (N::ENC < 16) {
@@ -604,9 +627,9 @@ __device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const _
       for (int k = 0; k < 2; ++k) X[(N::ENC + 2 * g + k) * kSRow + c] = 0;
     }
   }
-  stage1_f32<N::HD / 16>(reinterpret_cast<uint16_t*>(stage_y<N>(stage, buf)), dh1, g, c);
+  stage1_f32<N::HD / 16>(srow16<N>(stage, buf, SR::y(0)), dh1, g, c);
   __syncthreads();
-  dw.w0.add(stage_x<N>(stage, buf), stage_y<N>(stage, buf), w, lane);
+  dw.w0.add(srow<N>(stage, buf, SR::x(0)), srow<N>(stage, buf, SR::y(0)), w, lane);
   buf ^= 1;
   pend.s = s;
   pend.valid = valid;
@@ -624,7 +647,7 @@ __global__ __launch_bounds__(kBwdWaves8 * kWave, 1) void mixed_bwd8_kernel(
     const float* __restrict__ dsigma, const float* __restrict__ drgb, RecordBuffers rec,
     float* __restrict__ dw_partial) {
   using M = Mixed<N>;
-  constexpr int SBUF = (N::XROWS + N::YROWS) * kSRow;
+  constexpr int SBUF = StageRows<N>::ROWS * kSRow;
   static_assert(2 * SBUF * (int)sizeof(__bf16) >= N::NWEIGHTS * (int)sizeof(float),
                 "the weight-gradient sums reuse the staging buffers");
   __shared__ __attribute__((aligned(16))) __bf16 Af[M::FWD];
