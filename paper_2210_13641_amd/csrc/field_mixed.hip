@@ -1,6 +1,7 @@
 // Mixed-precision hash-grid field on gfx950: FP16 tables, BF16 weights and
 // activations on v_mfma_f32_16x16x32_bf16 with FP32 accumulation (weight
-// gradients too, with samples on the contraction axis),
+// gradients too, with samples on the contraction axis, on 32x32x16 tiles
+// where a layer's widths allow),
 // FP32 trilinear blending, FP32 table-gradient accumulation.
 //
 // Operand layouts follow the FP32 kernels (features as rows, 16 samples as
@@ -17,6 +18,12 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ f4 mfma32(bf8 a, bf8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ f16v mfma32x32(bf8 a, bf8 b, f16v c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
 typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
@@ -217,12 +224,42 @@ struct TileIn {
 };
 
 // acc[r] where the ReLU output (element 4*half + r of p) is positive, else 0.
-__device__ __forceinline__ f4 relu_grad(f4 acc, bf8 p, int half) {
-  const s8v q = __builtin_bit_cast(s8v, p);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) acc[r] = q[4 * half + r] > 0 ? acc[r] : 0.0f;
-  return acc;
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+
+// ReLU of eight BF16 values on their bits: a BF16 value is below zero exactly
+// when its bit pattern is negative as a 16-bit integer (and -0 becomes +0).
+// Rounding keeps the sign, so this equals rounding the FP32 ReLU.
+__device__ __forceinline__ bf8 relu8(bf8 v) {
+  uint4 u = __builtin_bit_cast(uint4, v);
+  const s16x2 z = {0, 0};
+  u.x = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, u.x), z));
+  u.y = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, u.y), z));
+  u.z = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, u.z), z));
+  u.w = __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s16x2, u.w), z));
+  return __builtin_bit_cast(bf8, u);
 }
+
+// The BF16 gradient g where the ReLU output p (bits of a value >= +0) is
+// above zero, else 0: the same values as masking in FP32 and rounding after.
+// (two packed 16-bit instructions: keep = min(p, 1), g * keep; written out
+// because the compiler otherwise selects each half apart, after converting
+// each value on its own)
+__device__ __forceinline__ uint32_t relu_mask2(uint32_t g, uint32_t p) {
+  uint32_t keep, r;
+  asm("v_pk_min_u16 %0, %1, %2" : "=v"(keep) : "v"(p), "v"(0x00010001u));
+  asm("v_pk_mul_lo_u16 %0, %1, %2" : "=v"(r) : "v"(g), "v"(keep));
+  return r;
+}
+__device__ __forceinline__ bf8 relu_mask8(bf8 g, bf8 p) {
+  uint4 a = __builtin_bit_cast(uint4, g);
+  const uint4 b = __builtin_bit_cast(uint4, p);
+  a.x = relu_mask2(a.x, b.x);
+  a.y = relu_mask2(a.y, b.y);
+  a.z = relu_mask2(a.z, b.z);
+  a.w = relu_mask2(a.w, b.w);
+  return __builtin_bit_cast(bf8, a);
+}
+
 
 template <class N, bool KEEP>
 __device__ __forceinline__ void fetch_tile(const SampleSrc& src, const _Float16* __restrict__ table,
@@ -289,11 +326,11 @@ __device__ __forceinline__ void fwd_tiles(const __bf16* __restrict__ Af, int lan
 #pragma unroll
     for (int m = 0; m < N::HD / 16; ++m)
 #pragma unroll
-      for (int t = 0; t < T; ++t) h[t][m] = relu4(mfma32(w0[m], a[t].e, zero));
+      for (int t = 0; t < T; ++t) h[t][m] = mfma32(w0[m], a[t].e, zero);
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
-      for (int s = 0; s < N::HD / 32; ++s) a[t].h1[s] = pack8(h[t][2 * s], h[t][2 * s + 1]);
+      for (int s = 0; s < N::HD / 32; ++s) a[t].h1[s] = relu8(pack8(h[t][2 * s], h[t][2 * s + 1]));
   }
   load_ops<N>(Af + M::foff(2), lane, w2);
   {
@@ -317,11 +354,11 @@ __device__ __forceinline__ void fwd_tiles(const __bf16* __restrict__ Af, int lan
 #pragma unroll
     for (int m = 0; m < N::HC / 16; ++m)
 #pragma unroll
-      for (int t = 0; t < T; ++t) h[t][m] = relu4(mfma32(w2[m], a[t].osh, zero));
+      for (int t = 0; t < T; ++t) h[t][m] = mfma32(w2[m], a[t].osh, zero);
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
-      for (int s = 0; s < N::HC / 32; ++s) a[t].h3[s] = pack8(h[t][2 * s], h[t][2 * s + 1]);
+      for (int s = 0; s < N::HC / 32; ++s) a[t].h3[s] = relu8(pack8(h[t][2 * s], h[t][2 * s + 1]));
   }
   if constexpr (N::NCH == 2) {
     load_ops<N>(Af + M::foff(N::NW - 1), lane, w4);
@@ -339,7 +376,7 @@ __device__ __forceinline__ void fwd_tiles(const __bf16* __restrict__ Af, int lan
 #pragma unroll
     for (int t = 0; t < T; ++t)
 #pragma unroll
-      for (int s = 0; s < N::HC / 32; ++s) a[t].h4[s] = pack8(relu4(acc[t][2 * s]), relu4(acc[t][2 * s + 1]));
+      for (int s = 0; s < N::HC / 32; ++s) a[t].h4[s] = relu8(pack8(acc[t][2 * s], acc[t][2 * s + 1]));
   }
   {
     f4 acc[T];
@@ -419,9 +456,11 @@ struct OwnAcc {
         v[k] = mfma32(*reinterpret_cast<const bf8*>(xr + 32 * c), *reinterpret_cast<const bf8*>(yr + 32 * c), v[k]);
     }
   }
+  static constexpr int SPLIT = 1;
   // dW (LDS, row-major kin x kout, zeroed) += the owned tiles (disjoint over
-  // the waves, so all waves may write at once)
-  __device__ __forceinline__ void flush(float* dW, int w, int lane) const {
+  // the waves, so all waves write at once, in phase 0)
+  __device__ __forceinline__ void flush(float* dW, int w, int lane, int phase) const {
+    if (phase != 0) return;
     const int gk = lane >> 4, i = lane & 15;
 #pragma unroll
     for (int k = 0; k < SLOTS; ++k) {
@@ -437,13 +476,59 @@ struct OwnAcc {
   }
 };
 
+// The weight-gradient products of a layer whose input and output widths are
+// multiples of 32, on 32x32x16 tiles: each tile goes to kBwdWaves8 / TILES
+// waves, each of which adds the products over its own share of the staged
+// samples (the operand reads per product are half those of 16x16 tiles).
+template <class N, int J>
+struct OwnAcc32 {
+  static constexpr int MI = N::kin(J) / 32, NJ = N::kout(J) / 32, TILES = MI * NJ;
+  static constexpr int SPLIT = kBwdWaves8 / TILES, KSTEPS = kStepSamples / SPLIT / 16;
+  f16v v;
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = 0.0f;
+  }
+  __device__ __forceinline__ void add(const __bf16* Xs, const __bf16* Ys, int w, int lane) {
+    const int t = w % TILES, sp = w / TILES, m = t / NJ, n = t % NJ;
+    const int i = lane & 31, c0 = sp * (kStepSamples / SPLIT) + 8 * (lane >> 5);
+    const __bf16* xr = Xs + (32 * m + i) * kSRow + c0;
+    const __bf16* yr = Ys + (32 * n + i) * kSRow + c0;
+#pragma unroll
+    for (int c = 0; c < KSTEPS; ++c)
+      v = mfma32x32(*reinterpret_cast<const bf8*>(xr + 16 * c), *reinterpret_cast<const bf8*>(yr + 16 * c), v);
+  }
+  // dW += this wave's partial tile; the waves sharing a tile write in
+  // different phases
+  __device__ __forceinline__ void flush(float* dW, int w, int lane, int phase) const {
+    const int t = w % TILES, sp = w / TILES, m = t / NJ, n = t % NJ;
+    if (sp != phase) return;
+    const int col = 32 * n + (lane & 31);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = 32 * m + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+      dW[row * N::kout(J) + col] += v[r];
+    }
+  }
+};
+
+template <class N, int J>
+constexpr bool kWideTiles = N::kin(J) % 32 == 0 && N::kout(J) % 32 == 0 &&
+                            kBwdWaves8 % ((N::kin(J) / 32) * (N::kout(J) / 32)) == 0;
+template <class N, int J>
+using LayerAcc = typename std::conditional<kWideTiles<N, J>, OwnAcc32<N, J>, OwnAcc<N, J>>::type;
+
 template <class N>
 struct OwnAll {
-  OwnAcc<N, 0> w0;
-  OwnAcc<N, 1> w1;
-  OwnAcc<N, 2> w2;
-  OwnAcc<N, N::NCH == 2 ? 3 : 2> w3;  // second colour hidden layer (unused with one)
-  OwnAcc<N, N::NW - 1> wl;
+  LayerAcc<N, 0> w0;
+  LayerAcc<N, 1> w1;
+  LayerAcc<N, 2> w2;
+  LayerAcc<N, N::NCH == 2 ? 3 : 2> w3;  // second colour hidden layer (unused with one)
+  LayerAcc<N, N::NW - 1> wl;
+  static constexpr int cmax(int a, int b) { return a > b ? a : b; }
+  static constexpr int PHASES =
+      cmax(cmax(LayerAcc<N, 0>::SPLIT, LayerAcc<N, 1>::SPLIT),
+           cmax(cmax(LayerAcc<N, 2>::SPLIT, LayerAcc<N, N::NCH == 2 ? 3 : 2>::SPLIT), LayerAcc<N, N::NW - 1>::SPLIT));
 };
 
 // One tile's staged values: rows 16m + 4g + r of column c (lane group g).
@@ -553,35 +638,38 @@ __device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const _
   load_ops<N>(Ab + M::boff(N::NW - 1), lane, w4);
   const bf8* hl = N::NCH == 2 ? a[0].h4 : a[0].h3;
   // colour layers: the last one, then (with two) the second hidden one
-  f4 dhl[N::HC / 16];
+  // the hidden-layer gradients are used only as BF16 (MFMA operands and
+  // staged values), so they are rounded once and masked on their bits
+  bf8 dhl[N::HC / 32];
   {
     const bf8 b = pack8(dz, zero);
+    f4 raw[N::HC / 16];
 #pragma unroll
-    for (int m = 0; m < N::HC / 16; ++m) dhl[m] = relu_grad(mfma32(w4[m], b, zero), hl[m >> 1], m & 1);
+    for (int m = 0; m < N::HC / 16; ++m) raw[m] = mfma32(w4[m], b, zero);
+#pragma unroll
+    for (int k = 0; k < N::HC / 32; ++k) dhl[k] = relu_mask8(pack8(raw[2 * k], raw[2 * k + 1]), hl[k]);
   }
   if constexpr (N::NCH == 2) load_ops<N>(Ab + M::boff(3), lane, w3);
   else load_ops<N>(Ab + M::boff(2), lane, w2);
   stage1_packed<N::HC / 16>(srow16<N>(stage, buf, SR::x(N::NW - 1)), hl, g, c);
   stage1_f32<1>(srow16<N>(stage, buf, SR::y(N::NW - 1)), &dz, g, c);
-  f4 dh3[N::HC / 16];
+  bf8 dh3[N::HC / 32];
   if constexpr (N::NCH == 2) {
     f4 acc[N::HC / 16];
 #pragma unroll
     for (int m = 0; m < N::HC / 16; ++m) acc[m] = zero;
 #pragma unroll
-    for (int k = 0; k < N::HC / 32; ++k) {
-      const bf8 b = pack8(dhl[2 * k], dhl[2 * k + 1]);
+    for (int k = 0; k < N::HC / 32; ++k)
 #pragma unroll
-      for (int m = 0; m < N::HC / 16; ++m) acc[m] = mfma32(w3[m * (N::HC / 32) + k], b, acc[m]);
-    }
+      for (int m = 0; m < N::HC / 16; ++m) acc[m] = mfma32(w3[m * (N::HC / 32) + k], dhl[k], acc[m]);
 #pragma unroll
-    for (int m = 0; m < N::HC / 16; ++m) dh3[m] = relu_grad(acc[m], a[0].h3[m >> 1], m & 1);
+    for (int k = 0; k < N::HC / 32; ++k) dh3[k] = relu_mask8(pack8(acc[2 * k], acc[2 * k + 1]), a[0].h3[k]);
     load_ops<N>(Ab + M::boff(2), lane, w2);
     stage1_packed<N::HC / 16>(srow16<N>(stage, buf, SR::x(3)), a[0].h3, g, c);
-    stage1_f32<N::HC / 16>(srow16<N>(stage, buf, SR::y(3)), dhl, g, c);
+    stage1_packed<N::HC / 16>(srow16<N>(stage, buf, SR::y(3)), dhl, g, c);
   } else {
 #pragma unroll
-    for (int m = 0; m < N::HC / 16; ++m) dh3[m] = dhl[m];
+    for (int k = 0; k < N::HC / 32; ++k) dh3[k] = dhl[k];
   }
   __syncthreads();
   dw.wl.add(srow<N>(stage, buf, SR::x(N::NW - 1)), srow<N>(stage, buf, SR::y(N::NW - 1)), w, lane);
@@ -590,16 +678,19 @@ __device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const _
   // first colour layer (gradient of the geometry features), second density layer
   f4 dgeo = zero;
 #pragma unroll
-  for (int k = 0; k < N::HC / 32; ++k) dgeo = mfma32(w2[k], pack8(dh3[2 * k], dh3[2 * k + 1]), dgeo);
+  for (int k = 0; k < N::HC / 32; ++k) dgeo = mfma32(w2[k], dh3[k], dgeo);
   load_ops<N>(Ab + M::boff(1), lane, w1);
   stage1_packed<2>(srow16<N>(stage, buf, SR::x(2)), &a[0].osh, g, c);
-  stage1_f32<N::HC / 16>(srow16<N>(stage, buf, SR::y(2)), dh3, g, c);
+  stage1_packed<N::HC / 16>(srow16<N>(stage, buf, SR::y(2)), dh3, g, c);
   if (g == 0) dgeo[0] += expf(a[0].o[0]) * in.ds;
-  f4 dh1[N::HD / 16];
+  bf8 dh1[N::HD / 32];
   {
     const bf8 b = pack8(dgeo, zero);
+    f4 raw[N::HD / 16];
 #pragma unroll
-    for (int m = 0; m < N::HD / 16; ++m) dh1[m] = relu_grad(mfma32(w1[m], b, zero), a[0].h1[m >> 1], m & 1);
+    for (int m = 0; m < N::HD / 16; ++m) raw[m] = mfma32(w1[m], b, zero);
+#pragma unroll
+    for (int k = 0; k < N::HD / 32; ++k) dh1[k] = relu_mask8(pack8(raw[2 * k], raw[2 * k + 1]), a[0].h1[k]);
   }
   load_ops<N>(Ab + M::boff(0), lane, w0);
   stage1_packed<N::HD / 16>(srow16<N>(stage, buf, SR::x(1)), a[0].h1, g, c);
@@ -613,11 +704,9 @@ __device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const _
 #pragma unroll
   for (int m = 0; m < MT0; ++m) de[m] = zero;
 #pragma unroll
-  for (int k = 0; k < N::HD / 32; ++k) {
-    const bf8 b = pack8(dh1[2 * k], dh1[2 * k + 1]);
+  for (int k = 0; k < N::HD / 32; ++k)
 #pragma unroll
-    for (int m = 0; m < MT0; ++m) de[m] = mfma32(w0[m * (N::HD / 32) + k], b, de[m]);
-  }
+    for (int m = 0; m < MT0; ++m) de[m] = mfma32(w0[m * (N::HD / 32) + k], dh1[k], de[m]);
   {
     uint16_t* X = srow16<N>(stage, buf, SR::x(0));
 #pragma unroll
@@ -627,7 +716,7 @@ __device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const _
       for (int k = 0; k < 2; ++k) X[(N::ENC + 2 * g + k) * kSRow + c] = 0;
     }
   }
-  stage1_f32<N::HD / 16>(srow16<N>(stage, buf, SR::y(0)), dh1, g, c);
+  stage1_packed<N::HD / 16>(srow16<N>(stage, buf, SR::y(0)), dh1, g, c);
   __syncthreads();
   dw.w0.add(srow<N>(stage, buf, SR::x(0)), srow<N>(stage, buf, SR::y(0)), w, lane);
   buf ^= 1;
@@ -700,12 +789,14 @@ __global__ __launch_bounds__(kBwdWaves8 * kWave, 1) void mixed_bwd8_kernel(
   float* dW = reinterpret_cast<float*>(stage);
   for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) dW[i] = 0.0f;
   __syncthreads();
-  dw.w0.flush(dW + N::woff(0), w, lane);
-  dw.w1.flush(dW + N::woff(1), w, lane);
-  dw.w2.flush(dW + N::woff(2), w, lane);
-  if constexpr (N::NCH == 2) dw.w3.flush(dW + N::woff(3), w, lane);
-  dw.wl.flush(dW + N::woff(N::NW - 1), w, lane);
-  __syncthreads();
+  for (int ph = 0; ph < OwnAll<N>::PHASES; ++ph) {
+    dw.w0.flush(dW + N::woff(0), w, lane, ph);
+    dw.w1.flush(dW + N::woff(1), w, lane, ph);
+    dw.w2.flush(dW + N::woff(2), w, lane, ph);
+    if constexpr (N::NCH == 2) dw.w3.flush(dW + N::woff(3), w, lane, ph);
+    dw.wl.flush(dW + N::woff(N::NW - 1), w, lane, ph);
+    __syncthreads();
+  }
   float* out = dw_partial + (size_t)blockIdx.x * N::NWEIGHTS;
   for (int i = threadIdx.x; i < N::NWEIGHTS; i += blockDim.x) out[i] = dW[i];
 }
