@@ -261,6 +261,11 @@ __device__ __forceinline__ bf8 relu_mask8(bf8 g, bf8 p) {
 }
 
 
+// Sigmoid through the hardware reciprocal (1 ulp) rather than an IEEE
+// division: in the backward the colour gradient it enters is rounded to BF16
+// right after, and in the forward it is far below the BF16 network's error.
+__device__ __forceinline__ float sigmoid_rcp(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+
 template <class N, bool KEEP>
 __device__ __forceinline__ void fetch_tile(const SampleSrc& src, const _Float16* __restrict__ table,
                                            const LevelInfo& lv, const LaneLevels<N>& ll,
@@ -627,7 +632,7 @@ __device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const _
   if (g == 0) {
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-      const float cc = sigmoidf(a[0].z[r]);
+      const float cc = sigmoid_rcp(a[0].z[r]);
       dz[r] = in.dr[r] * cc * (1.0f - cc);
     }
   }
@@ -682,7 +687,7 @@ __device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const _
   load_ops<N>(Ab + M::boff(1), lane, w1);
   stage1_packed<2>(srow16<N>(stage, buf, SR::x(2)), &a[0].osh, g, c);
   stage1_packed<N::HC / 16>(srow16<N>(stage, buf, SR::y(2)), dh3, g, c);
-  if (g == 0) dgeo[0] += expf(a[0].o[0]) * in.ds;
+  if (g == 0) dgeo[0] += __expf(a[0].o[0]) * in.ds;  // rounded to BF16 next
   bf8 dh1[N::HD / 32];
   {
     const bf8 b = pack8(dgeo, zero);
@@ -816,9 +821,9 @@ __device__ __forceinline__ void fwd_store(const PActs<N>& a, int g, int s, bool 
                                           float* __restrict__ rgb_out) {
   if (g == 0 && valid) {
     sigma_out[s] = expf(a.o[0]);
-    rgb_out[3 * s + 0] = sigmoidf(a.z[0]);
-    rgb_out[3 * s + 1] = sigmoidf(a.z[1]);
-    rgb_out[3 * s + 2] = sigmoidf(a.z[2]);
+    rgb_out[3 * s + 0] = sigmoid_rcp(a.z[0]);
+    rgb_out[3 * s + 1] = sigmoid_rcp(a.z[1]);
+    rgb_out[3 * s + 2] = sigmoid_rcp(a.z[2]);
   }
 }
 
