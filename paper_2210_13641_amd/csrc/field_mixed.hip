@@ -544,17 +544,6 @@ __device__ __forceinline__ void stage1_packed(uint16_t* S, const bf8* a, int g, 
 #pragma unroll
     for (int r = 0; r < 4; ++r) S[(16 * m + 4 * g + r) * kSRow + c] = (uint16_t)bf_bits(a[m >> 1], 4 * (m & 1) + r);
 }
-template <int MB>
-__device__ __forceinline__ void stage1_f32(uint16_t* S, const f4* v, int g, int c) {
-#pragma unroll
-  for (int m = 0; m < MB; ++m)
-#pragma unroll
-    for (int r = 0; r < 4; r += 2) {
-      const uint32_t w = bf16_pair(v[m][r], v[m][r + 1]);
-      S[(16 * m + 4 * g + r) * kSRow + c] = (uint16_t)(w & 0xFFFFu);
-      S[(16 * m + 4 * g + r + 1) * kSRow + c] = (uint16_t)(w >> 16);
-    }
-}
 
 // dL/de of one tile held back one step, stored after the next tile's
 // forward; as BF16 pairs (the table-gradient records it feeds are BF16 too).
@@ -646,18 +635,18 @@ __device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const _
   // the hidden-layer gradients are used only as BF16 (MFMA operands and
   // staged values), so they are rounded once and masked on their bits
   bf8 dhl[N::HC / 32];
+  const bf8 dzp = pack8(dz, zero);
   {
-    const bf8 b = pack8(dz, zero);
     f4 raw[N::HC / 16];
 #pragma unroll
-    for (int m = 0; m < N::HC / 16; ++m) raw[m] = mfma32(w4[m], b, zero);
+    for (int m = 0; m < N::HC / 16; ++m) raw[m] = mfma32(w4[m], dzp, zero);
 #pragma unroll
     for (int k = 0; k < N::HC / 32; ++k) dhl[k] = relu_mask8(pack8(raw[2 * k], raw[2 * k + 1]), hl[k]);
   }
   if constexpr (N::NCH == 2) load_ops<N>(Ab + M::boff(3), lane, w3);
   else load_ops<N>(Ab + M::boff(2), lane, w2);
   stage1_packed<N::HC / 16>(srow16<N>(stage, buf, SR::x(N::NW - 1)), hl, g, c);
-  stage1_f32<1>(srow16<N>(stage, buf, SR::y(N::NW - 1)), &dz, g, c);
+  stage1_packed<1>(srow16<N>(stage, buf, SR::y(N::NW - 1)), &dzp, g, c);
   bf8 dh3[N::HC / 32];
   if constexpr (N::NCH == 2) {
     f4 acc[N::HC / 16];
@@ -689,17 +678,17 @@ __device__ __forceinline__ void bwd_tile8(const __bf16* __restrict__ Af, const _
   stage1_packed<N::HC / 16>(srow16<N>(stage, buf, SR::y(2)), dh3, g, c);
   if (g == 0) dgeo[0] += __expf(a[0].o[0]) * in.ds;  // rounded to BF16 next
   bf8 dh1[N::HD / 32];
+  const bf8 dgp = pack8(dgeo, zero);
   {
-    const bf8 b = pack8(dgeo, zero);
     f4 raw[N::HD / 16];
 #pragma unroll
-    for (int m = 0; m < N::HD / 16; ++m) raw[m] = mfma32(w1[m], b, zero);
+    for (int m = 0; m < N::HD / 16; ++m) raw[m] = mfma32(w1[m], dgp, zero);
 #pragma unroll
     for (int k = 0; k < N::HD / 32; ++k) dh1[k] = relu_mask8(pack8(raw[2 * k], raw[2 * k + 1]), a[0].h1[k]);
   }
   load_ops<N>(Ab + M::boff(0), lane, w0);
   stage1_packed<N::HD / 16>(srow16<N>(stage, buf, SR::x(1)), a[0].h1, g, c);
-  stage1_f32<1>(srow16<N>(stage, buf, SR::y(1)), &dgeo, g, c);
+  stage1_packed<1>(srow16<N>(stage, buf, SR::y(1)), &dgp, g, c);
   __syncthreads();
   dw.w2.add(srow<N>(stage, buf, SR::x(2)), srow<N>(stage, buf, SR::y(2)), w, lane);
   dw.w1.add(srow<N>(stage, buf, SR::x(1)), srow<N>(stage, buf, SR::y(1)), w, lane);
